@@ -1,0 +1,210 @@
+/*
+ * lb.h - C ABI of the MI355X IMEX trust-region library for the
+ * Landau-Brazovskii (LB) energy (Bao, Deng, Jiang, Zhang, arXiv 2603.03933).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid (Section 2, grid set T_M^d): a periodic orthorhombic box
+ * [0,box[0]) x ... with n[a] points per axis, x_j = j * box[a] / n[a];
+ * reciprocal lattice B = diag(2 pi / box), reciprocal indices k_a in
+ * [-n_a/2, n_a/2). Supported axis lengths: 2^a 3^b with 8 <= n <= 512.
+ *
+ * Fields are real arrays of N = prod(n) doubles in C order (last axis
+ * fastest), `batch` instances back to back. Every array argument is a DEVICE
+ * pointer owned by the caller (for example a torch tensor's data_ptr()); the
+ * library never frees or keeps it beyond the call. Structs (lb_grid,
+ * lb_params, *_opts, *_info) are HOST pointers.
+ *
+ * Inner products and norms are those of the paper's Psi_hat coordinates
+ * (Section 2, discrete inner product): <a,b> = (1/N) sum_x a(x) b(x) and
+ * ||a|| = sqrt(<a,a>) = RMS(a). The mass constraint (Section 2, e_1^T
+ * Psi_hat = 0) is enforced by removing the k = 0 Fourier mode (projection P
+ * of Section 3); inputs are expected to have zero mean.
+ *
+ * Energy (eq. lb_energy, discretised in eq. interaction_bulk_energy):
+ *   E = 1/2 sum_k Lambda_k |psi_hat_k|^2 + (1/N) sum_x F(psi(x)),
+ *   Lambda_k = xi^2 (q^2 - |Bk|^2)^2, F = tau/2 psi^2 - gamma/6 psi^3 + psi^4/24.
+ * The paper has xi = q = 1.
+ *
+ * Streams: all work is enqueued on the plan's HIP stream (`stream` is a
+ * hipStream_t; NULL means the null stream). Calls that only launch kernels
+ * return before the GPU finishes; calls that fill a host `info` struct
+ * synchronise the stream before returning. A plan is not thread safe: use one
+ * plan per stream. Plans allocate all their device workspace in
+ * lb_plan_create; no other call allocates.
+ *
+ * Return codes: LB_OK, LB_NOT_CONVERGED (outputs valid, details in info), or a
+ * negative error; lb_last_error() returns a message for the last error of the
+ * calling thread.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_NOT_CONVERGED 1
+#define LB_ERR_ARG (-1)         /* null pointer, bad size, radius <= 0, ...  */
+#define LB_ERR_HIP (-2)         /* HIP runtime error                        */
+#define LB_ERR_MISMATCH (-3)    /* call does not fit the plan (batch, ...)  */
+#define LB_ERR_NONFINITE (-4)   /* NaN or Inf met in a reduction            */
+#define LB_ERR_UNSUPPORTED (-5) /* grid size or box the build cannot handle */
+
+/* Arithmetic of the FFT and pointwise stages of lb_hessvec and of the inner
+ * subproblem iteration. Energies, gradients, norms, dot products, the
+ * Lagrange-multiplier update and the trust-region ratio are always FP64. */
+#define LB_FP64 0
+#define LB_FP32 1
+
+typedef struct lb_grid {
+  int dim;        /* 2 or 3 */
+  int n[3];       /* points per axis (n[2] unused when dim == 2) */
+  double box[3];  /* box side per axis, > 0 */
+} lb_grid;
+
+typedef struct lb_params {
+  double tau;   /* reduced temperature (eq. lb_energy) */
+  double gamma; /* three-body coefficient (eq. lb_energy) */
+  double xi;    /* interaction strength, 1 in the paper */
+  double q;     /* critical wave number, 1 in the paper */
+} lb_params;
+
+/* Options of the subproblem solver (Algorithm 3). */
+typedef struct lb_sub_opts {
+  double eta;            /* IMEX step size eta (Section 4: 0.1) */
+  double eps_sub;        /* stop when ||g + (H + lambda I) d|| < eps_sub (Section 4: 1e-13) */
+  double eps_sub_rel;    /* ... or < eps_sub_rel * ||g|| (0 disables) */
+  int max_inner;         /* cap on iterations of Algorithm 3 */
+  int max_newton;        /* cap on Newton steps per iteration */
+  double newton_rtol;    /* Newton stops when phi(lambda) - r^2 <= newton_rtol r^2 */
+  double newton_steptol; /* ... or |delta lambda| <= newton_steptol max(1, lambda) */
+  int poll_every;        /* iterations enqueued between host reads of the stop flag */
+} lb_sub_opts;
+
+typedef struct lb_sub_info {
+  double lambda;      /* Lagrange multiplier of the returned d */
+  double resid;       /* ||g + (H + lambda I) d|| of the returned d */
+  double dnorm;       /* ||d|| */
+  double gnorm;       /* ||g|| */
+  int iters;          /* iterations of Algorithm 3 performed */
+  int newton_iters;   /* Newton steps summed over the iterations */
+  int status;         /* LB_OK or LB_NOT_CONVERGED (cap reached) */
+} lb_sub_info;
+
+/* Options of the outer IMEX-TR loop (Algorithms 1 and 2). Defaults from
+ * lb_tr_opts_default are the paper's Section 4 values plus the readings
+ * documented with each field. */
+typedef struct lb_tr_opts {
+  double theta, gamma_c, gamma_e, gamma_lambda; /* 1e-4, 0.5, 2, 1.5 */
+  double mu_lo, mu_hi, mu0, r0, nu0;            /* 1, 1e5, 1, 1, 5 */
+  double eps;           /* gradient tolerance (1e-10 with grad_norm_inf) */
+  int grad_norm_inf;    /* 1: ||g||_inf < eps (Algorithm 1); 0: ||g||_2 < eps */
+  double eta;           /* IMEX step size (0.1) */
+  int eta_safe;         /* 1: eta_j = min(eta, 0.9 / max|Gamma'(psi_j)|) so that the
+                           descent lemma's bound holds; 0: fixed eta */
+  int rho_taylor;       /* 1: E(v) - E(v+s) from the exact quartic expansion;
+                           0: from two energy evaluations */
+  int contract_else_old_step; /* CONTRACT else-branch radius: 0 -> gamma_C ||s|| with
+                                 the new s (as printed), 1 -> gamma_C ||s_j|| */
+  double nu_tol;        /* ||s_j|| = nu_j tested with relative tolerance nu_tol */
+  int max_outer;
+  lb_sub_opts sub;      /* subproblem options (eta is overwritten per iteration) */
+  double cg_rtol;       /* CONTRACT: CG relative tolerance on (H + lambda I) s = -g */
+  int cg_maxiter;
+  int verbose;          /* 1: one line per outer iteration on stderr */
+} lb_tr_opts;
+
+typedef struct lb_tr_info {
+  double energy;     /* E at the returned psi */
+  double gnorm;      /* ||g||_2 at the returned psi */
+  double gnorm_inf;  /* max_k |g_hat_k| at the returned psi */
+  int outer;         /* outer iterations performed */
+  int inner_total;   /* subproblem iterations summed */
+  int cg_total;      /* CG iterations spent in CONTRACT */
+  int accepted, contracted, expanded;
+  int status;        /* LB_OK or LB_NOT_CONVERGED */
+} lb_tr_info;
+
+typedef struct lb_plan lb_plan;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int lb_version(void);
+
+/* Message describing the last error returned on the calling thread. */
+const char *lb_last_error(void);
+
+/* Fill option structs with the defaults described above. */
+void lb_sub_opts_default(lb_sub_opts *opts);
+void lb_tr_opts_default(lb_tr_opts *opts);
+
+/* Create a plan for `batch` instances of `grid` computing in `precision`
+ * (LB_FP64 or LB_FP32) on `stream`. Allocates twiddle tables, the
+ * reciprocal-shell tables of the Newton step and every device workspace.
+ * Errors: LB_ERR_ARG, LB_ERR_UNSUPPORTED (axis length), LB_ERR_HIP. */
+int lb_plan_create(lb_plan **out, const lb_grid *grid, int batch, int precision, void *stream);
+int lb_plan_destroy(lb_plan *plan);
+int lb_plan_set_stream(lb_plan *plan, void *stream);
+/* Device bytes held by the plan. */
+size_t lb_plan_workspace_bytes(const lb_plan *plan);
+
+/* Energy and projected gradient (Section 2: grad G = Lambda Psi_hat,
+ * grad F = F_N Gamma F_N^{-1} Psi_hat; Section 3: projection P).
+ *   params : `batch` entries (host)
+ *   psi    : batch * N doubles (device, zero mean)
+ *   energy : batch doubles (device), written
+ *   grad   : batch * N doubles (device) or NULL; the physical form of the
+ *            projected gradient g = P(F_N^{-1} Lambda psi_hat + F'(psi)),
+ *            whose norm ||g|| is the paper's ||grad E_bar||.
+ * Always FP64. Asynchronous. */
+int lb_energy_grad(lb_plan *plan, const lb_params *params, const double *psi, double *energy, double *grad);
+
+/* Hessian-vector product (Section 2: grad^2 G = Lambda, grad^2 F = F_N Gamma' F_N^{-1};
+ * Section 3.2: H = D + T):
+ *   hv = P( F_N^{-1} Lambda F_N v + Gamma'(psi) v ),  Gamma' = tau - gamma psi + psi^2/2.
+ * The interaction part is applied after a forward FFT, the bulk part pointwise.
+ *   psi, v : batch * N doubles (device); hv : batch * N doubles (device), written
+ *   project: 1 removes the mean of hv (the operator on the zero-mean subspace);
+ *            0 returns F_N^{-1} P Lambda F_N v + Gamma' v.
+ * FFT arithmetic in the plan's precision. Asynchronous. */
+int lb_hessvec(lb_plan *plan, const lb_params *params, const double *psi, const double *v, double *hv, int project);
+
+/* Trust-region subproblem min_{||d|| <= radius} <g,d> + <d,Hd>/2 by the
+ * adaptive IMEX iteration (Section 3.2, Algorithm 3; eqs. imex-scheme and
+ * lambda_update_rule), batch must be 1.
+ *   psi   : N doubles (device); grad : N doubles (device), the projected
+ *           gradient g (as written by lb_energy_grad), nonzero
+ *   d0    : N doubles (device) initial feasible point, or NULL for the
+ *           paper's d_0 = -radius g / ||g||
+ *   d_out : N doubles (device), the step d (zero mean)
+ *   info  : host, filled on return (the call synchronises the stream)
+ * Returns LB_OK, LB_NOT_CONVERGED (max_inner reached, d_out valid) or an error. */
+int lb_tr_subproblem(lb_plan *plan, const lb_params *params, const double *psi, const double *grad, double radius,
+                     const lb_sub_opts *opts, const double *d0, double *d_out, lb_sub_info *info);
+
+/* Full IMEX-TR solve (Section 3.1, Algorithms 1 and 2 around Algorithm 3),
+ * batch must be 1. psi (device, N doubles, zero mean) is overwritten with
+ * the final iterate. info is filled on return. */
+int lb_imex_tr_solve(lb_plan *plan, const lb_params *params, double *psi, const lb_tr_opts *opts, lb_tr_info *info);
+
+/* CONTRACT's linear system (Algorithm 2): conjugate gradients for
+ * (H + shift I) s = -g on the zero-mean subspace (H + shift I must be
+ * positive definite). grad, s_out: N doubles (device). batch must be 1.
+ * *iters receives the CG iteration count. */
+int lb_shifted_solve(lb_plan *plan, const lb_params *params, const double *psi, const double *grad, double shift,
+                     double rtol, int maxiter, double *s_out, int *iters);
+
+/* Second-order check: smallest Ritz value of H on the zero-mean subspace
+ * after `steps` Lanczos steps (full reorthogonalisation) from v0 (device, N
+ * doubles). A Ritz value bounds sigma_1 from above; *resid is the Ritz
+ * residual norm. batch must be 1. Host outputs. */
+int lb_lanczos_min(lb_plan *plan, const lb_params *params, const double *psi, const double *v0, int steps,
+                   double *ritz_min, double *resid);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB_H */

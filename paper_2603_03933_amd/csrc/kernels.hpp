@@ -1,0 +1,858 @@
+// kernels.hpp - HIP kernels of the IMEX-TR hot path for gfx950.
+//
+// Spectral layout: the half spectrum of a real field, shape [n0][n1][nl/2+1]
+// (3D) or [n0][nl/2+1] (2D), complex, last axis fastest, `batch` instances
+// back to back. A mode with 0 < k_last < nl/2 stands for itself and its
+// conjugate partner, so sums over the full spectrum weigh it by 2.
+//
+// A 3D transform is a row pass (last axis, real <-> complex, two real rows
+// packed into one complex transform) plus column passes along axes 1 and 0
+// (strided, C neighbouring columns per workgroup so that every global access
+// is coalesced). The pointwise stages of the method ride on the row passes
+// and the diagonal reciprocal-space stages on the axis-0 pass. Reductions
+// write one partial per workgroup; a single workgroup sums them in a fixed
+// order, so every result is bitwise reproducible.
+#pragma once
+#include "fft.hpp"
+
+namespace lbk {
+using namespace lbfft;
+
+constexpr int MAXB = 8;  // instances per launch
+
+struct Prm {  // model coefficients per instance (kernel argument, by value)
+  double tau[MAXB], gamma[MAXB], xi[MAXB], q[MAXB];
+};
+
+struct Geo {
+  int dim;       // 2 or 3
+  int n0, n1;    // leading axes (n1 = 1 in 2D)
+  int nl, nhl;   // last axis and its half-spectrum length nl/2 + 1
+  long N;        // points per instance
+  long nh;       // half-spectrum modes per instance
+  int batch;
+  const double *kk0, *kk1, *kkl;  // (2 pi k / L)^2 per axis, index in storage order
+};
+
+__device__ __forceinline__ double lam_of(double kk, double xi, double q) {
+  const double t = q * q - kk;
+  return xi * xi * t * t;
+}
+
+// instance-relative half-spectrum offset -> (i0, i1, kl)
+__device__ __forceinline__ void decode(const Geo &g, long h, int &i0, int &i1, int &kl) {
+  kl = (int)(h % g.nhl);
+  const long r = h / g.nhl;
+  i1 = (int)(r % g.n1);
+  i0 = (int)(r / g.n1);
+}
+__device__ __forceinline__ double kk_at(const Geo &g, long h, int &kl) {
+  int i0, i1;
+  decode(g, h, i0, i1, kl);
+  double kk = g.kk0[i0] + g.kkl[kl];
+  if (g.dim == 3) kk += g.kk1[i1];
+  return kk;
+}
+__device__ __forceinline__ double herm_w(const Geo &g, int kl) { return (kl == 0 || 2 * kl == g.nl) ? 1.0 : 2.0; }
+
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+template <int N> struct Cfg {
+  static constexpr int TPF = Shape<N>::TPF;
+  static constexpr int C0 = pow2_floor(256 / TPF);
+  static constexpr int C = C0 > 64 ? 64 : (C0 < 1 ? 1 : C0);  // transforms per workgroup
+  static constexpr int NT = C * TPF;                            // threads per workgroup
+};
+
+// ---------------------------------------------------------------------------
+// Block reductions (wavefront shuffles, then LDS across waves)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// result valid in thread 0; `scratch` holds >= 16 doubles; all threads must call
+template <int NT> __device__ __forceinline__ double block_sum(double v, double *scratch) {
+  constexpr int NW = (NT + 63) / 64;
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NW; ++w) s += scratch[w];
+  return s;
+}
+// sum over the block returned to every thread; `scratch` holds >= 17 doubles
+template <int NT> __device__ __forceinline__ double block_sum_all(double v, double *scratch) {
+  const double s = block_sum<NT>(v, scratch);
+  if (threadIdx.x == 0) scratch[16] = s;
+  __syncthreads();
+  const double r = scratch[16];
+  __syncthreads();
+  return r;
+}
+template <int NT> __device__ __forceinline__ double block_max(double v, double *scratch) {
+  constexpr int NW = (NT + 63) / 64;
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NW; ++w) s = fmax(s, scratch[w]);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Inner-iteration state (one per instance, device memory)
+// ---------------------------------------------------------------------------
+struct SubState {
+  double lam[2];      // lambda_t for step t at lam[t & 1]
+  double eta, r2, tol;
+  double newton_rtol, newton_steptol;
+  double resid;       // residual norm of the iterate tested last
+  double lam_final;   // multiplier of the returned iterate
+  int step;           // current step t
+  int done;           // 0 running, 1 converged, 2 iteration cap
+  int final_step;
+  int newton_total;
+  int max_inner, max_newton;
+  int nonfinite;
+  int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Column passes
+// ---------------------------------------------------------------------------
+struct ColGeo {
+  int cpi;            // columns per instance
+  int bpi;            // workgroups per instance
+  long inner, outer;  // base(m) = (m / inner) * outer + m % inner
+  long S;             // element stride along the transformed axis
+  long inst;          // instance stride
+};
+
+template <typename T, int N, bool INV, class Op>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__restrict__ tw, Op op) {
+  using C = c2<T>;
+  constexpr int CC = Cfg<N>::C;
+  constexpr int NT = Cfg<N>::NT;
+  __shared__ C lds[N * CC];
+  if (op.skip()) return;
+  const int b = blockIdx.x / cg.bpi;
+  const int lb = blockIdx.x % cg.bpi;
+  const int c = threadIdx.x % CC, t = threadIdx.x / CC;
+  const long ml = (long)lb * CC + c;
+  const bool ok = ml < cg.cpi;
+  const long base = b * cg.inst + (ml / cg.inner) * cg.outer + (ml % cg.inner);
+  op.begin(b);
+  fft_run<T, N, INV>(
+      t, c, lds, [](int cc, int e) { return e * CC + cc; }, tw,
+      [&](int e) -> C { return ok ? op.load(b, base + e * cg.S, e) : C{T(0), T(0)}; },
+      [&](int e, C v) {
+        if (ok) op.store(b, base + e * cg.S, e, v);
+      });
+  op.template end<NT>(b, reinterpret_cast<double *>(lds));
+}
+
+// plain pass: out = scale * FFT(in); optional removal of the k = 0 mode
+template <typename T> struct OpPlain {
+  const c2<T> *in;
+  c2<T> *out;
+  T scale;
+  int zero_dc;  // only meaningful on the final (axis 0) pass
+  long nh;
+  const SubState *st;  // non-null: skip once the subproblem has stopped
+  __device__ bool skip() const { return st && st->done; }
+  __device__ void begin(int) {}
+  __device__ c2<T> load(int, long h, int) const { return in[h]; }
+  __device__ void store(int, long h, int, c2<T> v) const {
+    if (zero_dc && (h % nh) == 0) v = c2<T>{T(0), T(0)};
+    out[h] = c2<T>{v.x * scale, v.y * scale};
+  }
+  template <int NT> __device__ void end(int, double *) {}
+};
+
+// step t of the subproblem, axis-0 inverse pass: d_t = b_{t-1} / (1 + eta (Lambda + lambda_t))
+template <typename T> struct OpInvScaleD {
+  Geo g;
+  Prm p;
+  const c2<T> *b0, *b1;  // b buffers: b_{t-1} lives in (t - 1) & 1
+  c2<T> *out;
+  const SubState *st;
+  double fac_lam, eta;
+  const c2<T> *src;
+  __device__ bool skip() const { return st->done != 0; }
+  __device__ void begin(int b) {
+    const int t = st->step;
+    src = ((t - 1) & 1) ? b1 : b0;
+    fac_lam = st->lam[t & 1];
+    eta = st->eta;
+  }
+  __device__ c2<T> load(int b, long h, int) const {
+    int kl;
+    const long hl = h - (long)b * g.nh;
+    if (hl == 0) return c2<T>{T(0), T(0)};
+    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
+    const double s = 1.0 / (1.0 + eta * (lam + fac_lam));
+    const c2<T> v = src[h];
+    return c2<T>{T(v.x * s), T(v.y * s)};
+  }
+  __device__ void store(int, long h, int, c2<T> v) const { out[h] = v; }
+  template <int NT> __device__ void end(int, double *) {}
+};
+
+// step t, axis-0 forward pass of T d_t, then the diagonal update:
+//   Td = P F_N(Gamma' d_t),  r_t = g + (Lambda + lambda_t) d_t + Td  (residual of d_t),
+//   b_t = d_t - eta (g + Td),  bsq = w |b_t|^2 (for the secular function)
+template <typename T> struct OpFwdUpdate {
+  Geo g;
+  Prm p;
+  const c2<T> *tmp;  // axis-1/row transformed product Gamma' d_t
+  c2<T> *b0, *b1;
+  const c2<T> *gh;
+  double *bsq;
+  double *partial;   // one double per workgroup: sum w |r|^2
+  const SubState *st;
+  double inv_n;
+  double lam_t, eta;
+  const c2<T> *bprev;
+  c2<T> *bnext;
+  double acc;
+  __device__ bool skip() const { return st->done != 0; }
+  __device__ void begin(int) {
+    const int t = st->step;
+    bprev = ((t - 1) & 1) ? b1 : b0;
+    bnext = (t & 1) ? b1 : b0;
+    lam_t = st->lam[t & 1];
+    eta = st->eta;
+    acc = 0.0;
+  }
+  __device__ c2<T> load(int, long h, int) const { return tmp[h]; }
+  __device__ void store(int b, long h, int, c2<T> v) {
+    const long hl = h - (long)b * g.nh;
+    if (hl == 0) {
+      bnext[h] = c2<T>{T(0), T(0)};
+      bsq[h] = 0.0;
+      return;
+    }
+    int kl;
+    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
+    const double w = herm_w(g, kl);
+    const double s = 1.0 / (1.0 + eta * (lam + lam_t));
+    const c2<T> bp = bprev[h];
+    const double dx = double(bp.x) * s, dy = double(bp.y) * s;
+    const double tx = double(v.x) * inv_n, ty = double(v.y) * inv_n;
+    const c2<T> gg = gh[h];
+    const double gx = double(gg.x), gy = double(gg.y);
+    const double rx = gx + (lam + lam_t) * dx + tx, ry = gy + (lam + lam_t) * dy + ty;
+    acc += w * (rx * rx + ry * ry);
+    const double bx = dx - eta * (gx + tx), by = dy - eta * (gy + ty);
+    const c2<T> bn = c2<T>{T(bx), T(by)};
+    bnext[h] = bn;
+    const double bxr = double(bn.x), byr = double(bn.y);
+    bsq[h] = w * (bxr * bxr + byr * byr);
+  }
+  template <int NT> __device__ void end(int, double *scratch) {
+    const double s = block_sum<NT>(acc, scratch);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+};
+
+// axis-0 forward pass completing a spectral Hessian-vector product:
+//   out = Lambda x + P F_N(Gamma' F_N^{-1} x) + shift x
+template <typename T> struct OpFwdHess {
+  Geo g;
+  Prm p;
+  const c2<T> *tmp;
+  const c2<T> *x;
+  c2<T> *out;
+  double inv_n, shift;
+  __device__ bool skip() const { return false; }
+  __device__ void begin(int) {}
+  __device__ c2<T> load(int, long h, int) const { return tmp[h]; }
+  __device__ void store(int b, long h, int, c2<T> v) const {
+    const long hl = h - (long)b * g.nh;
+    if (hl == 0) {
+      out[h] = c2<T>{T(0), T(0)};
+      return;
+    }
+    int kl;
+    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]) + shift;
+    const c2<T> xv = x[h];
+    out[h] = c2<T>{T(lam * double(xv.x) + double(v.x) * inv_n), T(lam * double(xv.y) + double(v.y) * inv_n)};
+  }
+  template <int NT> __device__ void end(int, double *) {}
+};
+
+// Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
+// (k = 0 removed), inverse transform, all in one workgroup pass.
+template <typename T, int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo g, Prm p, const c2<T> *__restrict__ tw,
+                                                                  c2<T> *data, double inv_n) {
+  using C = c2<T>;
+  constexpr int CC = Cfg<N>::C;
+  __shared__ C lds[N * CC];
+  const int b = blockIdx.x / cg.bpi;
+  const int lb = blockIdx.x % cg.bpi;
+  const int c = threadIdx.x % CC, t = threadIdx.x / CC;
+  const long ml = (long)lb * CC + c;
+  const bool ok = ml < cg.cpi;
+  const long base = b * cg.inst + (ml / cg.inner) * cg.outer + (ml % cg.inner);
+  auto lidx = [](int cc, int e) { return e * CC + cc; };
+  fft_run<T, N, false>(
+      t, c, lds, lidx, tw, [&](int e) -> C { return ok ? data[base + e * cg.S] : C{T(0), T(0)}; },
+      [&](int e, C v) {
+        const long hl = base + e * cg.S - (long)b * g.nh;
+        double m = 0.0;
+        if (ok && hl != 0) {
+          int kl;
+          m = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]) * inv_n;
+        }
+        lds[lidx(c, e)] = C{T(double(v.x) * m), T(double(v.y) * m)};
+      });
+  __syncthreads();
+  fft_run<T, N, true>(
+      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; },
+      [&](int e, C v) {
+        if (ok) data[base + e * cg.S] = v;
+      });
+}
+
+// ---------------------------------------------------------------------------
+// Row passes (last axis). Two real rows a, b are packed as z = a + i b; the
+// half spectra follow from Z_k and conj(Z_{N-k}).
+// ---------------------------------------------------------------------------
+struct RowGeo {
+  long rpi;  // real rows per instance
+  int bpi;   // workgroups per instance
+};
+
+template <int N> struct RowLds {
+  static constexpr int LD = N + 1;  // padded row pitch in LDS
+};
+
+// Forward real-to-half-spectrum of pairs of rows with a fused prologue.
+//   MODE 0 (plain): z = (in[a], in[b])
+//   MODE 1 (hessian input): same, and partial sums of Gamma'(psi) v for the mean
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_rows_r2c(RowGeo rg, Geo g, Prm p, const c2<T> *__restrict__ tw,
+                                                          const double *__restrict__ in, const double *__restrict__ psi,
+                                                          c2<T> *__restrict__ out, double *partial) {
+  using C = c2<T>;
+  constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
+  __shared__ C lds[CC * LD];
+  const int b = blockIdx.x / rg.bpi;
+  const long pair0 = (long)(blockIdx.x % rg.bpi) * CC;
+  const long ppi = rg.rpi / 2;
+  const long rowbase = (long)b * rg.rpi;
+  double acc = 0.0;
+  const double tau = p.tau[b], gam = p.gamma[b];
+  for (int i = threadIdx.x; i < CC * N; i += NT) {
+    const int c = i / N, e = i % N;
+    const long pr = pair0 + c;
+    C z{T(0), T(0)};
+    if (pr < ppi) {
+      const long ia = (rowbase + 2 * pr) * N + e, ib = ia + N;
+      const double va = in[ia], vb = in[ib];
+      z = C{T(va), T(vb)};
+      if constexpr (MODE == 1) {
+        const double pa = psi[ia], pb = psi[ib];
+        acc += (tau - gam * pa + 0.5 * pa * pa) * va + (tau - gam * pb + 0.5 * pb * pb) * vb;
+      }
+    }
+    lds[c * LD + e] = z;
+  }
+  __syncthreads();
+  const int c = threadIdx.x % CC, t = threadIdx.x / CC;
+  auto lidx = [](int cc, int e) { return cc * LD + e; };
+  fft_run<T, N, false>(
+      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  __syncthreads();
+  for (int i = threadIdx.x; i < CC * NHL; i += NT) {
+    const int cc = i / NHL, k = i % NHL;
+    const long pr = pair0 + cc;
+    if (pr < ppi) {
+      const C zk = lds[cc * LD + k], zm = lds[cc * LD + ((N - k) % N)];
+      const C A{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+      const C B{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+      const long oa = (rowbase + 2 * pr) * NHL + k;
+      out[oa] = A;
+      out[oa + NHL] = B;
+    }
+  }
+  if constexpr (MODE == 1) {
+    const double s = block_sum<NT>(acc, reinterpret_cast<double *>(lds));
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// Energy row pass: one row per transform, z = psi + i F'(psi); writes the half
+// spectra of psi (out0) and of F'(psi) (out1), Gamma'(psi) in T precision, and
+// per-workgroup partials [sum F(psi), max |Gamma'|].
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_rows_energy(RowGeo rg, Geo g, Prm p, const double2 *__restrict__ tw,
+                                                            const double *__restrict__ psi, double2 *__restrict__ out0,
+                                                            double2 *__restrict__ out1, double *__restrict__ gp64,
+                                                            float *__restrict__ gp32, double *partial) {
+  using C = double2;
+  constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
+  __shared__ C lds[CC * LD];
+  const int b = blockIdx.x / rg.bpi;
+  const long row0 = (long)(blockIdx.x % rg.bpi) * CC;
+  const long rowbase = (long)b * rg.rpi;
+  const double tau = p.tau[b], gam = p.gamma[b];
+  double accF = 0.0, mx = 0.0;
+  for (int i = threadIdx.x; i < CC * N; i += NT) {
+    const int c = i / N, e = i % N;
+    const long rr = row0 + c;
+    C z{0.0, 0.0};
+    if (rr < rg.rpi) {
+      const long ix = (rowbase + rr) * N + e;
+      const double s = psi[ix];
+      const double s2 = s * s;
+      const double dF = tau * s - 0.5 * gam * s2 + s2 * s / 6.0;
+      const double Fv = 0.5 * tau * s2 - gam * s2 * s / 6.0 + s2 * s2 / 24.0;
+      const double gpv = tau - gam * s + 0.5 * s2;
+      accF += Fv;
+      mx = fmax(mx, fabs(gpv));
+      if (gp64) gp64[ix] = gpv;
+      if (gp32) gp32[ix] = float(gpv);
+      z = C{s, dF};
+    }
+    lds[c * LD + e] = z;
+  }
+  __syncthreads();
+  const int c = threadIdx.x % CC, t = threadIdx.x / CC;
+  auto lidx = [](int cc, int e) { return cc * LD + e; };
+  fft_run<double, N, false>(
+      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  __syncthreads();
+  for (int i = threadIdx.x; i < CC * NHL; i += NT) {
+    const int cc = i / NHL, k = i % NHL;
+    const long rr = row0 + cc;
+    if (rr < rg.rpi) {
+      const C zk = lds[cc * LD + k], zm = lds[cc * LD + ((N - k) % N)];
+      const long o = (rowbase + rr) * NHL + k;
+      out0[o] = C{0.5 * (zk.x + zm.x), 0.5 * (zk.y - zm.y)};
+      out1[o] = C{0.5 * (zk.y + zm.y), 0.5 * (zm.x - zk.x)};
+    }
+  }
+  const double sF = block_sum<NT>(accF, reinterpret_cast<double *>(lds));
+  const double sM = block_max<NT>(mx, reinterpret_cast<double *>(lds) + 32);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sF;
+    partial[2 * blockIdx.x + 1] = sM;
+  }
+}
+
+// Load half rows a, b of a pair into LDS as Z = A + i B over the full length
+// (Hermitian extension), dropping the imaginary parts that a real row's
+// k = 0 and k = N/2 coefficients cannot have.
+template <typename T, int N, class Src>
+__device__ __forceinline__ void pack_pairs(c2<T> *lds, long pair0, long ppi, const Src &src) {
+  using C = c2<T>;
+  constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
+  for (int i = threadIdx.x; i < CC * NHL; i += NT) {
+    const int c = i / NHL, k = i % NHL;
+    const long pr = pair0 + c;
+    C A{T(0), T(0)}, B{T(0), T(0)};
+    if (pr < ppi) src(pr, k, A, B);
+    if (k == 0 || 2 * k == N) {
+      A.y = T(0);
+      B.y = T(0);
+    }
+    lds[c * LD + k] = C{A.x - B.y, A.y + B.x};
+    if (k > 0 && 2 * k < N) lds[c * LD + N - k] = C{A.x + B.y, B.x - A.y};
+  }
+}
+
+// Inverse half-spectrum-to-real of pairs of rows with a fused epilogue.
+//   MODE 0 (plain):    out = x
+//   MODE 1 (hessian):  out = x + Gamma'(psi) v - mean, mean = (sum of the
+//                      matching r2c pass's per-workgroup partials `mpart`) / N
+//                      (mpart == nullptr: no mean removal)
+//   MODE 2 (taylor):   out = s = x, partial sums of
+//                      Gamma' s^2 / 2 + (psi - gamma) s^3 / 6 + s^4 / 24
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_rows_c2r(RowGeo rg, Geo g, Prm p, const c2<T> *__restrict__ tw,
+                                                          const c2<T> *__restrict__ in, double *__restrict__ out,
+                                                          const double *__restrict__ psi, const double *__restrict__ v,
+                                                          const double *__restrict__ mpart, int mbpi, double *partial) {
+  using C = c2<T>;
+  constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
+  __shared__ C lds[CC * LD];
+  const int b = blockIdx.x / rg.bpi;
+  const long pair0 = (long)(blockIdx.x % rg.bpi) * CC;
+  const long ppi = rg.rpi / 2;
+  const long rowbase = (long)b * rg.rpi;
+  double mean = 0.0;
+  if constexpr (MODE == 1) {
+    if (mpart) {
+      double a = 0.0;
+      for (int i = threadIdx.x; i < mbpi; i += NT) a += mpart[(long)b * mbpi + i];
+      mean = block_sum_all<NT>(a, reinterpret_cast<double *>(lds)) / (double)g.N;
+    }
+  }
+  pack_pairs<T, N>(lds, pair0, ppi, [&](long pr, int k, C &A, C &B) {
+    const long ia = (rowbase + 2 * pr) * NHL + k;
+    A = in[ia];
+    B = in[ia + NHL];
+  });
+  __syncthreads();
+  const int c = threadIdx.x % CC, t = threadIdx.x / CC;
+  auto lidx = [](int cc, int e) { return cc * LD + e; };
+  fft_run<T, N, true>(
+      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  __syncthreads();
+  const double tau = p.tau[b], gam = p.gamma[b];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < CC * N; i += NT) {
+    const int cc = i / N, e = i % N;
+    const long pr = pair0 + cc;
+    if (pr < ppi) {
+      const C z = lds[cc * LD + e];
+      const long ia = (rowbase + 2 * pr) * N + e, ib = ia + N;
+      double xa = double(z.x), xb = double(z.y);
+      if constexpr (MODE == 1) {
+        const double pa = psi[ia], pb = psi[ib];
+        xa += (tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean;
+        xb += (tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean;
+      }
+      if constexpr (MODE == 2) {
+        const double pa = psi[ia], pb = psi[ib];
+        const double a2 = xa * xa, b2 = xb * xb;
+        acc += 0.5 * (tau - gam * pa + 0.5 * pa * pa) * a2 + (pa - gam) * a2 * xa / 6.0 + a2 * a2 / 24.0;
+        acc += 0.5 * (tau - gam * pb + 0.5 * pb * pb) * b2 + (pb - gam) * b2 * xb / 6.0 + b2 * b2 / 24.0;
+      }
+      out[ia] = xa;
+      out[ib] = xb;
+    }
+  }
+  if constexpr (MODE == 2) {
+    const double s = block_sum<NT>(acc, reinterpret_cast<double *>(lds));
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// Row pass of one subproblem step: inverse row transform of d_t's partial
+// spectrum, multiply by Gamma'(psi) pointwise, forward row transform back.
+template <typename T, int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T> *__restrict__ tw, c2<T> *data,
+                                                            const T *__restrict__ gp, const SubState *st) {
+  using C = c2<T>;
+  constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
+  __shared__ C lds[CC * LD];
+  if (st && st->done) return;
+  const int b = blockIdx.x / rg.bpi;
+  const long pair0 = (long)(blockIdx.x % rg.bpi) * CC;
+  const long ppi = rg.rpi / 2;
+  const long rowbase = (long)b * rg.rpi;
+  pack_pairs<T, N>(lds, pair0, ppi, [&](long pr, int k, C &A, C &B) {
+    const long ia = (rowbase + 2 * pr) * NHL + k;
+    A = data[ia];
+    B = data[ia + NHL];
+  });
+  __syncthreads();
+  const int c = threadIdx.x % CC, t = threadIdx.x / CC;
+  auto lidx = [](int cc, int e) { return cc * LD + e; };
+  fft_run<T, N, true>(
+      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  __syncthreads();
+  for (int i = threadIdx.x; i < CC * N; i += NT) {
+    const int cc = i / N, e = i % N;
+    const long pr = pair0 + cc;
+    if (pr < ppi) {
+      const long ia = (rowbase + 2 * pr) * N + e;
+      const C z = lds[cc * LD + e];
+      lds[cc * LD + e] = C{z.x * gp[ia], z.y * gp[ia + N]};
+    }
+  }
+  __syncthreads();
+  fft_run<T, N, false>(
+      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  __syncthreads();
+  for (int i = threadIdx.x; i < CC * NHL; i += NT) {
+    const int cc = i / NHL, k = i % NHL;
+    const long pr = pair0 + cc;
+    if (pr < ppi) {
+      const C zk = lds[cc * LD + k], zm = lds[cc * LD + ((N - k) % N)];
+      const long oa = (rowbase + 2 * pr) * NHL + k;
+      data[oa] = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+      data[oa + NHL] = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise spectral kernels and reductions
+// ---------------------------------------------------------------------------
+constexpr int EW_NT = 256;
+
+// gradient assembly after the forward transforms of psi and F'(psi):
+//   g = P(Lambda psi_hat + F_N F'(psi)) and partials
+//   [1/2 sum w Lambda |psi_hat|^2, sum w |g|^2, max |g|] per workgroup
+template <typename TG>
+__global__ __launch_bounds__(EW_NT) void k_grad_assemble(Geo g, Prm p, int bpi, const double2 *__restrict__ ph,
+                                                         const double2 *__restrict__ fh, double2 *__restrict__ gh,
+                                                         c2<TG> *__restrict__ gh_t, double *partial) {
+  __shared__ double scratch[64];
+  const int b = blockIdx.x / bpi;
+  const long lb = blockIdx.x % bpi;
+  double aG = 0.0, aN = 0.0, aM = 0.0;
+  for (long hl = lb * EW_NT + threadIdx.x; hl < g.nh; hl += (long)bpi * EW_NT) {
+    const long h = (long)b * g.nh + hl;
+    int kl;
+    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
+    const double w = herm_w(g, kl);
+    const double2 a = ph[h], f = fh[h];
+    aG += 0.5 * w * lam * (a.x * a.x + a.y * a.y);
+    double2 gv{lam * a.x + f.x, lam * a.y + f.y};
+    if (hl == 0) gv = double2{0.0, 0.0};
+    const double m2 = gv.x * gv.x + gv.y * gv.y;
+    aN += w * m2;
+    aM = fmax(aM, sqrt(m2));
+    gh[h] = gv;
+    if (gh_t) gh_t[h] = c2<TG>{TG(gv.x), TG(gv.y)};
+  }
+  const double s0 = block_sum<EW_NT>(aG, scratch);
+  const double s1 = block_sum<EW_NT>(aN, scratch + 16);
+  const double s2 = block_max<EW_NT>(aM, scratch + 32);
+  if (threadIdx.x == 0) {
+    partial[3 * blockIdx.x + 0] = s0;
+    partial[3 * blockIdx.x + 1] = s1;
+    partial[3 * blockIdx.x + 2] = s2;
+  }
+}
+
+// Spectral reductions over one instance's half spectrum (weights w):
+//   MODE 0: sum w Re(a conj(b))          MODE 1: sum w Lambda |a|^2
+template <typename TA, int MODE>
+__global__ __launch_bounds__(EW_NT) void k_spec_reduce(Geo g, Prm p, int bpi, const c2<TA> *__restrict__ a,
+                                                       const c2<TA> *__restrict__ bb, double *partial) {
+  __shared__ double scratch[16];
+  const int b = blockIdx.x / bpi;
+  const long lb = blockIdx.x % bpi;
+  double acc = 0.0;
+  for (long hl = lb * EW_NT + threadIdx.x; hl < g.nh; hl += (long)bpi * EW_NT) {
+    const long h = (long)b * g.nh + hl;
+    int kl;
+    const double kk = kk_at(g, hl, kl);
+    const double w = herm_w(g, kl);
+    const c2<TA> x = a[h];
+    if constexpr (MODE == 0) {
+      const c2<TA> y = bb[h];
+      acc += w * (double(x.x) * double(y.x) + double(x.y) * double(y.y));
+    } else {
+      acc += w * lam_of(kk, p.xi[b], p.q[b]) * (double(x.x) * double(x.x) + double(x.y) * double(x.y));
+    }
+  }
+  const double s = block_sum<EW_NT>(acc, scratch);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out = alpha * x + beta * y over n complex entries (types may differ)
+template <typename TO, typename TX, typename TY>
+__global__ __launch_bounds__(EW_NT) void k_lincomb(long n, double alpha, const c2<TX> *__restrict__ x, double beta,
+                                                   const c2<TY> *__restrict__ y, c2<TO> *__restrict__ out) {
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < n; i += (long)gridDim.x * EW_NT) {
+    double ox = 0.0, oy = 0.0;
+    if (alpha != 0.0) {
+      const c2<TX> a = x[i];
+      ox += alpha * double(a.x);
+      oy += alpha * double(a.y);
+    }
+    if (beta != 0.0) {
+      const c2<TY> c = y[i];
+      ox += beta * double(c.x);
+      oy += beta * double(c.y);
+    }
+    out[i] = c2<TO>{TO(ox), TO(oy)};
+  }
+}
+
+// Initial point of the subproblem, stored as b_{-1} = d_0 (1 + eta Lambda) so
+// that step 0 recovers d_0 with lambda_0 = 0:
+//   d_0 = coef * src (coef = -r / ||g|| with src = g, or 1 with src = user d0)
+template <typename T, typename TS>
+__global__ __launch_bounds__(EW_NT) void k_init_b(Geo g, Prm p, const c2<TS> *__restrict__ src, double coef, double eta,
+                                                  c2<T> *__restrict__ bm1) {
+  const long total = (long)g.batch * g.nh;
+  for (long h = (long)blockIdx.x * EW_NT + threadIdx.x; h < total; h += (long)gridDim.x * EW_NT) {
+    const int b = (int)(h / g.nh);
+    const long hl = h - (long)b * g.nh;
+    int kl;
+    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
+    const c2<TS> s = src[h];
+    const double f = (hl == 0) ? 0.0 : coef * (1.0 + eta * lam);
+    bm1[h] = c2<T>{T(f * double(s.x)), T(f * double(s.y))};
+  }
+}
+
+// Final step of the subproblem: d = b_{t*-1} / (1 + eta (Lambda + lambda_{t*})) in FP64
+template <typename T>
+__global__ __launch_bounds__(EW_NT) void k_final_d(Geo g, Prm p, const c2<T> *__restrict__ b0, const c2<T> *__restrict__ b1,
+                                                   const SubState *st, double2 *__restrict__ d) {
+  const int t = st->final_step;
+  const c2<T> *src = ((t - 1) & 1) ? b1 : b0;
+  const double lamf = st->lam_final, eta = st->eta;
+  for (long h = (long)blockIdx.x * EW_NT + threadIdx.x; h < g.nh; h += (long)gridDim.x * EW_NT) {
+    int kl;
+    const double lam = lam_of(kk_at(g, h, kl), p.xi[0], p.q[0]);
+    const double s = (h == 0) ? 0.0 : 1.0 / (1.0 + eta * (lam + lamf));
+    const c2<T> v = src[h];
+    d[h] = double2{double(v.x) * s, double(v.y) * s};
+  }
+}
+
+// Non-template kernels: defined only in the library's main translation unit.
+#ifdef LB_MAIN_TU
+// Sum `nq` interleaved per-workgroup partials over the `bpi` workgroups of
+// each instance in a fixed order; q listed in `is_max` use max instead.
+// One workgroup per instance; out[b * nq + q].
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int bpi, int nq,
+                                                  unsigned is_max, double *__restrict__ out) {
+  __shared__ double scratch[64];
+  const int b = blockIdx.x;
+  for (int q = 0; q < nq; ++q) {
+    const bool mx = (is_max >> q) & 1u;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < bpi; i += 256) {
+      const double v = partial[((long)b * bpi + i) * nq + q];
+      a = mx ? fmax(a, v) : a + v;
+    }
+    const double s = mx ? block_max<256>(a, scratch) : block_sum<256>(a, scratch);
+    if (threadIdx.x == 0) out[b * nq + q] = s;
+  }
+}
+
+// energy from the finalised sums: E_b = G_b + F_b / N
+__global__ void k_energy_out(const double *sumG, int strideG, const double *sumF, int strideF, double invN, int batch,
+                             double *energy) {
+  const int b = threadIdx.x;
+  if (b < batch) energy[b] = sumG[b * strideG] + sumF[b * strideF] * invN;
+}
+
+// real arrays: y = y + a * x
+__global__ __launch_bounds__(EW_NT) void k_axpy_real(long n, double a, const double *__restrict__ x, double *y) {
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < n; i += (long)gridDim.x * EW_NT) y[i] += a * x[i];
+}
+
+// Group the weighted |b|^2 by reciprocal shell: one wavefront per (instance, shell).
+__global__ __launch_bounds__(256) void k_bins(const double *__restrict__ bsq, const int *__restrict__ perm,
+                                              const int *__restrict__ seg, int nbins, long nh, int batch,
+                                              const SubState *st, double *__restrict__ bins) {
+  if (st && st->done) return;
+  const long wid = ((long)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wid >= (long)nbins * batch) return;
+  const int b = (int)(wid / nbins), s = (int)(wid % nbins);
+  const double *src = bsq + (long)b * nh;
+  double a = 0.0;
+  for (int i = seg[s] + lane; i < seg[s + 1]; i += 64) a += src[perm[i]];
+  a = wave_sum(a);
+  if (lane == 0) bins[wid] = a;
+}
+
+// Stop test of step t and the multiplier lambda_{t+1} of Algorithm 3:
+//   resid_t = sqrt(sum of the residual partials); done if t >= 1 and
+//   resid_t < tol (converged) or t >= max_inner (cap); otherwise
+//   lambda_{t+1} = 0 if phi(0) <= r^2, else Newton from 0 on phi(lambda) = r^2,
+//   phi(lambda) = sum_shells w_s / (1 + eta (D_s + lambda))^2.
+// One workgroup per instance.
+constexpr int NEWTON_NT = 256;
+__global__ __launch_bounds__(NEWTON_NT) void k_newton(const double *__restrict__ bins, const double *__restrict__ kkbin,
+                                                      int nbins, Prm p, const double *__restrict__ rpart, int rbpi,
+                                                      SubState *st_all) {
+  __shared__ double scratch[64];
+  __shared__ double bc[2];
+  const int b = blockIdx.x;
+  SubState *st = st_all + b;
+  if (st->done) return;
+  const int t = st->step;
+  // residual of d_t
+  double a = 0.0;
+  for (int i = threadIdx.x; i < rbpi; i += NEWTON_NT) a += rpart[(long)b * rbpi + i];
+  const double rs = block_sum<NEWTON_NT>(a, scratch);
+  if (threadIdx.x == 0) bc[0] = rs;
+  __syncthreads();
+  const double resid = sqrt(bc[0]);
+  const double *w = bins + (long)b * nbins;
+  const double xi = p.xi[b], q = p.q[b];
+  const double eta = st->eta, r2 = st->r2;
+  bool stop = false;
+  if (t >= 1 && resid < st->tol) stop = true;
+  if (t >= st->max_inner) stop = true;
+  if (!(resid == resid) || resid > 1e300) stop = true;
+  if (stop) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      st->resid = resid;
+      st->done = (resid < st->tol) ? 1 : 2;
+      if (!(resid == resid) || resid > 1e300) st->nonfinite = 1;
+      st->final_step = t;
+      st->lam_final = st->lam[t & 1];
+    }
+    return;
+  }
+  // phi and phi' at lambda
+  auto eval = [&](double lam, double &phi, double &dphi) {
+    double f = 0.0, df = 0.0;
+    for (int s = threadIdx.x; s < nbins; s += NEWTON_NT) {
+      const double ws = w[s];
+      if (ws != 0.0) {
+        const double den = 1.0 + eta * (lam_of(kkbin[s], xi, q) + lam);
+        const double i2 = 1.0 / (den * den);
+        f += ws * i2;
+        df += -2.0 * eta * ws * i2 / den;
+      }
+    }
+    const double F = block_sum<NEWTON_NT>(f, scratch);
+    const double DF = block_sum<NEWTON_NT>(df, scratch + 16);
+    if (threadIdx.x == 0) {
+      bc[0] = F;
+      bc[1] = DF;
+    }
+    __syncthreads();
+    phi = bc[0];
+    dphi = bc[1];
+    __syncthreads();
+  };
+  double phi, dphi;
+  eval(0.0, phi, dphi);
+  double lam = 0.0;
+  int it = 0;
+  if (phi > r2) {
+    while (it < st->max_newton) {
+      if (phi - r2 <= st->newton_rtol * r2) break;
+      const double nl = lam - (phi - r2) / dphi;
+      ++it;
+      if (fabs(nl - lam) <= st->newton_steptol * fmax(1.0, fabs(lam))) {
+        lam = nl;
+        break;
+      }
+      lam = nl;
+      eval(lam, phi, dphi);
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->resid = resid;
+    st->lam[(t + 1) & 1] = lam;
+    st->newton_total += it;
+    st->step = t + 1;
+  }
+}
+
+#endif  // LB_MAIN_TU
+
+}  // namespace lbk

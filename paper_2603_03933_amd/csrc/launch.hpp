@@ -1,0 +1,163 @@
+// launch.hpp - per-length launch table. Each supported FFT length N is compiled
+// in its own translation unit (inst.hip with -DLB_N=N) into an NFuncs table
+// for FP64 and FP32; the library picks tables by axis length at run time.
+#pragma once
+#include "kernels.hpp"
+
+namespace lb {
+using lbk::ColGeo;
+using lbk::Geo;
+using lbk::Prm;
+using lbk::RowGeo;
+using lbk::SubState;
+
+struct PassArgs {
+  hipStream_t stream = nullptr;
+  int nblocks = 0;
+  Geo g{};
+  Prm p{};
+  ColGeo cg{};
+  RowGeo rg{};
+  const void *tw = nullptr;
+  const void *in = nullptr;
+  void *out = nullptr;
+  void *out2 = nullptr;
+  const double *psi = nullptr;
+  const double *v = nullptr;
+  const double *mpart = nullptr;
+  int mbpi = 0;
+  double *partial = nullptr;
+  void *b0 = nullptr;
+  void *b1 = nullptr;
+  const void *gh = nullptr;
+  double *bsq = nullptr;
+  SubState *st = nullptr;
+  const void *gp = nullptr;
+  double *gp64 = nullptr;
+  float *gp32 = nullptr;
+  double scale = 1.0, inv_n = 1.0, shift = 0.0;
+  int zero_dc = 0;
+};
+
+struct NFuncs {
+  int C = 0, NT = 0;  // transforms and threads per workgroup
+  void (*cols_plain)(const PassArgs &, bool inv) = nullptr;
+  void (*cols_inv_scale_d)(const PassArgs &) = nullptr;
+  void (*cols_fwd_update)(const PassArgs &) = nullptr;
+  void (*cols_fwd_hess)(const PassArgs &) = nullptr;
+  void (*cols_fwd_mul_inv)(const PassArgs &) = nullptr;
+  void (*rows_r2c)(const PassArgs &, int mode) = nullptr;
+  void (*rows_c2r)(const PassArgs &, int mode) = nullptr;
+  void (*rows_inner)(const PassArgs &) = nullptr;
+  void (*rows_energy)(const PassArgs &) = nullptr;  // FP64 tables only
+};
+
+template <typename T, int N> struct Impl {
+  using C2 = lbfft::c2<T>;
+  static constexpr int NT = lbk::Cfg<N>::NT;
+
+  static void cols_plain(const PassArgs &a, bool inv) {
+    lbk::OpPlain<T> op{(const C2 *)a.in, (C2 *)a.out, T(a.scale), a.zero_dc, a.g.nh, a.st};
+    if (inv)
+      hipLaunchKernelGGL((lbk::k_cols<T, N, true, lbk::OpPlain<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+                         (const C2 *)a.tw, op);
+    else
+      hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpPlain<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+                         (const C2 *)a.tw, op);
+  }
+  static void cols_inv_scale_d(const PassArgs &a) {
+    lbk::OpInvScaleD<T> op{};
+    op.g = a.g;
+    op.p = a.p;
+    op.b0 = (const C2 *)a.b0;
+    op.b1 = (const C2 *)a.b1;
+    op.out = (C2 *)a.out;
+    op.st = a.st;
+    hipLaunchKernelGGL((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+                       (const C2 *)a.tw, op);
+  }
+  static void cols_fwd_update(const PassArgs &a) {
+    lbk::OpFwdUpdate<T> op{};
+    op.g = a.g;
+    op.p = a.p;
+    op.tmp = (const C2 *)a.in;
+    op.b0 = (C2 *)a.b0;
+    op.b1 = (C2 *)a.b1;
+    op.gh = (const C2 *)a.gh;
+    op.bsq = a.bsq;
+    op.partial = a.partial;
+    op.st = a.st;
+    op.inv_n = a.inv_n;
+    hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+                       (const C2 *)a.tw, op);
+  }
+  static void cols_fwd_hess(const PassArgs &a) {
+    lbk::OpFwdHess<T> op{};
+    op.g = a.g;
+    op.p = a.p;
+    op.tmp = (const C2 *)a.in;
+    op.x = (const C2 *)a.gh;
+    op.out = (C2 *)a.out;
+    op.inv_n = a.inv_n;
+    op.shift = a.shift;
+    hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpFwdHess<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+                       (const C2 *)a.tw, op);
+  }
+  static void cols_fwd_mul_inv(const PassArgs &a) {
+    hipLaunchKernelGGL((lbk::k_cols_fwd_mul_inv<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
+                       (const C2 *)a.tw, (C2 *)a.out, a.inv_n);
+  }
+  static void rows_r2c(const PassArgs &a, int mode) {
+    if (mode == 1)
+      hipLaunchKernelGGL((lbk::k_rows_r2c<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+                         (const C2 *)a.tw, (const double *)a.in, a.psi, (C2 *)a.out, a.partial);
+    else
+      hipLaunchKernelGGL((lbk::k_rows_r2c<T, N, 0>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+                         (const C2 *)a.tw, (const double *)a.in, a.psi, (C2 *)a.out, a.partial);
+  }
+  static void rows_c2r(const PassArgs &a, int mode) {
+    if (mode == 1)
+      hipLaunchKernelGGL((lbk::k_rows_c2r<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
+    else if (mode == 2)
+      hipLaunchKernelGGL((lbk::k_rows_c2r<T, N, 2>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
+    else
+      hipLaunchKernelGGL((lbk::k_rows_c2r<T, N, 0>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
+  }
+  static void rows_inner(const PassArgs &a) {
+    hipLaunchKernelGGL((lbk::k_rows_inner<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, (const C2 *)a.tw,
+                       (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
+  }
+  static void rows_energy(const PassArgs &a) {
+    if constexpr (std::is_same<T, double>::value)
+      hipLaunchKernelGGL((lbk::k_rows_energy<N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+                         (const double2 *)a.tw, a.psi, (double2 *)a.out, (double2 *)a.out2, a.gp64, a.gp32, a.partial);
+  }
+
+  static NFuncs table() {
+    NFuncs f;
+    f.C = lbk::Cfg<N>::C;
+    f.NT = NT;
+    f.cols_plain = &cols_plain;
+    f.cols_inv_scale_d = &cols_inv_scale_d;
+    f.cols_fwd_update = &cols_fwd_update;
+    f.cols_fwd_hess = &cols_fwd_hess;
+    f.cols_fwd_mul_inv = &cols_fwd_mul_inv;
+    f.rows_r2c = &rows_r2c;
+    f.rows_c2r = &rows_c2r;
+    f.rows_inner = &rows_inner;
+    f.rows_energy = std::is_same<T, double>::value ? &rows_energy : nullptr;
+    return f;
+  }
+};
+
+// Defined once per supported length by inst.hip; prec is LB_FP64 or LB_FP32.
+#define LB_FOR_EACH_LENGTH(X) \
+  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define LB_DECLARE_TABLE(n) const NFuncs *funcs_##n(int prec);
+LB_FOR_EACH_LENGTH(LB_DECLARE_TABLE)
+#undef LB_DECLARE_TABLE
+
+}  // namespace lb

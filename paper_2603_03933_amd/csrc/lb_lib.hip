@@ -1,0 +1,1164 @@
+// lb_lib.hip - plan management and the C ABI of include/lb.h.
+//
+// Host code here only enqueues kernels and runs the O(1) scalar logic of the
+// trust-region method (ratio test, radius updates, CG and Lanczos scalars);
+// every array operation runs in the kernels of kernels.hpp / fft.hpp.
+#define LB_MAIN_TU 1
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "../../include/lb.h"
+#include "launch.hpp"
+
+using lb::NFuncs;
+using lb::PassArgs;
+using lbk::ColGeo;
+using lbk::Geo;
+using lbk::Prm;
+using lbk::RowGeo;
+using lbk::SubState;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+static int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+#define LB_HIP(call)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) return fail(LB_ERR_HIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+#define LB_TRY(expr)         \
+  do {                       \
+    int rc_ = (expr);        \
+    if (rc_ < 0) return rc_; \
+  } while (0)
+
+extern "C" const char *lb_last_error(void) { return g_last_error.c_str(); }
+extern "C" int lb_version(void) { return 100; }
+
+// ---------------------------------------------------------------------------
+// kernels used only here
+// ---------------------------------------------------------------------------
+namespace lbk {
+// Gamma'(psi) = tau - gamma psi + psi^2 / 2 pointwise, in FP64 and optionally FP32
+__global__ __launch_bounds__(EW_NT) void k_gamma_p(long N, int batch, Prm p, const double *__restrict__ psi,
+                                                   double *__restrict__ g64, float *__restrict__ g32) {
+  const long total = N * batch;
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < total; i += (long)gridDim.x * EW_NT) {
+    const int b = (int)(i / N);
+    const double s = psi[i];
+    const double v = p.tau[b] - p.gamma[b] * s + 0.5 * s * s;
+    g64[i] = v;
+    if (g32) g32[i] = float(v);
+  }
+}
+// out = x + y (real)
+__global__ __launch_bounds__(EW_NT) void k_add_real(long n, const double *__restrict__ x, const double *__restrict__ y,
+                                                    double *__restrict__ out) {
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < n; i += (long)gridDim.x * EW_NT) out[i] = x[i] + y[i];
+}
+}  // namespace lbk
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct AxisTab {
+  int n = 0;
+  const NFuncs *f64 = nullptr, *f32 = nullptr;
+  double2 *tw64 = nullptr;
+  float2 *tw32 = nullptr;
+  double *kk = nullptr;
+};
+
+struct lb_plan {
+  lb_grid grid{};
+  int dim = 0, n0 = 0, n1 = 1, nl = 0, nhl = 0;
+  long N = 0, nh = 0;
+  int batch = 1;
+  int prec = LB_FP64;
+  hipStream_t stream = nullptr;
+  AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
+  // reciprocal shells for the Newton step
+  int nbins = 0;
+  int *perm = nullptr, *seg = nullptr;
+  double *kkbin = nullptr;
+  // FP64 spectral buffers (batch * nh complex each; SP holds 2 * batch)
+  double2 *SP = nullptr, *GH = nullptr, *SH = nullptr, *W64 = nullptr;
+  double2 *X = nullptr, *R = nullptr, *Pv = nullptr, *AP = nullptr;
+  // inner-loop spectral buffers in the plan's precision
+  void *B0 = nullptr, *B1 = nullptr, *WT = nullptr, *GHT = nullptr;
+  // physical buffers (batch * N)
+  double *gp64 = nullptr, *sphys = nullptr, *ptrial = nullptr;
+  float *gp32 = nullptr;
+  double *bsq = nullptr, *bins = nullptr;
+  double *partial = nullptr;
+  long partial_len = 0;
+  double *sums = nullptr;  // small device scratch for finalised sums
+  SubState *st = nullptr;
+  // pinned host mirrors
+  SubState *st_h = nullptr;
+  double *sums_h = nullptr;
+  // Lanczos basis, allocated on first use
+  std::vector<double2 *> lz;
+  size_t bytes = 0;
+  std::vector<void *> allocs;
+};
+
+static const NFuncs *funcs_for(int n, int prec) {
+  switch (n) {
+#define LB_CASE(k) \
+  case k:          \
+    return lb::funcs_##k(prec);
+    LB_FOR_EACH_LENGTH(LB_CASE)
+#undef LB_CASE
+    default:
+      return nullptr;
+  }
+}
+
+template <typename T> static int dalloc(lb_plan *P, T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return 0;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(LB_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  P->allocs.push_back(q);
+  P->bytes += count * sizeof(T);
+  *p = (T *)q;
+  return 0;
+}
+
+// W[m] = exp(-2 pi i m / n), built quadrant by quadrant in long double so that
+// the axis points are exact and every entry is rounded once.
+static void twiddles(int n, std::vector<double2> &w64, std::vector<float2> &w32) {
+  w64.resize(n);
+  w32.resize(n);
+  const long double halfpi = 1.570796326794896619231321691639751442L;
+  for (int m = 0; m < n; ++m) {
+    const long m4 = 4L * m;
+    const int quad = (int)(m4 / n);
+    const long rem = m4 % n;
+    const long double th = halfpi * (long double)rem / (long double)n;
+    const long double c = cosl(th), s = sinl(th);
+    long double cc, ss;  // cos and sin of 2 pi m / n
+    switch (quad) {
+      case 0: cc = c; ss = s; break;
+      case 1: cc = -s; ss = c; break;
+      case 2: cc = -c; ss = -s; break;
+      default: cc = s; ss = -c; break;
+    }
+    w64[m] = double2{(double)cc, (double)(-ss)};
+    w32[m] = float2{(float)cc, (float)(-ss)};
+  }
+}
+
+static double kk_axis(int i, int n, double L, bool half) {
+  const int k = (half || i < n / 2) ? i : i - n;
+  const double t = 2.0 * M_PI * (double)k / L;
+  return t * t;
+}
+
+extern "C" size_t lb_plan_workspace_bytes(const lb_plan *P) { return P ? P->bytes : 0; }
+
+extern "C" int lb_plan_destroy(lb_plan *P) {
+  if (!P) return LB_OK;
+  for (void *q : P->allocs) (void)hipFree(q);
+  for (double2 *q : P->lz) (void)hipFree(q);
+  if (P->st_h) (void)hipHostFree(P->st_h);
+  if (P->sums_h) (void)hipHostFree(P->sums_h);
+  delete P;
+  return LB_OK;
+}
+
+extern "C" int lb_plan_set_stream(lb_plan *P, void *stream) {
+  if (!P) return fail(LB_ERR_ARG, "null plan");
+  P->stream = (hipStream_t)stream;
+  return LB_OK;
+}
+
+static long cdiv(long a, long b) { return (a + b - 1) / b; }
+
+// workgroups of each pass kind, per instance
+static long bpi_pairs(const lb_plan *P) {
+  const long rpi = (P->dim == 3) ? (long)P->n0 * P->n1 : P->n0;
+  return cdiv(rpi / 2, P->ax[2].f64->C);
+}
+static long bpi_rows(const lb_plan *P) {
+  const long rpi = (P->dim == 3) ? (long)P->n0 * P->n1 : P->n0;
+  return cdiv(rpi, P->ax[2].f64->C);
+}
+static long bpi_col1(const lb_plan *P) { return cdiv((long)P->n0 * P->nhl, P->ax[1].f64->C); }
+static long bpi_col0(const lb_plan *P) {
+  const long cpi = (P->dim == 3) ? (long)P->n1 * P->nhl : P->nhl;
+  return cdiv(cpi, P->ax[0].f64->C);
+}
+static long bpi_ew(const lb_plan *P) { return std::min<long>(cdiv(P->nh, lbk::EW_NT * 4), 512); }
+
+static int upload(lb_plan *P, void *dst, const void *src, size_t bytes) {
+  LB_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+  return 0;
+}
+
+extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int precision, void *stream) {
+  if (!out || !g) return fail(LB_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (g->dim != 2 && g->dim != 3) return fail(LB_ERR_ARG, "dim must be 2 or 3");
+  if (batch < 1 || batch > lbk::MAXB) return fail(LB_ERR_ARG, "batch must be in [1, 8]");
+  if (precision != LB_FP64 && precision != LB_FP32) return fail(LB_ERR_ARG, "precision must be LB_FP64 or LB_FP32");
+  for (int a = 0; a < g->dim; ++a) {
+    if (!(g->box[a] > 0.0) || !std::isfinite(g->box[a])) return fail(LB_ERR_ARG, "box sides must be positive");
+    if (!funcs_for(g->n[a], 0)) return fail(LB_ERR_UNSUPPORTED, "axis length not supported (2^a 3^b, 8..512)");
+  }
+  lb_plan *P = new lb_plan();
+  P->grid = *g;
+  P->dim = g->dim;
+  P->batch = batch;
+  P->prec = precision;
+  P->stream = (hipStream_t)stream;
+  P->n0 = g->n[0];
+  P->n1 = (g->dim == 3) ? g->n[1] : 1;
+  P->nl = g->n[g->dim - 1];
+  P->nhl = P->nl / 2 + 1;
+  P->N = (long)P->n0 * P->n1 * P->nl;
+  P->nh = (long)P->n0 * P->n1 * P->nhl;
+  auto cleanup = [&](int rc) {
+    lb_plan_destroy(P);
+    return rc;
+  };
+  // per-axis tables: ax[0] leading, ax[1] middle (3D) or unused, ax[2] last
+  const int axis_of[3] = {0, g->dim == 3 ? 1 : -1, g->dim - 1};
+  for (int s = 0; s < 3; ++s) {
+    const int a = axis_of[s];
+    if (a < 0) {
+      // 2D: the middle-axis slot carries a single zero wavenumber
+      int rc = dalloc(P, &P->ax[1].kk, 1);
+      if (rc) return cleanup(rc);
+      const double z = 0.0;
+      if ((rc = upload(P, P->ax[1].kk, &z, sizeof(double)))) return cleanup(rc);
+      P->ax[1].n = 1;
+      continue;
+    }
+    AxisTab &A = P->ax[s];
+    A.n = g->n[a];
+    A.f64 = funcs_for(A.n, LB_FP64);
+    A.f32 = funcs_for(A.n, LB_FP32);
+    std::vector<double2> w64;
+    std::vector<float2> w32;
+    twiddles(A.n, w64, w32);
+    int rc;
+    if ((rc = dalloc(P, &A.tw64, A.n)) || (rc = dalloc(P, &A.tw32, A.n))) return cleanup(rc);
+    if ((rc = upload(P, A.tw64, w64.data(), A.n * sizeof(double2)))) return cleanup(rc);
+    if ((rc = upload(P, A.tw32, w32.data(), A.n * sizeof(float2)))) return cleanup(rc);
+    const bool half = (s == 2);
+    const int cnt = half ? A.n / 2 + 1 : A.n;
+    std::vector<double> kk(cnt);
+    for (int i = 0; i < cnt; ++i) kk[i] = kk_axis(i, A.n, g->box[a], half);
+    if ((rc = dalloc(P, &A.kk, cnt))) return cleanup(rc);
+    if ((rc = upload(P, A.kk, kk.data(), cnt * sizeof(double)))) return cleanup(rc);
+  }
+  // reciprocal shells: group the modes h != 0 by their exact |Bk|^2 value
+  {
+    std::vector<double> k0(P->n0), k1(P->n1, 0.0), kl(P->nhl);
+    for (int i = 0; i < P->n0; ++i) k0[i] = kk_axis(i, P->n0, g->box[0], false);
+    if (P->dim == 3)
+      for (int i = 0; i < P->n1; ++i) k1[i] = kk_axis(i, P->n1, g->box[1], false);
+    for (int i = 0; i < P->nhl; ++i) kl[i] = kk_axis(i, P->nl, g->box[g->dim - 1], true);
+    std::vector<std::pair<double, int>> keys;
+    keys.reserve(P->nh - 1);
+    for (long h = 1; h < P->nh; ++h) {
+      const int kli = (int)(h % P->nhl);
+      const long r = h / P->nhl;
+      const int i1 = (int)(r % P->n1), i0 = (int)(r / P->n1);
+      double kk = k0[i0] + kl[kli];
+      if (P->dim == 3) kk += k1[i1];
+      keys.emplace_back(kk, (int)h);
+    }
+    std::sort(keys.begin(), keys.end());
+    std::vector<int> perm(keys.size()), seg;
+    std::vector<double> kb;
+    for (size_t i = 0; i < keys.size(); ++i) {
+      if (i == 0 || keys[i].first != keys[i - 1].first) {
+        seg.push_back((int)i);
+        kb.push_back(keys[i].first);
+      }
+      perm[i] = keys[i].second;
+    }
+    seg.push_back((int)keys.size());
+    P->nbins = (int)kb.size();
+    int rc;
+    if ((rc = dalloc(P, &P->perm, perm.size())) || (rc = dalloc(P, &P->seg, seg.size())) ||
+        (rc = dalloc(P, &P->kkbin, kb.size())))
+      return cleanup(rc);
+    if ((rc = upload(P, P->perm, perm.data(), perm.size() * sizeof(int))) ||
+        (rc = upload(P, P->seg, seg.data(), seg.size() * sizeof(int))) ||
+        (rc = upload(P, P->kkbin, kb.data(), kb.size() * sizeof(double))))
+      return cleanup(rc);
+  }
+  const long S = (long)batch * P->nh, Np = (long)batch * P->N;
+  int rc;
+  if ((rc = dalloc(P, &P->SP, 2 * S)) || (rc = dalloc(P, &P->GH, S)) || (rc = dalloc(P, &P->SH, S)) ||
+      (rc = dalloc(P, &P->W64, S)) || (rc = dalloc(P, &P->X, S)) || (rc = dalloc(P, &P->R, S)) ||
+      (rc = dalloc(P, &P->Pv, S)) || (rc = dalloc(P, &P->AP, S)))
+    return cleanup(rc);
+  if (precision == LB_FP64) {
+    double2 *b0, *b1;
+    if ((rc = dalloc(P, &b0, S)) || (rc = dalloc(P, &b1, S))) return cleanup(rc);
+    P->B0 = b0;
+    P->B1 = b1;
+    P->WT = P->W64;
+    P->GHT = P->GH;
+  } else {
+    float2 *b0, *b1, *wt, *gt;
+    if ((rc = dalloc(P, &b0, S)) || (rc = dalloc(P, &b1, S)) || (rc = dalloc(P, &wt, S)) || (rc = dalloc(P, &gt, S)))
+      return cleanup(rc);
+    P->B0 = b0;
+    P->B1 = b1;
+    P->WT = wt;
+    P->GHT = gt;
+    if ((rc = dalloc(P, &P->gp32, Np))) return cleanup(rc);
+  }
+  if ((rc = dalloc(P, &P->gp64, Np)) || (rc = dalloc(P, &P->sphys, Np)) || (rc = dalloc(P, &P->ptrial, Np)) ||
+      (rc = dalloc(P, &P->bsq, S)) || (rc = dalloc(P, &P->bins, (long)batch * P->nbins)))
+    return cleanup(rc);
+  const long mb = std::max({bpi_pairs(P), bpi_rows(P), bpi_col0(P), P->dim == 3 ? bpi_col1(P) : 1L, bpi_ew(P)});
+  P->partial_len = 8 * mb * batch + 64;
+  if ((rc = dalloc(P, &P->partial, P->partial_len)) || (rc = dalloc(P, &P->sums, 64 * lbk::MAXB)) ||
+      (rc = dalloc(P, &P->st, lbk::MAXB)))
+    return cleanup(rc);
+  if (hipHostMalloc((void **)&P->st_h, sizeof(SubState) * lbk::MAXB, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&P->sums_h, sizeof(double) * 64 * lbk::MAXB, hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(LB_ERR_HIP, "hipHostMalloc failed"));
+  *out = P;
+  return LB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// argument helpers
+// ---------------------------------------------------------------------------
+static int pack_params(const lb_plan *P, const lb_params *params, int count, Prm *p) {
+  if (!params) return fail(LB_ERR_ARG, "null params");
+  std::memset(p, 0, sizeof(Prm));
+  for (int b = 0; b < count; ++b) {
+    const lb_params &q = params[b];
+    if (!std::isfinite(q.tau) || !std::isfinite(q.gamma) || !std::isfinite(q.xi) || !std::isfinite(q.q))
+      return fail(LB_ERR_ARG, "non-finite model parameter");
+    p->tau[b] = q.tau;
+    p->gamma[b] = q.gamma;
+    p->xi[b] = q.xi;
+    p->q[b] = q.q;
+  }
+  return 0;
+}
+static Geo geo(const lb_plan *P, int batch) {
+  Geo g{};
+  g.dim = P->dim;
+  g.n0 = P->n0;
+  g.n1 = P->n1;
+  g.nl = P->nl;
+  g.nhl = P->nhl;
+  g.N = P->N;
+  g.nh = P->nh;
+  g.batch = batch;
+  g.kk0 = P->ax[0].kk;
+  g.kk1 = P->ax[1].kk;
+  g.kkl = P->ax[2].kk;
+  return g;
+}
+
+static const NFuncs *F(const lb_plan *P, int slot, int prec) { return prec == LB_FP64 ? P->ax[slot].f64 : P->ax[slot].f32; }
+static const void *TW(const lb_plan *P, int slot, int prec) {
+  return prec == LB_FP64 ? (const void *)P->ax[slot].tw64 : (const void *)P->ax[slot].tw32;
+}
+
+static PassArgs args_rows(const lb_plan *P, int prec, int batch, const Prm &p, bool pairs) {
+  PassArgs a;
+  a.stream = P->stream;
+  a.g = geo(P, batch);
+  a.p = p;
+  a.rg.rpi = (P->dim == 3) ? (long)P->n0 * P->n1 : P->n0;
+  a.rg.bpi = (int)(pairs ? bpi_pairs(P) : bpi_rows(P));
+  a.nblocks = a.rg.bpi * batch;
+  a.tw = TW(P, 2, prec);
+  return a;
+}
+static PassArgs args_col(const lb_plan *P, int prec, int batch, const Prm &p, int axis) {
+  PassArgs a;
+  a.stream = P->stream;
+  a.g = geo(P, batch);
+  a.p = p;
+  if (axis == 1) {
+    a.cg.cpi = P->n0 * P->nhl;
+    a.cg.inner = P->nhl;
+    a.cg.outer = (long)P->n1 * P->nhl;
+    a.cg.S = P->nhl;
+    a.cg.bpi = (int)bpi_col1(P);
+    a.tw = TW(P, 1, prec);
+  } else {
+    a.cg.cpi = (P->dim == 3) ? P->n1 * P->nhl : P->nhl;
+    a.cg.inner = a.cg.cpi;
+    a.cg.outer = P->nh;
+    a.cg.S = a.cg.cpi;
+    a.cg.bpi = (int)bpi_col0(P);
+    a.tw = TW(P, 0, prec);
+  }
+  a.cg.inst = P->nh;
+  a.nblocks = a.cg.bpi * batch;
+  return a;
+}
+
+static int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return 0;
+}
+
+// sum (or max) per-workgroup partials into P->sums[b * nq + q] (device)
+static void finalize(lb_plan *P, const double *partial, int bpi, int nq, unsigned maxmask, int batch, double *out) {
+  hipLaunchKernelGGL(lbk::k_finalize, dim3(batch), dim3(256), 0, P->stream, partial, bpi, nq, maxmask, out);
+}
+static int read_sums(lb_plan *P, const double *dev, int count) {
+  LB_HIP(hipMemcpyAsync(P->sums_h, dev, sizeof(double) * count, hipMemcpyDeviceToHost, P->stream));
+  LB_HIP(hipStreamSynchronize(P->stream));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// transforms
+// ---------------------------------------------------------------------------
+// real (batch fields) -> half spectrum with the 1/N normalisation
+static void fwd_r2c(lb_plan *P, int prec, int batch, const Prm &p, const double *in, void *out, int zero_dc) {
+  PassArgs r = args_rows(P, prec, batch, p, true);
+  r.in = in;
+  r.out = out;
+  F(P, 2, prec)->rows_r2c(r, 0);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, prec, batch, p, 1);
+    c1.in = out;
+    c1.out = out;
+    F(P, 1, prec)->cols_plain(c1, false);
+  }
+  PassArgs c0 = args_col(P, prec, batch, p, 0);
+  c0.in = out;
+  c0.out = out;
+  c0.scale = 1.0 / (double)P->N;
+  c0.zero_dc = zero_dc;
+  F(P, 0, prec)->cols_plain(c0, false);
+}
+
+// half spectrum -> real; `work` receives the partially inverted spectrum
+static void inv_c2r(lb_plan *P, int prec, int batch, const Prm &p, const void *in, void *work, double *out, int mode,
+                    const double *psi, double *partial) {
+  PassArgs c0 = args_col(P, prec, batch, p, 0);
+  c0.in = in;
+  c0.out = work;
+  F(P, 0, prec)->cols_plain(c0, true);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, prec, batch, p, 1);
+    c1.in = work;
+    c1.out = work;
+    F(P, 1, prec)->cols_plain(c1, true);
+  }
+  PassArgs r = args_rows(P, prec, batch, p, true);
+  r.in = work;
+  r.out = out;
+  r.psi = psi;
+  r.partial = partial;
+  F(P, 2, prec)->rows_c2r(r, mode);
+}
+
+// weighted spectral sums over the instances of a batch: MODE 0 <a,b>, MODE 1 sum Lambda |a|^2
+template <typename TA, int MODE>
+static void spec_reduce(lb_plan *P, int batch, const Prm &p, const void *a, const void *b, double *out_dev) {
+  const int bpi = (int)bpi_ew(P);
+  hipLaunchKernelGGL((lbk::k_spec_reduce<TA, MODE>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream, geo(P, batch), p,
+                     bpi, (const lbfft::c2<TA> *)a, (const lbfft::c2<TA> *)b, P->partial);
+  finalize(P, P->partial, bpi, 1, 0u, batch, out_dev);
+}
+static int spec_dot_host(lb_plan *P, const Prm &p, const double2 *a, const double2 *b, double *res) {
+  spec_reduce<double, 0>(P, 1, p, a, b, P->sums);
+  LB_TRY(read_sums(P, P->sums, 1));
+  *res = P->sums_h[0];
+  return 0;
+}
+static int spec_lam_host(lb_plan *P, const Prm &p, const double2 *a, double *res) {
+  spec_reduce<double, 1>(P, 1, p, a, a, P->sums);
+  LB_TRY(read_sums(P, P->sums, 1));
+  *res = P->sums_h[0];
+  return 0;
+}
+
+static void lincomb64(lb_plan *P, long n, double alpha, const double2 *x, double beta, const double2 *y, double2 *out) {
+  const long nb = std::min<long>(cdiv(n, lbk::EW_NT), 4096);
+  hipLaunchKernelGGL((lbk::k_lincomb<double, double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, n, alpha, x,
+                     beta, y, out);
+}
+
+// ---------------------------------------------------------------------------
+// energy and gradient
+// ---------------------------------------------------------------------------
+// After this call: GH holds g_hat (FP64), GHT its copy in the plan's precision,
+// gp64/gp32 hold Gamma'(psi), and P->sums holds per instance
+// [sum F, max |Gamma'|] at sums[0 .. 2B) and [G, ||g||^2, max |g|] at sums[32 ..).
+static void energy_grad_core(lb_plan *P, int batch, const Prm &p, const double *psi) {
+  PassArgs r = args_rows(P, LB_FP64, batch, p, false);
+  r.psi = psi;
+  r.out = P->SP;
+  r.out2 = P->SP + (long)batch * P->nh;
+  r.gp64 = P->gp64;
+  r.gp32 = P->gp32;
+  r.partial = P->partial;
+  F(P, 2, LB_FP64)->rows_energy(r);
+  finalize(P, P->partial, r.rg.bpi, 2, 0x2u, batch, P->sums);
+  // psi and F'(psi) go through the column passes as 2 * batch stacked fields
+  // (plain passes: the model parameters are not read)
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, LB_FP64, 2 * batch, p, 1);
+    c1.in = P->SP;
+    c1.out = P->SP;
+    F(P, 1, LB_FP64)->cols_plain(c1, false);
+  }
+  PassArgs c0 = args_col(P, LB_FP64, 2 * batch, p, 0);
+  c0.in = P->SP;
+  c0.out = P->SP;
+  c0.scale = 1.0 / (double)P->N;
+  F(P, 0, LB_FP64)->cols_plain(c0, false);
+  const int bpi = (int)bpi_ew(P);
+  double *part2 = P->partial + P->partial_len / 2;
+  if (P->prec == LB_FP64)
+    hipLaunchKernelGGL((lbk::k_grad_assemble<double>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
+                       geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
+                       P->GH, (double2 *)nullptr, part2);
+  else
+    hipLaunchKernelGGL((lbk::k_grad_assemble<float>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
+                       geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
+                       P->GH, (float2 *)P->GHT, part2);
+  finalize(P, part2, bpi, 3, 0x4u, batch, P->sums + 32);
+}
+
+extern "C" int lb_energy_grad(lb_plan *P, const lb_params *params, const double *psi, double *energy, double *grad) {
+  if (!P || !psi || !energy) return fail(LB_ERR_ARG, "null argument");
+  Prm p;
+  LB_TRY(pack_params(P, params, P->batch, &p));
+  const int B = P->batch;
+  energy_grad_core(P, B, p, psi);
+  hipLaunchKernelGGL(lbk::k_energy_out, dim3(1), dim3(64), 0, P->stream, (const double *)(P->sums + 32), 3,
+                     (const double *)P->sums, 2, 1.0 / (double)P->N, B, energy);
+  if (grad) inv_c2r(P, LB_FP64, B, p, P->GH, P->W64, grad, 0, nullptr, nullptr);
+  return check_launch("lb_energy_grad");
+}
+
+// ---------------------------------------------------------------------------
+// Hessian-vector product on physical fields
+// ---------------------------------------------------------------------------
+extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi, const double *v, double *hv,
+                          int project) {
+  if (!P || !psi || !v || !hv) return fail(LB_ERR_ARG, "null argument");
+  Prm p;
+  LB_TRY(pack_params(P, params, P->batch, &p));
+  const int B = P->batch, prec = P->prec;
+  void *work = P->WT;
+  PassArgs r = args_rows(P, prec, B, p, true);
+  r.in = v;
+  r.psi = psi;
+  r.out = work;
+  r.partial = P->partial;
+  F(P, 2, prec)->rows_r2c(r, project ? 1 : 0);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, prec, B, p, 1);
+    c1.in = work;
+    c1.out = work;
+    F(P, 1, prec)->cols_plain(c1, false);
+  }
+  PassArgs c0 = args_col(P, prec, B, p, 0);
+  c0.out = work;
+  c0.inv_n = 1.0 / (double)P->N;
+  F(P, 0, prec)->cols_fwd_mul_inv(c0);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, prec, B, p, 1);
+    c1.in = work;
+    c1.out = work;
+    F(P, 1, prec)->cols_plain(c1, true);
+  }
+  PassArgs o = args_rows(P, prec, B, p, true);
+  o.in = work;
+  o.out = hv;
+  o.psi = psi;
+  o.v = v;
+  o.mpart = project ? P->partial : nullptr;
+  o.mbpi = r.rg.bpi;
+  F(P, 2, prec)->rows_c2r(o, 1);
+  return check_launch("lb_hessvec");
+}
+
+// spectral Hessian-vector product in FP64: out = Lambda x + P F_N(Gamma' F_N^{-1} x) + shift x
+static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out, double shift) {
+  PassArgs c0 = args_col(P, LB_FP64, 1, p, 0);
+  c0.in = x;
+  c0.out = P->W64;
+  F(P, 0, LB_FP64)->cols_plain(c0, true);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
+    c1.in = P->W64;
+    c1.out = P->W64;
+    F(P, 1, LB_FP64)->cols_plain(c1, true);
+  }
+  PassArgs r = args_rows(P, LB_FP64, 1, p, true);
+  r.out = P->W64;
+  r.gp = P->gp64;
+  F(P, 2, LB_FP64)->rows_inner(r);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
+    c1.in = P->W64;
+    c1.out = P->W64;
+    F(P, 1, LB_FP64)->cols_plain(c1, false);
+  }
+  PassArgs f = args_col(P, LB_FP64, 1, p, 0);
+  f.in = P->W64;
+  f.gh = x;
+  f.out = out;
+  f.inv_n = 1.0 / (double)P->N;
+  f.shift = shift;
+  F(P, 0, LB_FP64)->cols_fwd_hess(f);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 3 on the device
+// ---------------------------------------------------------------------------
+struct SubOut {
+  double lam = 0, resid = 0, dnorm = 0;
+  int iters = 0, newton = 0, status = 0;
+};
+
+static void enqueue_step(lb_plan *P, const Prm &p) {
+  const int prec = P->prec;
+  PassArgs a = args_col(P, prec, 1, p, 0);
+  a.b0 = P->B0;
+  a.b1 = P->B1;
+  a.out = P->WT;
+  a.st = P->st;
+  F(P, 0, prec)->cols_inv_scale_d(a);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, prec, 1, p, 1);
+    c1.in = P->WT;
+    c1.out = P->WT;
+    c1.st = P->st;
+    F(P, 1, prec)->cols_plain(c1, true);
+  }
+  PassArgs r = args_rows(P, prec, 1, p, true);
+  r.out = P->WT;
+  r.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
+  r.st = P->st;
+  F(P, 2, prec)->rows_inner(r);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, prec, 1, p, 1);
+    c1.in = P->WT;
+    c1.out = P->WT;
+    c1.st = P->st;
+    F(P, 1, prec)->cols_plain(c1, false);
+  }
+  PassArgs u = args_col(P, prec, 1, p, 0);
+  u.in = P->WT;
+  u.b0 = P->B0;
+  u.b1 = P->B1;
+  u.gh = P->GHT;
+  u.bsq = P->bsq;
+  u.partial = P->partial;
+  u.st = P->st;
+  u.inv_n = 1.0 / (double)P->N;
+  F(P, 0, prec)->cols_fwd_update(u);
+  const long waves = (long)P->nbins;
+  hipLaunchKernelGGL(lbk::k_bins, dim3((unsigned)cdiv(waves * 64, 256)), dim3(256), 0, P->stream, P->bsq, P->perm,
+                     P->seg, P->nbins, P->nh, 1, (const SubState *)P->st, P->bins);
+  hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::NEWTON_NT), 0, P->stream, P->bins, P->kkbin, P->nbins, p,
+                     (const double *)P->partial, u.cg.bpi, P->st);
+}
+
+// Runs Algorithm 3 with g_hat in GH/GHT and Gamma' in gp64/gp32; the initial
+// point is -r g/||g|| or d0_spec (FP64 spectral, nullable). Leaves d in SH.
+static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts &o, double gnorm,
+                          const double2 *d0_spec, SubOut *out) {
+  const int prec = P->prec;
+  const long nb = std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096);
+  const Geo g1 = geo(P, 1);
+  if (d0_spec) {
+    if (prec == LB_FP64)
+      hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
+                         o.eta, (double2 *)P->B1);
+    else
+      hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
+                         o.eta, (float2 *)P->B1);
+  } else {
+    if (prec == LB_FP64)
+      hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+                         (const double2 *)P->GH, -r / gnorm, o.eta, (double2 *)P->B1);
+    else
+      hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+                         (const double2 *)P->GH, -r / gnorm, o.eta, (float2 *)P->B1);
+  }
+  SubState s{};
+  s.lam[0] = 0.0;
+  s.lam[1] = 0.0;
+  s.eta = o.eta;
+  s.r2 = r * r;
+  s.tol = std::max(o.eps_sub, o.eps_sub_rel * gnorm);
+  s.newton_rtol = o.newton_rtol;
+  s.newton_steptol = o.newton_steptol;
+  s.step = 0;
+  s.done = 0;
+  s.max_inner = o.max_inner;
+  s.max_newton = o.max_newton;
+  LB_HIP(hipStreamSynchronize(P->stream));  // the pinned mirror may still feed an earlier copy
+  *P->st_h = s;
+  LB_HIP(hipMemcpyAsync(P->st, P->st_h, sizeof(SubState), hipMemcpyHostToDevice, P->stream));
+  const int chunk = std::max(1, o.poll_every);
+  long launched = 0;
+  const long max_steps = (long)o.max_inner + 1;
+  while (true) {
+    const int n = (int)std::min<long>(chunk, max_steps - launched);
+    for (int i = 0; i < n; ++i) enqueue_step(P, p);
+    launched += n;
+    LB_TRY(check_launch("subproblem step"));
+    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
+    LB_HIP(hipStreamSynchronize(P->stream));
+    if (P->st_h->done || launched >= max_steps) break;
+  }
+  const SubState &f = *P->st_h;
+  if (!f.done) return fail(LB_ERR_HIP, "subproblem loop ended without a stop decision");
+  if (f.nonfinite) return fail(LB_ERR_NONFINITE, "non-finite residual in the subproblem");
+  if (prec == LB_FP64)
+    hipLaunchKernelGGL((lbk::k_final_d<double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+                       (const double2 *)P->B0, (const double2 *)P->B1, (const SubState *)P->st, P->SH);
+  else
+    hipLaunchKernelGGL((lbk::k_final_d<float>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, (const float2 *)P->B0,
+                       (const float2 *)P->B1, (const SubState *)P->st, P->SH);
+  double dd = 0.0;
+  LB_TRY(spec_dot_host(P, p, P->SH, P->SH, &dd));
+  out->lam = f.lam_final;
+  out->resid = f.resid;
+  out->dnorm = std::sqrt(std::max(dd, 0.0));
+  out->iters = f.final_step;
+  out->newton = f.newton_total;
+  out->status = (f.done == 1) ? LB_OK : LB_NOT_CONVERGED;
+  return 0;
+}
+
+extern "C" void lb_sub_opts_default(lb_sub_opts *o) {
+  if (!o) return;
+  o->eta = 0.1;
+  o->eps_sub = 1e-13;
+  o->eps_sub_rel = 0.0;
+  o->max_inner = 10000;
+  o->max_newton = 100;
+  o->newton_rtol = 1e-14;
+  o->newton_steptol = 1e-15;
+  o->poll_every = 32;
+}
+
+extern "C" void lb_tr_opts_default(lb_tr_opts *o) {
+  if (!o) return;
+  o->theta = 1e-4;
+  o->gamma_c = 0.5;
+  o->gamma_e = 2.0;
+  o->gamma_lambda = 1.5;
+  o->mu_lo = 1.0;
+  o->mu_hi = 1e5;
+  o->mu0 = 1.0;
+  o->r0 = 1.0;
+  o->nu0 = 5.0;
+  o->eps = 1e-10;
+  o->grad_norm_inf = 1;
+  o->eta = 0.1;
+  o->eta_safe = 1;
+  o->rho_taylor = 1;
+  o->contract_else_old_step = 0;
+  o->nu_tol = 1e-12;
+  o->max_outer = 500;
+  lb_sub_opts_default(&o->sub);
+  o->cg_rtol = 1e-12;
+  o->cg_maxiter = 1000;
+  o->verbose = 0;
+}
+
+static int check_sub_opts(const lb_sub_opts &o) {
+  if (!(o.eta > 0) || !(o.eps_sub >= 0) || !(o.eps_sub_rel >= 0) || o.max_inner < 1 || o.max_newton < 0)
+    return fail(LB_ERR_ARG, "bad subproblem options");
+  return 0;
+}
+
+extern "C" int lb_tr_subproblem(lb_plan *P, const lb_params *params, const double *psi, const double *grad,
+                                double radius, const lb_sub_opts *opts, const double *d0, double *d_out,
+                                lb_sub_info *info) {
+  if (!P || !psi || !grad || !d_out || !info) return fail(LB_ERR_ARG, "null argument");
+  if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_tr_subproblem needs a plan with batch 1");
+  if (!(radius > 0) || !std::isfinite(radius)) return fail(LB_ERR_ARG, "radius must be positive");
+  lb_sub_opts o;
+  if (opts) o = *opts;
+  else lb_sub_opts_default(&o);
+  LB_TRY(check_sub_opts(o));
+  Prm p;
+  LB_TRY(pack_params(P, params, 1, &p));
+  hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+                     P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  fwd_r2c(P, LB_FP64, 1, p, grad, P->GH, 1);
+  if (P->prec == LB_FP32)
+    hipLaunchKernelGGL((lbk::k_lincomb<float, double, double>), dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)),
+                       dim3(lbk::EW_NT), 0, P->stream, P->nh, 1.0, (const double2 *)P->GH, 0.0, (const double2 *)nullptr,
+                       (float2 *)P->GHT);
+  double gg = 0.0;
+  LB_TRY(spec_dot_host(P, p, P->GH, P->GH, &gg));
+  const double gnorm = std::sqrt(std::max(gg, 0.0));
+  if (!(gnorm > 0) || !std::isfinite(gnorm)) return fail(gnorm == 0 ? LB_ERR_ARG : LB_ERR_NONFINITE, "gradient norm is zero or not finite");
+  const double2 *d0s = nullptr;
+  if (d0) {
+    fwd_r2c(P, LB_FP64, 1, p, d0, P->X, 1);
+    d0s = P->X;
+  }
+  SubOut so;
+  LB_TRY(run_subproblem(P, p, radius, o, gnorm, d0s, &so));
+  inv_c2r(P, LB_FP64, 1, p, P->SH, P->W64, d_out, 0, nullptr, nullptr);
+  LB_TRY(check_launch("lb_tr_subproblem"));
+  LB_HIP(hipStreamSynchronize(P->stream));
+  info->lambda = so.lam;
+  info->resid = so.resid;
+  info->dnorm = so.dnorm;
+  info->gnorm = gnorm;
+  info->iters = so.iters;
+  info->newton_iters = so.newton;
+  info->status = so.status;
+  return so.status;
+}
+
+// ---------------------------------------------------------------------------
+// CG for (H + shift I) s = -g (Algorithm 2's linear systems), spectral FP64.
+// g_hat in GH; solution in X.
+// ---------------------------------------------------------------------------
+static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int maxiter, int *iters) {
+  const long n = P->nh;
+  lincomb64(P, n, 0.0, P->GH, 0.0, P->GH, P->X);   // x = 0
+  lincomb64(P, n, -1.0, P->GH, 0.0, P->GH, P->R);  // r = -g
+  lincomb64(P, n, 1.0, P->R, 0.0, P->R, P->Pv);    // p = r
+  double rr;
+  LB_TRY(spec_dot_host(P, p, P->R, P->R, &rr));
+  const double bn = std::sqrt(rr);
+  int it = 0;
+  while (it < maxiter && std::sqrt(rr) > rtol * bn) {
+    hess_spec64(P, p, P->Pv, P->AP, shift);
+    double pap;
+    LB_TRY(spec_dot_host(P, p, P->Pv, P->AP, &pap));
+    if (!(pap > 0)) return fail(LB_ERR_NONFINITE, "CG met a non-positive curvature; H + shift I is not positive definite");
+    const double alpha = rr / pap;
+    lincomb64(P, n, alpha, P->Pv, 1.0, P->X, P->X);
+    lincomb64(P, n, -alpha, P->AP, 1.0, P->R, P->R);
+    double rn;
+    LB_TRY(spec_dot_host(P, p, P->R, P->R, &rn));
+    lincomb64(P, n, 1.0, P->R, rn / rr, P->Pv, P->Pv);
+    rr = rn;
+    ++it;
+  }
+  *iters = it;
+  return 0;
+}
+
+extern "C" int lb_shifted_solve(lb_plan *P, const lb_params *params, const double *psi, const double *grad,
+                                double shift, double rtol, int maxiter, double *s_out, int *iters) {
+  if (!P || !psi || !grad || !s_out || !iters) return fail(LB_ERR_ARG, "null argument");
+  if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_shifted_solve needs a plan with batch 1");
+  Prm p;
+  LB_TRY(pack_params(P, params, 1, &p));
+  hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+                     P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  fwd_r2c(P, LB_FP64, 1, p, grad, P->GH, 1);
+  LB_TRY(cg_shifted(P, p, shift, rtol, maxiter, iters));
+  inv_c2r(P, LB_FP64, 1, p, P->X, P->W64, s_out, 0, nullptr, nullptr);
+  LB_TRY(check_launch("lb_shifted_solve"));
+  LB_HIP(hipStreamSynchronize(P->stream));
+  return LB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos (full reorthogonalisation), spectral FP64, Gamma' in gp64
+// ---------------------------------------------------------------------------
+// eigenvalues / eigenvectors of a small symmetric matrix by cyclic Jacobi
+static void jacobi_eig(int m, std::vector<double> &A, std::vector<double> &V) {
+  V.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) V[(size_t)i * m + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = i + 1; j < m; ++j) off += A[(size_t)i * m + j] * A[(size_t)i * m + j];
+    if (off < 1e-300) break;
+    for (int pi = 0; pi < m; ++pi)
+      for (int q = pi + 1; q < m; ++q) {
+        const double apq = A[(size_t)pi * m + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = A[(size_t)pi * m + pi], aqq = A[(size_t)q * m + q];
+        const double th = 0.5 * (aqq - app) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < m; ++k) {
+          const double akp = A[(size_t)k * m + pi], akq = A[(size_t)k * m + q];
+          A[(size_t)k * m + pi] = c * akp - s * akq;
+          A[(size_t)k * m + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double apk = A[(size_t)pi * m + k], aqk = A[(size_t)q * m + k];
+          A[(size_t)pi * m + k] = c * apk - s * aqk;
+          A[(size_t)q * m + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double vkp = V[(size_t)k * m + pi], vkq = V[(size_t)k * m + q];
+          V[(size_t)k * m + pi] = c * vkp - s * vkq;
+          V[(size_t)k * m + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+}
+
+static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, double *ritz, double *resid) {
+  if ((int)P->lz.size() < steps + 1) {
+    while ((int)P->lz.size() < steps + 1) {
+      void *q = nullptr;
+      LB_HIP(hipMalloc(&q, sizeof(double2) * P->nh));
+      P->lz.push_back((double2 *)q);
+    }
+  }
+  const long n = P->nh;
+  double nn;
+  LB_TRY(spec_dot_host(P, p, v0, v0, &nn));
+  if (!(nn > 0)) return fail(LB_ERR_ARG, "Lanczos start vector has no zero-mean component");
+  lincomb64(P, n, 1.0 / std::sqrt(nn), v0, 0.0, v0, P->lz[0]);
+  std::vector<double> alpha, beta;
+  for (int i = 0; i < steps; ++i) {
+    hess_spec64(P, p, P->lz[i], P->AP, 0.0);
+    if (i > 0) lincomb64(P, n, 1.0, P->AP, -beta[i - 1], P->lz[i - 1], P->AP);
+    double a;
+    LB_TRY(spec_dot_host(P, p, P->AP, P->lz[i], &a));
+    lincomb64(P, n, 1.0, P->AP, -a, P->lz[i], P->AP);
+    for (int k = 0; k <= i; ++k) {
+      double c;
+      LB_TRY(spec_dot_host(P, p, P->AP, P->lz[k], &c));
+      lincomb64(P, n, 1.0, P->AP, -c, P->lz[k], P->AP);
+    }
+    alpha.push_back(a);
+    double bb;
+    LB_TRY(spec_dot_host(P, p, P->AP, P->AP, &bb));
+    const double b = std::sqrt(std::max(bb, 0.0));
+    beta.push_back(b);
+    if (i == steps - 1 || b < 1e-300) break;
+    lincomb64(P, n, 1.0 / b, P->AP, 0.0, P->AP, P->lz[i + 1]);
+  }
+  const int m = (int)alpha.size();
+  std::vector<double> A((size_t)m * m, 0.0), V;
+  for (int i = 0; i < m; ++i) {
+    A[(size_t)i * m + i] = alpha[i];
+    if (i + 1 < m) A[(size_t)i * m + i + 1] = A[(size_t)(i + 1) * m + i] = beta[i];
+  }
+  jacobi_eig(m, A, V);
+  int imin = 0;
+  for (int i = 1; i < m; ++i)
+    if (A[(size_t)i * m + i] < A[(size_t)imin * m + imin]) imin = i;
+  *ritz = A[(size_t)imin * m + imin];
+  *resid = std::fabs(beta[m - 1] * V[(size_t)(m - 1) * m + imin]);
+  return 0;
+}
+
+extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double *psi, const double *v0, int steps,
+                              double *ritz_min, double *resid) {
+  if (!P || !psi || !v0 || !ritz_min || !resid) return fail(LB_ERR_ARG, "null argument");
+  if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_lanczos_min needs a plan with batch 1");
+  if (steps < 1 || steps > 1000) return fail(LB_ERR_ARG, "steps must be in [1, 1000]");
+  Prm p;
+  LB_TRY(pack_params(P, params, 1, &p));
+  hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+                     P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  fwd_r2c(P, LB_FP64, 1, p, v0, P->R, 1);
+  LB_TRY(lanczos_core(P, p, P->R, steps, ritz_min, resid));
+  return check_launch("lb_lanczos_min");
+}
+
+// ---------------------------------------------------------------------------
+// Algorithms 1 and 2 (host-driven outer loop)
+// ---------------------------------------------------------------------------
+struct EG {
+  double E, gnorm, gninf, gpmax;
+};
+static int energy_grad_host(lb_plan *P, const Prm &p, const double *psi, EG *eg) {
+  energy_grad_core(P, 1, p, psi);
+  LB_TRY(check_launch("energy"));
+  LB_TRY(read_sums(P, P->sums, 40));
+  const double *s = P->sums_h;
+  eg->E = s[32] + s[0] / (double)P->N;
+  eg->gnorm = std::sqrt(std::max(s[33], 0.0));
+  eg->gninf = s[34];
+  eg->gpmax = s[1];
+  if (!std::isfinite(eg->E) || !std::isfinite(eg->gnorm)) return fail(LB_ERR_NONFINITE, "non-finite energy or gradient");
+  return 0;
+}
+
+// energy only at psi + s (s in sphys), for the direct ratio numerator; leaves
+// the current iterate's g_hat and Gamma' untouched
+static int energy_at_trial(lb_plan *P, const Prm &p, const double *psi, double *E) {
+  const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
+  hipLaunchKernelGGL(lbk::k_add_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, psi, (const double *)P->sphys,
+                     P->ptrial);
+  PassArgs r = args_rows(P, LB_FP64, 1, p, false);
+  r.psi = P->ptrial;
+  r.out = P->SP;
+  r.out2 = P->SP + P->nh;
+  r.partial = P->partial;
+  F(P, 2, LB_FP64)->rows_energy(r);
+  finalize(P, P->partial, r.rg.bpi, 2, 0x2u, 1, P->sums);
+  if (P->dim == 3) {
+    PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
+    c1.in = P->SP;
+    c1.out = P->SP;
+    F(P, 1, LB_FP64)->cols_plain(c1, false);
+  }
+  PassArgs c0 = args_col(P, LB_FP64, 1, p, 0);
+  c0.in = P->SP;
+  c0.out = P->SP;
+  c0.scale = 1.0 / (double)P->N;
+  F(P, 0, LB_FP64)->cols_plain(c0, false);
+  spec_reduce<double, 1>(P, 1, p, P->SP, P->SP, P->sums + 32);
+  LB_TRY(check_launch("trial energy"));
+  LB_TRY(read_sums(P, P->sums, 40));
+  *E = 0.5 * P->sums_h[32] + P->sums_h[0] / (double)P->N;
+  if (!std::isfinite(*E)) return fail(LB_ERR_NONFINITE, "non-finite trial energy");
+  return 0;
+}
+
+extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi, const lb_tr_opts *opts,
+                                lb_tr_info *info) {
+  if (!P || !psi || !info) return fail(LB_ERR_ARG, "null argument");
+  if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_imex_tr_solve needs a plan with batch 1");
+  lb_tr_opts o;
+  if (opts) o = *opts;
+  else lb_tr_opts_default(&o);
+  LB_TRY(check_sub_opts(o.sub));
+  if (!(o.theta > 0 && o.theta < 1) || !(o.gamma_c > 0 && o.gamma_c < 1) || !(o.gamma_e > 1) || !(o.gamma_lambda > 1) ||
+      !(o.mu_lo > 0 && o.mu_lo <= o.mu_hi) || !(o.mu0 >= o.mu_lo) || !(o.r0 > 0 && o.r0 <= o.nu0) || !(o.eps > 0))
+    return fail(LB_ERR_ARG, "bad trust-region options");
+  Prm p;
+  LB_TRY(pack_params(P, params, 1, &p));
+  std::memset(info, 0, sizeof(*info));
+  double r = o.r0, nu = o.nu0, mu = o.mu0;
+  double rho_prev = 0.0;
+  bool have_prev = false;
+  EG eg;
+  LB_TRY(energy_grad_host(P, p, psi, &eg));
+  int j = 0;
+  int status = LB_NOT_CONVERGED;
+  for (; j < o.max_outer; ++j) {
+    const double gtest = o.grad_norm_inf ? eg.gninf : eg.gnorm;
+    if (gtest < o.eps) {
+      status = LB_OK;
+      break;
+    }
+    lb_sub_opts so = o.sub;
+    so.eta = o.eta_safe && eg.gpmax > 0 ? std::min(o.eta, 0.9 / eg.gpmax) : o.eta;
+    SubOut sub;
+    LB_TRY(run_subproblem(P, p, r, so, eg.gnorm, nullptr, &sub));
+    info->inner_total += sub.iters;
+    const double lam = sub.lam, sn = sub.dnorm;
+    if (!(sn > 0)) return fail(LB_ERR_NONFINITE, "zero trial step");
+    if (j > 0 && have_prev && rho_prev < o.theta) mu = std::max(mu, lam / sn);
+    double dE;
+    if (o.rho_taylor) {
+      double gs, quad;
+      LB_TRY(spec_dot_host(P, p, P->GH, P->SH, &gs));
+      LB_TRY(spec_lam_host(P, p, P->SH, &quad));
+      inv_c2r(P, LB_FP64, 1, p, P->SH, P->W64, P->sphys, 2, psi, P->partial);
+      finalize(P, P->partial, (int)bpi_pairs(P), 1, 0u, 1, P->sums);
+      LB_TRY(read_sums(P, P->sums, 1));
+      const double pw = P->sums_h[0] / (double)P->N;
+      dE = -(gs + 0.5 * quad + pw);
+    } else {
+      inv_c2r(P, LB_FP64, 1, p, P->SH, P->W64, P->sphys, 0, nullptr, nullptr);
+      double Et;
+      LB_TRY(energy_at_trial(P, p, psi, &Et));
+      dE = eg.E - Et;
+    }
+    const double rho = dE / (sn * sn * sn);
+    const char *branch;
+    const bool on_nu = std::fabs(sn - nu) <= o.nu_tol * nu;
+    if (rho >= o.theta && (lam <= mu * sn || on_nu)) {
+      const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
+      hipLaunchKernelGGL(lbk::k_axpy_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, 1.0, (const double *)P->sphys,
+                         psi);
+      nu = std::max(nu, o.gamma_e * sn);
+      r = std::min(nu, std::max(r, o.gamma_e * sn));
+      mu = std::max(mu, lam / sn);
+      LB_TRY(energy_grad_host(P, p, psi, &eg));
+      info->accepted++;
+      branch = "accept";
+    } else if (rho < o.theta) {
+      // Algorithm 2 (CONTRACT); needs Gamma'(psi_j) and g_j, still in gp64 / GH
+      int it = 0;
+      if (lam < o.mu_lo * sn) {
+        const double lam_hat = lam + std::sqrt(o.mu_lo * eg.gnorm);
+        LB_TRY(cg_shifted(P, p, lam_hat, o.cg_rtol, o.cg_maxiter, &it));
+        info->cg_total += it;
+        double xx;
+        LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
+        double snew = std::sqrt(xx);
+        if (lam_hat / snew <= o.mu_hi) {
+          r = snew;
+        } else {
+          double lo = lam, hi = lam_hat;
+          for (int k = 0; k < 200; ++k) {
+            const double mid = 0.5 * (lo + hi);
+            LB_TRY(cg_shifted(P, p, mid, o.cg_rtol, o.cg_maxiter, &it));
+            info->cg_total += it;
+            LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
+            snew = std::sqrt(xx);
+            const double ratio = mid / snew;
+            if (ratio < o.mu_lo) lo = mid;
+            else if (ratio > o.mu_hi) hi = mid;
+            else break;
+          }
+          r = snew;
+        }
+      } else {
+        const double lt = o.gamma_lambda * lam;
+        LB_TRY(cg_shifted(P, p, lt, o.cg_rtol, o.cg_maxiter, &it));
+        info->cg_total += it;
+        double xx;
+        LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
+        const double snew = std::sqrt(xx);
+        if (snew >= o.gamma_c * sn) r = snew;
+        else r = o.contract_else_old_step ? o.gamma_c * sn : o.gamma_c * snew;
+      }
+      info->contracted++;
+      branch = "contract";
+    } else {
+      r = std::min(nu, lam / mu);
+      info->expanded++;
+      branch = "expand";
+    }
+    if (o.verbose)
+      std::fprintf(stderr,
+                   "[lb] j=%d E=%.15e |g|=%.3e |g|inf=%.3e r=%.3e nu=%.3e mu=%.3e lam=%.6e |s|=%.3e rho=%.6e eta=%.4f "
+                   "inner=%d resid=%.2e %s\n",
+                   j, eg.E, eg.gnorm, eg.gninf, r, nu, mu, lam, sn, rho, so.eta, sub.iters, sub.resid, branch);
+    rho_prev = rho;
+    have_prev = true;
+  }
+  LB_TRY(check_launch("lb_imex_tr_solve"));
+  LB_HIP(hipStreamSynchronize(P->stream));
+  info->energy = eg.E;
+  info->gnorm = eg.gnorm;
+  info->gnorm_inf = eg.gninf;
+  info->outer = j;
+  info->status = status;
+  return status;
+}

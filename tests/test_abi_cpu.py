@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/lb.h declares, the ctypes structs match the C layout, and the default
+options are the paper's Section 4 values. No GPU work is done here."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb.h")
+LIB = os.path.join(ROOT, "paper_2603_03933_amd", "liblbtr.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="liblbtr.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for n in ("lb_energy_grad", "lb_hessvec", "lb_tr_subproblem", "lb_imex_tr_solve", "lb_plan_create", "lb_plan_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2603_03933_amd import lb
+
+    L = lb.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(lb.exported_symbols())
+
+
+def test_struct_layouts_match_c():
+    from paper_2603_03933_amd import lb
+
+    structs = {
+        "lb_grid": lb.LbGrid,
+        "lb_params": lb.LbParams,
+        "lb_sub_opts": lb.LbSubOpts,
+        "lb_sub_info": lb.LbSubInfo,
+        "lb_tr_opts": lb.LbTrOpts,
+        "lb_tr_info": lb.LbTrInfo,
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", "-o", exe, src], check=True)
+        out = subprocess.run([exe], check=True, stdout=subprocess.PIPE, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_default_options_are_section4_values():
+    from paper_2603_03933_amd import lb
+
+    o = lb.tr_opts()
+    assert (o.gamma_c, o.gamma_e, o.gamma_lambda, o.theta) == (0.5, 2.0, 1.5, 1e-4)
+    assert (o.mu_lo, o.mu_hi, o.mu0, o.r0, o.nu0) == (1.0, 1e5, 1.0, 1.0, 5.0)
+    assert o.eps == 1e-10 and o.grad_norm_inf == 1
+    assert o.eta == 0.1 and o.sub.eps_sub == 1e-13
+    s = lb.sub_opts()
+    assert s.eta == 0.1 and s.eps_sub == 1e-13 and s.max_inner > 0
+
+
+def test_version_and_error_string():
+    from paper_2603_03933_amd import lb
+
+    assert lb.lib().lb_version() >= 100
+    assert isinstance(lb.lib().lb_last_error(), bytes)

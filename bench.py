@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""IMEX-TR benchmark on the 128^3 BCC Landau-Brazovskii workload, one GPU.
+
+A step is one pass of the whole hot path on the workload: a full IMEX-TR
+solve (energy and gradient, Algorithm 3's FFT-based subproblem iteration with
+its Newton multiplier update and stop test, the ratio test and CONTRACT of
+Algorithms 1-2) from the BCC trial state to ||grad E|| < 1e-8, followed by a
+30-step Lanczos estimate of the smallest Hessian eigenvalue (second-order
+check). The input field is resident on the GPU before timing starts; each step
+starts from a device copy of it.
+
+Printed: one JSON line with solves/s (FP64), Hessian-vector products/s at
+128^3 in FP64 and FP32, the FP32-inner solve rate, the roofline of the
+dominant kernel (timed live with HIP events on the plan's stream during the
+timed steps) and the CPU oracle's rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Hessian-vector products/s + IMEX-TR solves/s at 128³ (FP64 vs FP32+FP64, batched)"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+TOL = 1e-8
+
+
+def kernel_bytes(name: str, prec: str, N: int, nh: int) -> float | None:
+    """Compulsory bytes one launch of a hot-path kernel must move (each array it
+    reads or writes, once), for one 128^3 instance. c = complex size, r = real."""
+    c = 16 if prec == "fp64" else 8
+    r = 8 if prec == "fp64" else 4
+    table = {
+        "col0_fwd_update": nh * (4 * c + 8),  # read T d, b_prev, g; write b_next; write w|b|^2 (FP64)
+        "col0_inv_scale_d": nh * 2 * c,  # read b_prev, write partial transform
+        "col1_inv": nh * 2 * c,
+        "col1_fwd": nh * 2 * c,
+        "col0_inv": nh * 2 * c,
+        "col0_fwd": nh * 2 * c,
+        "rows_inner": nh * 2 * c + N * r,  # read/write the partial transform, read Gamma'
+        "bins": nh * (8 + 4),  # w|b|^2 gathered through the shell permutation
+    }
+    return table.get(name)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2603_03933_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hpp", ".hip")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(inst, inner_total: int, outer_total: int, cg_total: int, budget_s: float):
+    """Time the CPU oracle on a bounded sample of the same workload and scale to solves/s."""
+    import numpy as np
+
+    from oracle import lb_oracle as O
+
+    m = O.Model(O.Grid(inst.grid.n, inst.grid.box), inst.params.tau, inst.params.gamma)
+    psi = inst.psi0
+    t0 = time.perf_counter()
+    g = O.gradient(m, psi)
+    E = O.energy(m, psi)
+    t_eg = time.perf_counter() - t0
+    gmax = float(np.max(np.abs(O.Gamma_p(psi, m.tau, m.gamma))))
+    eta = min(0.1, 0.9 / gmax)
+    # one inner iteration at a time until the budget is spent
+    k = 0
+    t1 = time.perf_counter()
+    while True:
+        O.imex_subproblem(m, psi, g, 1.0, O.SubOpts(eta=eta, max_inner=1))
+        k += 1
+        if time.perf_counter() - t1 > budget_s or k >= 64:
+            break
+    t_in = (time.perf_counter() - t1) / k
+    # an outer iteration evaluates energy and gradient about twice; a CG step costs one Hv (~ one inner step)
+    t_solve = t_in * (inner_total + cg_total) + 2.0 * t_eg * outer_total
+    return {
+        "value": 1.0 / t_solve,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (
+            f"oracle (NumPy FP64, single-threaded pocketfft) on the 128^3 BCC input: {k} inner IMEX iterations "
+            f"({t_in:.3f} s each) and one energy+gradient ({t_eg:.3f} s); scaled by the GPU solve's counts "
+            f"({inner_total} inner, {cg_total} CG, {outer_total} outer)"
+        ),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--size", type=int, default=128)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_03933_amd import inputs as I
+    from paper_2603_03933_amd import lb
+
+    dev = torch.device("cuda:0")
+    inst = I.bcc_3d(args.size)
+    n, box = inst.grid.n, inst.grid.box
+    N = inst.grid.N
+    nh = n[0] * n[1] * (n[2] // 2 + 1)
+    prm = lb.Params(inst.params.tau, inst.params.gamma)
+    psi0 = torch.from_numpy(inst.psi0).to(dev)
+    v0 = torch.from_numpy(I.hessvec_direction(n, 2)).to(dev)
+    psi = torch.empty_like(psi0)
+    plan = lb.Plan(n, box, precision="fp64")
+    opts = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64})
+
+    def step(p, o):
+        psi.copy_(psi0)
+        info, rc = p.lb_imex_tr_solve(prm, psi, o)
+        ritz, res = p.lb_lanczos_min(prm, psi, v0, 30)
+        return info, rc, ritz, res
+
+    # warmup, with every kernel timed to find the dominant one
+    plan.lb_plan_set_timing(True, "")
+    for _ in range(max(1, args.warmup)):
+        info, rc, ritz, res = step(plan, opts)
+    warm = plan.timings()
+    dominant = max((k for k in warm if kernel_bytes(k, "fp64", N, nh) is not None), key=lambda k: warm[k][1])
+    total_ms = sum(v[1] for v in warm.values())
+
+    # timed steps: events only around the dominant kernel
+    plan.lb_plan_set_timing(True, dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(step(plan, opts))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = plan.timings()
+    plan.lb_plan_set_timing(False, "")
+    elapsed = t1 - t0
+    info, rc, ritz, res = infos[-1]
+    launches, dom_ms = tm.get(dominant, (0, 0.0))
+    avg_s = dom_ms / max(1, launches) * 1e-3
+    alg = kernel_bytes(dominant, "fp64", N, nh)
+    achieved = alg / avg_s / 1e9 if avg_s > 0 else None
+    roofline = {
+        "kernel": dominant,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS if achieved else None,
+        "traffic": traffic_from_profiles(dominant),
+        "alg_bytes_per_launch": alg,
+        "avg_launch_us": avg_s * 1e6,
+        "launches_timed": launches,
+        "share_of_kernel_time": warm[dominant][1] / total_ms if total_ms else None,
+    }
+
+    # Hessian-vector products/s (lb_hessvec, projected) in FP64 and FP32
+    def hv_rate(precision):
+        p = plan if precision == "fp64" else lb.Plan(n, box, precision=precision)
+        out = torch.empty_like(psi0)
+        for _ in range(5):
+            p.lb_hessvec(prm, psi0, v0, out=out)
+        torch.cuda.synchronize()
+        reps = 200
+        s = time.perf_counter()
+        for _ in range(reps):
+            p.lb_hessvec(prm, psi0, v0, out=out)
+        torch.cuda.synchronize()
+        return reps / (time.perf_counter() - s)
+
+    hv = {"fp64": hv_rate("fp64")}
+    fp32 = None
+    if not args.no_fp32:
+        hv["fp32"] = hv_rate("fp32")
+        p32 = lb.Plan(n, box, precision="fp32")
+        o32 = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64, "eps_sub_rel": 1e-6})
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        i32, rc32, ritz32, _ = step(p32, o32)
+        torch.cuda.synchronize()
+        d32 = time.perf_counter() - s
+        fp32 = {
+            "solves_per_s": 1.0 / d32,
+            "status": "converged" if rc32 == 0 else "not_converged",
+            "energy": i32.energy,
+            "gnorm": i32.gnorm,
+            "outer": i32.outer,
+            "inner": i32.inner_total,
+            "lambda_min_ritz": ritz32,
+        }
+    # lb_hessvec reads psi and v and writes hv as FP64 arrays in either precision: 24 N bytes
+    for k in list(hv):
+        hv[k + "_alg_hbm_frac"] = 24.0 * N * hv[k] / (HBM_PEAK_GBS * 1e9)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inst, info.inner_total, info.outer, info.cg_total, args.cpu_budget)
+
+    inner_per_s = sum(i[0].inner_total for i in infos) / elapsed
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"bcc_3d {n[0]}^3 FP64 IMEX-TR solve to ||g||<{TOL:g} + 30-step Lanczos",
+            "grid": list(n),
+            "box": box[0],
+            "tau": inst.params.tau,
+            "gamma": inst.params.gamma,
+            "psi0": "BCC {110} unit amplitude + N(0,0.01^2), seed 0",
+        },
+        "solve": {
+            "status": "converged" if rc == 0 else "not_converged",
+            "energy": info.energy,
+            "gnorm": info.gnorm,
+            "outer": info.outer,
+            "inner": info.inner_total,
+            "cg": info.cg_total,
+            "accepted": info.accepted,
+            "contracted": info.contracted,
+            "lambda_min_ritz": ritz,
+            "ritz_residual": res,
+            "inner_iterations_per_s": inner_per_s,
+        },
+        "hessvec_per_s": hv,
+        "solve_fp32_inner": fp32,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_share_warmup": {k: round(v[1] / total_ms, 4) for k, v in sorted(warm.items(), key=lambda kv: -kv[1][1])[:8]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -31,7 +31,8 @@
  * return before the GPU finishes; calls that fill a host `info` struct
  * synchronise the stream before returning. A plan is not thread safe: use one
  * plan per stream. Plans allocate all their device workspace in
- * lb_plan_create; no other call allocates.
+ * lb_plan_create; no other call allocates, except lb_lanczos_min, which adds
+ * its Krylov basis to the plan the first time it needs more vectors.
  *
  * Return codes: LB_OK, LB_NOT_CONVERGED (outputs valid, details in info), or a
  * negative error; lb_last_error() returns a message for the last error of the
@@ -83,6 +84,10 @@ typedef struct lb_sub_opts {
   double newton_rtol;    /* Newton stops when phi(lambda) - r^2 <= newton_rtol r^2 */
   double newton_steptol; /* ... or |delta lambda| <= newton_steptol max(1, lambda) */
   int poll_every;        /* iterations enqueued between host reads of the stop flag */
+  int newton_phi;        /* root of phi(lambda) = r^2 (eq. lambda_update_rule) by Newton from
+                            lambda = 0 applied to: 1 -> phi(lambda) - r^2 as printed;
+                            0 (default) -> the equivalent 1/sqrt(phi) - 1/r, which is concave
+                            and converges monotonically to the same root in fewer steps */
 } lb_sub_opts;
 
 typedef struct lb_sub_info {
@@ -151,6 +156,19 @@ int lb_plan_set_stream(lb_plan *plan, void *stream);
 /* Device bytes held by the plan. */
 size_t lb_plan_workspace_bytes(const lb_plan *plan);
 
+/* Kernel timing, a measurement aid. When enabled, every kernel launch of the
+ * plan whose name equals `filter` (all launches when filter is NULL or "")
+ * is bracketed by HIP events on the plan's stream; durations accumulate per
+ * kernel name until timing is set again. Names: rows_r2c, rows_c2r,
+ * rows_c2r_hv, rows_energy, rows_inner, col1_fwd, col1_inv, col0_fwd,
+ * col0_inv, col0_fwd_mul_inv, col0_inv_scale_d, col0_fwd_update,
+ * col0_fwd_hess, bins, newton, grad_assemble, spec_reduce, finalize,
+ * lincomb, init_b, final_d, gamma_p, energy_out, add_real, axpy_real. */
+int lb_plan_set_timing(lb_plan *plan, int enable, const char *filter);
+/* Entry `index` (0-based) of the accumulated timings: kernel name, launches
+ * and total milliseconds. Synchronises the stream. LB_ERR_ARG past the end. */
+int lb_plan_timing_entry(lb_plan *plan, int index, char *name, int name_len, long *count, double *total_ms);
+
 /* Energy and projected gradient (Section 2: grad G = Lambda Psi_hat,
  * grad F = F_N Gamma F_N^{-1} Psi_hat; Section 3: projection P).
  *   params : `batch` entries (host)
@@ -200,7 +218,8 @@ int lb_shifted_solve(lb_plan *plan, const lb_params *params, const double *psi, 
 /* Second-order check: smallest Ritz value of H on the zero-mean subspace
  * after `steps` Lanczos steps (full reorthogonalisation) from v0 (device, N
  * doubles). A Ritz value bounds sigma_1 from above; *resid is the Ritz
- * residual norm. batch must be 1. Host outputs. */
+ * residual norm. batch must be 1. Host outputs. Allocates steps + 1 spectral
+ * vectors on first use (kept by the plan). */
 int lb_lanczos_min(lb_plan *plan, const lb_params *params, const double *psi, const double *v0, int steps,
                    double *ritz_min, double *resid);
 

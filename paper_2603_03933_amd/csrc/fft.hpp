@@ -147,13 +147,20 @@ template <typename T, int R, bool INV> __device__ __forceinline__ void dft(c2<T>
 // The pass loop. `t` in [0, TPF) is this thread's lane within the transform,
 // `c` the transform's slot in the workgroup, `lds` the workgroup's buffer and
 // lidx(c, e) the LDS position of element e of slot c. load(e) supplies the
-// first pass's inputs, store(e, v) takes the last pass's outputs. Every
-// thread of the workgroup must call this (it contains barriers); threads of
-// slots without data simply pass zeros through.
+// first pass's inputs. For the last pass, fetch(e) is called for every output
+// element before the butterflies (so that a caller's extra loads are all in
+// flight while the pass computes) and store(e, v, aux) receives the output
+// with what fetch returned. Every thread of the workgroup must call this (it
+// contains barriers); threads of slots without data pass zeros through.
 // ---------------------------------------------------------------------------
-template <typename T, int N, bool INV, int P = 0, class LIdx, class Load, class Store>
+struct NoAux {};
+struct NoFetch {
+  __device__ NoAux operator()(int) const { return NoAux{}; }
+};
+
+template <typename T, int N, bool INV, int P = 0, class LIdx, class Load, class Fetch, class Store>
 __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &lidx, const c2<T> *__restrict__ tw,
-                                        const Load &load, const Store &store) {
+                                        const Load &load, const Fetch &fetch, const Store &store) {
   using C = c2<T>;
   constexpr int NP = num_passes(N);
   constexpr int R = radix_at(N, P);
@@ -175,35 +182,74 @@ __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &li
       }
     }
   }
-  __syncthreads();  // all reads of the buffer finish before it is rewritten
+  if constexpr (P == NP - 1) {
+    using Aux = decltype(fetch(0));
+    Aux aux[S][R];
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int j = t + s * TPF;
-    if (EXACT || j < NB) {
-      const int k = j % NS;
-      if constexpr (NS > 1) {
+    for (int s = 0; s < S; ++s) {
+      const int j = t + s * TPF;
+      if (EXACT || j < NB) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C w = tw[r * k * (N / (NS * R))];
-          if constexpr (INV) w.y = -w.y;
-          v[s][r] = cmul(v[s][r], w);
-        }
+        for (int r = 0; r < R; ++r) aux[s][r] = fetch(j + r * NB);
       }
-      dft<T, R, INV>(v[s]);
-      if constexpr (P == NP - 1) {
+    }
+    __syncthreads();  // all reads of the buffer finish before it is rewritten
 #pragma unroll
-        for (int r = 0; r < R; ++r) store(j + r * NB, v[s][r]);
-      } else {
+    for (int s = 0; s < S; ++s) {
+      const int j = t + s * TPF;
+      if (EXACT || j < NB) {
+        const int k = j % NS;
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            C w = tw[r * k * (N / (NS * R))];
+            if constexpr (INV) w.y = -w.y;
+            v[s][r] = cmul(v[s][r], w);
+          }
+        }
+        dft<T, R, INV>(v[s]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = t + s * TPF;
+      if (EXACT || j < NB) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) store(j + r * NB, v[s][r], aux[s][r]);
+      }
+    }
+  } else {
+    __syncthreads();  // all reads of the buffer finish before it is rewritten
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = t + s * TPF;
+      if (EXACT || j < NB) {
+        const int k = j % NS;
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            C w = tw[r * k * (N / (NS * R))];
+            if constexpr (INV) w.y = -w.y;
+            v[s][r] = cmul(v[s][r], w);
+          }
+        }
+        dft<T, R, INV>(v[s]);
         const int base = (j / NS) * NS * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) lds[lidx(c, base + r * NS)] = v[s][r];
       }
     }
-  }
-  if constexpr (P < NP - 1) {
     __syncthreads();
-    fft_run<T, N, INV, P + 1>(t, c, lds, lidx, tw, load, store);
+    fft_run<T, N, INV, P + 1>(t, c, lds, lidx, tw, load, fetch, store);
   }
+}
+
+// LDS-to-LDS transform of slot c (rows kernels): no extra loads
+template <typename T, int N, bool INV, class LIdx>
+__device__ __forceinline__ void fft_lds(int t, int c, c2<T> *lds, const LIdx &lidx, const c2<T> *__restrict__ tw) {
+  fft_run<T, N, INV>(
+      t, c, lds, lidx, tw, [&](int e) -> c2<T> { return lds[lidx(c, e)]; }, NoFetch{},
+      [&](int e, c2<T> v, NoAux) { lds[lidx(c, e)] = v; });
 }
 
 }  // namespace lbfft

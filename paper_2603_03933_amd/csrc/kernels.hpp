@@ -39,21 +39,51 @@ __device__ __forceinline__ double lam_of(double kk, double xi, double q) {
   return xi * xi * t * t;
 }
 
-// instance-relative half-spectrum offset -> (i0, i1, kl)
-__device__ __forceinline__ void decode(const Geo &g, long h, int &i0, int &i1, int &kl) {
-  kl = (int)(h % g.nhl);
-  const long r = h / g.nhl;
-  i1 = (int)(r % g.n1);
-  i0 = (int)(r / g.n1);
+// instance-relative half-spectrum offset -> (i0, i1, kl); 32-bit arithmetic
+__device__ __forceinline__ void decode(const Geo &g, int h, int &i0, int &i1, int &kl) {
+  const int r = h / g.nhl;
+  kl = h - r * g.nhl;
+  i0 = r / g.n1;
+  i1 = r - i0 * g.n1;
 }
-__device__ __forceinline__ double kk_at(const Geo &g, long h, int &kl) {
+// |Bk|^2 summed as kk0 + (kkl + kk1), the order the host uses to group shells
+__device__ __forceinline__ double kk_col_part(const Geo &g, int i1, int kl) {
+  return g.dim == 3 ? g.kkl[kl] + g.kk1[i1] : g.kkl[kl];
+}
+__device__ __forceinline__ double kk_at(const Geo &g, int h, int &kl) {
   int i0, i1;
   decode(g, h, i0, i1, kl);
-  double kk = g.kk0[i0] + g.kkl[kl];
-  if (g.dim == 3) kk += g.kk1[i1];
-  return kk;
+  return g.kk0[i0] + kk_col_part(g, i1, kl);
 }
 __device__ __forceinline__ double herm_w(const Geo &g, int kl) { return (kl == 0 || 2 * kl == g.nl) ? 1.0 : 2.0; }
+
+// 1 / x for x >= 1 to full FP64 accuracy: hardware estimate + two Newton steps
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Reciprocal-space data shared by all elements of one axis-0 column
+struct ColInfo {
+  double kkc;  // |Bk|^2 contribution of the column's (k1, k_last)
+  double w;    // Hermitian weight of the column
+  int dc;      // the column holds k = 0 at element 0
+};
+__device__ __forceinline__ ColInfo col_info(const Geo &g, int ml) {
+  int i1 = 0, kl = ml;
+  if (g.dim == 3) {
+    i1 = ml / g.nhl;
+    kl = ml - i1 * g.nhl;
+  }
+  ColInfo c;
+  c.kkc = kk_col_part(g, i1, kl);
+  c.w = herm_w(g, kl);
+  c.dc = (ml == 0);
+  return c;
+}
 
 constexpr int pow2_floor(int x) {
   int p = 1;
@@ -128,59 +158,79 @@ struct SubState {
   int newton_total;
   int max_inner, max_newton;
   int nonfinite;
-  int pad;
+  int newton_phi;     // 1: Newton on phi(lambda) = r^2; 0: on 1/sqrt(phi) = 1/r
 };
 
 // ---------------------------------------------------------------------------
 // Column passes
 // ---------------------------------------------------------------------------
 struct ColGeo {
-  int cpi;            // columns per instance
-  int bpi;            // workgroups per instance
-  long inner, outer;  // base(m) = (m / inner) * outer + m % inner
-  long S;             // element stride along the transformed axis
-  long inst;          // instance stride
+  int cpi;    // columns per instance
+  int bpi;    // workgroups per instance
+  int inner;  // base(m) = (m / inner) * outer + m % inner
+  long outer;
+  long S;     // element stride along the transformed axis
+  long inst;  // instance stride
 };
 
+// Ops are stateless: begin(b) returns per-workgroup state and column(...)
+// per-column state by value; fetch(...) returns what the final store needs
+// besides the transform output (loaded ahead of the last pass).
 template <typename T, int N, bool INV, class Op>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__restrict__ tw, Op op) {
+__global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__restrict__ tw, const Op op) {
   using C = c2<T>;
   constexpr int CC = Cfg<N>::C;
   constexpr int NT = Cfg<N>::NT;
   __shared__ C lds[N * CC];
   if (op.skip()) return;
   const int b = blockIdx.x / cg.bpi;
-  const int lb = blockIdx.x % cg.bpi;
+  const int lb = blockIdx.x - b * cg.bpi;
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
-  const long ml = (long)lb * CC + c;
+  const int ml = lb * CC + c;
   const bool ok = ml < cg.cpi;
-  const long base = b * cg.inst + (ml / cg.inner) * cg.outer + (ml % cg.inner);
-  op.begin(b);
+  const int mo = ml / cg.inner;
+  const long base = b * cg.inst + (long)mo * cg.outer + (ml - mo * cg.inner);
+  const auto bs = op.begin(b);
+  const auto cs = op.column(b, ok ? ml : 0);
+  double acc = 0.0;
   fft_run<T, N, INV>(
       t, c, lds, [](int cc, int e) { return e * CC + cc; }, tw,
-      [&](int e) -> C { return ok ? op.load(b, base + e * cg.S, e) : C{T(0), T(0)}; },
-      [&](int e, C v) {
-        if (ok) op.store(b, base + e * cg.S, e, v);
+      [&](int e) -> C { return ok ? op.load(bs, cs, base + e * cg.S, e) : C{T(0), T(0)}; },
+      [&](int e) { return op.fetch(bs, cs, ok, base + e * cg.S, e); },
+      [&](int e, C v, const auto &aux) {
+        if (ok) op.store(bs, cs, base + e * cg.S, e, v, aux, acc);
       });
-  op.template end<NT>(b, reinterpret_cast<double *>(lds));
+  op.template end<NT>(acc, reinterpret_cast<double *>(lds));
 }
 
+struct Empty {};
+
 // plain pass: out = scale * FFT(in); optional removal of the k = 0 mode
+// (zero_dc only on the final axis-0 pass)
 template <typename T> struct OpPlain {
   const c2<T> *in;
   c2<T> *out;
   T scale;
-  int zero_dc;  // only meaningful on the final (axis 0) pass
+  int zero_dc;
   long nh;
   const SubState *st;  // non-null: skip once the subproblem has stopped
   __device__ bool skip() const { return st && st->done; }
-  __device__ void begin(int) {}
-  __device__ c2<T> load(int, long h, int) const { return in[h]; }
-  __device__ void store(int, long h, int, c2<T> v) const {
-    if (zero_dc && (h % nh) == 0) v = c2<T>{T(0), T(0)};
+  __device__ Empty begin(int) const { return Empty{}; }
+  __device__ int column(int, int ml) const { return zero_dc && ml == 0; }
+  __device__ c2<T> load(const Empty &, int, long h, int) const { return in[h]; }
+  __device__ Empty fetch(const Empty &, int, bool, long, int) const { return Empty{}; }
+  __device__ void store(const Empty &, int dccol, long h, int e, c2<T> v, const Empty &, double &) const {
+    if (dccol && e == 0) v = c2<T>{T(0), T(0)};
     out[h] = c2<T>{v.x * scale, v.y * scale};
   }
-  template <int NT> __device__ void end(int, double *) {}
+  template <int NT> __device__ void end(double, double *) const {}
+};
+
+// per-workgroup subproblem state read from SubState
+template <typename T> struct StepBlk {
+  const c2<T> *bprev;
+  c2<T> *bnext;
+  double lam_t, eta, xi, q;
 };
 
 // step t of the subproblem, axis-0 inverse pass: d_t = b_{t-1} / (1 + eta (Lambda + lambda_t))
@@ -190,80 +240,97 @@ template <typename T> struct OpInvScaleD {
   const c2<T> *b0, *b1;  // b buffers: b_{t-1} lives in (t - 1) & 1
   c2<T> *out;
   const SubState *st;
-  double fac_lam, eta;
-  const c2<T> *src;
   __device__ bool skip() const { return st->done != 0; }
-  __device__ void begin(int b) {
+  __device__ StepBlk<T> begin(int b) const {
     const int t = st->step;
-    src = ((t - 1) & 1) ? b1 : b0;
-    fac_lam = st->lam[t & 1];
-    eta = st->eta;
+    StepBlk<T> s;
+    s.bprev = ((t - 1) & 1) ? b1 : b0;
+    s.bnext = nullptr;
+    s.lam_t = st->lam[t & 1];
+    s.eta = st->eta;
+    s.xi = p.xi[b];
+    s.q = p.q[b];
+    return s;
   }
-  __device__ c2<T> load(int b, long h, int) const {
-    int kl;
-    const long hl = h - (long)b * g.nh;
-    if (hl == 0) return c2<T>{T(0), T(0)};
-    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
-    const double s = 1.0 / (1.0 + eta * (lam + fac_lam));
-    const c2<T> v = src[h];
-    return c2<T>{T(v.x * s), T(v.y * s)};
+  __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
+  __device__ c2<T> load(const StepBlk<T> &bs, const ColInfo &ci, long h, int e) const {
+    if (ci.dc && e == 0) return c2<T>{T(0), T(0)};
+    const double lam = lam_of(g.kk0[e] + ci.kkc, bs.xi, bs.q);
+    const double s = rcp64(1.0 + bs.eta * (lam + bs.lam_t));
+    const c2<T> v = bs.bprev[h];
+    return c2<T>{T(double(v.x) * s), T(double(v.y) * s)};
   }
-  __device__ void store(int, long h, int, c2<T> v) const { out[h] = v; }
-  template <int NT> __device__ void end(int, double *) {}
+  __device__ Empty fetch(const StepBlk<T> &, const ColInfo &, bool, long, int) const { return Empty{}; }
+  __device__ void store(const StepBlk<T> &, const ColInfo &, long h, int, c2<T> v, const Empty &, double &) const {
+    out[h] = v;
+  }
+  template <int NT> __device__ void end(double, double *) const {}
 };
 
 // step t, axis-0 forward pass of T d_t, then the diagonal update:
 //   Td = P F_N(Gamma' d_t),  r_t = g + (Lambda + lambda_t) d_t + Td  (residual of d_t),
 //   b_t = d_t - eta (g + Td),  bsq = w |b_t|^2 (for the secular function)
+template <typename T> struct UpdAux {
+  c2<T> bp, gg;
+  double kk0;
+};
 template <typename T> struct OpFwdUpdate {
   Geo g;
   Prm p;
-  const c2<T> *tmp;  // axis-1/row transformed product Gamma' d_t
+  const c2<T> *tmp;  // row/axis-1 transformed product Gamma' d_t
   c2<T> *b0, *b1;
   const c2<T> *gh;
   double *bsq;
-  double *partial;   // one double per workgroup: sum w |r|^2
+  double *partial;  // one double per workgroup: sum w |r|^2
   const SubState *st;
   double inv_n;
-  double lam_t, eta;
-  const c2<T> *bprev;
-  c2<T> *bnext;
-  double acc;
   __device__ bool skip() const { return st->done != 0; }
-  __device__ void begin(int) {
+  __device__ StepBlk<T> begin(int b) const {
     const int t = st->step;
-    bprev = ((t - 1) & 1) ? b1 : b0;
-    bnext = (t & 1) ? b1 : b0;
-    lam_t = st->lam[t & 1];
-    eta = st->eta;
-    acc = 0.0;
+    StepBlk<T> s;
+    s.bprev = ((t - 1) & 1) ? b1 : b0;
+    s.bnext = (t & 1) ? b1 : b0;
+    s.lam_t = st->lam[t & 1];
+    s.eta = st->eta;
+    s.xi = p.xi[b];
+    s.q = p.q[b];
+    return s;
   }
-  __device__ c2<T> load(int, long h, int) const { return tmp[h]; }
-  __device__ void store(int b, long h, int, c2<T> v) {
-    const long hl = h - (long)b * g.nh;
-    if (hl == 0) {
-      bnext[h] = c2<T>{T(0), T(0)};
+  __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
+  __device__ c2<T> load(const StepBlk<T> &, const ColInfo &, long h, int) const { return tmp[h]; }
+  __device__ UpdAux<T> fetch(const StepBlk<T> &bs, const ColInfo &, bool ok, long h, int e) const {
+    UpdAux<T> a;
+    if (ok) {
+      a.bp = bs.bprev[h];
+      a.gg = gh[h];
+    } else {
+      a.bp = c2<T>{T(0), T(0)};
+      a.gg = a.bp;
+    }
+    a.kk0 = g.kk0[e];
+    return a;
+  }
+  __device__ void store(const StepBlk<T> &bs, const ColInfo &ci, long h, int e, c2<T> v, const UpdAux<T> &a,
+                        double &acc) const {
+    if (ci.dc && e == 0) {
+      bs.bnext[h] = c2<T>{T(0), T(0)};
       bsq[h] = 0.0;
       return;
     }
-    int kl;
-    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
-    const double w = herm_w(g, kl);
-    const double s = 1.0 / (1.0 + eta * (lam + lam_t));
-    const c2<T> bp = bprev[h];
-    const double dx = double(bp.x) * s, dy = double(bp.y) * s;
+    const double lam = lam_of(a.kk0 + ci.kkc, bs.xi, bs.q);
+    const double s = rcp64(1.0 + bs.eta * (lam + bs.lam_t));
+    const double dx = double(a.bp.x) * s, dy = double(a.bp.y) * s;
     const double tx = double(v.x) * inv_n, ty = double(v.y) * inv_n;
-    const c2<T> gg = gh[h];
-    const double gx = double(gg.x), gy = double(gg.y);
-    const double rx = gx + (lam + lam_t) * dx + tx, ry = gy + (lam + lam_t) * dy + ty;
-    acc += w * (rx * rx + ry * ry);
-    const double bx = dx - eta * (gx + tx), by = dy - eta * (gy + ty);
+    const double gx = double(a.gg.x), gy = double(a.gg.y);
+    const double rx = gx + (lam + bs.lam_t) * dx + tx, ry = gy + (lam + bs.lam_t) * dy + ty;
+    acc += ci.w * (rx * rx + ry * ry);
+    const double bx = dx - bs.eta * (gx + tx), by = dy - bs.eta * (gy + ty);
     const c2<T> bn = c2<T>{T(bx), T(by)};
-    bnext[h] = bn;
+    bs.bnext[h] = bn;
     const double bxr = double(bn.x), byr = double(bn.y);
-    bsq[h] = w * (bxr * bxr + byr * byr);
+    bsq[h] = ci.w * (bxr * bxr + byr * byr);
   }
-  template <int NT> __device__ void end(int, double *scratch) {
+  template <int NT> __device__ void end(double acc, double *scratch) const {
     const double s = block_sum<NT>(acc, scratch);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
@@ -271,6 +338,13 @@ template <typename T> struct OpFwdUpdate {
 
 // axis-0 forward pass completing a spectral Hessian-vector product:
 //   out = Lambda x + P F_N(Gamma' F_N^{-1} x) + shift x
+struct HessBlk {
+  double xi, q;
+};
+template <typename T> struct HessAux {
+  c2<T> xv;
+  double kk0;
+};
 template <typename T> struct OpFwdHess {
   Geo g;
   Prm p;
@@ -279,20 +353,25 @@ template <typename T> struct OpFwdHess {
   c2<T> *out;
   double inv_n, shift;
   __device__ bool skip() const { return false; }
-  __device__ void begin(int) {}
-  __device__ c2<T> load(int, long h, int) const { return tmp[h]; }
-  __device__ void store(int b, long h, int, c2<T> v) const {
-    const long hl = h - (long)b * g.nh;
-    if (hl == 0) {
+  __device__ HessBlk begin(int b) const { return HessBlk{p.xi[b], p.q[b]}; }
+  __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
+  __device__ c2<T> load(const HessBlk &, const ColInfo &, long h, int) const { return tmp[h]; }
+  __device__ HessAux<T> fetch(const HessBlk &, const ColInfo &, bool ok, long h, int e) const {
+    HessAux<T> a;
+    a.xv = ok ? x[h] : c2<T>{T(0), T(0)};
+    a.kk0 = g.kk0[e];
+    return a;
+  }
+  __device__ void store(const HessBlk &hb, const ColInfo &ci, long h, int e, c2<T> v, const HessAux<T> &a,
+                        double &) const {
+    if (ci.dc && e == 0) {
       out[h] = c2<T>{T(0), T(0)};
       return;
     }
-    int kl;
-    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]) + shift;
-    const c2<T> xv = x[h];
-    out[h] = c2<T>{T(lam * double(xv.x) + double(v.x) * inv_n), T(lam * double(xv.y) + double(v.y) * inv_n)};
+    const double lam = lam_of(a.kk0 + ci.kkc, hb.xi, hb.q) + shift;
+    out[h] = c2<T>{T(lam * double(a.xv.x) + double(v.x) * inv_n), T(lam * double(a.xv.y) + double(v.y) * inv_n)};
   }
-  template <int NT> __device__ void end(int, double *) {}
+  template <int NT> __device__ void end(double, double *) const {}
 };
 
 // Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
@@ -304,27 +383,26 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   constexpr int CC = Cfg<N>::C;
   __shared__ C lds[N * CC];
   const int b = blockIdx.x / cg.bpi;
-  const int lb = blockIdx.x % cg.bpi;
+  const int lb = blockIdx.x - b * cg.bpi;
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
-  const long ml = (long)lb * CC + c;
+  const int ml = lb * CC + c;
   const bool ok = ml < cg.cpi;
-  const long base = b * cg.inst + (ml / cg.inner) * cg.outer + (ml % cg.inner);
+  const long base = b * cg.inst + ml;  // axis 0: every column starts in the first slab
+  const ColInfo ci = col_info(g, ok ? ml : 0);
+  const double xi = p.xi[b], q = p.q[b];
   auto lidx = [](int cc, int e) { return e * CC + cc; };
   fft_run<T, N, false>(
       t, c, lds, lidx, tw, [&](int e) -> C { return ok ? data[base + e * cg.S] : C{T(0), T(0)}; },
-      [&](int e, C v) {
-        const long hl = base + e * cg.S - (long)b * g.nh;
-        double m = 0.0;
-        if (ok && hl != 0) {
-          int kl;
-          m = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]) * inv_n;
-        }
+      [&](int e) { return g.kk0[e]; },
+      [&](int e, C v, double kk0) {
+        double m = lam_of(kk0 + ci.kkc, xi, q) * inv_n;
+        if (!ok || (ci.dc && e == 0)) m = 0.0;
         lds[lidx(c, e)] = C{T(double(v.x) * m), T(double(v.y) * m)};
       });
   __syncthreads();
   fft_run<T, N, true>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; },
-      [&](int e, C v) {
+      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, NoFetch{},
+      [&](int e, C v, NoAux) {
         if (ok) data[base + e * cg.S] = v;
       });
 }
@@ -376,8 +454,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_r2c(RowGeo rg, Geo g, Prm p
   __syncthreads();
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
   auto lidx = [](int cc, int e) { return cc * LD + e; };
-  fft_run<T, N, false>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  fft_lds<T, N, false>(t, c, lds, lidx, tw);
   __syncthreads();
   for (int i = threadIdx.x; i < CC * NHL; i += NT) {
     const int cc = i / NHL, k = i % NHL;
@@ -435,8 +512,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_energy(RowGeo rg, Geo g, Pr
   __syncthreads();
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
   auto lidx = [](int cc, int e) { return cc * LD + e; };
-  fft_run<double, N, false>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  fft_lds<double, N, false>(t, c, lds, lidx, tw);
   __syncthreads();
   for (int i = threadIdx.x; i < CC * NHL; i += NT) {
     const int cc = i / NHL, k = i % NHL;
@@ -512,8 +588,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_c2r(RowGeo rg, Geo g, Prm p
   __syncthreads();
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
   auto lidx = [](int cc, int e) { return cc * LD + e; };
-  fft_run<T, N, true>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  fft_lds<T, N, true>(t, c, lds, lidx, tw);
   __syncthreads();
   const double tau = p.tau[b], gam = p.gamma[b];
   double acc = 0.0;
@@ -566,8 +641,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T
   __syncthreads();
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
   auto lidx = [](int cc, int e) { return cc * LD + e; };
-  fft_run<T, N, true>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  fft_lds<T, N, true>(t, c, lds, lidx, tw);
   __syncthreads();
   for (int i = threadIdx.x; i < CC * N; i += NT) {
     const int cc = i / N, e = i % N;
@@ -579,8 +653,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T
     }
   }
   __syncthreads();
-  fft_run<T, N, false>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, [&](int e, C v) { lds[lidx(c, e)] = v; });
+  fft_lds<T, N, false>(t, c, lds, lidx, tw);
   __syncthreads();
   for (int i = threadIdx.x; i < CC * NHL; i += NT) {
     const int cc = i / NHL, k = i % NHL;
@@ -613,7 +686,7 @@ __global__ __launch_bounds__(EW_NT) void k_grad_assemble(Geo g, Prm p, int bpi, 
   for (long hl = lb * EW_NT + threadIdx.x; hl < g.nh; hl += (long)bpi * EW_NT) {
     const long h = (long)b * g.nh + hl;
     int kl;
-    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
+    const double lam = lam_of(kk_at(g, (int)hl, kl), p.xi[b], p.q[b]);
     const double w = herm_w(g, kl);
     const double2 a = ph[h], f = fh[h];
     aG += 0.5 * w * lam * (a.x * a.x + a.y * a.y);
@@ -647,7 +720,7 @@ __global__ __launch_bounds__(EW_NT) void k_spec_reduce(Geo g, Prm p, int bpi, co
   for (long hl = lb * EW_NT + threadIdx.x; hl < g.nh; hl += (long)bpi * EW_NT) {
     const long h = (long)b * g.nh + hl;
     int kl;
-    const double kk = kk_at(g, hl, kl);
+    const double kk = kk_at(g, (int)hl, kl);
     const double w = herm_w(g, kl);
     const c2<TA> x = a[h];
     if constexpr (MODE == 0) {
@@ -692,7 +765,7 @@ __global__ __launch_bounds__(EW_NT) void k_init_b(Geo g, Prm p, const c2<TS> *__
     const int b = (int)(h / g.nh);
     const long hl = h - (long)b * g.nh;
     int kl;
-    const double lam = lam_of(kk_at(g, hl, kl), p.xi[b], p.q[b]);
+    const double lam = lam_of(kk_at(g, (int)hl, kl), p.xi[b], p.q[b]);
     const c2<TS> s = src[h];
     const double f = (hl == 0) ? 0.0 : coef * (1.0 + eta * lam);
     bm1[h] = c2<T>{T(f * double(s.x)), T(f * double(s.y))};
@@ -708,7 +781,7 @@ __global__ __launch_bounds__(EW_NT) void k_final_d(Geo g, Prm p, const c2<T> *__
   const double lamf = st->lam_final, eta = st->eta;
   for (long h = (long)blockIdx.x * EW_NT + threadIdx.x; h < g.nh; h += (long)gridDim.x * EW_NT) {
     int kl;
-    const double lam = lam_of(kk_at(g, h, kl), p.xi[0], p.q[0]);
+    const double lam = lam_of(kk_at(g, (int)h, kl), p.xi[0], p.q[0]);
     const double s = (h == 0) ? 0.0 : 1.0 / (1.0 + eta * (lam + lamf));
     const c2<T> v = src[h];
     d[h] = double2{double(v.x) * s, double(v.y) * s};
@@ -767,75 +840,104 @@ __global__ __launch_bounds__(256) void k_bins(const double *__restrict__ bsq, co
 // Stop test of step t and the multiplier lambda_{t+1} of Algorithm 3:
 //   resid_t = sqrt(sum of the residual partials); done if t >= 1 and
 //   resid_t < tol (converged) or t >= max_inner (cap); otherwise
-//   lambda_{t+1} = 0 if phi(0) <= r^2, else Newton from 0 on phi(lambda) = r^2,
-//   phi(lambda) = sum_shells w_s / (1 + eta (D_s + lambda))^2.
-// One workgroup per instance.
-constexpr int NEWTON_NT = 256;
+//   lambda_{t+1} = 0 if phi(0) <= r^2, else the root of phi(lambda) = r^2,
+//   phi(lambda) = sum_shells w_s / (1 + eta (D_s + lambda))^2, by Newton's
+//   method from lambda = 0, applied either to phi(lambda) - r^2 (newton_phi)
+//   or to the equivalent 1/sqrt(phi(lambda)) - 1/r. The latter is concave and
+//   increasing in lambda (phi is the squared norm of a diagonal shifted
+//   solve), so its Newton iterates also rise monotonically to the same root
+//   and stop by the same test, in a few steps. One workgroup per instance;
+//   the shell weights stay in registers across the Newton steps.
+constexpr int NEWTON_NT = 1024;
+constexpr int NEWTON_PT = 16;  // shells per thread held in registers
+
+// sums of two values over the block, returned to every thread
+__device__ __forceinline__ void block_sum2_all(double &a, double &b, double *scratch /* >= 2 * 16 + 2 */) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    scratch[w] = a;
+    scratch[16 + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < NEWTON_NT / 64; ++i) {
+    sa += scratch[i];
+    sb += scratch[16 + i];
+  }
+  a = sa;
+  b = sb;
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(NEWTON_NT) void k_newton(const double *__restrict__ bins, const double *__restrict__ kkbin,
                                                       int nbins, Prm p, const double *__restrict__ rpart, int rbpi,
                                                       SubState *st_all) {
-  __shared__ double scratch[64];
-  __shared__ double bc[2];
+  __shared__ double scratch[40];
   const int b = blockIdx.x;
   SubState *st = st_all + b;
   if (st->done) return;
   const int t = st->step;
-  // residual of d_t
-  double a = 0.0;
-  for (int i = threadIdx.x; i < rbpi; i += NEWTON_NT) a += rpart[(long)b * rbpi + i];
-  const double rs = block_sum<NEWTON_NT>(a, scratch);
-  if (threadIdx.x == 0) bc[0] = rs;
-  __syncthreads();
-  const double resid = sqrt(bc[0]);
-  const double *w = bins + (long)b * nbins;
-  const double xi = p.xi[b], q = p.q[b];
-  const double eta = st->eta, r2 = st->r2;
-  bool stop = false;
-  if (t >= 1 && resid < st->tol) stop = true;
-  if (t >= st->max_inner) stop = true;
-  if (!(resid == resid) || resid > 1e300) stop = true;
-  if (stop) {
-    __syncthreads();
+  double ra = 0.0, rb = 0.0;
+  for (int i = threadIdx.x; i < rbpi; i += NEWTON_NT) ra += rpart[(long)b * rbpi + i];
+  block_sum2_all(ra, rb, scratch);
+  const double resid = sqrt(ra);
+  const bool bad = !(resid == resid) || resid > 1e300;
+  if ((t >= 1 && resid < st->tol) || t >= st->max_inner || bad) {
     if (threadIdx.x == 0) {
       st->resid = resid;
       st->done = (resid < st->tol) ? 1 : 2;
-      if (!(resid == resid) || resid > 1e300) st->nonfinite = 1;
+      if (bad) st->nonfinite = 1;
       st->final_step = t;
       st->lam_final = st->lam[t & 1];
     }
     return;
   }
-  // phi and phi' at lambda
+  const double *w = bins + (long)b * nbins;
+  const double xi = p.xi[b], q = p.q[b];
+  const double eta = st->eta, r2 = st->r2;
+  // x_s = 1 + eta D_s and w_s in registers
+  double xs[NEWTON_PT], ws[NEWTON_PT];
+#pragma unroll
+  for (int i = 0; i < NEWTON_PT; ++i) {
+    const int s = threadIdx.x + i * NEWTON_NT;
+    xs[i] = 1.0;
+    ws[i] = 0.0;
+    if (s < nbins) {
+      xs[i] = 1.0 + eta * lam_of(kkbin[s], xi, q);
+      ws[i] = w[s];
+    }
+  }
   auto eval = [&](double lam, double &phi, double &dphi) {
-    double f = 0.0, df = 0.0;
-    for (int s = threadIdx.x; s < nbins; s += NEWTON_NT) {
-      const double ws = w[s];
-      if (ws != 0.0) {
-        const double den = 1.0 + eta * (lam_of(kkbin[s], xi, q) + lam);
-        const double i2 = 1.0 / (den * den);
-        f += ws * i2;
-        df += -2.0 * eta * ws * i2 / den;
-      }
+    double f = 0.0, g3 = 0.0;
+    const double el = eta * lam;
+#pragma unroll
+    for (int i = 0; i < NEWTON_PT; ++i) {
+      const double r = rcp64(xs[i] + el);
+      const double r2i = r * r;
+      f = fma(ws[i], r2i, f);
+      g3 = fma(ws[i], r2i * r, g3);
     }
-    const double F = block_sum<NEWTON_NT>(f, scratch);
-    const double DF = block_sum<NEWTON_NT>(df, scratch + 16);
-    if (threadIdx.x == 0) {
-      bc[0] = F;
-      bc[1] = DF;
+    for (int s = threadIdx.x + NEWTON_PT * NEWTON_NT; s < nbins; s += NEWTON_NT) {
+      const double r = rcp64(1.0 + eta * lam_of(kkbin[s], xi, q) + el);
+      f += w[s] * r * r;
+      g3 += w[s] * r * r * r;
     }
-    __syncthreads();
-    phi = bc[0];
-    dphi = bc[1];
-    __syncthreads();
+    block_sum2_all(f, g3, scratch);
+    phi = f;
+    dphi = -2.0 * eta * g3;
   };
   double phi, dphi;
   eval(0.0, phi, dphi);
   double lam = 0.0;
   int it = 0;
   if (phi > r2) {
+    const bool form_phi = st->newton_phi != 0;
+    const double rr = sqrt(r2);
     while (it < st->max_newton) {
       if (phi - r2 <= st->newton_rtol * r2) break;
-      const double nl = lam - (phi - r2) / dphi;
+      const double nl = form_phi ? lam - (phi - r2) / dphi : lam + 2.0 * phi * (1.0 - sqrt(phi) / rr) / dphi;
       ++it;
       if (fabs(nl - lam) <= st->newton_steptol * fmax(1.0, fabs(lam))) {
         lam = nl;

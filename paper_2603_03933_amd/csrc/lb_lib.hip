@@ -72,6 +72,28 @@ __global__ __launch_bounds__(EW_NT) void k_add_real(long n, const double *__rest
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// kernel timing (measurement aid): events on the plan's stream around every
+// launch whose name contains the filter; resolved at the next host sync
+// ---------------------------------------------------------------------------
+struct TimingEntry {
+  std::string name;
+  long count = 0;
+  double total_ms = 0.0;
+};
+struct PendingTiming {
+  hipEvent_t a, b;
+  int idx;
+};
+struct TimingState {
+  bool on = false;
+  std::string filter;
+  std::vector<TimingEntry> entries;
+  std::vector<PendingTiming> pending;
+  std::vector<hipEvent_t> pool;
+};
+
 struct AxisTab {
   int n = 0;
   const NFuncs *f64 = nullptr, *f32 = nullptr;
@@ -110,6 +132,7 @@ struct lb_plan {
   double *sums_h = nullptr;
   // Lanczos basis, allocated on first use
   std::vector<double2 *> lz;
+  TimingState timing;
   size_t bytes = 0;
   std::vector<void *> allocs;
 };
@@ -168,12 +191,91 @@ static double kk_axis(int i, int n, double L, bool half) {
   return t * t;
 }
 
+
+static hipEvent_t timing_event(lb_plan *P) {
+  hipEvent_t e = nullptr;
+  if (!P->timing.pool.empty()) {
+    e = P->timing.pool.back();
+    P->timing.pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+static void timing_flush(lb_plan *P) {
+  for (const PendingTiming &q : P->timing.pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+      P->timing.entries[q.idx].count += 1;
+      P->timing.entries[q.idx].total_ms += ms;
+    }
+    P->timing.pool.push_back(q.a);
+    P->timing.pool.push_back(q.b);
+  }
+  P->timing.pending.clear();
+}
+struct KT {
+  lb_plan *P;
+  int idx = -1;
+  hipEvent_t a = nullptr, b = nullptr;
+  KT(lb_plan *P_, const char *name) : P(P_) {
+    TimingState &T = P->timing;
+    if (!T.on || (!T.filter.empty() && T.filter != name)) return;
+    for (size_t i = 0; i < T.entries.size(); ++i)
+      if (T.entries[i].name == name) idx = (int)i;
+    if (idx < 0) {
+      T.entries.push_back(TimingEntry{name, 0, 0.0});
+      idx = (int)T.entries.size() - 1;
+    }
+    a = timing_event(P);
+    b = timing_event(P);
+    if (!a || !b) {
+      idx = -1;
+      return;
+    }
+    (void)hipEventRecord(a, P->stream);
+  }
+  ~KT() {
+    if (idx < 0) return;
+    (void)hipEventRecord(b, P->stream);
+    P->timing.pending.push_back(PendingTiming{a, b, idx});
+    if (P->timing.pending.size() > 4096) timing_flush(P);
+  }
+};
+
+extern "C" int lb_plan_set_timing(lb_plan *P, int enable, const char *filter) {
+  if (!P) return fail(LB_ERR_ARG, "null plan");
+  (void)hipStreamSynchronize(P->stream);
+  timing_flush(P);
+  P->timing.on = enable != 0;
+  P->timing.filter = filter ? filter : "";
+  P->timing.entries.clear();
+  return LB_OK;
+}
+
+extern "C" int lb_plan_timing_entry(lb_plan *P, int index, char *name, int name_len, long *count, double *total_ms) {
+  if (!P || !name || name_len < 1 || !count || !total_ms) return fail(LB_ERR_ARG, "null argument");
+  LB_HIP(hipStreamSynchronize(P->stream));
+  timing_flush(P);
+  if (index < 0 || index >= (int)P->timing.entries.size()) return fail(LB_ERR_ARG, "timing index out of range");
+  const TimingEntry &e = P->timing.entries[index];
+  std::snprintf(name, (size_t)name_len, "%s", e.name.c_str());
+  *count = e.count;
+  *total_ms = e.total_ms;
+  return LB_OK;
+}
+
 extern "C" size_t lb_plan_workspace_bytes(const lb_plan *P) { return P ? P->bytes : 0; }
 
 extern "C" int lb_plan_destroy(lb_plan *P) {
   if (!P) return LB_OK;
   for (void *q : P->allocs) (void)hipFree(q);
   for (double2 *q : P->lz) (void)hipFree(q);
+  for (const PendingTiming &q : P->timing.pending) {
+    (void)hipEventDestroy(q.a);
+    (void)hipEventDestroy(q.b);
+  }
+  for (hipEvent_t e : P->timing.pool) (void)hipEventDestroy(e);
   if (P->st_h) (void)hipHostFree(P->st_h);
   if (P->sums_h) (void)hipHostFree(P->sums_h);
   delete P;
@@ -279,8 +381,8 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
       const int kli = (int)(h % P->nhl);
       const long r = h / P->nhl;
       const int i1 = (int)(r % P->n1), i0 = (int)(r / P->n1);
-      double kk = k0[i0] + kl[kli];
-      if (P->dim == 3) kk += k1[i1];
+      // same summation order as the kernels: kk0 + (kk_last + kk1)
+      const double kk = k0[i0] + (P->dim == 3 ? kl[kli] + k1[i1] : kl[kli]);
       keys.emplace_back(kk, (int)h);
     }
     std::sort(keys.begin(), keys.end());
@@ -424,11 +526,15 @@ static int check_launch(const char *what) {
 
 // sum (or max) per-workgroup partials into P->sums[b * nq + q] (device)
 static void finalize(lb_plan *P, const double *partial, int bpi, int nq, unsigned maxmask, int batch, double *out) {
-  hipLaunchKernelGGL(lbk::k_finalize, dim3(batch), dim3(256), 0, P->stream, partial, bpi, nq, maxmask, out);
+  {
+    KT kt_(P, "finalize");
+    hipLaunchKernelGGL(lbk::k_finalize, dim3(batch), dim3(256), 0, P->stream, partial, bpi, nq, maxmask, out);
+  }
 }
 static int read_sums(lb_plan *P, const double *dev, int count) {
   LB_HIP(hipMemcpyAsync(P->sums_h, dev, sizeof(double) * count, hipMemcpyDeviceToHost, P->stream));
   LB_HIP(hipStreamSynchronize(P->stream));
+  if (!P->timing.pending.empty()) timing_flush(P);
   return 0;
 }
 
@@ -440,19 +546,28 @@ static void fwd_r2c(lb_plan *P, int prec, int batch, const Prm &p, const double 
   PassArgs r = args_rows(P, prec, batch, p, true);
   r.in = in;
   r.out = out;
-  F(P, 2, prec)->rows_r2c(r, 0);
+  {
+    KT kt_(P, "rows_r2c");
+    F(P, 2, prec)->rows_r2c(r, 0);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, prec, batch, p, 1);
     c1.in = out;
     c1.out = out;
-    F(P, 1, prec)->cols_plain(c1, false);
+    {
+      KT kt_(P, "col1_fwd");
+      F(P, 1, prec)->cols_plain(c1, false);
+    }
   }
   PassArgs c0 = args_col(P, prec, batch, p, 0);
   c0.in = out;
   c0.out = out;
   c0.scale = 1.0 / (double)P->N;
   c0.zero_dc = zero_dc;
-  F(P, 0, prec)->cols_plain(c0, false);
+  {
+    KT kt_(P, "col0_fwd");
+    F(P, 0, prec)->cols_plain(c0, false);
+  }
 }
 
 // half spectrum -> real; `work` receives the partially inverted spectrum
@@ -461,27 +576,39 @@ static void inv_c2r(lb_plan *P, int prec, int batch, const Prm &p, const void *i
   PassArgs c0 = args_col(P, prec, batch, p, 0);
   c0.in = in;
   c0.out = work;
-  F(P, 0, prec)->cols_plain(c0, true);
+  {
+    KT kt_(P, "col0_inv");
+    F(P, 0, prec)->cols_plain(c0, true);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, prec, batch, p, 1);
     c1.in = work;
     c1.out = work;
-    F(P, 1, prec)->cols_plain(c1, true);
+    {
+      KT kt_(P, "col1_inv");
+      F(P, 1, prec)->cols_plain(c1, true);
+    }
   }
   PassArgs r = args_rows(P, prec, batch, p, true);
   r.in = work;
   r.out = out;
   r.psi = psi;
   r.partial = partial;
-  F(P, 2, prec)->rows_c2r(r, mode);
+  {
+    KT kt_(P, "rows_c2r");
+    F(P, 2, prec)->rows_c2r(r, mode);
+  }
 }
 
 // weighted spectral sums over the instances of a batch: MODE 0 <a,b>, MODE 1 sum Lambda |a|^2
 template <typename TA, int MODE>
 static void spec_reduce(lb_plan *P, int batch, const Prm &p, const void *a, const void *b, double *out_dev) {
   const int bpi = (int)bpi_ew(P);
-  hipLaunchKernelGGL((lbk::k_spec_reduce<TA, MODE>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream, geo(P, batch), p,
-                     bpi, (const lbfft::c2<TA> *)a, (const lbfft::c2<TA> *)b, P->partial);
+  {
+    KT kt_(P, "spec_reduce");
+    hipLaunchKernelGGL((lbk::k_spec_reduce<TA, MODE>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream, geo(P, batch), p,
+                       bpi, (const lbfft::c2<TA> *)a, (const lbfft::c2<TA> *)b, P->partial);
+  }
   finalize(P, P->partial, bpi, 1, 0u, batch, out_dev);
 }
 static int spec_dot_host(lb_plan *P, const Prm &p, const double2 *a, const double2 *b, double *res) {
@@ -499,8 +626,11 @@ static int spec_lam_host(lb_plan *P, const Prm &p, const double2 *a, double *res
 
 static void lincomb64(lb_plan *P, long n, double alpha, const double2 *x, double beta, const double2 *y, double2 *out) {
   const long nb = std::min<long>(cdiv(n, lbk::EW_NT), 4096);
-  hipLaunchKernelGGL((lbk::k_lincomb<double, double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, n, alpha, x,
-                     beta, y, out);
+  {
+    KT kt_(P, "lincomb");
+    hipLaunchKernelGGL((lbk::k_lincomb<double, double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, n, alpha, x,
+                       beta, y, out);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -517,7 +647,10 @@ static void energy_grad_core(lb_plan *P, int batch, const Prm &p, const double *
   r.gp64 = P->gp64;
   r.gp32 = P->gp32;
   r.partial = P->partial;
-  F(P, 2, LB_FP64)->rows_energy(r);
+  {
+    KT kt_(P, "rows_energy");
+    F(P, 2, LB_FP64)->rows_energy(r);
+  }
   finalize(P, P->partial, r.rg.bpi, 2, 0x2u, batch, P->sums);
   // psi and F'(psi) go through the column passes as 2 * batch stacked fields
   // (plain passes: the model parameters are not read)
@@ -525,23 +658,35 @@ static void energy_grad_core(lb_plan *P, int batch, const Prm &p, const double *
     PassArgs c1 = args_col(P, LB_FP64, 2 * batch, p, 1);
     c1.in = P->SP;
     c1.out = P->SP;
-    F(P, 1, LB_FP64)->cols_plain(c1, false);
+    {
+      KT kt_(P, "col1_fwd");
+      F(P, 1, LB_FP64)->cols_plain(c1, false);
+    }
   }
   PassArgs c0 = args_col(P, LB_FP64, 2 * batch, p, 0);
   c0.in = P->SP;
   c0.out = P->SP;
   c0.scale = 1.0 / (double)P->N;
-  F(P, 0, LB_FP64)->cols_plain(c0, false);
+  {
+    KT kt_(P, "col0_fwd");
+    F(P, 0, LB_FP64)->cols_plain(c0, false);
+  }
   const int bpi = (int)bpi_ew(P);
   double *part2 = P->partial + P->partial_len / 2;
   if (P->prec == LB_FP64)
-    hipLaunchKernelGGL((lbk::k_grad_assemble<double>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
-                       geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
-                       P->GH, (double2 *)nullptr, part2);
+    {
+      KT kt_(P, "grad_assemble");
+      hipLaunchKernelGGL((lbk::k_grad_assemble<double>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
+                         geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
+                         P->GH, (double2 *)nullptr, part2);
+    }
   else
-    hipLaunchKernelGGL((lbk::k_grad_assemble<float>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
-                       geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
-                       P->GH, (float2 *)P->GHT, part2);
+    {
+      KT kt_(P, "grad_assemble");
+      hipLaunchKernelGGL((lbk::k_grad_assemble<float>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
+                         geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
+                         P->GH, (float2 *)P->GHT, part2);
+    }
   finalize(P, part2, bpi, 3, 0x4u, batch, P->sums + 32);
 }
 
@@ -551,8 +696,11 @@ extern "C" int lb_energy_grad(lb_plan *P, const lb_params *params, const double 
   LB_TRY(pack_params(P, params, P->batch, &p));
   const int B = P->batch;
   energy_grad_core(P, B, p, psi);
-  hipLaunchKernelGGL(lbk::k_energy_out, dim3(1), dim3(64), 0, P->stream, (const double *)(P->sums + 32), 3,
-                     (const double *)P->sums, 2, 1.0 / (double)P->N, B, energy);
+  {
+    KT kt_(P, "energy_out");
+    hipLaunchKernelGGL(lbk::k_energy_out, dim3(1), dim3(64), 0, P->stream, (const double *)(P->sums + 32), 3,
+                       (const double *)P->sums, 2, 1.0 / (double)P->N, B, energy);
+  }
   if (grad) inv_c2r(P, LB_FP64, B, p, P->GH, P->W64, grad, 0, nullptr, nullptr);
   return check_launch("lb_energy_grad");
 }
@@ -572,22 +720,34 @@ extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi
   r.psi = psi;
   r.out = work;
   r.partial = P->partial;
-  F(P, 2, prec)->rows_r2c(r, project ? 1 : 0);
+  {
+    KT kt_(P, "rows_r2c");
+    F(P, 2, prec)->rows_r2c(r, project ? 1 : 0);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, prec, B, p, 1);
     c1.in = work;
     c1.out = work;
-    F(P, 1, prec)->cols_plain(c1, false);
+    {
+      KT kt_(P, "col1_fwd");
+      F(P, 1, prec)->cols_plain(c1, false);
+    }
   }
   PassArgs c0 = args_col(P, prec, B, p, 0);
   c0.out = work;
   c0.inv_n = 1.0 / (double)P->N;
-  F(P, 0, prec)->cols_fwd_mul_inv(c0);
+  {
+    KT kt_(P, "col0_fwd_mul_inv");
+    F(P, 0, prec)->cols_fwd_mul_inv(c0);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, prec, B, p, 1);
     c1.in = work;
     c1.out = work;
-    F(P, 1, prec)->cols_plain(c1, true);
+    {
+      KT kt_(P, "col1_inv");
+      F(P, 1, prec)->cols_plain(c1, true);
+    }
   }
   PassArgs o = args_rows(P, prec, B, p, true);
   o.in = work;
@@ -596,7 +756,10 @@ extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi
   o.v = v;
   o.mpart = project ? P->partial : nullptr;
   o.mbpi = r.rg.bpi;
-  F(P, 2, prec)->rows_c2r(o, 1);
+  {
+    KT kt_(P, "rows_c2r_hv");
+    F(P, 2, prec)->rows_c2r(o, 1);
+  }
   return check_launch("lb_hessvec");
 }
 
@@ -605,22 +768,34 @@ static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out
   PassArgs c0 = args_col(P, LB_FP64, 1, p, 0);
   c0.in = x;
   c0.out = P->W64;
-  F(P, 0, LB_FP64)->cols_plain(c0, true);
+  {
+    KT kt_(P, "col0_inv");
+    F(P, 0, LB_FP64)->cols_plain(c0, true);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
     c1.in = P->W64;
     c1.out = P->W64;
-    F(P, 1, LB_FP64)->cols_plain(c1, true);
+    {
+      KT kt_(P, "col1_inv");
+      F(P, 1, LB_FP64)->cols_plain(c1, true);
+    }
   }
   PassArgs r = args_rows(P, LB_FP64, 1, p, true);
   r.out = P->W64;
   r.gp = P->gp64;
-  F(P, 2, LB_FP64)->rows_inner(r);
+  {
+    KT kt_(P, "rows_inner");
+    F(P, 2, LB_FP64)->rows_inner(r);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
     c1.in = P->W64;
     c1.out = P->W64;
-    F(P, 1, LB_FP64)->cols_plain(c1, false);
+    {
+      KT kt_(P, "col1_fwd");
+      F(P, 1, LB_FP64)->cols_plain(c1, false);
+    }
   }
   PassArgs f = args_col(P, LB_FP64, 1, p, 0);
   f.in = P->W64;
@@ -628,7 +803,10 @@ static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out
   f.out = out;
   f.inv_n = 1.0 / (double)P->N;
   f.shift = shift;
-  F(P, 0, LB_FP64)->cols_fwd_hess(f);
+  {
+    KT kt_(P, "col0_fwd_hess");
+    F(P, 0, LB_FP64)->cols_fwd_hess(f);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -646,25 +824,37 @@ static void enqueue_step(lb_plan *P, const Prm &p) {
   a.b1 = P->B1;
   a.out = P->WT;
   a.st = P->st;
-  F(P, 0, prec)->cols_inv_scale_d(a);
+  {
+    KT kt_(P, "col0_inv_scale_d");
+    F(P, 0, prec)->cols_inv_scale_d(a);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, prec, 1, p, 1);
     c1.in = P->WT;
     c1.out = P->WT;
     c1.st = P->st;
-    F(P, 1, prec)->cols_plain(c1, true);
+    {
+      KT kt_(P, "col1_inv");
+      F(P, 1, prec)->cols_plain(c1, true);
+    }
   }
   PassArgs r = args_rows(P, prec, 1, p, true);
   r.out = P->WT;
   r.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
   r.st = P->st;
-  F(P, 2, prec)->rows_inner(r);
+  {
+    KT kt_(P, "rows_inner");
+    F(P, 2, prec)->rows_inner(r);
+  }
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, prec, 1, p, 1);
     c1.in = P->WT;
     c1.out = P->WT;
     c1.st = P->st;
-    F(P, 1, prec)->cols_plain(c1, false);
+    {
+      KT kt_(P, "col1_fwd");
+      F(P, 1, prec)->cols_plain(c1, false);
+    }
   }
   PassArgs u = args_col(P, prec, 1, p, 0);
   u.in = P->WT;
@@ -675,12 +865,21 @@ static void enqueue_step(lb_plan *P, const Prm &p) {
   u.partial = P->partial;
   u.st = P->st;
   u.inv_n = 1.0 / (double)P->N;
-  F(P, 0, prec)->cols_fwd_update(u);
+  {
+    KT kt_(P, "col0_fwd_update");
+    F(P, 0, prec)->cols_fwd_update(u);
+  }
   const long waves = (long)P->nbins;
-  hipLaunchKernelGGL(lbk::k_bins, dim3((unsigned)cdiv(waves * 64, 256)), dim3(256), 0, P->stream, P->bsq, P->perm,
-                     P->seg, P->nbins, P->nh, 1, (const SubState *)P->st, P->bins);
-  hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::NEWTON_NT), 0, P->stream, P->bins, P->kkbin, P->nbins, p,
-                     (const double *)P->partial, u.cg.bpi, P->st);
+  {
+    KT kt_(P, "bins");
+    hipLaunchKernelGGL(lbk::k_bins, dim3((unsigned)cdiv(waves * 64, 256)), dim3(256), 0, P->stream, P->bsq, P->perm,
+                       P->seg, P->nbins, P->nh, 1, (const SubState *)P->st, P->bins);
+  }
+  {
+    KT kt_(P, "newton");
+    hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::NEWTON_NT), 0, P->stream, P->bins, P->kkbin, P->nbins, p,
+                       (const double *)P->partial, u.cg.bpi, P->st);
+  }
 }
 
 // Runs Algorithm 3 with g_hat in GH/GHT and Gamma' in gp64/gp32; the initial
@@ -692,18 +891,30 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   const Geo g1 = geo(P, 1);
   if (d0_spec) {
     if (prec == LB_FP64)
-      hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
-                         o.eta, (double2 *)P->B1);
+      {
+        KT kt_(P, "init_b");
+        hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
+                           o.eta, (double2 *)P->B1);
+      }
     else
-      hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
-                         o.eta, (float2 *)P->B1);
+      {
+        KT kt_(P, "init_b");
+        hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
+                           o.eta, (float2 *)P->B1);
+      }
   } else {
     if (prec == LB_FP64)
-      hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
-                         (const double2 *)P->GH, -r / gnorm, o.eta, (double2 *)P->B1);
+      {
+        KT kt_(P, "init_b");
+        hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+                           (const double2 *)P->GH, -r / gnorm, o.eta, (double2 *)P->B1);
+      }
     else
-      hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
-                         (const double2 *)P->GH, -r / gnorm, o.eta, (float2 *)P->B1);
+      {
+        KT kt_(P, "init_b");
+        hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+                           (const double2 *)P->GH, -r / gnorm, o.eta, (float2 *)P->B1);
+      }
   }
   SubState s{};
   s.lam[0] = 0.0;
@@ -717,6 +928,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   s.done = 0;
   s.max_inner = o.max_inner;
   s.max_newton = o.max_newton;
+  s.newton_phi = o.newton_phi;
   LB_HIP(hipStreamSynchronize(P->stream));  // the pinned mirror may still feed an earlier copy
   *P->st_h = s;
   LB_HIP(hipMemcpyAsync(P->st, P->st_h, sizeof(SubState), hipMemcpyHostToDevice, P->stream));
@@ -730,17 +942,24 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
     LB_TRY(check_launch("subproblem step"));
     LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
     LB_HIP(hipStreamSynchronize(P->stream));
+    if (!P->timing.pending.empty()) timing_flush(P);
     if (P->st_h->done || launched >= max_steps) break;
   }
   const SubState &f = *P->st_h;
   if (!f.done) return fail(LB_ERR_HIP, "subproblem loop ended without a stop decision");
   if (f.nonfinite) return fail(LB_ERR_NONFINITE, "non-finite residual in the subproblem");
   if (prec == LB_FP64)
-    hipLaunchKernelGGL((lbk::k_final_d<double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
-                       (const double2 *)P->B0, (const double2 *)P->B1, (const SubState *)P->st, P->SH);
+    {
+      KT kt_(P, "final_d");
+      hipLaunchKernelGGL((lbk::k_final_d<double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+                         (const double2 *)P->B0, (const double2 *)P->B1, (const SubState *)P->st, P->SH);
+    }
   else
-    hipLaunchKernelGGL((lbk::k_final_d<float>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, (const float2 *)P->B0,
-                       (const float2 *)P->B1, (const SubState *)P->st, P->SH);
+    {
+      KT kt_(P, "final_d");
+      hipLaunchKernelGGL((lbk::k_final_d<float>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, (const float2 *)P->B0,
+                         (const float2 *)P->B1, (const SubState *)P->st, P->SH);
+    }
   double dd = 0.0;
   LB_TRY(spec_dot_host(P, p, P->SH, P->SH, &dd));
   out->lam = f.lam_final;
@@ -762,6 +981,7 @@ extern "C" void lb_sub_opts_default(lb_sub_opts *o) {
   o->newton_rtol = 1e-14;
   o->newton_steptol = 1e-15;
   o->poll_every = 32;
+  o->newton_phi = 0;
 }
 
 extern "C" void lb_tr_opts_default(lb_tr_opts *o) {
@@ -807,13 +1027,19 @@ extern "C" int lb_tr_subproblem(lb_plan *P, const lb_params *params, const doubl
   LB_TRY(check_sub_opts(o));
   Prm p;
   LB_TRY(pack_params(P, params, 1, &p));
-  hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
-                     P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  {
+    KT kt_(P, "gamma_p");
+    hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+                       P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  }
   fwd_r2c(P, LB_FP64, 1, p, grad, P->GH, 1);
   if (P->prec == LB_FP32)
-    hipLaunchKernelGGL((lbk::k_lincomb<float, double, double>), dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)),
-                       dim3(lbk::EW_NT), 0, P->stream, P->nh, 1.0, (const double2 *)P->GH, 0.0, (const double2 *)nullptr,
-                       (float2 *)P->GHT);
+    {
+      KT kt_(P, "lincomb");
+      hipLaunchKernelGGL((lbk::k_lincomb<float, double, double>), dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)),
+                         dim3(lbk::EW_NT), 0, P->stream, P->nh, 1.0, (const double2 *)P->GH, 0.0, (const double2 *)nullptr,
+                         (float2 *)P->GHT);
+    }
   double gg = 0.0;
   LB_TRY(spec_dot_host(P, p, P->GH, P->GH, &gg));
   const double gnorm = std::sqrt(std::max(gg, 0.0));
@@ -875,8 +1101,11 @@ extern "C" int lb_shifted_solve(lb_plan *P, const lb_params *params, const doubl
   if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_shifted_solve needs a plan with batch 1");
   Prm p;
   LB_TRY(pack_params(P, params, 1, &p));
-  hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
-                     P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  {
+    KT kt_(P, "gamma_p");
+    hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+                       P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  }
   fwd_r2c(P, LB_FP64, 1, p, grad, P->GH, 1);
   LB_TRY(cg_shifted(P, p, shift, rtol, maxiter, iters));
   inv_c2r(P, LB_FP64, 1, p, P->X, P->W64, s_out, 0, nullptr, nullptr);
@@ -979,8 +1208,11 @@ extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double 
   if (steps < 1 || steps > 1000) return fail(LB_ERR_ARG, "steps must be in [1, 1000]");
   Prm p;
   LB_TRY(pack_params(P, params, 1, &p));
-  hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
-                     P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  {
+    KT kt_(P, "gamma_p");
+    hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+                       P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
+  }
   fwd_r2c(P, LB_FP64, 1, p, v0, P->R, 1);
   LB_TRY(lanczos_core(P, p, P->R, steps, ritz_min, resid));
   return check_launch("lb_lanczos_min");
@@ -1009,26 +1241,38 @@ static int energy_grad_host(lb_plan *P, const Prm &p, const double *psi, EG *eg)
 // the current iterate's g_hat and Gamma' untouched
 static int energy_at_trial(lb_plan *P, const Prm &p, const double *psi, double *E) {
   const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
-  hipLaunchKernelGGL(lbk::k_add_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, psi, (const double *)P->sphys,
-                     P->ptrial);
+  {
+    KT kt_(P, "add_real");
+    hipLaunchKernelGGL(lbk::k_add_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, psi, (const double *)P->sphys,
+                       P->ptrial);
+  }
   PassArgs r = args_rows(P, LB_FP64, 1, p, false);
   r.psi = P->ptrial;
   r.out = P->SP;
   r.out2 = P->SP + P->nh;
   r.partial = P->partial;
-  F(P, 2, LB_FP64)->rows_energy(r);
+  {
+    KT kt_(P, "rows_energy");
+    F(P, 2, LB_FP64)->rows_energy(r);
+  }
   finalize(P, P->partial, r.rg.bpi, 2, 0x2u, 1, P->sums);
   if (P->dim == 3) {
     PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
     c1.in = P->SP;
     c1.out = P->SP;
-    F(P, 1, LB_FP64)->cols_plain(c1, false);
+    {
+      KT kt_(P, "col1_fwd");
+      F(P, 1, LB_FP64)->cols_plain(c1, false);
+    }
   }
   PassArgs c0 = args_col(P, LB_FP64, 1, p, 0);
   c0.in = P->SP;
   c0.out = P->SP;
   c0.scale = 1.0 / (double)P->N;
-  F(P, 0, LB_FP64)->cols_plain(c0, false);
+  {
+    KT kt_(P, "col0_fwd");
+    F(P, 0, LB_FP64)->cols_plain(c0, false);
+  }
   spec_reduce<double, 1>(P, 1, p, P->SP, P->SP, P->sums + 32);
   LB_TRY(check_launch("trial energy"));
   LB_TRY(read_sums(P, P->sums, 40));
@@ -1093,8 +1337,11 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
     const bool on_nu = std::fabs(sn - nu) <= o.nu_tol * nu;
     if (rho >= o.theta && (lam <= mu * sn || on_nu)) {
       const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
-      hipLaunchKernelGGL(lbk::k_axpy_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, 1.0, (const double *)P->sphys,
-                         psi);
+      {
+        KT kt_(P, "axpy_real");
+        hipLaunchKernelGGL(lbk::k_axpy_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, 1.0, (const double *)P->sphys,
+                           psi);
+      }
       nu = std::max(nu, o.gamma_e * sn);
       r = std::min(nu, std::max(r, o.gamma_e * sn));
       mu = std::max(mu, lam / sn);

@@ -42,6 +42,7 @@ class LbSubOpts(C.Structure):
         ("newton_rtol", C.c_double),
         ("newton_steptol", C.c_double),
         ("poll_every", C.c_int),
+        ("newton_phi", C.c_int),
     ]
 
 
@@ -118,6 +119,8 @@ _SIGS = {
     "lb_plan_destroy": (_I, [_P]),
     "lb_plan_set_stream": (_I, [_P, _P]),
     "lb_plan_workspace_bytes": (C.c_size_t, [_P]),
+    "lb_plan_set_timing": (_I, [_P, _I, C.c_char_p]),
+    "lb_plan_timing_entry": (_I, [_P, _I, C.c_char_p, _I, C.POINTER(C.c_long), C.POINTER(_D)]),
     "lb_energy_grad": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
     "lb_hessvec": (_I, [_P, C.POINTER(LbParams), _P, _P, _P, _I]),
     "lb_tr_subproblem": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, C.POINTER(LbSubOpts), _P, _P, C.POINTER(LbSubInfo)]),
@@ -241,6 +244,22 @@ class Plan:
     @property
     def workspace_bytes(self) -> int:
         return int(lib().lb_plan_workspace_bytes(self._h))
+
+    def lb_plan_set_timing(self, enable: bool, filter: str = ""):
+        self._sync_stream()
+        _check(lib().lb_plan_set_timing(self._h, 1 if enable else 0, filter.encode()))
+
+    def timings(self):
+        """{kernel name: (launches, total ms)} accumulated since timing was set."""
+        out = {}
+        buf = C.create_string_buffer(128)
+        cnt = C.c_long()
+        ms = C.c_double()
+        i = 0
+        while lib().lb_plan_timing_entry(self._h, i, buf, 128, C.byref(cnt), C.byref(ms)) == 0:
+            out[buf.value.decode()] = (cnt.value, ms.value)
+            i += 1
+        return out
 
     def lb_energy_grad(self, params, psi, energy=None, grad=None, want_grad=True):
         self._sync_stream()

@@ -144,7 +144,8 @@ def test_full_size_bcc_128_energy_grad_hessvec():
         ((16, 16), (2 * math.pi, 2 * math.pi), -0.15, 0.05, 0.2),
         ((16, 16), (2 * math.pi, 2 * math.pi), 0.3, 50.0, 0.2),
         ((8, 8, 8), (2 * math.pi,) * 3, -0.1, 0.1, 0.3),
-        ((12, 24), (3 * math.pi, 6 * math.pi), -0.15, 0.2, 0.1),
+        ((12, 24), (3 * math.pi, 6 * math.pi), -0.15, 0.1, 0.1),  # ~6000 iterations, indefinite
+        ((12, 24), (3 * math.pi, 6 * math.pi), 0.05, 0.5, 0.1),  # interior solution, lambda = 0
     ],
 )
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -171,6 +172,27 @@ def test_tr_subproblem_matches_oracle(shape, box, tau, r, amp, precision):
         assert math.sqrt(np.mean((d - d_or) ** 2)) <= 1e-4 * max(dn, 1e-30)
     assert info.dnorm <= r * (1 + 1e-12)
     assert abs(info.lambda_ * (info.dnorm - r)) <= 1e-8 * max(1.0, info.lambda_)
+
+
+@pytest.mark.parametrize("newton_phi", [0, 1])
+def test_tr_subproblem_newton_forms_agree(newton_phi):
+    """Both Newton forms for lambda (on phi, as printed, and on 1/sqrt(phi)) reach
+    the oracle's multiplier and iterate; the printed form also its iteration count."""
+    shape, box = (16, 16), (2 * math.pi, 2 * math.pi)
+    m = model_for(shape, box, -0.15, 0.25)
+    psi = I.zero_mean_noise(shape, 0.2, 21)
+    g_hat = O.gradient(m, psi)
+    r = 0.05
+    ref = O.imex_subproblem(m, psi, g_hat, r, O.SubOpts(eta=0.1, eps_sub=1e-10, max_inner=20000))
+    plan = lb.Plan(shape, box)
+    d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), r, lb.sub_opts(eps_sub=1e-10, max_inner=20000, newton_phi=newton_phi))
+    assert rc == lb.LB_OK and abs(info.iters - ref.iters) <= 1
+    assert abs(info.lambda_ - ref.lam) <= 1e-9 * max(1.0, ref.lam)
+    assert np.max(np.abs(host(d) - O.inv(ref.d))) < 1e-9 * np.max(np.abs(O.inv(ref.d)))
+    if newton_phi:
+        assert abs(info.newton_iters - ref.newton_iters) <= max(2, 0.01 * ref.newton_iters)
+    else:
+        assert info.newton_iters < ref.newton_iters
 
 
 def test_tr_subproblem_global_minimiser_dense():
@@ -232,8 +254,13 @@ def test_shifted_solve_matches_oracle_cg():
     s_or, it_or = O.cg_shifted(m, psi, g_hat, shift, 1e-12, 1000)
     plan = lb.Plan(shape, box)
     s, it = plan.lb_shifted_solve(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), shift)
-    assert abs(it - it_or) <= 2
-    assert np.max(np.abs(host(s) - O.inv(s_or))) < 1e-10 * np.max(np.abs(O.inv(s_or)))
+    # hundreds of CG steps on an ill-conditioned system: counts differ by rounding,
+    # the solutions agree to the CG tolerance
+    assert abs(it - it_or) <= 0.1 * it_or
+    assert np.max(np.abs(host(s) - O.inv(s_or))) < 1e-9 * np.max(np.abs(O.inv(s_or)))
+    # and both solve the system: ||(H + shift) s + g|| small
+    res = O.hessvec(m, psi, O.project(O.fwd(host(s)))) + shift * O.project(O.fwd(host(s))) + g_hat
+    assert O.norm(res) < 1e-10 * O.norm(g_hat)
 
 
 def test_lanczos_matches_dense_eigenvalue():

@@ -148,7 +148,7 @@ def main():
     def step(p, o):
         psi.copy_(psi0)
         info, rc = p.lb_imex_tr_solve(prm, psi, o)
-        ritz, res = p.lb_lanczos_min(prm, psi, v0, 30)
+        ritz, res = p.lb_lanczos_min(prm, psi, v0, 30, precond_shift=1.0)
         return info, rc, ritz, res
 
     # warmup, with every kernel timed to find the dominant one

@@ -215,13 +215,21 @@ int lb_imex_tr_solve(lb_plan *plan, const lb_params *params, double *psi, const 
 int lb_shifted_solve(lb_plan *plan, const lb_params *params, const double *psi, const double *grad, double shift,
                      double rtol, int maxiter, double *s_out, int *iters);
 
-/* Second-order check: smallest Ritz value of H on the zero-mean subspace
- * after `steps` Lanczos steps (full reorthogonalisation) from v0 (device, N
- * doubles). A Ritz value bounds sigma_1 from above; *resid is the Ritz
- * residual norm. batch must be 1. Host outputs. Allocates steps + 1 spectral
- * vectors on first use (kept by the plan). */
+/* Second-order check (the paper's SP-II test, Section 1 definition: grad = 0
+ * and H >= 0): an estimate of sigma_1, the smallest eigenvalue of H on the
+ * zero-mean subspace, by `steps` Lanczos steps with full reorthogonalisation
+ * from v0 (device, N doubles).
+ *   precond_shift <= 0: Lanczos on H; *ritz_min is its smallest Ritz value and
+ *     *resid the Ritz residual norm.
+ *   precond_shift = c > 0: Lanczos on K = S H S with S = (Lambda_k + c)^(-1/2)
+ *     diagonal in Fourier space. K is congruent to H (same inertia) with a
+ *     clustered spectrum, so its lowest Ritz vector y converges in few steps;
+ *     *ritz_min is the Rayleigh quotient of H at x = S y and *resid is
+ *     ||Hx - ritz x|| / ||x||.
+ * Either value bounds sigma_1 from above. batch must be 1. Host outputs.
+ * Allocates steps + 1 spectral vectors on first use (kept by the plan). */
 int lb_lanczos_min(lb_plan *plan, const lb_params *params, const double *psi, const double *v0, int steps,
-                   double *ritz_min, double *resid);
+                   double precond_shift, double *ritz_min, double *resid);
 
 #ifdef __cplusplus
 }

@@ -683,12 +683,30 @@ def imex_tr_solve(
 # ---------------------------------------------------------------------------
 
 
-def lanczos_min(m: Model, psi: np.ndarray, v0_hat: np.ndarray, steps: int) -> Tuple[float, float]:
+def lanczos_min(m: Model, psi: np.ndarray, v0_hat: np.ndarray, steps: int, precond_shift: float = 0.0) -> Tuple[float, float]:
     """Smallest Ritz value of H after ``steps`` Lanczos steps with full reorthogonalisation.
 
-    Returns (ritz_min, residual_norm). A Ritz value is an upper bound on
-    sigma_1, so this is an estimate, not a certificate.
+    Returns (value, residual_norm). Without preconditioning (precond_shift <= 0)
+    value is the smallest Ritz value of H and the residual the usual Ritz
+    residual |beta_m y_m|. With precond_shift = c > 0 the iteration runs on
+    K = S H S, S = diag((Lambda_k + c)^(-1/2)) in Fourier space; K is congruent
+    to H (Sylvester: same inertia) and its spectrum is clustered, so the lowest
+    Ritz vector y of K converges quickly; the result is the Rayleigh quotient
+    rho = <x, Hx>/<x, x> of H at x = S y and ||Hx - rho x|| / ||x||. Either
+    value bounds sigma_1 from above; it is an estimate, not a certificate.
     """
+    if precond_shift > 0:
+        Sd = np.where(np.arange(m.Lam.size).reshape(m.Lam.shape) == 0, 0.0, 1.0 / np.sqrt(m.Lam + precond_shift))
+
+        def op(v):
+            return Sd * hessvec(m, psi, Sd * v)
+
+    else:
+        Sd = None
+
+        def op(v):
+            return hessvec(m, psi, v)
+
     q = project(v0_hat)
     q = q / norm(q)
     Qs = [q]
@@ -696,21 +714,26 @@ def lanczos_min(m: Model, psi: np.ndarray, v0_hat: np.ndarray, steps: int) -> Tu
     b = 0.0
     q_prev = np.zeros_like(q)
     for i in range(steps):
-        w = hessvec(m, psi, q) - b * q_prev
+        w = op(q) - b * q_prev
         a = dot(w, q)
         w = w - a * q
         for qq in Qs:  # full reorthogonalisation
             w = w - dot(w, qq) * qq
         alpha.append(a)
         b = norm(w)
-        if i == steps - 1 or b < 1e-300:
-            beta.append(b)
-            break
         beta.append(b)
+        if i == steps - 1 or b < 1e-300:
+            break
         q_prev = q
         q = w / b
         Qs.append(q)
     k = len(alpha)
     Tm = np.diag(alpha) + np.diag(beta[: k - 1], 1) + np.diag(beta[: k - 1], -1)
     ev, evec = np.linalg.eigh(Tm)
-    return float(ev[0]), float(abs(beta[k - 1] * evec[k - 1, 0]))
+    if Sd is None:
+        return float(ev[0]), float(abs(beta[k - 1] * evec[k - 1, 0]))
+    y = sum(evec[i, 0] * Qs[i] for i in range(k))
+    x = Sd * y
+    Hx = hessvec(m, psi, x)
+    rho = dot(x, Hx) / dot(x, x)
+    return float(rho), float(norm(Hx - rho * x) / norm(x))

@@ -198,9 +198,11 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
       [&](int e) -> C { return ok ? op.load(bs, cs, base + e * cg.S, e) : C{T(0), T(0)}; },
       [&](int e) { return op.fetch(bs, cs, ok, base + e * cg.S, e); },
       [&](int e, C v, const auto &aux) {
-        if (ok) op.store(bs, cs, base + e * cg.S, e, v, aux, acc);
+        double *sq = reinterpret_cast<double *>(lds) + e * CC + c;
+        if (ok) op.store(bs, cs, base + e * cg.S, e, v, aux, acc, sq);
+        else *sq = 0.0;
       });
-  op.template end<NT>(acc, reinterpret_cast<double *>(lds));
+  op.template end<NT, N, CC>(acc, reinterpret_cast<double *>(lds), b, lb, c);
 }
 
 struct Empty {};
@@ -219,11 +221,11 @@ template <typename T> struct OpPlain {
   __device__ int column(int, int ml) const { return zero_dc && ml == 0; }
   __device__ c2<T> load(const Empty &, int, long h, int) const { return in[h]; }
   __device__ Empty fetch(const Empty &, int, bool, long, int) const { return Empty{}; }
-  __device__ void store(const Empty &, int dccol, long h, int e, c2<T> v, const Empty &, double &) const {
+  __device__ void store(const Empty &, int dccol, long h, int e, c2<T> v, const Empty &, double &, double *) const {
     if (dccol && e == 0) v = c2<T>{T(0), T(0)};
     out[h] = c2<T>{v.x * scale, v.y * scale};
   }
-  template <int NT> __device__ void end(double, double *) const {}
+  template <int NT, int N, int CC> __device__ void end(double, double *, int, int, int) const {}
 };
 
 // per-workgroup subproblem state read from SubState
@@ -261,10 +263,11 @@ template <typename T> struct OpInvScaleD {
     return c2<T>{T(double(v.x) * s), T(double(v.y) * s)};
   }
   __device__ Empty fetch(const StepBlk<T> &, const ColInfo &, bool, long, int) const { return Empty{}; }
-  __device__ void store(const StepBlk<T> &, const ColInfo &, long h, int, c2<T> v, const Empty &, double &) const {
+  __device__ void store(const StepBlk<T> &, const ColInfo &, long h, int, c2<T> v, const Empty &, double &,
+                        double *) const {
     out[h] = v;
   }
-  template <int NT> __device__ void end(double, double *) const {}
+  template <int NT, int N, int CC> __device__ void end(double, double *, int, int, int) const {}
 };
 
 // step t, axis-0 forward pass of T d_t, then the diagonal update:
@@ -280,10 +283,11 @@ template <typename T> struct OpFwdUpdate {
   const c2<T> *tmp;  // row/axis-1 transformed product Gamma' d_t
   c2<T> *b0, *b1;
   const c2<T> *gh;
-  double *bsq;
+  double *bsq2;     // w (|b(k0)|^2 + |b(-k0)|^2) per (|k0|, column): [n0/2 + 1][columns]
   double *partial;  // one double per workgroup: sum w |r|^2
   const SubState *st;
   double inv_n;
+  int cpi;          // columns per instance
   __device__ bool skip() const { return st->done != 0; }
   __device__ StepBlk<T> begin(int b) const {
     const int t = st->step;
@@ -310,11 +314,13 @@ template <typename T> struct OpFwdUpdate {
     a.kk0 = g.kk0[e];
     return a;
   }
+  // the LDS buffer is free once the last pass has read it: w |b_t|^2 goes to
+  // sq[e * CC + c] for the pair sums formed in end()
   __device__ void store(const StepBlk<T> &bs, const ColInfo &ci, long h, int e, c2<T> v, const UpdAux<T> &a,
-                        double &acc) const {
+                        double &acc, double *sq) const {
     if (ci.dc && e == 0) {
       bs.bnext[h] = c2<T>{T(0), T(0)};
-      bsq[h] = 0.0;
+      *sq = 0.0;
       return;
     }
     const double lam = lam_of(a.kk0 + ci.kkc, bs.xi, bs.q);
@@ -328,10 +334,22 @@ template <typename T> struct OpFwdUpdate {
     const c2<T> bn = c2<T>{T(bx), T(by)};
     bs.bnext[h] = bn;
     const double bxr = double(bn.x), byr = double(bn.y);
-    bsq[h] = ci.w * (bxr * bxr + byr * byr);
+    *sq = ci.w * (bxr * bxr + byr * byr);
   }
-  template <int NT> __device__ void end(double acc, double *scratch) const {
-    const double s = block_sum<NT>(acc, scratch);
+  template <int NT, int N, int CC>
+  __device__ void end(double acc, double *sq, int b, int lb, int) const {
+    __syncthreads();
+    constexpr int NH0 = N / 2 + 1;
+    for (int i = threadIdx.x; i < NH0 * CC; i += NT) {
+      const int e = i / CC, cc = i - e * CC;
+      const int ml = lb * CC + cc;
+      if (ml < cpi) {
+        double v = sq[e * CC + cc];
+        if (e != 0 && 2 * e != N) v += sq[(N - e) * CC + cc];
+        bsq2[((long)b * NH0 + e) * cpi + ml] = v;
+      }
+    }
+    const double s = block_sum<NT>(acc, sq);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
 };
@@ -363,7 +381,7 @@ template <typename T> struct OpFwdHess {
     return a;
   }
   __device__ void store(const HessBlk &hb, const ColInfo &ci, long h, int e, c2<T> v, const HessAux<T> &a,
-                        double &) const {
+                        double &, double *) const {
     if (ci.dc && e == 0) {
       out[h] = c2<T>{T(0), T(0)};
       return;
@@ -371,7 +389,7 @@ template <typename T> struct OpFwdHess {
     const double lam = lam_of(a.kk0 + ci.kkc, hb.xi, hb.q) + shift;
     out[h] = c2<T>{T(lam * double(a.xv.x) + double(v.x) * inv_n), T(lam * double(a.xv.y) + double(v.y) * inv_n)};
   }
-  template <int NT> __device__ void end(double, double *) const {}
+  template <int NT, int N, int CC> __device__ void end(double, double *, int, int, int) const {}
 };
 
 // Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
@@ -821,68 +839,100 @@ __global__ __launch_bounds__(EW_NT) void k_axpy_real(long n, double a, const dou
   for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < n; i += (long)gridDim.x * EW_NT) y[i] += a * x[i];
 }
 
-// Group the weighted |b|^2 by reciprocal shell: one wavefront per (instance, shell).
-__global__ __launch_bounds__(256) void k_bins(const double *__restrict__ bsq, const int *__restrict__ perm,
-                                              const int *__restrict__ seg, int nbins, long nh, int batch,
-                                              const SubState *st, double *__restrict__ bins) {
-  if (st && st->done) return;
-  const long wid = ((long)blockIdx.x * 256 + threadIdx.x) >> 6;
+// Shell sums of w |b|^2: one wavefront per reciprocal shell, gathering the
+// shell's (|k0|, column) pair entries through the shell-sorted list `perm`.
+constexpr int BN_NT = 1024;
+__global__ __launch_bounds__(256) void k_bins(const double *__restrict__ bsq2, const int *__restrict__ perm,
+                                              const int *__restrict__ seg, int nbins, const SubState *st,
+                                              double *__restrict__ wsum) {
+  if (st->done) return;
+  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (wid >= (long)nbins * batch) return;
-  const int b = (int)(wid / nbins), s = (int)(wid % nbins);
-  const double *src = bsq + (long)b * nh;
-  double a = 0.0;
-  for (int i = seg[s] + lane; i < seg[s + 1]; i += 64) a += src[perm[i]];
-  a = wave_sum(a);
-  if (lane == 0) bins[wid] = a;
+  if (s >= nbins) return;
+  double a = 0.0, a2 = 0.0;
+  const int i1 = seg[s + 1];
+  int i = seg[s] + lane;
+  for (; i + 64 < i1; i += 128) {
+    a += bsq2[perm[i]];
+    a2 += bsq2[perm[i + 64]];
+  }
+  if (i < i1) a += bsq2[perm[i]];
+  a = wave_sum(a + a2);
+  if (lane == 0) wsum[s] = a;
 }
 
-// Stop test of step t and the multiplier lambda_{t+1} of Algorithm 3:
+// The stop test of step t and the multiplier lambda_{t+1} of Algorithm 3
+// (one workgroup):
 //   resid_t = sqrt(sum of the residual partials); done if t >= 1 and
 //   resid_t < tol (converged) or t >= max_inner (cap); otherwise
 //   lambda_{t+1} = 0 if phi(0) <= r^2, else the root of phi(lambda) = r^2,
 //   phi(lambda) = sum_shells w_s / (1 + eta (D_s + lambda))^2, by Newton's
-//   method from lambda = 0, applied either to phi(lambda) - r^2 (newton_phi)
-//   or to the equivalent 1/sqrt(phi(lambda)) - 1/r. The latter is concave and
-//   increasing in lambda (phi is the squared norm of a diagonal shifted
-//   solve), so its Newton iterates also rise monotonically to the same root
-//   and stop by the same test, in a few steps. One workgroup per instance;
-//   the shell weights stay in registers across the Newton steps.
-constexpr int NEWTON_NT = 1024;
+//   method applied either to phi(lambda) - r^2 from lambda = 0 (newton_phi,
+//   as printed) or to the equivalent 1/sqrt(phi(lambda)) - 1/r. The latter is
+//   concave and increasing in lambda (phi is the squared norm of a diagonal
+//   shifted solve), so from the previous multiplier its first step lands at or
+//   below the root and the iterates then rise monotonically to it; both stop
+//   by the same test.
 constexpr int NEWTON_PT = 16;  // shells per thread held in registers
-
-// sums of two values over the block, returned to every thread
-__device__ __forceinline__ void block_sum2_all(double &a, double &b, double *scratch /* >= 2 * 16 + 2 */) {
-  a = wave_sum(a);
-  b = wave_sum(b);
+// sums of four values over the block, returned to every thread
+__device__ __forceinline__ void block_sum4_all(double *v, double *scratch /* >= 4 * 16 */) {
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    scratch[w] = a;
-    scratch[16 + w] = b;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = wave_sum(v[q]);
+    if ((threadIdx.x & 63) == 0) scratch[16 * q + w] = v[q];
   }
   __syncthreads();
-  double sa = 0.0, sb = 0.0;
-  for (int i = 0; i < NEWTON_NT / 64; ++i) {
-    sa += scratch[i];
-    sb += scratch[16 + i];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double s = 0.0;
+    for (int i = 0; i < BN_NT / 64; ++i) s += scratch[16 * q + i];
+    v[q] = s;
   }
-  a = sa;
-  b = sb;
   __syncthreads();
 }
 
-__global__ __launch_bounds__(NEWTON_NT) void k_newton(const double *__restrict__ bins, const double *__restrict__ kkbin,
-                                                      int nbins, Prm p, const double *__restrict__ rpart, int rbpi,
-                                                      SubState *st_all) {
-  __shared__ double scratch[40];
-  const int b = blockIdx.x;
-  SubState *st = st_all + b;
+__global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsum, int nbins,
+                                                  const double *__restrict__ kkbin, Prm p,
+                                                  const double *__restrict__ rpart, int rbpi, SubState *st) {
+  __shared__ double scratch[64];
   if (st->done) return;
   const int t = st->step;
-  double ra = 0.0, rb = 0.0;
-  for (int i = threadIdx.x; i < rbpi; i += NEWTON_NT) ra += rpart[(long)b * rbpi + i];
-  block_sum2_all(ra, rb, scratch);
-  const double resid = sqrt(ra);
+  const double eta = st->eta, r2 = st->r2;
+  const double xi = p.xi[0], q = p.q[0];
+  const double lam_prev = st->lam[t & 1];
+  double xs[NEWTON_PT], ws[NEWTON_PT];
+#pragma unroll
+  for (int i = 0; i < NEWTON_PT; ++i) {
+    const int s = threadIdx.x + i * BN_NT;
+    xs[i] = 1.0;
+    ws[i] = 0.0;
+    if (s < nbins) {
+      xs[i] = 1.0 + eta * lam_of(kkbin[s], xi, q);
+      ws[i] = wsum[s];
+    }
+  }
+  // residual of d_t and phi, phi' at lambda = 0 and at the previous multiplier, in one reduction
+  double v4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < rbpi; i += BN_NT) v4[0] += rpart[i];
+  const double el = eta * lam_prev;
+#pragma unroll
+  for (int i = 0; i < NEWTON_PT; ++i) {
+    const double r0 = rcp64(xs[i]);
+    const double rl = rcp64(xs[i] + el);
+    v4[1] = fma(ws[i], r0 * r0, v4[1]);
+    v4[2] = fma(ws[i], rl * rl, v4[2]);
+    v4[3] = fma(ws[i], rl * rl * rl, v4[3]);
+  }
+  for (int s = threadIdx.x + NEWTON_PT * BN_NT; s < nbins; s += BN_NT) {
+    const double w = wsum[s], x = 1.0 + eta * lam_of(kkbin[s], xi, q);
+    const double r0 = rcp64(x), rl = rcp64(x + el);
+    v4[1] += w * r0 * r0;
+    v4[2] += w * rl * rl;
+    v4[3] += w * rl * rl * rl;
+  }
+  block_sum4_all(v4, scratch);
+  const double resid = sqrt(v4[0]);
   const bool bad = !(resid == resid) || resid > 1e300;
   if ((t >= 1 && resid < st->tol) || t >= st->max_inner || bad) {
     if (threadIdx.x == 0) {
@@ -890,54 +940,48 @@ __global__ __launch_bounds__(NEWTON_NT) void k_newton(const double *__restrict__
       st->done = (resid < st->tol) ? 1 : 2;
       if (bad) st->nonfinite = 1;
       st->final_step = t;
-      st->lam_final = st->lam[t & 1];
+      st->lam_final = lam_prev;
     }
     return;
   }
-  const double *w = bins + (long)b * nbins;
-  const double xi = p.xi[b], q = p.q[b];
-  const double eta = st->eta, r2 = st->r2;
-  // x_s = 1 + eta D_s and w_s in registers
-  double xs[NEWTON_PT], ws[NEWTON_PT];
-#pragma unroll
-  for (int i = 0; i < NEWTON_PT; ++i) {
-    const int s = threadIdx.x + i * NEWTON_NT;
-    xs[i] = 1.0;
-    ws[i] = 0.0;
-    if (s < nbins) {
-      xs[i] = 1.0 + eta * lam_of(kkbin[s], xi, q);
-      ws[i] = w[s];
-    }
-  }
   auto eval = [&](double lam, double &phi, double &dphi) {
-    double f = 0.0, g3 = 0.0;
-    const double el = eta * lam;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const double e2 = eta * lam;
 #pragma unroll
     for (int i = 0; i < NEWTON_PT; ++i) {
-      const double r = rcp64(xs[i] + el);
+      const double r = rcp64(xs[i] + e2);
       const double r2i = r * r;
-      f = fma(ws[i], r2i, f);
-      g3 = fma(ws[i], r2i * r, g3);
+      v[0] = fma(ws[i], r2i, v[0]);
+      v[1] = fma(ws[i], r2i * r, v[1]);
     }
-    for (int s = threadIdx.x + NEWTON_PT * NEWTON_NT; s < nbins; s += NEWTON_NT) {
-      const double r = rcp64(1.0 + eta * lam_of(kkbin[s], xi, q) + el);
-      f += w[s] * r * r;
-      g3 += w[s] * r * r * r;
+    for (int s = threadIdx.x + NEWTON_PT * BN_NT; s < nbins; s += BN_NT) {
+      const double r = rcp64(1.0 + eta * lam_of(kkbin[s], xi, q) + e2);
+      const double w = wsum[s];
+      v[0] += w * r * r;
+      v[1] += w * r * r * r;
     }
-    block_sum2_all(f, g3, scratch);
-    phi = f;
-    dphi = -2.0 * eta * g3;
+    block_sum4_all(v, scratch);
+    phi = v[0];
+    dphi = -2.0 * eta * v[1];
   };
-  double phi, dphi;
-  eval(0.0, phi, dphi);
   double lam = 0.0;
   int it = 0;
-  if (phi > r2) {
+  if (v4[1] > r2) {  // phi(0) > r^2: the multiplier is the root of phi(lambda) = r^2
     const bool form_phi = st->newton_phi != 0;
+    double phi, dphi;
+    if (form_phi || !(lam_prev > 0.0)) {
+      lam = 0.0;  // the printed iteration: Newton from lambda = 0
+      eval(0.0, phi, dphi);
+    } else {
+      lam = lam_prev;  // warm start at the previous multiplier
+      phi = v4[2];
+      dphi = -2.0 * eta * v4[3];
+    }
     const double rr = sqrt(r2);
     while (it < st->max_newton) {
-      if (phi - r2 <= st->newton_rtol * r2) break;
-      const double nl = form_phi ? lam - (phi - r2) / dphi : lam + 2.0 * phi * (1.0 - sqrt(phi) / rr) / dphi;
+      if (phi >= r2 && phi - r2 <= st->newton_rtol * r2) break;
+      double nl = form_phi ? lam - (phi - r2) / dphi : lam + 2.0 * phi * (1.0 - sqrt(phi) / rr) / dphi;
+      if (nl < 0.0) nl = 0.0;
       ++it;
       if (fabs(nl - lam) <= st->newton_steptol * fmax(1.0, fabs(lam))) {
         lam = nl;

@@ -84,10 +84,11 @@ template <typename T, int N> struct Impl {
     op.b0 = (C2 *)a.b0;
     op.b1 = (C2 *)a.b1;
     op.gh = (const C2 *)a.gh;
-    op.bsq = a.bsq;
+    op.bsq2 = a.bsq;
     op.partial = a.partial;
     op.st = a.st;
     op.inv_n = a.inv_n;
+    op.cpi = a.cg.cpi;
     hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                        (const C2 *)a.tw, op);
   }

@@ -62,6 +62,17 @@ __global__ __launch_bounds__(EW_NT) void k_gamma_p(long N, int batch, Prm p, con
     if (g32) g32[i] = float(v);
   }
 }
+// out = x / sqrt(Lambda + c) over the half spectrum (k = 0 removed)
+__global__ __launch_bounds__(EW_NT) void k_prec_scale(Geo g, Prm p, const double2 *__restrict__ x, double c,
+                                                      double2 *__restrict__ out) {
+  for (long h = (long)blockIdx.x * EW_NT + threadIdx.x; h < g.nh; h += (long)gridDim.x * EW_NT) {
+    int kl;
+    const double lam = lam_of(kk_at(g, (int)h, kl), p.xi[0], p.q[0]);
+    const double s = (h == 0) ? 0.0 : 1.0 / sqrt(lam + c);
+    const double2 v = x[h];
+    out[h] = double2{v.x * s, v.y * s};
+  }
+}
 // out = x + y (real)
 __global__ __launch_bounds__(EW_NT) void k_add_real(long n, const double *__restrict__ x, const double *__restrict__ y,
                                                     double *__restrict__ out) {
@@ -112,8 +123,10 @@ struct lb_plan {
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
   // reciprocal shells for the Newton step
   int nbins = 0;
-  int *perm = nullptr, *seg = nullptr;
-  double *kkbin = nullptr;
+  long npair = 0;                        // (|k0|, column) entries per instance
+  int *perm = nullptr, *seg = nullptr;   // shell-sorted entries, shell -> range of perm
+  double *kkbin = nullptr;               // |Bk|^2 of each shell
+  double *wsum = nullptr;                // per-shell sums of w |b|^2
   // FP64 spectral buffers (batch * nh complex each; SP holds 2 * batch)
   double2 *SP = nullptr, *GH = nullptr, *SH = nullptr, *W64 = nullptr;
   double2 *X = nullptr, *R = nullptr, *Pv = nullptr, *AP = nullptr;
@@ -122,7 +135,7 @@ struct lb_plan {
   // physical buffers (batch * N)
   double *gp64 = nullptr, *sphys = nullptr, *ptrial = nullptr;
   float *gp32 = nullptr;
-  double *bsq = nullptr, *bins = nullptr;
+  double *bsq = nullptr;
   double *partial = nullptr;
   long partial_len = 0;
   double *sums = nullptr;  // small device scratch for finalised sums
@@ -368,23 +381,28 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
     if ((rc = dalloc(P, &A.kk, cnt))) return cleanup(rc);
     if ((rc = upload(P, A.kk, kk.data(), cnt * sizeof(double)))) return cleanup(rc);
   }
-  // reciprocal shells: group the modes h != 0 by their exact |Bk|^2 value
+  // reciprocal shells of the Newton step. The update pass reduces w |b|^2 over
+  // the +-k0 pairs of each axis-0 column, so the entries are (|k0|, column)
+  // pairs, p = |k0| * columns + column; they are grouped by their exact
+  // |Bk|^2 value, summed in the kernels' order kk0 + (kk_last + kk1).
   {
     std::vector<double> k0(P->n0), k1(P->n1, 0.0), kl(P->nhl);
     for (int i = 0; i < P->n0; ++i) k0[i] = kk_axis(i, P->n0, g->box[0], false);
     if (P->dim == 3)
       for (int i = 0; i < P->n1; ++i) k1[i] = kk_axis(i, P->n1, g->box[1], false);
     for (int i = 0; i < P->nhl; ++i) kl[i] = kk_axis(i, P->nl, g->box[g->dim - 1], true);
+    const int cpi = P->n1 * P->nhl;  // axis-0 columns per instance
+    const int nh0 = P->n0 / 2 + 1;
+    P->npair = (long)nh0 * cpi;
     std::vector<std::pair<double, int>> keys;
-    keys.reserve(P->nh - 1);
-    for (long h = 1; h < P->nh; ++h) {
-      const int kli = (int)(h % P->nhl);
-      const long r = h / P->nhl;
-      const int i1 = (int)(r % P->n1), i0 = (int)(r / P->n1);
-      // same summation order as the kernels: kk0 + (kk_last + kk1)
-      const double kk = k0[i0] + (P->dim == 3 ? kl[kli] + k1[i1] : kl[kli]);
-      keys.emplace_back(kk, (int)h);
-    }
+    keys.reserve(P->npair - 1);
+    for (int e = 0; e < nh0; ++e)
+      for (int ml = 0; ml < cpi; ++ml) {
+        if (e == 0 && ml == 0) continue;  // k = 0 is not a variable
+        const int i1 = ml / P->nhl, kli = ml - i1 * P->nhl;
+        const double kkc = P->dim == 3 ? kl[kli] + k1[i1] : kl[kli];
+        keys.emplace_back(k0[e] + kkc, e * cpi + ml);
+      }
     std::sort(keys.begin(), keys.end());
     std::vector<int> perm(keys.size()), seg;
     std::vector<double> kb;
@@ -430,7 +448,8 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
     if ((rc = dalloc(P, &P->gp32, Np))) return cleanup(rc);
   }
   if ((rc = dalloc(P, &P->gp64, Np)) || (rc = dalloc(P, &P->sphys, Np)) || (rc = dalloc(P, &P->ptrial, Np)) ||
-      (rc = dalloc(P, &P->bsq, S)) || (rc = dalloc(P, &P->bins, (long)batch * P->nbins)))
+      (rc = dalloc(P, &P->bsq, (long)batch * P->npair)) || (rc = dalloc(P, &P->wsum, (long)batch * P->nbins)) ||
+      false)
     return cleanup(rc);
   const long mb = std::max({bpi_pairs(P), bpi_rows(P), bpi_col0(P), P->dim == 3 ? bpi_col1(P) : 1L, bpi_ew(P)});
   P->partial_len = 8 * mb * batch + 64;
@@ -869,16 +888,15 @@ static void enqueue_step(lb_plan *P, const Prm &p) {
     KT kt_(P, "col0_fwd_update");
     F(P, 0, prec)->cols_fwd_update(u);
   }
-  const long waves = (long)P->nbins;
   {
     KT kt_(P, "bins");
-    hipLaunchKernelGGL(lbk::k_bins, dim3((unsigned)cdiv(waves * 64, 256)), dim3(256), 0, P->stream, P->bsq, P->perm,
-                       P->seg, P->nbins, P->nh, 1, (const SubState *)P->st, P->bins);
+    hipLaunchKernelGGL(lbk::k_bins, dim3((unsigned)cdiv(P->nbins, 4)), dim3(256), 0, P->stream, (const double *)P->bsq,
+                       (const int *)P->perm, (const int *)P->seg, P->nbins, (const SubState *)P->st, P->wsum);
   }
   {
     KT kt_(P, "newton");
-    hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::NEWTON_NT), 0, P->stream, P->bins, P->kkbin, P->nbins, p,
-                       (const double *)P->partial, u.cg.bpi, P->st);
+    hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::BN_NT), 0, P->stream, (const double *)P->wsum, P->nbins,
+                       (const double *)P->kkbin, p, (const double *)P->partial, u.cg.bpi, P->st);
   }
 }
 
@@ -1153,7 +1171,16 @@ static void jacobi_eig(int m, std::vector<double> &A, std::vector<double> &V) {
   }
 }
 
-static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, double *ritz, double *resid) {
+static void prec_scale(lb_plan *P, const Prm &p, const double2 *x, double c, double2 *out) {
+  KT kt_(P, "prec_scale");
+  hipLaunchKernelGGL(lbk::k_prec_scale, dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+                     P->stream, geo(P, 1), p, x, c, out);
+}
+
+// Lanczos with full reorthogonalisation on H, or with c > 0 on K = S H S,
+// S = (Lambda + c)^(-1/2) (congruent to H, same inertia, clustered spectrum);
+// then the Rayleigh quotient of H at x = S y for the lowest Ritz vector y.
+static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, double c, double *ritz, double *resid) {
   if ((int)P->lz.size() < steps + 1) {
     while ((int)P->lz.size() < steps + 1) {
       void *q = nullptr;
@@ -1162,21 +1189,31 @@ static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, 
     }
   }
   const long n = P->nh;
+  const bool pc = c > 0.0;
+  auto op = [&](const double2 *v, double2 *out) {
+    if (pc) {
+      prec_scale(P, p, v, c, P->Pv);
+      hess_spec64(P, p, P->Pv, P->X, 0.0);
+      prec_scale(P, p, P->X, c, out);
+    } else {
+      hess_spec64(P, p, v, out, 0.0);
+    }
+  };
   double nn;
   LB_TRY(spec_dot_host(P, p, v0, v0, &nn));
   if (!(nn > 0)) return fail(LB_ERR_ARG, "Lanczos start vector has no zero-mean component");
   lincomb64(P, n, 1.0 / std::sqrt(nn), v0, 0.0, v0, P->lz[0]);
   std::vector<double> alpha, beta;
   for (int i = 0; i < steps; ++i) {
-    hess_spec64(P, p, P->lz[i], P->AP, 0.0);
+    op(P->lz[i], P->AP);
     if (i > 0) lincomb64(P, n, 1.0, P->AP, -beta[i - 1], P->lz[i - 1], P->AP);
     double a;
     LB_TRY(spec_dot_host(P, p, P->AP, P->lz[i], &a));
     lincomb64(P, n, 1.0, P->AP, -a, P->lz[i], P->AP);
     for (int k = 0; k <= i; ++k) {
-      double c;
-      LB_TRY(spec_dot_host(P, p, P->AP, P->lz[k], &c));
-      lincomb64(P, n, 1.0, P->AP, -c, P->lz[k], P->AP);
+      double cc;
+      LB_TRY(spec_dot_host(P, p, P->AP, P->lz[k], &cc));
+      lincomb64(P, n, 1.0, P->AP, -cc, P->lz[k], P->AP);
     }
     alpha.push_back(a);
     double bb;
@@ -1196,13 +1233,30 @@ static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, 
   int imin = 0;
   for (int i = 1; i < m; ++i)
     if (A[(size_t)i * m + i] < A[(size_t)imin * m + imin]) imin = i;
-  *ritz = A[(size_t)imin * m + imin];
-  *resid = std::fabs(beta[m - 1] * V[(size_t)(m - 1) * m + imin]);
+  if (!pc) {
+    *ritz = A[(size_t)imin * m + imin];
+    *resid = std::fabs(beta[m - 1] * V[(size_t)(m - 1) * m + imin]);
+    return 0;
+  }
+  // y = sum_i V[i, imin] q_i ; x = S y ; rho = <x, Hx> / <x, x>
+  lincomb64(P, n, 0.0, P->lz[0], 0.0, P->lz[0], P->R);
+  for (int i = 0; i < m; ++i) lincomb64(P, n, V[(size_t)i * m + imin], P->lz[i], 1.0, P->R, P->R);
+  prec_scale(P, p, P->R, c, P->Pv);
+  hess_spec64(P, p, P->Pv, P->AP, 0.0);
+  double xx, xhx;
+  LB_TRY(spec_dot_host(P, p, P->Pv, P->Pv, &xx));
+  LB_TRY(spec_dot_host(P, p, P->Pv, P->AP, &xhx));
+  const double rho = xhx / xx;
+  lincomb64(P, n, 1.0, P->AP, -rho, P->Pv, P->AP);
+  double rr;
+  LB_TRY(spec_dot_host(P, p, P->AP, P->AP, &rr));
+  *ritz = rho;
+  *resid = std::sqrt(std::max(rr, 0.0) / xx);
   return 0;
 }
 
 extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double *psi, const double *v0, int steps,
-                              double *ritz_min, double *resid) {
+                              double precond_shift, double *ritz_min, double *resid) {
   if (!P || !psi || !v0 || !ritz_min || !resid) return fail(LB_ERR_ARG, "null argument");
   if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_lanczos_min needs a plan with batch 1");
   if (steps < 1 || steps > 1000) return fail(LB_ERR_ARG, "steps must be in [1, 1000]");
@@ -1214,7 +1268,9 @@ extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double 
                        P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
   }
   fwd_r2c(P, LB_FP64, 1, p, v0, P->R, 1);
-  LB_TRY(lanczos_core(P, p, P->R, steps, ritz_min, resid));
+  if (!std::isfinite(precond_shift)) return fail(LB_ERR_ARG, "precond_shift must be finite");
+  lincomb64(P, P->nh, 1.0, P->R, 0.0, P->R, P->SH);  // start vector out of the work buffers
+  LB_TRY(lanczos_core(P, p, P->SH, steps, precond_shift, ritz_min, resid));
   return check_launch("lb_lanczos_min");
 }
 

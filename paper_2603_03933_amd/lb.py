@@ -126,7 +126,7 @@ _SIGS = {
     "lb_tr_subproblem": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, C.POINTER(LbSubOpts), _P, _P, C.POINTER(LbSubInfo)]),
     "lb_imex_tr_solve": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo)]),
     "lb_shifted_solve": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, _D, _I, _P, C.POINTER(_I)]),
-    "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, C.POINTER(_D), C.POINTER(_D)]),
+    "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, _D, C.POINTER(_D), C.POINTER(_D)]),
 }
 
 
@@ -306,11 +306,11 @@ class Plan:
         _check(lib().lb_shifted_solve(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(grad, self.N, "grad"), float(shift), float(rtol), int(maxiter), _ptr(out, self.N, "s_out"), C.byref(it)))
         return out, it.value
 
-    def lb_lanczos_min(self, params, psi, v0, steps):
+    def lb_lanczos_min(self, params, psi, v0, steps, precond_shift=0.0):
         self._sync_stream()
         ritz = C.c_double()
         res = C.c_double()
-        _check(lib().lb_lanczos_min(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(v0, self.N, "v0"), int(steps), C.byref(ritz), C.byref(res)))
+        _check(lib().lb_lanczos_min(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(v0, self.N, "v0"), int(steps), float(precond_shift), C.byref(ritz), C.byref(res)))
         return ritz.value, res.value
 
 

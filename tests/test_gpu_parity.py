@@ -277,6 +277,22 @@ def test_lanczos_matches_dense_eigenvalue():
     assert abs(ritz12 - ritz_or) < 1e-10 * max(1, abs(ritz_or))
 
 
+@pytest.mark.parametrize("shape,box", [((16, 16), (2 * math.pi, 2 * math.pi)), ((8, 12, 16), (2 * math.pi, 3 * math.pi, 4 * math.pi))])
+def test_preconditioned_lanczos_matches_oracle_and_dense(shape, box):
+    m = model_for(shape, box, -0.15, 0.25)
+    psi = I.zero_mean_noise(shape, 0.3, 7)
+    v0 = I.zero_mean_noise(shape, 1.0, 8)
+    plan = lb.Plan(shape, box)
+    rho, res = plan.lb_lanczos_min(lb.Params(m.tau, m.gamma), dev(psi), dev(v0), 20, precond_shift=1.0)
+    rho_or, res_or = O.lanczos_min(m, psi, O.fwd(v0), 20, precond_shift=1.0)
+    assert abs(rho - rho_or) < 1e-9 * max(1.0, abs(rho_or))
+    assert abs(res - res_or) < 1e-6 * max(1.0, res_or)
+    if math.prod(shape) <= 512:
+        ev = O.hessian_eigs(m, psi)
+        assert rho >= ev[0] - 1e-10  # a Rayleigh quotient bounds sigma_1 from above
+        assert rho - ev[0] < 1e-4
+
+
 def _power(psi):
     return np.sort(np.abs(np.fft.fftn(psi)).ravel() ** 2)
 

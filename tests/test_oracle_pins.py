@@ -412,3 +412,19 @@ def test_lanczos_matches_dense_min_eigenvalue():
     assert abs(ritz - ev[0]) < 1e-9 * max(1.0, abs(ev[0]))
     ritz10, _ = O.lanczos_min(m, psi, v0, 10)
     assert ritz10 >= ev[0] - 1e-12  # a Ritz value bounds sigma_1 from above
+
+
+def test_preconditioned_lanczos_rayleigh_quotient_bounds_sigma1():
+    """Lanczos on K = S H S (congruent to H) gives a Rayleigh quotient of H that
+    bounds sigma_1 from above and reaches it far sooner than plain Lanczos."""
+    m = O.Model(O.Grid((16, 16), (2 * math.pi, 2 * math.pi)), -0.15, 0.25)
+    psi = rand_field(m.grid.n, 0.3, 7)
+    ev = O.hessian_eigs(m, psi)
+    v0 = O.fwd(rand_field(m.grid.n, 1.0, 8))
+    rho, res = O.lanczos_min(m, psi, v0, 20, precond_shift=1.0)
+    plain, _ = O.lanczos_min(m, psi, v0, 20)
+    assert ev[0] - 1e-12 <= rho < ev[0] + 1e-5
+    assert plain > rho + 1.0
+    # at psi = 0, H = Lambda + tau is diagonal: K's lowest vector maps to an exact eigenvector
+    rho0, res0 = O.lanczos_min(m, np.zeros(m.grid.n), v0, 30, precond_shift=1.0)
+    assert abs(rho0 - m.tau) < 1e-10 and res0 < 1e-8

@@ -100,15 +100,37 @@ template <int N> struct Cfg {
 // ---------------------------------------------------------------------------
 // Block reductions (wavefront shuffles, then LDS across waves)
 // ---------------------------------------------------------------------------
+// Wavefront reductions with DPP lane moves (no LDS round trips): row_shr 1, 2,
+// 4, 8 leave each row's total in its lane 15, row_bcast15 / row_bcast31 fold
+// the rows into lane 63, which is then read back as a uniform value. Lanes
+// whose source is outside the row read 0, so wave_max needs values >= 0.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO> __device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xf, BOUND_ZERO);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane63(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0x111, 0xf, true>(v);   // row_shr:1
+  v += dpp_d<0x112, 0xf, true>(v);   // row_shr:2
+  v += dpp_d<0x114, 0xf, true>(v);   // row_shr:4
+  v += dpp_d<0x118, 0xf, true>(v);   // row_shr:8
+  v += dpp_d<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
+  return lane63(v);
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_d<0x111, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x112, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x114, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x118, 0xf, true>(v));
+  v = fmax(v, dpp_d<0x142, 0xa, false>(v));
+  v = fmax(v, dpp_d<0x143, 0xc, false>(v));
+  return lane63(v);
 }
 // result valid in thread 0; `scratch` holds >= 16 doubles; all threads must call
 template <int NT> __device__ __forceinline__ double block_sum(double v, double *scratch) {
@@ -242,9 +264,9 @@ template <typename T> struct OpInvScaleD {
   const c2<T> *b0, *b1;  // b buffers: b_{t-1} lives in (t - 1) & 1
   c2<T> *out;
   const SubState *st;
+  int t;  // step index (known to the host when it enqueues the step)
   __device__ bool skip() const { return st->done != 0; }
   __device__ StepBlk<T> begin(int b) const {
-    const int t = st->step;
     StepBlk<T> s;
     s.bprev = ((t - 1) & 1) ? b1 : b0;
     s.bnext = nullptr;
@@ -288,9 +310,9 @@ template <typename T> struct OpFwdUpdate {
   const SubState *st;
   double inv_n;
   int cpi;          // columns per instance
+  int t;            // step index
   __device__ bool skip() const { return st->done != 0; }
   __device__ StepBlk<T> begin(int b) const {
-    const int t = st->step;
     StepBlk<T> s;
     s.bprev = ((t - 1) & 1) ? b1 : b0;
     s.bnext = (t & 1) ? b1 : b0;
@@ -686,6 +708,112 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T
 }
 
 // ---------------------------------------------------------------------------
+// Plane pass (3D grids with n1 = n_last = N whose half-spectrum plane fits in
+// LDS): one workgroup per (instance, i0) plane does the axis-1 inverse, the row
+// half-spectrum-to-real, the product with Gamma'(psi), the row real-to-half-
+// spectrum and the axis-1 forward transform, in place in LDS. This replaces
+// three passes through HBM in each subproblem step.
+// ---------------------------------------------------------------------------
+template <typename T, int N> struct PlaneCfg {
+  static constexpr int NH = N / 2 + 1;
+  static constexpr bool fits = (long)N * NH * sizeof(c2<T>) <= 160 * 1024;
+  static constexpr int NT = N >= 96 ? 1024 : (N >= 48 ? 512 : 256);
+};
+
+// half rows (2p, 2p+1) of the plane -> Z_p = A + i B over the full row length, in place
+template <typename T, int N, int NT> __device__ __forceinline__ void plane_pack(c2<T> *P) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1;
+  constexpr int TOT = (N / 2) * NH;
+  constexpr int K = (TOT + NT - 1) / NT;
+  C a[K], bb[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < TOT) {
+      const int pr = i / NH, k = i - pr * NH;
+      a[q] = P[2 * pr * NH + k];
+      bb[q] = P[(2 * pr + 1) * NH + k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < TOT) {
+      const int pr = i / NH, k = i - pr * NH;
+      C A = a[q], B = bb[q];
+      if (k == 0 || 2 * k == N) {
+        A.y = T(0);
+        B.y = T(0);
+      }
+      P[2 * pr * NH + k] = C{A.x - B.y, A.y + B.x};
+      if (k > 0 && 2 * k < N) P[2 * pr * NH + N - k] = C{A.x + B.y, B.x - A.y};
+    }
+  }
+  __syncthreads();
+}
+
+// Z_p -> half rows (2p, 2p+1), in place
+template <typename T, int N, int NT> __device__ __forceinline__ void plane_unpack(c2<T> *P) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1;
+  constexpr int TOT = (N / 2) * NH;
+  constexpr int K = (TOT + NT - 1) / NT;
+  C a[K], bb[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < TOT) {
+      const int pr = i / NH, k = i - pr * NH;
+      const C zk = P[2 * pr * NH + k], zm = P[2 * pr * NH + ((N - k) % N)];
+      a[q] = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+      bb[q] = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int i = threadIdx.x + q * NT;
+    if (i < TOT) {
+      const int pr = i / NH, k = i - pr * NH;
+      P[2 * pr * NH + k] = a[q];
+      P[(2 * pr + 1) * NH + k] = bb[q];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__((PlaneCfg<T, N>::NT)) void k_plane_inner(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
+                                                                  c2<T> *data, const T *__restrict__ gp,
+                                                                  const SubState *st) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1;
+  constexpr int NT = PlaneCfg<T, N>::NT;
+  __shared__ C P[N * NH];
+  if (st && st->done) return;
+  const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
+  C *plane = data + b * nh + (long)i0 * (N * NH);
+  const T *g = gp + b * Np + (long)i0 * (N * N);
+  for (int i = threadIdx.x; i < N * NH; i += NT) P[i] = plane[i];
+  __syncthreads();
+  fft_lds_batch<T, N, true, NT, NH, true>(P, 1, NH, tw);  // axis 1, inverse
+  plane_pack<T, N, NT>(P);
+  fft_lds_batch<T, N, true, NT, N / 2, false>(P, 2 * NH, 1, tw);  // rows, inverse
+  for (int i = threadIdx.x; i < (N / 2) * N; i += NT) {
+    const int pr = i / N, e = i - pr * N;
+    const C z = P[2 * pr * NH + e];
+    P[2 * pr * NH + e] = C{z.x * g[(2 * pr) * N + e], z.y * g[(2 * pr + 1) * N + e]};
+  }
+  __syncthreads();
+  fft_lds_batch<T, N, false, NT, N / 2, false>(P, 2 * NH, 1, tw);  // rows, forward
+  plane_unpack<T, N, NT>(P);
+  fft_lds_batch<T, N, false, NT, NH, true>(P, 1, NH, tw);  // axis 1, forward
+  for (int i = threadIdx.x; i < N * NH; i += NT) plane[i] = P[i];
+}
+
+// ---------------------------------------------------------------------------
 // Elementwise spectral kernels and reductions
 // ---------------------------------------------------------------------------
 constexpr int EW_NT = 256;
@@ -841,7 +969,7 @@ __global__ __launch_bounds__(EW_NT) void k_axpy_real(long n, double a, const dou
 
 // Shell sums of w |b|^2: one wavefront per reciprocal shell, gathering the
 // shell's (|k0|, column) pair entries through the shell-sorted list `perm`.
-constexpr int BN_NT = 1024;
+constexpr int BN_NT = 512;
 __global__ __launch_bounds__(256) void k_bins(const double *__restrict__ bsq2, const int *__restrict__ perm,
                                               const int *__restrict__ seg, int nbins, const SubState *st,
                                               double *__restrict__ wsum) {
@@ -875,29 +1003,37 @@ __global__ __launch_bounds__(256) void k_bins(const double *__restrict__ bsq2, c
 //   by the same test.
 constexpr int NEWTON_PT = 16;  // shells per thread held in registers
 // sums of four values over the block, returned to every thread
-__device__ __forceinline__ void block_sum4_all(double *v, double *scratch /* >= 4 * 16 */) {
+__device__ __forceinline__ void block_sum4_all(double &a, double &b, double &c, double &d,
+                                               double *scratch /* >= 4 * 16 */) {
   const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    v[q] = wave_sum(v[q]);
-    if ((threadIdx.x & 63) == 0) scratch[16 * q + w] = v[q];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  d = wave_sum(d);
+  if ((threadIdx.x & 63) == 0) {
+    scratch[w] = a;
+    scratch[16 + w] = b;
+    scratch[32 + w] = c;
+    scratch[48 + w] = d;
   }
   __syncthreads();
+  a = b = c = d = 0.0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double s = 0.0;
-    for (int i = 0; i < BN_NT / 64; ++i) s += scratch[16 * q + i];
-    v[q] = s;
+  for (int i = 0; i < BN_NT / 64; ++i) {
+    a += scratch[i];
+    b += scratch[16 + i];
+    c += scratch[32 + i];
+    d += scratch[48 + i];
   }
   __syncthreads();
 }
 
 __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsum, int nbins,
                                                   const double *__restrict__ kkbin, Prm p,
-                                                  const double *__restrict__ rpart, int rbpi, SubState *st) {
+                                                  const double *__restrict__ rpart, int rbpi, SubState *st, int t) {
   __shared__ double scratch[64];
   if (st->done) return;
-  const int t = st->step;
+  const int npt = (nbins + BN_NT - 1) / BN_NT;  // shell slots in use (uniform)
   const double eta = st->eta, r2 = st->r2;
   const double xi = p.xi[0], q = p.q[0];
   const double lam_prev = st->lam[t & 1];
@@ -907,7 +1043,7 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
     const int s = threadIdx.x + i * BN_NT;
     xs[i] = 1.0;
     ws[i] = 0.0;
-    if (s < nbins) {
+    if (i < npt && s < nbins) {
       xs[i] = 1.0 + eta * lam_of(kkbin[s], xi, q);
       ws[i] = wsum[s];
     }
@@ -915,14 +1051,17 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
   // residual of d_t and phi, phi' at lambda = 0 and at the previous multiplier, in one reduction
   double v4[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < rbpi; i += BN_NT) v4[0] += rpart[i];
+#define V4 v4[0], v4[1], v4[2], v4[3]
   const double el = eta * lam_prev;
 #pragma unroll
   for (int i = 0; i < NEWTON_PT; ++i) {
-    const double r0 = rcp64(xs[i]);
-    const double rl = rcp64(xs[i] + el);
-    v4[1] = fma(ws[i], r0 * r0, v4[1]);
-    v4[2] = fma(ws[i], rl * rl, v4[2]);
-    v4[3] = fma(ws[i], rl * rl * rl, v4[3]);
+    if (i < npt) {
+      const double r0 = rcp64(xs[i]);
+      const double rl = rcp64(xs[i] + el);
+      v4[1] = fma(ws[i], r0 * r0, v4[1]);
+      v4[2] = fma(ws[i], rl * rl, v4[2]);
+      v4[3] = fma(ws[i], rl * rl * rl, v4[3]);
+    }
   }
   for (int s = threadIdx.x + NEWTON_PT * BN_NT; s < nbins; s += BN_NT) {
     const double w = wsum[s], x = 1.0 + eta * lam_of(kkbin[s], xi, q);
@@ -931,7 +1070,8 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
     v4[2] += w * rl * rl;
     v4[3] += w * rl * rl * rl;
   }
-  block_sum4_all(v4, scratch);
+  block_sum4_all(V4, scratch);
+#undef V4
   const double resid = sqrt(v4[0]);
   const bool bad = !(resid == resid) || resid > 1e300;
   if ((t >= 1 && resid < st->tol) || t >= st->max_inner || bad) {
@@ -949,10 +1089,12 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
     const double e2 = eta * lam;
 #pragma unroll
     for (int i = 0; i < NEWTON_PT; ++i) {
-      const double r = rcp64(xs[i] + e2);
-      const double r2i = r * r;
-      v[0] = fma(ws[i], r2i, v[0]);
-      v[1] = fma(ws[i], r2i * r, v[1]);
+      if (i < npt) {
+        const double r = rcp64(xs[i] + e2);
+        const double r2i = r * r;
+        v[0] = fma(ws[i], r2i, v[0]);
+        v[1] = fma(ws[i], r2i * r, v[1]);
+      }
     }
     for (int s = threadIdx.x + NEWTON_PT * BN_NT; s < nbins; s += BN_NT) {
       const double r = rcp64(1.0 + eta * lam_of(kkbin[s], xi, q) + e2);
@@ -960,7 +1102,8 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
       v[0] += w * r * r;
       v[1] += w * r * r * r;
     }
-    block_sum4_all(v, scratch);
+    double z0 = 0.0, z1 = 0.0;
+    block_sum4_all(v[0], v[1], z0, z1, scratch);
     phi = v[0];
     dphi = -2.0 * eta * v[1];
   };

@@ -37,6 +37,7 @@ struct PassArgs {
   float *gp32 = nullptr;
   double scale = 1.0, inv_n = 1.0, shift = 0.0;
   int zero_dc = 0;
+  int step = 0;  // subproblem step index
 };
 
 struct NFuncs {
@@ -50,6 +51,8 @@ struct NFuncs {
   void (*rows_c2r)(const PassArgs &, int mode) = nullptr;
   void (*rows_inner)(const PassArgs &) = nullptr;
   void (*rows_energy)(const PassArgs &) = nullptr;  // FP64 tables only
+  // plane pass for n1 = n_last = N (null when the plane does not fit in LDS)
+  void (*plane_inner)(const PassArgs &, int n0) = nullptr;
 };
 
 template <typename T, int N> struct Impl {
@@ -73,6 +76,7 @@ template <typename T, int N> struct Impl {
     op.b1 = (const C2 *)a.b1;
     op.out = (C2 *)a.out;
     op.st = a.st;
+    op.t = a.step;
     hipLaunchKernelGGL((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                        (const C2 *)a.tw, op);
   }
@@ -89,6 +93,7 @@ template <typename T, int N> struct Impl {
     op.st = a.st;
     op.inv_n = a.inv_n;
     op.cpi = a.cg.cpi;
+    op.t = a.step;
     hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                        (const C2 *)a.tw, op);
   }
@@ -137,6 +142,12 @@ template <typename T, int N> struct Impl {
                          (const double2 *)a.tw, a.psi, (double2 *)a.out, (double2 *)a.out2, a.gp64, a.gp32, a.partial);
   }
 
+  static void plane_inner(const PassArgs &a, int n0) {
+    if constexpr (lbk::PlaneCfg<T, N>::fits)
+      hipLaunchKernelGGL((lbk::k_plane_inner<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream,
+                         n0, a.g.nh, a.g.N, (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
+  }
+
   static NFuncs table() {
     NFuncs f;
     f.C = lbk::Cfg<N>::C;
@@ -150,6 +161,7 @@ template <typename T, int N> struct Impl {
     f.rows_c2r = &rows_c2r;
     f.rows_inner = &rows_inner;
     f.rows_energy = std::is_same<T, double>::value ? &rows_energy : nullptr;
+    f.plane_inner = lbk::PlaneCfg<T, N>::fits ? &plane_inner : nullptr;
     return f;
   }
 };

@@ -791,27 +791,32 @@ static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out
     KT kt_(P, "col0_inv");
     F(P, 0, LB_FP64)->cols_plain(c0, true);
   }
-  if (P->dim == 3) {
-    PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
-    c1.in = P->W64;
-    c1.out = P->W64;
-    {
+  const NFuncs *f1 = P->dim == 3 ? F(P, 1, LB_FP64) : nullptr;
+  if (f1 && f1->plane_inner && P->n1 == P->nl) {
+    PassArgs pl = args_col(P, LB_FP64, 1, p, 1);
+    pl.out = P->W64;
+    pl.gp = P->gp64;
+    KT kt_(P, "plane_inner");
+    f1->plane_inner(pl, P->n0);
+  } else {
+    if (P->dim == 3) {
+      PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
+      c1.in = P->W64;
+      c1.out = P->W64;
       KT kt_(P, "col1_inv");
       F(P, 1, LB_FP64)->cols_plain(c1, true);
     }
-  }
-  PassArgs r = args_rows(P, LB_FP64, 1, p, true);
-  r.out = P->W64;
-  r.gp = P->gp64;
-  {
-    KT kt_(P, "rows_inner");
-    F(P, 2, LB_FP64)->rows_inner(r);
-  }
-  if (P->dim == 3) {
-    PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
-    c1.in = P->W64;
-    c1.out = P->W64;
+    PassArgs r = args_rows(P, LB_FP64, 1, p, true);
+    r.out = P->W64;
+    r.gp = P->gp64;
     {
+      KT kt_(P, "rows_inner");
+      F(P, 2, LB_FP64)->rows_inner(r);
+    }
+    if (P->dim == 3) {
+      PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
+      c1.in = P->W64;
+      c1.out = P->W64;
       KT kt_(P, "col1_fwd");
       F(P, 1, LB_FP64)->cols_plain(c1, false);
     }
@@ -836,9 +841,10 @@ struct SubOut {
   int iters = 0, newton = 0, status = 0;
 };
 
-static void enqueue_step(lb_plan *P, const Prm &p) {
+static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   const int prec = P->prec;
   PassArgs a = args_col(P, prec, 1, p, 0);
+  a.step = t;
   a.b0 = P->B0;
   a.b1 = P->B1;
   a.out = P->WT;
@@ -847,32 +853,43 @@ static void enqueue_step(lb_plan *P, const Prm &p) {
     KT kt_(P, "col0_inv_scale_d");
     F(P, 0, prec)->cols_inv_scale_d(a);
   }
-  if (P->dim == 3) {
-    PassArgs c1 = args_col(P, prec, 1, p, 1);
-    c1.in = P->WT;
-    c1.out = P->WT;
-    c1.st = P->st;
-    {
-      KT kt_(P, "col1_inv");
-      F(P, 1, prec)->cols_plain(c1, true);
+  const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
+  if (f1 && f1->plane_inner && P->n1 == P->nl) {
+    // axis-1 inverse, rows with Gamma', axis-1 forward: one plane pass in LDS
+    PassArgs pl = args_col(P, prec, 1, p, 1);
+    pl.out = P->WT;
+    pl.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
+    pl.st = P->st;
+    KT kt_(P, "plane_inner");
+    f1->plane_inner(pl, P->n0);
+  } else {
+    if (P->dim == 3) {
+      PassArgs c1 = args_col(P, prec, 1, p, 1);
+      c1.in = P->WT;
+      c1.out = P->WT;
+      c1.st = P->st;
+      {
+        KT kt_(P, "col1_inv");
+        F(P, 1, prec)->cols_plain(c1, true);
+      }
     }
-  }
-  PassArgs r = args_rows(P, prec, 1, p, true);
-  r.out = P->WT;
-  r.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
-  r.st = P->st;
-  {
-    KT kt_(P, "rows_inner");
-    F(P, 2, prec)->rows_inner(r);
-  }
-  if (P->dim == 3) {
-    PassArgs c1 = args_col(P, prec, 1, p, 1);
-    c1.in = P->WT;
-    c1.out = P->WT;
-    c1.st = P->st;
+    PassArgs r = args_rows(P, prec, 1, p, true);
+    r.out = P->WT;
+    r.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
+    r.st = P->st;
     {
-      KT kt_(P, "col1_fwd");
-      F(P, 1, prec)->cols_plain(c1, false);
+      KT kt_(P, "rows_inner");
+      F(P, 2, prec)->rows_inner(r);
+    }
+    if (P->dim == 3) {
+      PassArgs c1 = args_col(P, prec, 1, p, 1);
+      c1.in = P->WT;
+      c1.out = P->WT;
+      c1.st = P->st;
+      {
+        KT kt_(P, "col1_fwd");
+        F(P, 1, prec)->cols_plain(c1, false);
+      }
     }
   }
   PassArgs u = args_col(P, prec, 1, p, 0);
@@ -884,6 +901,7 @@ static void enqueue_step(lb_plan *P, const Prm &p) {
   u.partial = P->partial;
   u.st = P->st;
   u.inv_n = 1.0 / (double)P->N;
+  u.step = t;
   {
     KT kt_(P, "col0_fwd_update");
     F(P, 0, prec)->cols_fwd_update(u);
@@ -896,7 +914,7 @@ static void enqueue_step(lb_plan *P, const Prm &p) {
   {
     KT kt_(P, "newton");
     hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::BN_NT), 0, P->stream, (const double *)P->wsum, P->nbins,
-                       (const double *)P->kkbin, p, (const double *)P->partial, u.cg.bpi, P->st);
+                       (const double *)P->kkbin, p, (const double *)P->partial, u.cg.bpi, P->st, t);
   }
 }
 
@@ -955,7 +973,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   const long max_steps = (long)o.max_inner + 1;
   while (true) {
     const int n = (int)std::min<long>(chunk, max_steps - launched);
-    for (int i = 0; i < n; ++i) enqueue_step(P, p);
+    for (int i = 0; i < n; ++i) enqueue_step(P, p, (int)(launched + i));
     launched += n;
     LB_TRY(check_launch("subproblem step"));
     LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));

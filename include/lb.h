@@ -84,10 +84,15 @@ typedef struct lb_sub_opts {
   double newton_rtol;    /* Newton stops when phi(lambda) - r^2 <= newton_rtol r^2 */
   double newton_steptol; /* ... or |delta lambda| <= newton_steptol max(1, lambda) */
   int poll_every;        /* iterations enqueued between host reads of the stop flag */
-  int newton_phi;        /* root of phi(lambda) = r^2 (eq. lambda_update_rule) by Newton from
-                            lambda = 0 applied to: 1 -> phi(lambda) - r^2 as printed;
-                            0 (default) -> the equivalent 1/sqrt(phi) - 1/r, which is concave
-                            and converges monotonically to the same root in fewer steps */
+  int newton_phi;        /* root of phi(lambda) = r^2 (eq. lambda_update_rule) by Newton applied
+                            to: 1 -> phi(lambda) - r^2 from lambda = 0, as printed;
+                            0 (default) -> the equivalent 1/sqrt(phi) - 1/r from the previous
+                            iteration's multiplier: concave, so it converges monotonically to
+                            the same root in fewer steps */
+  int newton_direct;     /* 1: every Newton evaluation sums phi over the whole spectrum, as
+                            printed; 0 (default): from power sums of |b|^2 taken once per
+                            iteration (a truncated series with a rigorous tail bound far below
+                            rounding), falling back to the full sum when the bound fails */
 } lb_sub_opts;
 
 typedef struct lb_sub_info {
@@ -97,6 +102,7 @@ typedef struct lb_sub_info {
   double gnorm;       /* ||g|| */
   int iters;          /* iterations of Algorithm 3 performed */
   int newton_iters;   /* Newton steps summed over the iterations */
+  int newton_direct;  /* Newton evaluations that summed phi over the spectrum */
   int status;         /* LB_OK or LB_NOT_CONVERGED (cap reached) */
 } lb_sub_info;
 
@@ -147,8 +153,8 @@ void lb_sub_opts_default(lb_sub_opts *opts);
 void lb_tr_opts_default(lb_tr_opts *opts);
 
 /* Create a plan for `batch` instances of `grid` computing in `precision`
- * (LB_FP64 or LB_FP32) on `stream`. Allocates twiddle tables, the
- * reciprocal-shell tables of the Newton step and every device workspace.
+ * (LB_FP64 or LB_FP32) on `stream`. Allocates twiddle tables, |Bk|^2 tables
+ * and every device workspace.
  * Errors: LB_ERR_ARG, LB_ERR_UNSUPPORTED (axis length), LB_ERR_HIP. */
 int lb_plan_create(lb_plan **out, const lb_grid *grid, int batch, int precision, void *stream);
 int lb_plan_destroy(lb_plan *plan);

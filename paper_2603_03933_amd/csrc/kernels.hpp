@@ -46,7 +46,7 @@ __device__ __forceinline__ void decode(const Geo &g, int h, int &i0, int &i1, in
   i0 = r / g.n1;
   i1 = r - i0 * g.n1;
 }
-// |Bk|^2 summed as kk0 + (kkl + kk1), the order the host uses to group shells
+// |Bk|^2 of a mode: kk0 + (kk_last + kk1)
 __device__ __forceinline__ double kk_col_part(const Geo &g, int i1, int kl) {
   return g.dim == 3 ? g.kkl[kl] + g.kk1[i1] : g.kkl[kl];
 }
@@ -181,7 +181,40 @@ struct SubState {
   int max_inner, max_newton;
   int nonfinite;
   int newton_phi;     // 1: Newton on phi(lambda) = r^2; 0: on 1/sqrt(phi) = 1/r
+  int newton_direct_only;  // 1: every Newton evaluation sums phi over the spectrum
+  int newton_direct;       // Newton evaluations that summed phi over the spectrum
 };
+
+// ---------------------------------------------------------------------------
+// The multiplier update of Algorithm 3 (eq. lambda_update_rule)
+// ---------------------------------------------------------------------------
+// phi(lambda) = sum_k w_k |b_k|^2 / (x_k + eta lambda)^2 with x_k = 1 + eta D_k.
+// Rather than re-reading the spectrum for every Newton evaluation, one pass
+// per step forms the power sums
+//   M_j = sum_k w_k |b_k|^2 u_k^j,  u_k = 1 / (x_k + mu0),  j = 2 .. NMOM + 1,
+// around mu0 = eta lambda_t, the previous multiplier. Every pole of phi as a
+// function of mu = eta lambda lies at mu <= -1, so for D = mu - mu0
+//   phi   = sum_{m >= 0} (m + 1) (-D)^m M_{m+2}
+//   dphi/dmu = -sum_{m >= 0} (m + 1)(m + 2) (-D)^m M_{m+3},
+// and since u_k <= 1 / (1 + mu0) the tail after NMOM terms is at most
+// M_2 (NMOM + 1) rho^NMOM / (1 - rho)^2 with rho = |D| / (1 + mu0). A Newton
+// evaluation uses the truncated series when that bound is below 1e-17 phi
+// (far below rounding), and otherwise sums phi directly over the spectrum.
+// phi(0), which decides whether the constraint is active, is summed exactly.
+constexpr int NMOM = 20;          // series terms
+constexpr int MOM_NV = NMOM + 1;  // phi(0) and M_2 .. M_{NMOM+1}
+
+// |Bk|^2 of pair entry i = e * cpi + ml (e = |k0|, ml = column of the instance)
+__device__ __forceinline__ double kk_pair(const Geo &g, int cpi, int i) {
+  const int e = i / cpi;
+  const int ml = i - e * cpi;
+  int i1 = 0, kl = ml;
+  if (g.dim == 3) {
+    i1 = ml / g.nhl;
+    kl = ml - i1 * g.nhl;
+  }
+  return g.kk0[e] + kk_col_part(g, i1, kl);
+}
 
 // ---------------------------------------------------------------------------
 // Column passes
@@ -224,7 +257,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
         if (ok) op.store(bs, cs, base + e * cg.S, e, v, aux, acc, sq);
         else *sq = 0.0;
       });
-  op.template end<NT, N, CC>(acc, reinterpret_cast<double *>(lds), b, lb, c);
+  op.template end<NT, N, CC>(bs, acc, reinterpret_cast<double *>(lds), b, lb, c);
 }
 
 struct Empty {};
@@ -247,7 +280,7 @@ template <typename T> struct OpPlain {
     if (dccol && e == 0) v = c2<T>{T(0), T(0)};
     out[h] = c2<T>{v.x * scale, v.y * scale};
   }
-  template <int NT, int N, int CC> __device__ void end(double, double *, int, int, int) const {}
+  template <int NT, int N, int CC, class B> __device__ void end(const B &, double, double *, int, int, int) const {}
 };
 
 // per-workgroup subproblem state read from SubState
@@ -289,7 +322,7 @@ template <typename T> struct OpInvScaleD {
                         double *) const {
     out[h] = v;
   }
-  template <int NT, int N, int CC> __device__ void end(double, double *, int, int, int) const {}
+  template <int NT, int N, int CC, class B> __device__ void end(const B &, double, double *, int, int, int) const {}
 };
 
 // step t, axis-0 forward pass of T d_t, then the diagonal update:
@@ -307,6 +340,7 @@ template <typename T> struct OpFwdUpdate {
   const c2<T> *gh;
   double *bsq2;     // w (|b(k0)|^2 + |b(-k0)|^2) per (|k0|, column): [n0/2 + 1][columns]
   double *partial;  // one double per workgroup: sum w |r|^2
+  double *mom;      // MOM_NV doubles per workgroup: phi(0), M_2 .. M_{NMOM+1}
   const SubState *st;
   double inv_n;
   int cpi;          // columns per instance
@@ -358,21 +392,64 @@ template <typename T> struct OpFwdUpdate {
     const double bxr = double(bn.x), byr = double(bn.y);
     *sq = ci.w * (bxr * bxr + byr * byr);
   }
+  // Pair sums w (|b(k0)|^2 + |b(-k0)|^2) go to bsq2; the block's shares of
+  // phi(0) and of the power sums M_j around mu0 = eta lambda_t, and of the
+  // squared residual, go to mom[j * blocks + block] and partial[block].
   template <int NT, int N, int CC>
-  __device__ void end(double acc, double *sq, int b, int lb, int) const {
+  __device__ void end(const StepBlk<T> &bs, double acc, double *sq, int b, int lb, int) const {
+    static_assert(NT % CC == 0, "each thread keeps one column");
     __syncthreads();
     constexpr int NH0 = N / 2 + 1;
-    for (int i = threadIdx.x; i < NH0 * CC; i += NT) {
-      const int e = i / CC, cc = i - e * CC;
-      const int ml = lb * CC + cc;
-      if (ml < cpi) {
+    const int cc = threadIdx.x % CC;
+    const int ml = lb * CC + cc;
+    const bool okc = ml < cpi;
+    const double kkc = col_info(g, okc ? ml : 0).kkc;
+    const double mu0 = bs.eta * bs.lam_t;
+    double m[MOM_NV];
+#pragma unroll
+    for (int j = 0; j < MOM_NV; ++j) m[j] = 0.0;
+    if (okc) {
+      for (int e = threadIdx.x / CC; e < NH0; e += NT / CC) {
         double v = sq[e * CC + cc];
         if (e != 0 && 2 * e != N) v += sq[(N - e) * CC + cc];
         bsq2[((long)b * NH0 + e) * cpi + ml] = v;
+        if (e != 0 || ml != 0) {
+          const double x = 1.0 + bs.eta * lam_of(g.kk0[e] + kkc, bs.xi, bs.q);
+          const double u0 = rcp64(x);
+          m[0] = fma(v, u0 * u0, m[0]);
+          const double u = rcp64(x + mu0);
+          double pw = v * u * u;
+#pragma unroll
+          for (int j = 1; j < MOM_NV; ++j) {
+            m[j] += pw;
+            pw *= u;
+          }
+        }
       }
     }
-    const double s = block_sum<NT>(acc, sq);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    constexpr int NW = NT / 64;
+    constexpr int RS = MOM_NV + 1;
+    const int wv = threadIdx.x >> 6;
+    __syncthreads();  // sq becomes the reduction scratch [NW][RS]
+    {
+      const double v = wave_sum(acc);
+      if ((threadIdx.x & 63) == 0) sq[wv * RS + MOM_NV] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < MOM_NV; ++j) {
+      const double v = wave_sum(m[j]);
+      if ((threadIdx.x & 63) == 0) sq[wv * RS + j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < RS) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += sq[w * RS + threadIdx.x];
+      if (threadIdx.x == MOM_NV)
+        partial[blockIdx.x] = s;
+      else
+        mom[(long)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
   }
 };
 
@@ -411,7 +488,7 @@ template <typename T> struct OpFwdHess {
     const double lam = lam_of(a.kk0 + ci.kkc, hb.xi, hb.q) + shift;
     out[h] = c2<T>{T(lam * double(a.xv.x) + double(v.x) * inv_n), T(lam * double(a.xv.y) + double(v.y) * inv_n)};
   }
-  template <int NT, int N, int CC> __device__ void end(double, double *, int, int, int) const {}
+  template <int NT, int N, int CC, class B> __device__ void end(const B &, double, double *, int, int, int) const {}
 };
 
 // Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
@@ -967,113 +1044,61 @@ __global__ __launch_bounds__(EW_NT) void k_axpy_real(long n, double a, const dou
   for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < n; i += (long)gridDim.x * EW_NT) y[i] += a * x[i];
 }
 
-// Shell sums of w |b|^2: one wavefront per reciprocal shell, gathering the
-// shell's (|k0|, column) pair entries through the shell-sorted list `perm`.
-constexpr int BN_NT = 512;
-__global__ __launch_bounds__(256) void k_bins(const double *__restrict__ bsq2, const int *__restrict__ perm,
-                                              const int *__restrict__ seg, int nbins, const SubState *st,
-                                              double *__restrict__ wsum) {
-  if (st->done) return;
-  const int s = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (s >= nbins) return;
-  double a = 0.0, a2 = 0.0;
-  const int i1 = seg[s + 1];
-  int i = seg[s] + lane;
-  for (; i + 64 < i1; i += 128) {
-    a += bsq2[perm[i]];
-    a2 += bsq2[perm[i + 64]];
-  }
-  if (i < i1) a += bsq2[perm[i]];
-  a = wave_sum(a + a2);
-  if (lane == 0) wsum[s] = a;
-}
-
-// The stop test of step t and the multiplier lambda_{t+1} of Algorithm 3
-// (one workgroup):
+// The stop test of step t and the multiplier lambda_{t+1} (one workgroup):
 //   resid_t = sqrt(sum of the residual partials); done if t >= 1 and
 //   resid_t < tol (converged) or t >= max_inner (cap); otherwise
-//   lambda_{t+1} = 0 if phi(0) <= r^2, else the root of phi(lambda) = r^2,
-//   phi(lambda) = sum_shells w_s / (1 + eta (D_s + lambda))^2, by Newton's
-//   method applied either to phi(lambda) - r^2 from lambda = 0 (newton_phi,
-//   as printed) or to the equivalent 1/sqrt(phi(lambda)) - 1/r. The latter is
-//   concave and increasing in lambda (phi is the squared norm of a diagonal
-//   shifted solve), so from the previous multiplier its first step lands at or
+//   lambda_{t+1} = 0 if phi(0) <= r^2, else the root of phi(lambda) = r^2 by
+//   Newton's method, applied either to phi(lambda) - r^2 from lambda = 0
+//   (newton_phi, as printed) or to the equivalent 1/sqrt(phi(lambda)) - 1/r
+//   from lambda_t. The latter is concave and increasing in lambda (phi is the
+//   squared norm of a diagonal shifted solve), so its first step lands at or
 //   below the root and the iterates then rise monotonically to it; both stop
-//   by the same test.
-constexpr int NEWTON_PT = 16;  // shells per thread held in registers
-// sums of four values over the block, returned to every thread
-__device__ __forceinline__ void block_sum4_all(double &a, double &b, double &c, double &d,
-                                               double *scratch /* >= 4 * 16 */) {
+//   by the same test. All threads run the scalar iteration on identical
+//   values, so its control flow is uniform.
+constexpr int NW_NT = 1024;
+__device__ __forceinline__ void block_sum2_all(double &a, double &b, double *scratch /* >= 2 * 16 */) {
   const int w = threadIdx.x >> 6;
   a = wave_sum(a);
   b = wave_sum(b);
-  c = wave_sum(c);
-  d = wave_sum(d);
   if ((threadIdx.x & 63) == 0) {
     scratch[w] = a;
     scratch[16 + w] = b;
-    scratch[32 + w] = c;
-    scratch[48 + w] = d;
   }
   __syncthreads();
-  a = b = c = d = 0.0;
+  a = b = 0.0;
 #pragma unroll
-  for (int i = 0; i < BN_NT / 64; ++i) {
+  for (int i = 0; i < NW_NT / 64; ++i) {
     a += scratch[i];
     b += scratch[16 + i];
-    c += scratch[32 + i];
-    d += scratch[48 + i];
   }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsum, int nbins,
-                                                  const double *__restrict__ kkbin, Prm p,
-                                                  const double *__restrict__ rpart, int rbpi, SubState *st, int t) {
-  __shared__ double scratch[64];
+__global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__restrict__ mom, int nmb,
+                                                  const double *__restrict__ rpart, int rbpi,
+                                                  const double *__restrict__ bsq2, int npair, SubState *st, int t) {
+  __shared__ double M[MOM_NV + 1];
+  __shared__ double scratch[32];
+  // wave v sums value v over the moment blocks (v = MOM_NV: residual partials)
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int v = wv; v <= MOM_NV; v += NW_NT / 64) {
+    const double *src = v < MOM_NV ? mom + (long)v * nmb : rpart;
+    const int cnt = v < MOM_NV ? nmb : rbpi;
+    double a = 0.0, a2 = 0.0;
+    int i = lane;
+    for (; i + 64 < cnt; i += 128) {
+      a += src[i];
+      a2 += src[i + 64];
+    }
+    if (i < cnt) a += src[i];
+    a = wave_sum(a + a2);
+    if (lane == 0) M[v] = a;
+  }
+  __syncthreads();
   if (st->done) return;
-  const int npt = (nbins + BN_NT - 1) / BN_NT;  // shell slots in use (uniform)
-  const double eta = st->eta, r2 = st->r2;
-  const double xi = p.xi[0], q = p.q[0];
-  const double lam_prev = st->lam[t & 1];
-  double xs[NEWTON_PT], ws[NEWTON_PT];
-#pragma unroll
-  for (int i = 0; i < NEWTON_PT; ++i) {
-    const int s = threadIdx.x + i * BN_NT;
-    xs[i] = 1.0;
-    ws[i] = 0.0;
-    if (i < npt && s < nbins) {
-      xs[i] = 1.0 + eta * lam_of(kkbin[s], xi, q);
-      ws[i] = wsum[s];
-    }
-  }
-  // residual of d_t and phi, phi' at lambda = 0 and at the previous multiplier, in one reduction
-  double v4[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int i = threadIdx.x; i < rbpi; i += BN_NT) v4[0] += rpart[i];
-#define V4 v4[0], v4[1], v4[2], v4[3]
-  const double el = eta * lam_prev;
-#pragma unroll
-  for (int i = 0; i < NEWTON_PT; ++i) {
-    if (i < npt) {
-      const double r0 = rcp64(xs[i]);
-      const double rl = rcp64(xs[i] + el);
-      v4[1] = fma(ws[i], r0 * r0, v4[1]);
-      v4[2] = fma(ws[i], rl * rl, v4[2]);
-      v4[3] = fma(ws[i], rl * rl * rl, v4[3]);
-    }
-  }
-  for (int s = threadIdx.x + NEWTON_PT * BN_NT; s < nbins; s += BN_NT) {
-    const double w = wsum[s], x = 1.0 + eta * lam_of(kkbin[s], xi, q);
-    const double r0 = rcp64(x), rl = rcp64(x + el);
-    v4[1] += w * r0 * r0;
-    v4[2] += w * rl * rl;
-    v4[3] += w * rl * rl * rl;
-  }
-  block_sum4_all(V4, scratch);
-#undef V4
-  const double resid = sqrt(v4[0]);
+  const double resid = sqrt(M[MOM_NV]);
   const bool bad = !(resid == resid) || resid > 1e300;
+  const double lam_prev = st->lam[t & 1];
   if ((t >= 1 && resid < st->tol) || t >= st->max_inner || bad) {
     if (threadIdx.x == 0) {
       st->resid = resid;
@@ -1084,32 +1109,51 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
     }
     return;
   }
+  const double eta = st->eta, r2 = st->r2;
+  const double mu0 = eta * lam_prev;
+  const bool direct_only = st->newton_direct_only != 0;
+  int ndirect = 0;
+  // phi and dphi/dlambda at lambda
   auto eval = [&](double lam, double &phi, double &dphi) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    const double e2 = eta * lam;
+    const double D = eta * (lam - lam_prev);
+    const double rho = fabs(D) / (1.0 + mu0);
+    if (!direct_only && rho < 0.5) {
+      double rn = 1.0;
 #pragma unroll
-    for (int i = 0; i < NEWTON_PT; ++i) {
-      if (i < npt) {
-        const double r = rcp64(xs[i] + e2);
-        const double r2i = r * r;
-        v[0] = fma(ws[i], r2i, v[0]);
-        v[1] = fma(ws[i], r2i * r, v[1]);
+      for (int j = 0; j < NMOM; ++j) rn *= rho;
+      const double tail = M[1] * (NMOM + 1) * rn / ((1.0 - rho) * (1.0 - rho));
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int m = NMOM - 1; m >= 0; --m) a = fma(a, -D, (m + 1) * M[1 + m]);
+#pragma unroll
+      for (int m = NMOM - 2; m >= 0; --m) b = fma(b, -D, (double)((m + 1) * (m + 2)) * M[2 + m]);
+      if (tail <= 1e-17 * a) {
+        phi = a;
+        dphi = -eta * b;
+        return;
       }
     }
-    for (int s = threadIdx.x + NEWTON_PT * BN_NT; s < nbins; s += BN_NT) {
-      const double r = rcp64(1.0 + eta * lam_of(kkbin[s], xi, q) + e2);
-      const double w = wsum[s];
-      v[0] += w * r * r;
-      v[1] += w * r * r * r;
+    // direct sum over the spectrum (pair entries)
+    ++ndirect;
+    const double xi = p.xi[0], q = p.q[0];
+    const double e2 = eta * lam;
+    const int cpi = npair / (g.n0 / 2 + 1);
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < npair; i += NW_NT) {
+      if (i == 0) continue;
+      const double r = rcp64(1.0 + eta * lam_of(kk_pair(g, cpi, i), xi, q) + e2);
+      const double w = bsq2[i];
+      const double r2i = r * r;
+      a = fma(w, r2i, a);
+      b = fma(w, r2i * r, b);
     }
-    double z0 = 0.0, z1 = 0.0;
-    block_sum4_all(v[0], v[1], z0, z1, scratch);
-    phi = v[0];
-    dphi = -2.0 * eta * v[1];
+    block_sum2_all(a, b, scratch);
+    phi = a;
+    dphi = -2.0 * eta * b;
   };
   double lam = 0.0;
   int it = 0;
-  if (v4[1] > r2) {  // phi(0) > r^2: the multiplier is the root of phi(lambda) = r^2
+  if (M[0] > r2) {  // phi(0) > r^2: the multiplier is the root of phi(lambda) = r^2
     const bool form_phi = st->newton_phi != 0;
     double phi, dphi;
     if (form_phi || !(lam_prev > 0.0)) {
@@ -1117,8 +1161,7 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
       eval(0.0, phi, dphi);
     } else {
       lam = lam_prev;  // warm start at the previous multiplier
-      phi = v4[2];
-      dphi = -2.0 * eta * v4[3];
+      eval(lam, phi, dphi);
     }
     const double rr = sqrt(r2);
     while (it < st->max_newton) {
@@ -1138,6 +1181,7 @@ __global__ __launch_bounds__(BN_NT) void k_newton(const double *__restrict__ wsu
     st->resid = resid;
     st->lam[(t + 1) & 1] = lam;
     st->newton_total += it;
+    st->newton_direct += ndirect;
     st->step = t + 1;
   }
 }

@@ -27,6 +27,7 @@ struct PassArgs {
   const double *mpart = nullptr;
   int mbpi = 0;
   double *partial = nullptr;
+  double *mom = nullptr;
   void *b0 = nullptr;
   void *b1 = nullptr;
   const void *gh = nullptr;
@@ -90,6 +91,7 @@ template <typename T, int N> struct Impl {
     op.gh = (const C2 *)a.gh;
     op.bsq2 = a.bsq;
     op.partial = a.partial;
+    op.mom = a.mom;
     op.st = a.st;
     op.inv_n = a.inv_n;
     op.cpi = a.cg.cpi;

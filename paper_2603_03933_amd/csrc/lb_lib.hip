@@ -121,12 +121,8 @@ struct lb_plan {
   int prec = LB_FP64;
   hipStream_t stream = nullptr;
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
-  // reciprocal shells for the Newton step
-  int nbins = 0;
-  long npair = 0;                        // (|k0|, column) entries per instance
-  int *perm = nullptr, *seg = nullptr;   // shell-sorted entries, shell -> range of perm
-  double *kkbin = nullptr;               // |Bk|^2 of each shell
-  double *wsum = nullptr;                // per-shell sums of w |b|^2
+  long npair = 0;         // (|k0|, column) entries per instance
+  double *mom = nullptr;  // moment partials of the update pass, MOM_NV x its blocks
   // FP64 spectral buffers (batch * nh complex each; SP holds 2 * batch)
   double2 *SP = nullptr, *GH = nullptr, *SH = nullptr, *W64 = nullptr;
   double2 *X = nullptr, *R = nullptr, *Pv = nullptr, *AP = nullptr;
@@ -381,49 +377,9 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
     if ((rc = dalloc(P, &A.kk, cnt))) return cleanup(rc);
     if ((rc = upload(P, A.kk, kk.data(), cnt * sizeof(double)))) return cleanup(rc);
   }
-  // reciprocal shells of the Newton step. The update pass reduces w |b|^2 over
-  // the +-k0 pairs of each axis-0 column, so the entries are (|k0|, column)
-  // pairs, p = |k0| * columns + column; they are grouped by their exact
-  // |Bk|^2 value, summed in the kernels' order kk0 + (kk_last + kk1).
-  {
-    std::vector<double> k0(P->n0), k1(P->n1, 0.0), kl(P->nhl);
-    for (int i = 0; i < P->n0; ++i) k0[i] = kk_axis(i, P->n0, g->box[0], false);
-    if (P->dim == 3)
-      for (int i = 0; i < P->n1; ++i) k1[i] = kk_axis(i, P->n1, g->box[1], false);
-    for (int i = 0; i < P->nhl; ++i) kl[i] = kk_axis(i, P->nl, g->box[g->dim - 1], true);
-    const int cpi = P->n1 * P->nhl;  // axis-0 columns per instance
-    const int nh0 = P->n0 / 2 + 1;
-    P->npair = (long)nh0 * cpi;
-    std::vector<std::pair<double, int>> keys;
-    keys.reserve(P->npair - 1);
-    for (int e = 0; e < nh0; ++e)
-      for (int ml = 0; ml < cpi; ++ml) {
-        if (e == 0 && ml == 0) continue;  // k = 0 is not a variable
-        const int i1 = ml / P->nhl, kli = ml - i1 * P->nhl;
-        const double kkc = P->dim == 3 ? kl[kli] + k1[i1] : kl[kli];
-        keys.emplace_back(k0[e] + kkc, e * cpi + ml);
-      }
-    std::sort(keys.begin(), keys.end());
-    std::vector<int> perm(keys.size()), seg;
-    std::vector<double> kb;
-    for (size_t i = 0; i < keys.size(); ++i) {
-      if (i == 0 || keys[i].first != keys[i - 1].first) {
-        seg.push_back((int)i);
-        kb.push_back(keys[i].first);
-      }
-      perm[i] = keys[i].second;
-    }
-    seg.push_back((int)keys.size());
-    P->nbins = (int)kb.size();
-    int rc;
-    if ((rc = dalloc(P, &P->perm, perm.size())) || (rc = dalloc(P, &P->seg, seg.size())) ||
-        (rc = dalloc(P, &P->kkbin, kb.size())))
-      return cleanup(rc);
-    if ((rc = upload(P, P->perm, perm.data(), perm.size() * sizeof(int))) ||
-        (rc = upload(P, P->seg, seg.data(), seg.size() * sizeof(int))) ||
-        (rc = upload(P, P->kkbin, kb.data(), kb.size() * sizeof(double))))
-      return cleanup(rc);
-  }
+  // the update pass reduces w |b|^2 over the +-k0 pairs of each axis-0
+  // column: entries p = |k0| * columns + column, per instance
+  P->npair = (long)(P->n0 / 2 + 1) * (P->nh / P->n0);
   const long S = (long)batch * P->nh, Np = (long)batch * P->N;
   int rc;
   if ((rc = dalloc(P, &P->SP, 2 * S)) || (rc = dalloc(P, &P->GH, S)) || (rc = dalloc(P, &P->SH, S)) ||
@@ -448,8 +404,7 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
     if ((rc = dalloc(P, &P->gp32, Np))) return cleanup(rc);
   }
   if ((rc = dalloc(P, &P->gp64, Np)) || (rc = dalloc(P, &P->sphys, Np)) || (rc = dalloc(P, &P->ptrial, Np)) ||
-      (rc = dalloc(P, &P->bsq, (long)batch * P->npair)) || (rc = dalloc(P, &P->wsum, (long)batch * P->nbins)) ||
-      false)
+      (rc = dalloc(P, &P->bsq, (long)batch * P->npair)) || (rc = dalloc(P, &P->mom, (long)lbk::MOM_NV * bpi_col0(P))))
     return cleanup(rc);
   const long mb = std::max({bpi_pairs(P), bpi_rows(P), bpi_col0(P), P->dim == 3 ? bpi_col1(P) : 1L, bpi_ew(P)});
   P->partial_len = 8 * mb * batch + 64;
@@ -838,7 +793,7 @@ static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out
 // ---------------------------------------------------------------------------
 struct SubOut {
   double lam = 0, resid = 0, dnorm = 0;
-  int iters = 0, newton = 0, status = 0;
+  int iters = 0, newton = 0, newton_direct = 0, status = 0;
 };
 
 static void enqueue_step(lb_plan *P, const Prm &p, int t) {
@@ -899,6 +854,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   u.gh = P->GHT;
   u.bsq = P->bsq;
   u.partial = P->partial;
+  u.mom = P->mom;
   u.st = P->st;
   u.inv_n = 1.0 / (double)P->N;
   u.step = t;
@@ -907,14 +863,9 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
     F(P, 0, prec)->cols_fwd_update(u);
   }
   {
-    KT kt_(P, "bins");
-    hipLaunchKernelGGL(lbk::k_bins, dim3((unsigned)cdiv(P->nbins, 4)), dim3(256), 0, P->stream, (const double *)P->bsq,
-                       (const int *)P->perm, (const int *)P->seg, P->nbins, (const SubState *)P->st, P->wsum);
-  }
-  {
     KT kt_(P, "newton");
-    hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::BN_NT), 0, P->stream, (const double *)P->wsum, P->nbins,
-                       (const double *)P->kkbin, p, (const double *)P->partial, u.cg.bpi, P->st, t);
+    hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom, u.cg.bpi,
+                       (const double *)P->partial, u.cg.bpi, (const double *)P->bsq, (int)P->npair, P->st, t);
   }
 }
 
@@ -965,6 +916,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   s.max_inner = o.max_inner;
   s.max_newton = o.max_newton;
   s.newton_phi = o.newton_phi;
+  s.newton_direct_only = o.newton_direct;
   LB_HIP(hipStreamSynchronize(P->stream));  // the pinned mirror may still feed an earlier copy
   *P->st_h = s;
   LB_HIP(hipMemcpyAsync(P->st, P->st_h, sizeof(SubState), hipMemcpyHostToDevice, P->stream));
@@ -1003,6 +955,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   out->dnorm = std::sqrt(std::max(dd, 0.0));
   out->iters = f.final_step;
   out->newton = f.newton_total;
+  out->newton_direct = f.newton_direct;
   out->status = (f.done == 1) ? LB_OK : LB_NOT_CONVERGED;
   return 0;
 }
@@ -1018,6 +971,7 @@ extern "C" void lb_sub_opts_default(lb_sub_opts *o) {
   o->newton_steptol = 1e-15;
   o->poll_every = 32;
   o->newton_phi = 0;
+  o->newton_direct = 0;
 }
 
 extern "C" void lb_tr_opts_default(lb_tr_opts *o) {
@@ -1096,6 +1050,7 @@ extern "C" int lb_tr_subproblem(lb_plan *P, const lb_params *params, const doubl
   info->gnorm = gnorm;
   info->iters = so.iters;
   info->newton_iters = so.newton;
+  info->newton_direct = so.newton_direct;
   info->status = so.status;
   return so.status;
 }

@@ -43,6 +43,7 @@ class LbSubOpts(C.Structure):
         ("newton_steptol", C.c_double),
         ("poll_every", C.c_int),
         ("newton_phi", C.c_int),
+        ("newton_direct", C.c_int),
     ]
 
 
@@ -54,6 +55,7 @@ class LbSubInfo(C.Structure):
         ("gnorm", C.c_double),
         ("iters", C.c_int),
         ("newton_iters", C.c_int),
+        ("newton_direct", C.c_int),
         ("status", C.c_int),
     ]
 

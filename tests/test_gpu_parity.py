@@ -175,9 +175,12 @@ def test_tr_subproblem_matches_oracle(shape, box, tau, r, amp, precision):
 
 
 @pytest.mark.parametrize("newton_phi", [0, 1])
-def test_tr_subproblem_newton_forms_agree(newton_phi):
-    """Both Newton forms for lambda (on phi, as printed, and on 1/sqrt(phi)) reach
-    the oracle's multiplier and iterate; the printed form also its iteration count."""
+@pytest.mark.parametrize("newton_direct", [0, 1])
+def test_tr_subproblem_newton_forms_agree(newton_phi, newton_direct):
+    """Both Newton forms for lambda (on phi, as printed, and on 1/sqrt(phi)),
+    with phi evaluated by full spectral sums (as printed) or by the power-sum
+    series, reach the oracle's multiplier and iterate; the printed form also
+    its Newton step count."""
     shape, box = (16, 16), (2 * math.pi, 2 * math.pi)
     m = model_for(shape, box, -0.15, 0.25)
     psi = I.zero_mean_noise(shape, 0.2, 21)
@@ -185,7 +188,9 @@ def test_tr_subproblem_newton_forms_agree(newton_phi):
     r = 0.05
     ref = O.imex_subproblem(m, psi, g_hat, r, O.SubOpts(eta=0.1, eps_sub=1e-10, max_inner=20000))
     plan = lb.Plan(shape, box)
-    d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), r, lb.sub_opts(eps_sub=1e-10, max_inner=20000, newton_phi=newton_phi))
+    opts = lb.sub_opts(eps_sub=1e-10, max_inner=20000, newton_phi=newton_phi, newton_direct=newton_direct)
+    d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), r, opts)
+    print(f"iters {info.iters} newton {info.newton_iters} direct evaluations {info.newton_direct}")
     assert rc == lb.LB_OK and abs(info.iters - ref.iters) <= 1
     assert abs(info.lambda_ - ref.lam) <= 1e-9 * max(1.0, ref.lam)
     assert np.max(np.abs(host(d) - O.inv(ref.d))) < 1e-9 * np.max(np.abs(O.inv(ref.d)))
@@ -193,6 +198,10 @@ def test_tr_subproblem_newton_forms_agree(newton_phi):
         assert abs(info.newton_iters - ref.newton_iters) <= max(2, 0.01 * ref.newton_iters)
     else:
         assert info.newton_iters < ref.newton_iters
+    if newton_direct:
+        assert info.newton_direct >= info.newton_iters  # every evaluation summed over the spectrum
+    elif not newton_phi:
+        assert info.newton_direct <= max(10, 0.01 * info.iters)  # the series serves the warm-started steps
 
 
 def test_tr_subproblem_global_minimiser_dense():

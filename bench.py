@@ -33,20 +33,25 @@ TOL = 1e-8
 LANCZOS_STEPS = 60
 
 
-def kernel_bytes(name: str, prec: str, N: int, nh: int) -> float | None:
+def kernel_bytes(name: str, prec: str, n) -> float | None:
     """Compulsory bytes one launch of a hot-path kernel must move (each array it
-    reads or writes, once), for one 128^3 instance. c = complex size, r = real."""
+    reads or writes, once), for one instance. c = complex size, r = real."""
     c = 16 if prec == "fp64" else 8
     r = 8 if prec == "fp64" else 4
+    N = math.prod(n)
+    nh = N // n[-1] * (n[-1] // 2 + 1)
+    npair = (n[0] // 2 + 1) * (nh // n[0])  # (|k0|, column) pair sums, FP64
     table = {
-        "col0_fwd_update": nh * (4 * c + 8),  # read T d, b_prev, g; write b_next; write w|b|^2 (FP64)
-        "col0_inv_scale_d": nh * 2 * c,  # read b_prev, write partial transform
+        # read T d, b_prev, g; write b_next and the pair sums of w|b|^2
+        "col0_fwd_update": nh * 4 * c + npair * 8,
+        "col0_inv_scale_d": nh * 2 * c,  # read b_prev, write the partial transform
+        # read/write the partial transform, read Gamma' (one plane per workgroup)
+        "plane_inner": nh * 2 * c + N * r,
+        "rows_inner": nh * 2 * c + N * r,
         "col1_inv": nh * 2 * c,
         "col1_fwd": nh * 2 * c,
         "col0_inv": nh * 2 * c,
         "col0_fwd": nh * 2 * c,
-        "rows_inner": nh * 2 * c + N * r,  # read/write the partial transform, read Gamma'
-        "bins": nh * (8 + 4),  # w|b|^2 gathered through the shell permutation
     }
     return table.get(name)
 
@@ -123,6 +128,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--kernel-sample", type=int, default=0, metavar="K",
+                    help="only run K iterations of Algorithm 3 on the workload (for counter collection) and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (scales HBM counters) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -135,10 +144,17 @@ def main():
     from paper_2603_03933_amd import lb
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"kernel": "torch.neg float64", "read_bytes": 8 << 27, "write_bytes": 8 << 27, "launches": 5}}))
+        return
     inst = I.bcc_3d(args.size)
     n, box = inst.grid.n, inst.grid.box
     N = inst.grid.N
-    nh = n[0] * n[1] * (n[2] // 2 + 1)
     prm = lb.Params(inst.params.tau, inst.params.gamma)
     psi0 = torch.from_numpy(inst.psi0).to(dev)
     v0 = torch.from_numpy(I.hessvec_direction(n, 2)).to(dev)
@@ -152,12 +168,19 @@ def main():
         ritz, res = p.lb_lanczos_min(prm, psi, v0, LANCZOS_STEPS, precond_shift=1.0)
         return info, rc, ritz, res
 
+    if args.kernel_sample:
+        E, g = plan.lb_energy_grad(prm, psi0)
+        d, sinfo, src = plan.lb_tr_subproblem(prm, psi0, g, 1.0, lb.sub_opts(eta=0.0132, max_inner=args.kernel_sample))
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_sample": {"iterations": sinfo.iters, "workload": f"bcc_3d {n[0]}^3 FP64, Algorithm 3 at psi0, r = 1"}}))
+        return
+
     # warmup, with every kernel timed to find the dominant one
     plan.lb_plan_set_timing(True, "")
     for _ in range(max(1, args.warmup)):
         info, rc, ritz, res = step(plan, opts)
     warm = plan.timings()
-    dominant = max((k for k in warm if kernel_bytes(k, "fp64", N, nh) is not None), key=lambda k: warm[k][1])
+    dominant = max((k for k in warm if kernel_bytes(k, "fp64", n) is not None), key=lambda k: warm[k][1])
     total_ms = sum(v[1] for v in warm.values())
 
     # timed steps: events only around the dominant kernel
@@ -175,7 +198,7 @@ def main():
     info, rc, ritz, res = infos[-1]
     launches, dom_ms = tm.get(dominant, (0, 0.0))
     avg_s = dom_ms / max(1, launches) * 1e-3
-    alg = kernel_bytes(dominant, "fp64", N, nh)
+    alg = kernel_bytes(dominant, "fp64", n)
     achieved = alg / avg_s / 1e9 if avg_s > 0 else None
     roofline = {
         "kernel": dominant,

@@ -63,6 +63,26 @@ constexpr int span_before(int N, int p) {  // product of the radices of passes <
   for (int i = 0; i < p; ++i) s *= radix_at(N, i);
   return s;
 }
+// Radix plan 1: a first pass of radix 16 when 16 divides N, then plan 0
+// (two passes for N = 128 instead of three; used where data lives in LDS).
+template <int PLAN> constexpr int radix_p(int N, int p) {
+  if constexpr (PLAN == 0) {
+    return radix_at(N, p);
+  } else {
+    if (N % 16 == 0 && N > 16) return p == 0 ? 16 : radix_at(N / 16, p - 1);
+    return radix_at(N, p);
+  }
+}
+template <int PLAN> constexpr int npass_p(int N) {
+  int p = 0;
+  while (radix_p<PLAN>(N, p) != 0) ++p;
+  return p;
+}
+template <int PLAN> constexpr int span_p(int N, int p) {
+  int s = 1;
+  for (int i = 0; i < p; ++i) s *= radix_p<PLAN>(N, i);
+  return s;
+}
 constexpr bool supported_length(int N) {
   if (N < 2) return false;
   int n = N;
@@ -136,11 +156,51 @@ template <typename T, bool INV> __device__ __forceinline__ void dft3(c2<T> *v) {
   v[2] = csub(m, iu);
 }
 
+// 16 points as 4 x 4: length-4 DFTs over the samples n2 + 4 n1 (index k1),
+// twiddles w^(n2 k1) with w = exp(-+ 2 pi i / 16), then length-4 DFTs over n2
+// giving X_{k1 + 4 k2}.
+template <typename T, bool INV> __device__ __forceinline__ void dft16(c2<T> *v) {
+  c2<T> y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    y[n2][0] = v[n2];
+    y[n2][1] = v[n2 + 4];
+    y[n2][2] = v[n2 + 8];
+    y[n2][3] = v[n2 + 12];
+    dft4<T, INV>(y[n2]);
+  }
+  const T c = T(0.92387953251128675612818318939678829);  // cos(pi / 8)
+  const T s = T(0.38268343236508977172845998403039887);  // sin(pi / 8)
+  const T h = T(0.70710678118654752440084436210484904);
+  const T sg = INV ? T(1) : T(-1);  // sign of the imaginary parts of w^m
+  // w^m for m = n2 k1 in {1, 2, 3, 4, 6, 9}
+  const c2<T> w1{c, sg * s}, w2{h, sg * h}, w3{s, sg * c}, w6{-h, sg * h}, w9{-c, -sg * s};
+  y[1][1] = cmul(y[1][1], w1);
+  y[1][2] = cmul(y[1][2], w2);
+  y[1][3] = cmul(y[1][3], w3);
+  y[2][1] = cmul(y[2][1], w2);
+  y[2][2] = mul_mi<INV>(y[2][2]);  // w^4
+  y[2][3] = cmul(y[2][3], w6);
+  y[3][1] = cmul(y[3][1], w3);
+  y[3][2] = cmul(y[3][2], w6);
+  y[3][3] = cmul(y[3][3], w9);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    c2<T> b[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    dft4<T, INV>(b);
+    v[k1] = b[0];
+    v[k1 + 4] = b[1];
+    v[k1 + 8] = b[2];
+    v[k1 + 12] = b[3];
+  }
+}
+
 template <typename T, int R, bool INV> __device__ __forceinline__ void dft(c2<T> *v) {
   if constexpr (R == 2) dft2<T, INV>(v);
   else if constexpr (R == 3) dft3<T, INV>(v);
   else if constexpr (R == 4) dft4<T, INV>(v);
-  else dft8<T, INV>(v);
+  else if constexpr (R == 8) dft8<T, INV>(v);
+  else dft16<T, INV>(v);
 }
 
 // ---------------------------------------------------------------------------

@@ -793,101 +793,175 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T
 // ---------------------------------------------------------------------------
 template <typename T, int N> struct PlaneCfg {
   static constexpr int NH = N / 2 + 1;
-  static constexpr bool fits = (long)N * NH * sizeof(c2<T>) <= 160 * 1024;
-  static constexpr int NT = N >= 96 ? 1024 : (N >= 48 ? 512 : 256);
+  // the plane must fit in LDS, and the butterflies plus the prefetched Gamma'
+  // in registers (beyond N = 128 they spill)
+  static constexpr bool fits = (long)N * NH * sizeof(c2<T>) <= 160 * 1024 && N <= 128;
+  // FP64 butterflies need the registers of 512 threads; FP32 fits 1024
+  static constexpr int NT = sizeof(T) == 8 ? (N >= 48 ? 512 : 256) : (N >= 96 ? 1024 : (N >= 48 ? 512 : 256));
 };
 
-// half rows (2p, 2p+1) of the plane -> Z_p = A + i B over the full row length, in place
-template <typename T, int N, int NT> __device__ __forceinline__ void plane_pack(c2<T> *P) {
+// One Stockham pass (radix plan 1) over NXF transforms of length N. Butterfly
+// inputs come from load(f, e), outputs go to store(f, e, v, k, r) (k, r: the
+// thread's butterfly slot and output, for per-output data held in registers).
+// FAST puts consecutive threads on consecutive transforms, else on consecutive
+// butterflies of one transform. MID: barrier between all loads and all stores
+// (the pass updates one LDS buffer in place).
+template <typename T, int N, bool INV, int NT, int NXF, bool FAST, int P> struct PassShape {
+  static constexpr int R = lbfft::radix_p<1>(N, P);
+  static constexpr int NS = lbfft::span_p<1>(N, P);
+  static constexpr int NB = N / R;
+  static constexpr int TOT = NXF * NB;
+  static constexpr int K = (TOT + NT - 1) / NT;
+  __device__ static int f_of(int bi) { return FAST ? bi % NXF : bi / NB; }
+  __device__ static int j_of(int bi) { return FAST ? bi / NXF : bi % NB; }
+};
+template <typename T, int N, bool INV, int NT, int NXF, bool FAST, int P, bool MID, class Load, class Store>
+__device__ __forceinline__ void sk_pass(const c2<T> *__restrict__ tw, const Load &load, const Store &store) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1;
-  constexpr int TOT = (N / 2) * NH;
-  constexpr int K = (TOT + NT - 1) / NT;
-  C a[K], bb[K];
+  using S = PassShape<T, N, INV, NT, NXF, FAST, P>;
+  constexpr int R = S::R, NS = S::NS, NB = S::NB, K = S::K;
+  C v[K][R];
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < TOT) {
-      const int pr = i / NH, k = i - pr * NH;
-      a[q] = P[2 * pr * NH + k];
-      bb[q] = P[(2 * pr + 1) * NH + k];
+  for (int k = 0; k < K; ++k) {
+    const int bi = threadIdx.x + k * NT;
+    if (bi < S::TOT) {
+      const int f = S::f_of(bi), j = S::j_of(bi);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k][r] = load(f, j + r * NB);
     }
   }
-  __syncthreads();
+  if constexpr (MID) __syncthreads();
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < TOT) {
-      const int pr = i / NH, k = i - pr * NH;
-      C A = a[q], B = bb[q];
-      if (k == 0 || 2 * k == N) {
-        A.y = T(0);
-        B.y = T(0);
+  for (int k = 0; k < K; ++k) {
+    const int bi = threadIdx.x + k * NT;
+    if (bi < S::TOT) {
+      const int f = S::f_of(bi), j = S::j_of(bi);
+      const int kk = j % NS;
+      if constexpr (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[r * kk * (N / (NS * R))];
+          if constexpr (INV) w.y = -w.y;
+          v[k][r] = cmul(v[k][r], w);
+        }
       }
-      P[2 * pr * NH + k] = C{A.x - B.y, A.y + B.x};
-      if (k > 0 && 2 * k < N) P[2 * pr * NH + N - k] = C{A.x + B.y, B.x - A.y};
+      dft<T, R, INV>(v[k]);
+      const int base = (j / NS) * NS * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(f, base + r * NS, v[k][r], k, r);
     }
   }
-  __syncthreads();
+}
+// LDS-to-LDS passes P .. PE - 1 of NXF transforms at buf[f * fs + e * es]
+template <typename T, int N, bool INV, int NT, int NXF, bool FAST, int P, int PE>
+__device__ __forceinline__ void sk_lds_passes(c2<T> *buf, int fs, int es, const c2<T> *__restrict__ tw) {
+  if constexpr (P < PE) {
+    using C = c2<T>;
+    sk_pass<T, N, INV, NT, NXF, FAST, P, true>(
+        tw, [&](int f, int e) -> C { return buf[f * fs + e * es]; },
+        [&](int f, int e, C v, int, int) { buf[f * fs + e * es] = v; });
+    __syncthreads();
+    sk_lds_passes<T, N, INV, NT, NXF, FAST, P + 1, PE>(buf, fs, es, tw);
+  }
 }
 
-// Z_p -> half rows (2p, 2p+1), in place
-template <typename T, int N, int NT> __device__ __forceinline__ void plane_unpack(c2<T> *P) {
+// Axes 1 and 2 of the inner iteration for one plane of fixed k0 (the
+// half-spectrum plane, N x (N/2 + 1), held in LDS):
+//   inverse along axis 1 (columns, read straight from memory), inverse real
+//   transforms of the rows (two real rows packed as one complex row of length
+//   N), multiply by Gamma', forward real transforms of the rows, forward along
+//   axis 1 (written straight to memory). The packing is folded into the first
+//   row pass's loads, Gamma' into the last inverse row pass's stores and the
+//   unpacking into the first forward column pass's loads.
+template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
+                                                    c2<T> *data, const T *__restrict__ gp, const SubState *st) {
   using C = c2<T>;
   constexpr int NH = N / 2 + 1;
-  constexpr int TOT = (N / 2) * NH;
-  constexpr int K = (TOT + NT - 1) / NT;
-  C a[K], bb[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < TOT) {
-      const int pr = i / NH, k = i - pr * NH;
-      const C zk = P[2 * pr * NH + k], zm = P[2 * pr * NH + ((N - k) % N)];
-      a[q] = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-      bb[q] = C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)};
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    const int i = threadIdx.x + q * NT;
-    if (i < TOT) {
-      const int pr = i / NH, k = i - pr * NH;
-      P[2 * pr * NH + k] = a[q];
-      P[(2 * pr + 1) * NH + k] = bb[q];
-    }
-  }
-  __syncthreads();
-}
-
-template <typename T, int N>
-__global__ __launch_bounds__((PlaneCfg<T, N>::NT)) void k_plane_inner(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
-                                                                  c2<T> *data, const T *__restrict__ gp,
-                                                                  const SubState *st) {
-  using C = c2<T>;
-  constexpr int NH = N / 2 + 1;
-  constexpr int NT = PlaneCfg<T, N>::NT;
-  __shared__ C P[N * NH];
+  constexpr int NP = lbfft::npass_p<1>(N);
+  constexpr int NR = N / 2;  // packed rows
+  __shared__ C L[N * NH];    // element (row e, column k) at L[e * NH + k]
   if (st && st->done) return;
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
   C *plane = data + b * nh + (long)i0 * (N * NH);
   const T *g = gp + b * Np + (long)i0 * (N * N);
-  for (int i = threadIdx.x; i < N * NH; i += NT) P[i] = plane[i];
-  __syncthreads();
-  fft_lds_batch<T, N, true, NT, NH, true>(P, 1, NH, tw);  // axis 1, inverse
-  plane_pack<T, N, NT>(P);
-  fft_lds_batch<T, N, true, NT, N / 2, false>(P, 2 * NH, 1, tw);  // rows, inverse
-  for (int i = threadIdx.x; i < (N / 2) * N; i += NT) {
-    const int pr = i / N, e = i - pr * N;
-    const C z = P[2 * pr * NH + e];
-    P[2 * pr * NH + e] = C{z.x * g[(2 * pr) * N + e], z.y * g[(2 * pr + 1) * N + e]};
+  auto lds_load_col = [&](int f, int e) -> C { return L[e * NH + f]; };
+  auto lds_store_col = [&](int f, int e, C v, int, int) { L[e * NH + f] = v; };
+  auto lds_load_row = [&](int f, int e) -> C { return L[f * 2 * NH + e]; };
+  auto lds_store_row = [&](int f, int e, C v, int, int) { L[f * 2 * NH + e] = v; };
+
+  // axis 1, inverse: first pass from memory
+  if constexpr (NP == 1) {
+    sk_pass<T, N, true, NT, NH, true, 0, false>(
+        tw, [&](int f, int e) -> C { return plane[e * NH + f]; }, lds_store_col);
+  } else {
+    sk_pass<T, N, true, NT, NH, true, 0, false>(
+        tw, [&](int f, int e) -> C { return plane[e * NH + f]; }, lds_store_col);
+    __syncthreads();
+    sk_lds_passes<T, N, true, NT, NH, true, 1, NP>(L, 1, NH, tw);
   }
   __syncthreads();
-  fft_lds_batch<T, N, false, NT, N / 2, false>(P, 2 * NH, 1, tw);  // rows, forward
-  plane_unpack<T, N, NT>(P);
-  fft_lds_batch<T, N, false, NT, NH, true>(P, 1, NH, tw);  // axis 1, forward
-  for (int i = threadIdx.x; i < N * NH; i += NT) plane[i] = P[i];
+
+  // rows, inverse. Packed row p: Z_p = A + i B from half rows 2p (A), 2p+1 (B).
+  auto packed = [&](int p, int e) -> C {
+    const bool lo = 2 * e <= N;
+    const int k = lo ? e : N - e;
+    C A = L[2 * p * NH + k], B = L[(2 * p + 1) * NH + k];
+    if (k == 0 || 2 * k == N) {
+      A.y = T(0);
+      B.y = T(0);
+    }
+    return lo ? C{A.x - B.y, A.y + B.x} : C{A.x + B.y, B.x - A.y};
+  };
+  // last inverse row pass: consecutive threads on consecutive outputs of one
+  // row, so the Gamma' loads are coalesced; they are issued before the first
+  // row pass and held in registers
+  using LastS = PassShape<T, N, true, NT, NR, false, NP - 1>;
+  T g0[LastS::K][LastS::R], g1[LastS::K][LastS::R];
+#pragma unroll
+  for (int k = 0; k < LastS::K; ++k) {
+    const int bi = threadIdx.x + k * NT;
+    if (bi < LastS::TOT) {
+      const int f = LastS::f_of(bi), j = LastS::j_of(bi);
+#pragma unroll
+      for (int r = 0; r < LastS::R; ++r) {
+        const int e = j + r * LastS::NS;  // last pass: outputs j + r NS
+        g0[k][r] = g[(2 * f) * N + e];
+        g1[k][r] = g[(2 * f + 1) * N + e];
+      }
+    }
+  }
+  auto store_mul = [&](int f, int e, C v, int k, int r) { L[f * 2 * NH + e] = C{v.x * g0[k][r], v.y * g1[k][r]}; };
+  if constexpr (NP == 1) {
+    sk_pass<T, N, true, NT, NR, false, 0, true>(tw, packed, store_mul);
+  } else {
+    sk_pass<T, N, true, NT, NR, true, 0, true>(tw, packed, lds_store_row);
+    __syncthreads();
+    sk_lds_passes<T, N, true, NT, NR, true, 1, NP - 1>(L, 2 * NH, 1, tw);
+    sk_pass<T, N, true, NT, NR, false, NP - 1, true>(tw, lds_load_row, store_mul);
+  }
+  __syncthreads();
+
+  // rows, forward
+  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, 2 * NH, 1, tw);
+
+  // axis 1, forward: the first pass unpacks Z_p into half rows 2p, 2p+1; the
+  // last pass writes to memory
+  auto unpacked = [&](int k, int e) -> C {
+    const int p = e >> 1;
+    const C zk = L[2 * p * NH + k], zm = L[2 * p * NH + ((N - k) % N)];
+    return (e & 1) ? C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)}
+                   : C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+  };
+  auto store_mem = [&](int f, int e, C v, int, int) { plane[e * NH + f] = v; };
+  if constexpr (NP == 1) {
+    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_mem);
+  } else {
+    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, lds_store_col);
+    __syncthreads();
+    sk_lds_passes<T, N, false, NT, NH, true, 1, NP - 1>(L, 1, NH, tw);
+    sk_pass<T, N, false, NT, NH, true, NP - 1, false>(tw, lds_load_col, store_mem);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -2,7 +2,23 @@
 // in its own translation unit (inst.hip with -DLB_N=N) into an NFuncs table
 // for FP64 and FP32; the library picks tables by axis length at run time.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "kernels.hpp"
+
+namespace lb {
+// Start/stop events of the enclosing timed scope (null when none). The next
+// LB_LAUNCH consumes them: the runtime then records the kernel's own start and
+// end, so the measured interval excludes launch gaps.
+extern thread_local hipEvent_t kt_ev[2];
+}  // namespace lb
+
+#define LB_LAUNCH(K, G, B, SH, S, ...)                                \
+  do {                                                                \
+    hipEvent_t lb_e0_ = ::lb::kt_ev[0], lb_e1_ = ::lb::kt_ev[1];     \
+    ::lb::kt_ev[0] = ::lb::kt_ev[1] = nullptr;                        \
+    hipExtLaunchKernelGGL(K, G, B, SH, S, lb_e0_, lb_e1_, 0, __VA_ARGS__); \
+  } while (0)
 
 namespace lb {
 using lbk::ColGeo;
@@ -63,10 +79,10 @@ template <typename T, int N> struct Impl {
   static void cols_plain(const PassArgs &a, bool inv) {
     lbk::OpPlain<T> op{(const C2 *)a.in, (C2 *)a.out, T(a.scale), a.zero_dc, a.g.nh, a.st};
     if (inv)
-      hipLaunchKernelGGL((lbk::k_cols<T, N, true, lbk::OpPlain<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+      LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpPlain<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                          (const C2 *)a.tw, op);
     else
-      hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpPlain<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+      LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpPlain<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                          (const C2 *)a.tw, op);
   }
   static void cols_inv_scale_d(const PassArgs &a) {
@@ -78,7 +94,7 @@ template <typename T, int N> struct Impl {
     op.out = (C2 *)a.out;
     op.st = a.st;
     op.t = a.step;
-    hipLaunchKernelGGL((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                        (const C2 *)a.tw, op);
   }
   static void cols_fwd_update(const PassArgs &a) {
@@ -96,7 +112,7 @@ template <typename T, int N> struct Impl {
     op.inv_n = a.inv_n;
     op.cpi = a.cg.cpi;
     op.t = a.step;
-    hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                        (const C2 *)a.tw, op);
   }
   static void cols_fwd_hess(const PassArgs &a) {
@@ -108,45 +124,45 @@ template <typename T, int N> struct Impl {
     op.out = (C2 *)a.out;
     op.inv_n = a.inv_n;
     op.shift = a.shift;
-    hipLaunchKernelGGL((lbk::k_cols<T, N, false, lbk::OpFwdHess<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdHess<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                        (const C2 *)a.tw, op);
   }
   static void cols_fwd_mul_inv(const PassArgs &a) {
-    hipLaunchKernelGGL((lbk::k_cols_fwd_mul_inv<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
+    LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
                        (const C2 *)a.tw, (C2 *)a.out, a.inv_n);
   }
   static void rows_r2c(const PassArgs &a, int mode) {
     if (mode == 1)
-      hipLaunchKernelGGL((lbk::k_rows_r2c<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+      LB_LAUNCH((lbk::k_rows_r2c<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
                          (const C2 *)a.tw, (const double *)a.in, a.psi, (C2 *)a.out, a.partial);
     else
-      hipLaunchKernelGGL((lbk::k_rows_r2c<T, N, 0>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+      LB_LAUNCH((lbk::k_rows_r2c<T, N, 0>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
                          (const C2 *)a.tw, (const double *)a.in, a.psi, (C2 *)a.out, a.partial);
   }
   static void rows_c2r(const PassArgs &a, int mode) {
     if (mode == 1)
-      hipLaunchKernelGGL((lbk::k_rows_c2r<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+      LB_LAUNCH((lbk::k_rows_c2r<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
                          (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
     else if (mode == 2)
-      hipLaunchKernelGGL((lbk::k_rows_c2r<T, N, 2>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+      LB_LAUNCH((lbk::k_rows_c2r<T, N, 2>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
                          (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
     else
-      hipLaunchKernelGGL((lbk::k_rows_c2r<T, N, 0>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+      LB_LAUNCH((lbk::k_rows_c2r<T, N, 0>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
                          (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
   }
   static void rows_inner(const PassArgs &a) {
-    hipLaunchKernelGGL((lbk::k_rows_inner<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, (const C2 *)a.tw,
+    LB_LAUNCH((lbk::k_rows_inner<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, (const C2 *)a.tw,
                        (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
   }
   static void rows_energy(const PassArgs &a) {
     if constexpr (std::is_same<T, double>::value)
-      hipLaunchKernelGGL((lbk::k_rows_energy<N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
+      LB_LAUNCH((lbk::k_rows_energy<N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
                          (const double2 *)a.tw, a.psi, (double2 *)a.out, (double2 *)a.out2, a.gp64, a.gp32, a.partial);
   }
 
   static void plane_inner(const PassArgs &a, int n0) {
     if constexpr (lbk::PlaneCfg<T, N>::fits)
-      hipLaunchKernelGGL((lbk::k_plane_inner<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream,
+      LB_LAUNCH((lbk::k_plane_inner<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream,
                          n0, a.g.nh, a.g.N, (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
   }
 

@@ -223,6 +223,12 @@ static void timing_flush(lb_plan *P) {
   }
   P->timing.pending.clear();
 }
+namespace lb {
+thread_local hipEvent_t kt_ev[2] = {nullptr, nullptr};
+}
+using lb::kt_ev;
+
+// Times the first LB_LAUNCH in its scope when timing is on for `name`.
 struct KT {
   lb_plan *P;
   int idx = -1;
@@ -239,14 +245,22 @@ struct KT {
     a = timing_event(P);
     b = timing_event(P);
     if (!a || !b) {
+      if (a) P->timing.pool.push_back(a);
+      if (b) P->timing.pool.push_back(b);
       idx = -1;
       return;
     }
-    (void)hipEventRecord(a, P->stream);
+    kt_ev[0] = a;
+    kt_ev[1] = b;
   }
   ~KT() {
     if (idx < 0) return;
-    (void)hipEventRecord(b, P->stream);
+    if (kt_ev[0] == a) {  // no launch in the scope
+      kt_ev[0] = kt_ev[1] = nullptr;
+      P->timing.pool.push_back(a);
+      P->timing.pool.push_back(b);
+      return;
+    }
     P->timing.pending.push_back(PendingTiming{a, b, idx});
     if (P->timing.pending.size() > 4096) timing_flush(P);
   }
@@ -502,7 +516,7 @@ static int check_launch(const char *what) {
 static void finalize(lb_plan *P, const double *partial, int bpi, int nq, unsigned maxmask, int batch, double *out) {
   {
     KT kt_(P, "finalize");
-    hipLaunchKernelGGL(lbk::k_finalize, dim3(batch), dim3(256), 0, P->stream, partial, bpi, nq, maxmask, out);
+    LB_LAUNCH(lbk::k_finalize, dim3(batch), dim3(256), 0, P->stream, partial, bpi, nq, maxmask, out);
   }
 }
 static int read_sums(lb_plan *P, const double *dev, int count) {
@@ -580,7 +594,7 @@ static void spec_reduce(lb_plan *P, int batch, const Prm &p, const void *a, cons
   const int bpi = (int)bpi_ew(P);
   {
     KT kt_(P, "spec_reduce");
-    hipLaunchKernelGGL((lbk::k_spec_reduce<TA, MODE>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream, geo(P, batch), p,
+    LB_LAUNCH((lbk::k_spec_reduce<TA, MODE>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream, geo(P, batch), p,
                        bpi, (const lbfft::c2<TA> *)a, (const lbfft::c2<TA> *)b, P->partial);
   }
   finalize(P, P->partial, bpi, 1, 0u, batch, out_dev);
@@ -602,7 +616,7 @@ static void lincomb64(lb_plan *P, long n, double alpha, const double2 *x, double
   const long nb = std::min<long>(cdiv(n, lbk::EW_NT), 4096);
   {
     KT kt_(P, "lincomb");
-    hipLaunchKernelGGL((lbk::k_lincomb<double, double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, n, alpha, x,
+    LB_LAUNCH((lbk::k_lincomb<double, double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, n, alpha, x,
                        beta, y, out);
   }
 }
@@ -650,14 +664,14 @@ static void energy_grad_core(lb_plan *P, int batch, const Prm &p, const double *
   if (P->prec == LB_FP64)
     {
       KT kt_(P, "grad_assemble");
-      hipLaunchKernelGGL((lbk::k_grad_assemble<double>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
+      LB_LAUNCH((lbk::k_grad_assemble<double>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
                          geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
                          P->GH, (double2 *)nullptr, part2);
     }
   else
     {
       KT kt_(P, "grad_assemble");
-      hipLaunchKernelGGL((lbk::k_grad_assemble<float>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
+      LB_LAUNCH((lbk::k_grad_assemble<float>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
                          geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
                          P->GH, (float2 *)P->GHT, part2);
     }
@@ -672,7 +686,7 @@ extern "C" int lb_energy_grad(lb_plan *P, const lb_params *params, const double 
   energy_grad_core(P, B, p, psi);
   {
     KT kt_(P, "energy_out");
-    hipLaunchKernelGGL(lbk::k_energy_out, dim3(1), dim3(64), 0, P->stream, (const double *)(P->sums + 32), 3,
+    LB_LAUNCH(lbk::k_energy_out, dim3(1), dim3(64), 0, P->stream, (const double *)(P->sums + 32), 3,
                        (const double *)P->sums, 2, 1.0 / (double)P->N, B, energy);
   }
   if (grad) inv_c2r(P, LB_FP64, B, p, P->GH, P->W64, grad, 0, nullptr, nullptr);
@@ -864,7 +878,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   }
   {
     KT kt_(P, "newton");
-    hipLaunchKernelGGL(lbk::k_newton, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom, u.cg.bpi,
+    LB_LAUNCH(lbk::k_newton, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom, u.cg.bpi,
                        (const double *)P->partial, u.cg.bpi, (const double *)P->bsq, (int)P->npair, P->st, t);
   }
 }
@@ -880,26 +894,26 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
     if (prec == LB_FP64)
       {
         KT kt_(P, "init_b");
-        hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
+        LB_LAUNCH((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
                            o.eta, (double2 *)P->B1);
       }
     else
       {
         KT kt_(P, "init_b");
-        hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
+        LB_LAUNCH((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
                            o.eta, (float2 *)P->B1);
       }
   } else {
     if (prec == LB_FP64)
       {
         KT kt_(P, "init_b");
-        hipLaunchKernelGGL((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+        LB_LAUNCH((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
                            (const double2 *)P->GH, -r / gnorm, o.eta, (double2 *)P->B1);
       }
     else
       {
         KT kt_(P, "init_b");
-        hipLaunchKernelGGL((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+        LB_LAUNCH((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
                            (const double2 *)P->GH, -r / gnorm, o.eta, (float2 *)P->B1);
       }
   }
@@ -939,13 +953,13 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   if (prec == LB_FP64)
     {
       KT kt_(P, "final_d");
-      hipLaunchKernelGGL((lbk::k_final_d<double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
+      LB_LAUNCH((lbk::k_final_d<double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
                          (const double2 *)P->B0, (const double2 *)P->B1, (const SubState *)P->st, P->SH);
     }
   else
     {
       KT kt_(P, "final_d");
-      hipLaunchKernelGGL((lbk::k_final_d<float>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, (const float2 *)P->B0,
+      LB_LAUNCH((lbk::k_final_d<float>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, (const float2 *)P->B0,
                          (const float2 *)P->B1, (const SubState *)P->st, P->SH);
     }
   double dd = 0.0;
@@ -1019,14 +1033,14 @@ extern "C" int lb_tr_subproblem(lb_plan *P, const lb_params *params, const doubl
   LB_TRY(pack_params(P, params, 1, &p));
   {
     KT kt_(P, "gamma_p");
-    hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+    LB_LAUNCH(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
                        P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
   }
   fwd_r2c(P, LB_FP64, 1, p, grad, P->GH, 1);
   if (P->prec == LB_FP32)
     {
       KT kt_(P, "lincomb");
-      hipLaunchKernelGGL((lbk::k_lincomb<float, double, double>), dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)),
+      LB_LAUNCH((lbk::k_lincomb<float, double, double>), dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)),
                          dim3(lbk::EW_NT), 0, P->stream, P->nh, 1.0, (const double2 *)P->GH, 0.0, (const double2 *)nullptr,
                          (float2 *)P->GHT);
     }
@@ -1094,7 +1108,7 @@ extern "C" int lb_shifted_solve(lb_plan *P, const lb_params *params, const doubl
   LB_TRY(pack_params(P, params, 1, &p));
   {
     KT kt_(P, "gamma_p");
-    hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+    LB_LAUNCH(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
                        P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
   }
   fwd_r2c(P, LB_FP64, 1, p, grad, P->GH, 1);
@@ -1146,7 +1160,7 @@ static void jacobi_eig(int m, std::vector<double> &A, std::vector<double> &V) {
 
 static void prec_scale(lb_plan *P, const Prm &p, const double2 *x, double c, double2 *out) {
   KT kt_(P, "prec_scale");
-  hipLaunchKernelGGL(lbk::k_prec_scale, dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+  LB_LAUNCH(lbk::k_prec_scale, dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
                      P->stream, geo(P, 1), p, x, c, out);
 }
 
@@ -1237,7 +1251,7 @@ extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double 
   LB_TRY(pack_params(P, params, 1, &p));
   {
     KT kt_(P, "gamma_p");
-    hipLaunchKernelGGL(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+    LB_LAUNCH(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
                        P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
   }
   fwd_r2c(P, LB_FP64, 1, p, v0, P->R, 1);
@@ -1272,7 +1286,7 @@ static int energy_at_trial(lb_plan *P, const Prm &p, const double *psi, double *
   const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
   {
     KT kt_(P, "add_real");
-    hipLaunchKernelGGL(lbk::k_add_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, psi, (const double *)P->sphys,
+    LB_LAUNCH(lbk::k_add_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, psi, (const double *)P->sphys,
                        P->ptrial);
   }
   PassArgs r = args_rows(P, LB_FP64, 1, p, false);
@@ -1368,7 +1382,7 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
       const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
       {
         KT kt_(P, "axpy_real");
-        hipLaunchKernelGGL(lbk::k_axpy_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, 1.0, (const double *)P->sphys,
+        LB_LAUNCH(lbk::k_axpy_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, 1.0, (const double *)P->sphys,
                            psi);
       }
       nu = std::max(nu, o.gamma_e * sn);

@@ -214,24 +214,30 @@ def main():
         "share_of_kernel_time": warm[dominant][1] / total_ms if total_ms else None,
     }
 
-    # Hessian-vector products/s (lb_hessvec, projected) in FP64 and FP32
-    def hv_rate(precision):
-        p = plan if precision == "fp64" else lb.Plan(n, box, precision=precision)
-        out = torch.empty_like(psi0)
+    # Hessian-vector products/s (lb_hessvec, projected) in FP64 and FP32, one
+    # field per call and a batch of 8 fields per call (aggregate products/s)
+    v_dev = v0.contiguous()
+
+    def hv_rate(precision, batch=1):
+        p = plan if (precision == "fp64" and batch == 1) else lb.Plan(n, box, batch=batch, precision=precision)
+        ps = psi0 if batch == 1 else psi0.expand(batch, *psi0.shape).contiguous()
+        vv = v_dev if batch == 1 else v_dev.expand(batch, *v_dev.shape).contiguous()
+        out = torch.empty_like(vv)
         for _ in range(5):
-            p.lb_hessvec(prm, psi0, v0, out=out)
+            p.lb_hessvec(prm, ps, vv, out=out)
         torch.cuda.synchronize()
-        reps = 200
+        reps = 200 if batch == 1 else 40
         s = time.perf_counter()
         for _ in range(reps):
-            p.lb_hessvec(prm, psi0, v0, out=out)
+            p.lb_hessvec(prm, ps, vv, out=out)
         torch.cuda.synchronize()
-        return reps / (time.perf_counter() - s)
+        return batch * reps / (time.perf_counter() - s)
 
-    hv = {"fp64": hv_rate("fp64")}
+    hv = {"fp64": hv_rate("fp64"), "fp64_batch8": hv_rate("fp64", 8)}
     fp32 = None
     if not args.no_fp32:
         hv["fp32"] = hv_rate("fp32")
+        hv["fp32_batch8"] = hv_rate("fp32", 8)
         p32 = lb.Plan(n, box, precision="fp32")
         o32 = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64, "eps_sub_rel": 1e-6})
         torch.cuda.synchronize()

@@ -865,44 +865,29 @@ __device__ __forceinline__ void sk_lds_passes(c2<T> *buf, int fs, int es, const 
   }
 }
 
-// Axes 1 and 2 of the inner iteration for one plane of fixed k0 (the
-// half-spectrum plane, N x (N/2 + 1), held in LDS):
-//   inverse along axis 1 (columns, read straight from memory), inverse real
-//   transforms of the rows (two real rows packed as one complex row of length
-//   N), multiply by Gamma', forward real transforms of the rows, forward along
-//   axis 1 (written straight to memory). The packing is folded into the first
-//   row pass's loads, Gamma' into the last inverse row pass's stores and the
-//   unpacking into the first forward column pass's loads.
-template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
-__global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
-                                                    c2<T> *data, const T *__restrict__ gp, const SubState *st) {
+// Stages of the plane kernels. A plane of fixed i0 is held in LDS as the
+// half spectrum along the last axis: element (row e, column k) at L[e NH + k];
+// row passes pack half rows 2p, 2p+1 as one complex row Z_p of length N at
+// L[p 2 NH + x].
+
+// axis 1, inverse, first pass read from src (plane layout)
+template <typename T, int N, int NT>
+__device__ __forceinline__ void plane_cols_inv_from(c2<T> *L, const c2<T> *src, const c2<T> *__restrict__ tw) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1;
-  constexpr int NP = lbfft::npass_p<1>(N);
-  constexpr int NR = N / 2;  // packed rows
-  __shared__ C L[N * NH];    // element (row e, column k) at L[e * NH + k]
-  if (st && st->done) return;
-  const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
-  C *plane = data + b * nh + (long)i0 * (N * NH);
-  const T *g = gp + b * Np + (long)i0 * (N * N);
-  auto lds_load_col = [&](int f, int e) -> C { return L[e * NH + f]; };
-  auto lds_store_col = [&](int f, int e, C v, int, int) { L[e * NH + f] = v; };
-  auto lds_load_row = [&](int f, int e) -> C { return L[f * 2 * NH + e]; };
-  auto lds_store_row = [&](int f, int e, C v, int, int) { L[f * 2 * NH + e] = v; };
-
-  // axis 1, inverse: first pass from memory
-  if constexpr (NP == 1) {
-    sk_pass<T, N, true, NT, NH, true, 0, false>(
-        tw, [&](int f, int e) -> C { return plane[e * NH + f]; }, lds_store_col);
-  } else {
-    sk_pass<T, N, true, NT, NH, true, 0, false>(
-        tw, [&](int f, int e) -> C { return plane[e * NH + f]; }, lds_store_col);
-    __syncthreads();
-    sk_lds_passes<T, N, true, NT, NH, true, 1, NP>(L, 1, NH, tw);
-  }
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N);
+  sk_pass<T, N, true, NT, NH, true, 0, false>(
+      tw, [&](int f, int e) -> C { return src[e * NH + f]; }, [&](int f, int e, C v, int, int) { L[e * NH + f] = v; });
   __syncthreads();
+  sk_lds_passes<T, N, true, NT, NH, true, 1, NP>(L, 1, NH, tw);
+}
 
-  // rows, inverse. Packed row p: Z_p = A + i B from half rows 2p (A), 2p+1 (B).
+// rows, inverse: the first pass packs half rows 2p, 2p+1 into Z_p = A + i B;
+// the last pass (consecutive threads on consecutive outputs x = j + r NS of
+// one row) hands its outputs to last(p, x, z, k, r)
+template <typename T, int N, int NT, class Last>
+__device__ __forceinline__ void plane_rows_inv(c2<T> *L, const c2<T> *__restrict__ tw, const Last &last) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
   auto packed = [&](int p, int e) -> C {
     const bool lo = 2 * e <= N;
     const int k = lo ? e : N - e;
@@ -913,9 +898,59 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
     }
     return lo ? C{A.x - B.y, A.y + B.x} : C{A.x + B.y, B.x - A.y};
   };
-  // last inverse row pass: consecutive threads on consecutive outputs of one
-  // row, so the Gamma' loads are coalesced; they are issued before the first
-  // row pass and held in registers
+  if constexpr (NP == 1) {
+    sk_pass<T, N, true, NT, NR, false, 0, true>(tw, packed, last);
+  } else {
+    sk_pass<T, N, true, NT, NR, true, 0, true>(tw, packed,
+                                               [&](int f, int e, C v, int, int) { L[f * 2 * NH + e] = v; });
+    __syncthreads();
+    sk_lds_passes<T, N, true, NT, NR, true, 1, NP - 1>(L, 2 * NH, 1, tw);
+    sk_pass<T, N, true, NT, NR, false, NP - 1, true>(
+        tw, [&](int f, int e) -> C { return L[f * 2 * NH + e]; }, last);
+  }
+}
+
+// axis 1, forward: the first pass unpacks Z_p into half rows 2p, 2p+1; the
+// last pass writes to dst (plane layout)
+template <typename T, int N, int NT>
+__device__ __forceinline__ void plane_cols_fwd_to(c2<T> *L, c2<T> *dst, const c2<T> *__restrict__ tw) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N);
+  auto unpacked = [&](int k, int e) -> C {
+    const int p = e >> 1;
+    const C zk = L[2 * p * NH + k], zm = L[2 * p * NH + ((N - k) % N)];
+    return (e & 1) ? C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)}
+                   : C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
+  };
+  auto store_mem = [&](int f, int e, C v, int, int) { dst[e * NH + f] = v; };
+  auto store_lds = [&](int f, int e, C v, int, int) { L[e * NH + f] = v; };
+  if constexpr (NP == 1) {
+    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_mem);
+  } else {
+    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_lds);
+    __syncthreads();
+    sk_lds_passes<T, N, false, NT, NH, true, 1, NP - 1>(L, 1, NH, tw);
+    sk_pass<T, N, false, NT, NH, true, NP - 1, false>(
+        tw, [&](int f, int e) -> C { return L[e * NH + f]; }, store_mem);
+  }
+}
+
+// Axes 1 and 2 of the inner iteration for one plane of fixed k0: inverse
+// along axis 1, inverse real row transforms, multiply by Gamma', forward real
+// row transforms, forward along axis 1. Gamma' is applied by the last inverse
+// row pass, its values loaded (coalesced) before the row passes start.
+template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
+                                                    c2<T> *data, const T *__restrict__ gp, const SubState *st) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  __shared__ C L[N * NH];
+  if (st && st->done) return;
+  const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
+  C *plane = data + b * nh + (long)i0 * (N * NH);
+  const T *g = gp + b * Np + (long)i0 * (N * N);
+  plane_cols_inv_from<T, N, NT>(L, plane, tw);
+  __syncthreads();
   using LastS = PassShape<T, N, true, NT, NR, false, NP - 1>;
   T g0[LastS::K][LastS::R], g1[LastS::K][LastS::R];
 #pragma unroll
@@ -925,43 +960,82 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
       const int f = LastS::f_of(bi), j = LastS::j_of(bi);
 #pragma unroll
       for (int r = 0; r < LastS::R; ++r) {
-        const int e = j + r * LastS::NS;  // last pass: outputs j + r NS
+        const int e = j + r * LastS::NS;
         g0[k][r] = g[(2 * f) * N + e];
         g1[k][r] = g[(2 * f + 1) * N + e];
       }
     }
   }
-  auto store_mul = [&](int f, int e, C v, int k, int r) { L[f * 2 * NH + e] = C{v.x * g0[k][r], v.y * g1[k][r]}; };
-  if constexpr (NP == 1) {
-    sk_pass<T, N, true, NT, NR, false, 0, true>(tw, packed, store_mul);
-  } else {
-    sk_pass<T, N, true, NT, NR, true, 0, true>(tw, packed, lds_store_row);
-    __syncthreads();
-    sk_lds_passes<T, N, true, NT, NR, true, 1, NP - 1>(L, 2 * NH, 1, tw);
-    sk_pass<T, N, true, NT, NR, false, NP - 1, true>(tw, lds_load_row, store_mul);
+  plane_rows_inv<T, N, NT>(L, tw, [&](int f, int e, C v, int k, int r) {
+    L[f * 2 * NH + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
+  });
+  __syncthreads();
+  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, 2 * NH, 1, tw);  // rows, forward
+  plane_cols_fwd_to<T, N, NT>(L, plane, tw);
+}
+
+// Hessian-vector product, axes 2 and 1 forward from the physical field v:
+// real rows 2p, 2p+1 packed as Z_p, forward row transforms, forward along
+// axis 1 into the half-spectrum plane of out. With partial non-null, the
+// plane's share of sum Gamma'(psi) v goes to partial[block] (for the mean).
+template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_plane_fwd_phys(int n0, long nh, long Np, Prm p, const c2<T> *__restrict__ tw,
+                                                       const double *__restrict__ v, const double *__restrict__ psi,
+                                                       c2<T> *out, double *partial) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  __shared__ C L[N * NH];
+  const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
+  const long off = b * Np + (long)i0 * (N * N);
+  const double tau = p.tau[b], gam = p.gamma[b];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < NR * N; i += NT) {
+    const int q = i / N, x = i - q * N;
+    const long ia = off + (long)(2 * q) * N + x, ib = ia + N;
+    const double va = v[ia], vb = v[ib];
+    if (partial) {
+      const double pa = psi[ia], pb = psi[ib];
+      acc += (tau - gam * pa + 0.5 * pa * pa) * va + (tau - gam * pb + 0.5 * pb * pb) * vb;
+    }
+    L[q * 2 * NH + x] = C{T(va), T(vb)};
   }
   __syncthreads();
-
-  // rows, forward
   sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, 2 * NH, 1, tw);
-
-  // axis 1, forward: the first pass unpacks Z_p into half rows 2p, 2p+1; the
-  // last pass writes to memory
-  auto unpacked = [&](int k, int e) -> C {
-    const int p = e >> 1;
-    const C zk = L[2 * p * NH + k], zm = L[2 * p * NH + ((N - k) % N)];
-    return (e & 1) ? C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)}
-                   : C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
-  };
-  auto store_mem = [&](int f, int e, C v, int, int) { plane[e * NH + f] = v; };
-  if constexpr (NP == 1) {
-    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_mem);
-  } else {
-    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, lds_store_col);
-    __syncthreads();
-    sk_lds_passes<T, N, false, NT, NH, true, 1, NP - 1>(L, 1, NH, tw);
-    sk_pass<T, N, false, NT, NH, true, NP - 1, false>(tw, lds_load_col, store_mem);
+  plane_cols_fwd_to<T, N, NT>(L, out + b * nh + (long)i0 * (N * NH), tw);
+  if (partial) {
+    const double s = block_sum<NT>(acc, reinterpret_cast<double *>(L));
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
+}
+
+// Hessian-vector product, axes 1 and 2 inverse into the physical result:
+//   hv = F^-1(...) + Gamma'(psi) v - mean,  mean = sum of the n0 partials / N
+// (mean = 0 when mpart is null).
+template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np, Prm p, const c2<T> *__restrict__ tw,
+                                                       const c2<T> *__restrict__ in, const double *__restrict__ psi,
+                                                       const double *__restrict__ v, const double *__restrict__ mpart,
+                                                       double *hv) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1;
+  __shared__ C L[N * NH];
+  const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
+  double mean = 0.0;
+  if (mpart) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n0; i += NT) a += mpart[(long)b * n0 + i];
+    mean = block_sum_all<NT>(a, reinterpret_cast<double *>(L)) / (double)Np;
+  }
+  plane_cols_inv_from<T, N, NT>(L, in + b * nh + (long)i0 * (N * NH), tw);
+  __syncthreads();
+  const long off = b * Np + (long)i0 * (N * N);
+  const double tau = p.tau[b], gam = p.gamma[b];
+  plane_rows_inv<T, N, NT>(L, tw, [&](int f, int x, C z, int, int) {
+    const long ia = off + (long)(2 * f) * N + x, ib = ia + N;
+    const double pa = psi[ia], pb = psi[ib];
+    hv[ia] = double(z.x) + (tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean;
+    hv[ib] = double(z.y) + (tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean;
+  });
 }
 
 // ---------------------------------------------------------------------------

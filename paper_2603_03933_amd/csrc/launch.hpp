@@ -68,8 +68,10 @@ struct NFuncs {
   void (*rows_c2r)(const PassArgs &, int mode) = nullptr;
   void (*rows_inner)(const PassArgs &) = nullptr;
   void (*rows_energy)(const PassArgs &) = nullptr;  // FP64 tables only
-  // plane pass for n1 = n_last = N (null when the plane does not fit in LDS)
+  // plane passes for n1 = n_last = N (null when the plane does not fit in LDS)
   void (*plane_inner)(const PassArgs &, int n0) = nullptr;
+  void (*plane_fwd_phys)(const PassArgs &, int n0) = nullptr;  // v -> out (+ Gamma' v partials)
+  void (*plane_inv_phys)(const PassArgs &, int n0) = nullptr;  // in -> hv
 };
 
 template <typename T, int N> struct Impl {
@@ -166,6 +168,17 @@ template <typename T, int N> struct Impl {
                          n0, a.g.nh, a.g.N, (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
   }
 
+  static void plane_fwd_phys(const PassArgs &a, int n0) {
+    if constexpr (lbk::PlaneCfg<T, N>::fits)
+      LB_LAUNCH((lbk::k_plane_fwd_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
+                a.g.nh, a.g.N, a.p, (const C2 *)a.tw, a.v, a.psi, (C2 *)a.out, a.partial);
+  }
+  static void plane_inv_phys(const PassArgs &a, int n0) {
+    if constexpr (lbk::PlaneCfg<T, N>::fits)
+      LB_LAUNCH((lbk::k_plane_inv_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
+                a.g.nh, a.g.N, a.p, (const C2 *)a.tw, (const C2 *)a.in, a.psi, a.v, a.mpart, (double *)a.out);
+  }
+
   static NFuncs table() {
     NFuncs f;
     f.C = lbk::Cfg<N>::C;
@@ -180,6 +193,8 @@ template <typename T, int N> struct Impl {
     f.rows_inner = &rows_inner;
     f.rows_energy = std::is_same<T, double>::value ? &rows_energy : nullptr;
     f.plane_inner = lbk::PlaneCfg<T, N>::fits ? &plane_inner : nullptr;
+    f.plane_fwd_phys = lbk::PlaneCfg<T, N>::fits ? &plane_fwd_phys : nullptr;
+    f.plane_inv_phys = lbk::PlaneCfg<T, N>::fits ? &plane_inv_phys : nullptr;
     return f;
   }
 };

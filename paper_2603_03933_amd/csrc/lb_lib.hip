@@ -703,6 +703,37 @@ extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi
   LB_TRY(pack_params(P, params, P->batch, &p));
   const int B = P->batch, prec = P->prec;
   void *work = P->WT;
+  const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
+  if (f1 && f1->plane_fwd_phys && P->n1 == P->nl) {
+    // three passes: axes 2 and 1 forward per plane, axis 0 with Lambda, axes 1 and 2 inverse per plane
+    PassArgs a = args_col(P, prec, B, p, 1);
+    a.v = v;
+    a.psi = psi;
+    a.out = work;
+    a.partial = project ? P->partial : nullptr;
+    {
+      KT kt_(P, "plane_fwd_phys");
+      f1->plane_fwd_phys(a, P->n0);
+    }
+    PassArgs c0 = args_col(P, prec, B, p, 0);
+    c0.out = work;
+    c0.inv_n = 1.0 / (double)P->N;
+    {
+      KT kt_(P, "col0_fwd_mul_inv");
+      F(P, 0, prec)->cols_fwd_mul_inv(c0);
+    }
+    PassArgs o = args_col(P, prec, B, p, 1);
+    o.in = work;
+    o.out = hv;
+    o.psi = psi;
+    o.v = v;
+    o.mpart = project ? P->partial : nullptr;
+    {
+      KT kt_(P, "plane_inv_phys");
+      f1->plane_inv_phys(o, P->n0);
+    }
+    return check_launch("lb_hessvec");
+  }
   PassArgs r = args_rows(P, prec, B, p, true);
   r.in = v;
   r.psi = psi;

@@ -82,8 +82,10 @@ def test_hessvec_matches_oracle(shape, box, precision, tol):
     assert err <= tol * scale, (err, scale)
 
 
-def test_hessvec_unprojected_keeps_mean():
-    shape, box = (32, 48), (4 * math.pi, 6 * math.pi)
+@pytest.mark.parametrize(
+    "shape,box", [((32, 48), (4 * math.pi, 6 * math.pi)), ((16, 16, 16), (2 * math.pi, 2 * math.pi, 2 * math.pi))]
+)
+def test_hessvec_unprojected_keeps_mean(shape, box):
     m = model_for(shape, box)
     psi = I.zero_mean_noise(shape, 0.4, 14)
     v = I.hessvec_direction(shape, 15)

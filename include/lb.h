@@ -196,6 +196,28 @@ int lb_energy_grad(lb_plan *plan, const lb_params *params, const double *psi, do
  * FFT arithmetic in the plan's precision. Asynchronous. */
 int lb_hessvec(lb_plan *plan, const lb_params *params, const double *psi, const double *v, double *hv, int project);
 
+/* Derivatives with respect to the N grid values (for automatic
+ * differentiation frameworks), of E as printed in eq. lb_energy with the sum
+ * over every k including k = 0 and no mass constraint (on zero-mean fields
+ * this is the paper's E):
+ *   lb_energy_grad_raw: energy (batch doubles, device) and
+ *     grad[x] = dE/dpsi_x = (F_N^{-1} Lambda psi_hat + F'(psi))_x / N
+ *     (batch * N doubles, device). Always FP64. Asynchronous.
+ *   lb_hessvec_raw: hv = (F_N^{-1} Lambda F_N v + Gamma'(psi) v) / N, the
+ *     Hessian of E in these coordinates times v. FFT arithmetic in the plan's
+ *     precision. Asynchronous.
+ * Arguments as for lb_energy_grad / lb_hessvec; psi need not have zero mean. */
+int lb_energy_grad_raw(lb_plan *plan, const lb_params *params, const double *psi, double *energy, double *grad);
+int lb_hessvec_raw(lb_plan *plan, const lb_params *params, const double *psi, const double *v, double *hv);
+
+/* Field moments per instance, the parameter derivatives of E (eq. lb_energy:
+ * dE/dtau = mean(psi^2)/2, dE/dgamma = -mean(psi^3)/6) and of its gradient:
+ *   out[4 b + 0] = mean(psi^2), out[4 b + 1] = mean(psi^3),
+ *   out[4 b + 2] = mean(w psi), out[4 b + 3] = mean(w psi^2)  (0 if w is NULL)
+ *   psi, w : batch * N doubles (device; w nullable); out : 4 * batch doubles
+ *   (device), written. FP64. Asynchronous. */
+int lb_field_moments(lb_plan *plan, const double *psi, const double *w, double *out);
+
 /* Trust-region subproblem min_{||d|| <= radius} <g,d> + <d,Hd>/2 by the
  * adaptive IMEX iteration (Section 3.2, Algorithm 3; eqs. imex-scheme and
  * lambda_update_rule), batch must be 1.

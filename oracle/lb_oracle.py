@@ -237,6 +237,25 @@ def gradient_phys(m: Model, psi: np.ndarray) -> np.ndarray:
     return inv(gradient(m, psi))
 
 
+def gradient_raw(m: Model, psi: np.ndarray) -> np.ndarray:
+    """dE/dpsi_x for E of eq. lb_energy as a function of all N grid values (sum
+    over every k, no mass constraint): (F_N^{-1}(Lambda psi_hat) + F'(psi)) / N."""
+    return (inv(m.Lam * fwd(psi)) + dF_bulk(psi, m.tau, m.gamma)) / psi.size
+
+
+def hessvec_raw(m: Model, psi: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Hessian of the same function times v: (F_N^{-1} Lambda F_N v + Gamma'(psi) v) / N."""
+    return (inv(m.Lam * fwd(v)) + Gamma_p(psi, m.tau, m.gamma) * v) / psi.size
+
+
+def field_moments(psi: np.ndarray, w: Optional[np.ndarray] = None) -> np.ndarray:
+    """[mean(psi^2), mean(psi^3), mean(w psi), mean(w psi^2)]: dE/dtau = first / 2,
+    dE/dgamma = -second / 6 (eq. lb_energy); the last two are the tau and gamma
+    derivatives (times 1 and -1/2) of <w, grad_raw E>."""
+    z = np.zeros_like(psi) if w is None else w
+    return np.array([np.mean(psi**2), np.mean(psi**3), np.mean(z * psi), np.mean(z * psi**2)])
+
+
 def hessvec_phys(m: Model, psi: np.ndarray, v: np.ndarray) -> np.ndarray:
     return inv(hessvec(m, psi, project(fwd(v))))
 

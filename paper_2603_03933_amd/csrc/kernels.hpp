@@ -492,10 +492,10 @@ template <typename T> struct OpFwdHess {
 };
 
 // Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
-// (k = 0 removed), inverse transform, all in one workgroup pass.
+// (k = 0 removed unless keep_dc), inverse transform, all in one workgroup pass.
 template <typename T, int N>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo g, Prm p, const c2<T> *__restrict__ tw,
-                                                                  c2<T> *data, double inv_n) {
+                                                                  c2<T> *data, double inv_n, int keep_dc) {
   using C = c2<T>;
   constexpr int CC = Cfg<N>::C;
   __shared__ C lds[N * CC];
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
       [&](int e) { return g.kk0[e]; },
       [&](int e, C v, double kk0) {
         double m = lam_of(kk0 + ci.kkc, xi, q) * inv_n;
-        if (!ok || (ci.dc && e == 0)) m = 0.0;
+        if (!ok || (ci.dc && e == 0 && !keep_dc)) m = 0.0;
         lds[lidx(c, e)] = C{T(double(v.x) * m), T(double(v.y) * m)};
       });
   __syncthreads();
@@ -681,7 +681,8 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_c2r(RowGeo rg, Geo g, Prm p, const c2<T> *__restrict__ tw,
                                                           const c2<T> *__restrict__ in, double *__restrict__ out,
                                                           const double *__restrict__ psi, const double *__restrict__ v,
-                                                          const double *__restrict__ mpart, int mbpi, double *partial) {
+                                                          const double *__restrict__ mpart, int mbpi, double *partial,
+                                                          double bscale) {
   using C = c2<T>;
   constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
   __shared__ C lds[CC * LD];
@@ -718,8 +719,8 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_c2r(RowGeo rg, Geo g, Prm p
       double xa = double(z.x), xb = double(z.y);
       if constexpr (MODE == 1) {
         const double pa = psi[ia], pb = psi[ib];
-        xa += (tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean;
-        xb += (tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean;
+        xa += bscale * ((tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean);
+        xb += bscale * ((tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean);
       }
       if constexpr (MODE == 2) {
         const double pa = psi[ia], pb = psi[ib];
@@ -1009,13 +1010,13 @@ __global__ __launch_bounds__(NT) void k_plane_fwd_phys(int n0, long nh, long Np,
 }
 
 // Hessian-vector product, axes 1 and 2 inverse into the physical result:
-//   hv = F^-1(...) + Gamma'(psi) v - mean,  mean = sum of the n0 partials / N
-// (mean = 0 when mpart is null).
+//   hv = F^-1(...) + bscale (Gamma'(psi) v - mean),  mean = sum of the n0
+// partials / N (mean = 0 when mpart is null).
 template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
 __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np, Prm p, const c2<T> *__restrict__ tw,
                                                        const c2<T> *__restrict__ in, const double *__restrict__ psi,
                                                        const double *__restrict__ v, const double *__restrict__ mpart,
-                                                       double *hv) {
+                                                       double *hv, double bscale) {
   using C = c2<T>;
   constexpr int NH = N / 2 + 1;
   __shared__ C L[N * NH];
@@ -1033,8 +1034,8 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np,
   plane_rows_inv<T, N, NT>(L, tw, [&](int f, int x, C z, int, int) {
     const long ia = off + (long)(2 * f) * N + x, ib = ia + N;
     const double pa = psi[ia], pb = psi[ib];
-    hv[ia] = double(z.x) + (tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean;
-    hv[ib] = double(z.y) + (tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean;
+    hv[ia] = double(z.x) + bscale * ((tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean);
+    hv[ib] = double(z.y) + bscale * ((tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean);
   });
 }
 
@@ -1046,10 +1047,12 @@ constexpr int EW_NT = 256;
 // gradient assembly after the forward transforms of psi and F'(psi):
 //   g = P(Lambda psi_hat + F_N F'(psi)) and partials
 //   [1/2 sum w Lambda |psi_hat|^2, sum w |g|^2, max |g|] per workgroup
+// With raw != 0 the k = 0 entry is kept and g is scaled by 1/N: the gradient
+// with respect to the N grid values of E as printed (no mass constraint).
 template <typename TG>
 __global__ __launch_bounds__(EW_NT) void k_grad_assemble(Geo g, Prm p, int bpi, const double2 *__restrict__ ph,
                                                          const double2 *__restrict__ fh, double2 *__restrict__ gh,
-                                                         c2<TG> *__restrict__ gh_t, double *partial) {
+                                                         c2<TG> *__restrict__ gh_t, double *partial, int raw) {
   __shared__ double scratch[64];
   const int b = blockIdx.x / bpi;
   const long lb = blockIdx.x % bpi;
@@ -1062,7 +1065,12 @@ __global__ __launch_bounds__(EW_NT) void k_grad_assemble(Geo g, Prm p, int bpi, 
     const double2 a = ph[h], f = fh[h];
     aG += 0.5 * w * lam * (a.x * a.x + a.y * a.y);
     double2 gv{lam * a.x + f.x, lam * a.y + f.y};
-    if (hl == 0) gv = double2{0.0, 0.0};
+    if (raw) {
+      const double sN = 1.0 / (double)g.N;
+      gv = double2{gv.x * sN, gv.y * sN};
+    } else if (hl == 0) {
+      gv = double2{0.0, 0.0};
+    }
     const double m2 = gv.x * gv.x + gv.y * gv.y;
     aN += w * m2;
     aM = fmax(aM, sqrt(m2));
@@ -1164,6 +1172,37 @@ __global__ __launch_bounds__(EW_NT) void k_final_d(Geo g, Prm p, const c2<T> *__
 // Sum `nq` interleaved per-workgroup partials over the `bpi` workgroups of
 // each instance in a fixed order; q listed in `is_max` use max instead.
 // One workgroup per instance; out[b * nq + q].
+// Per-workgroup partial sums [psi^2, psi^3, w psi, w psi^2] over instance b's
+// N points (w nullable: zeros); partial[(b * bpi + block) * 4 + q]
+__global__ __launch_bounds__(EW_NT) void k_field_moments(long N, int bpi, const double *__restrict__ psi,
+                                                         const double *__restrict__ w, double *partial) {
+  __shared__ double scratch[64];
+  const int b = blockIdx.x / bpi;
+  const long lb = blockIdx.x % bpi;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long i = lb * EW_NT + threadIdx.x; i < N; i += (long)bpi * EW_NT) {
+    const double x = psi[(long)b * N + i], x2 = x * x;
+    a[0] += x2;
+    a[1] += x2 * x;
+    if (w) {
+      const double y = w[(long)b * N + i];
+      a[2] += y * x;
+      a[3] += y * x2;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double s = block_sum<EW_NT>(a[q], scratch + 16 * q);
+    if (threadIdx.x == 0) partial[((long)blockIdx.x) * 4 + q] = s;
+  }
+}
+
+// out[b * nq + q] = scale * sums[b * nq + q]
+__global__ void k_scale_out(const double *sums, int count, double scale, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = scale * sums[i];
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int bpi, int nq,
                                                   unsigned is_max, double *__restrict__ out) {
   __shared__ double scratch[64];

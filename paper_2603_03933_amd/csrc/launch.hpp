@@ -54,7 +54,8 @@ struct PassArgs {
   float *gp32 = nullptr;
   double scale = 1.0, inv_n = 1.0, shift = 0.0;
   int zero_dc = 0;
-  int step = 0;  // subproblem step index
+  int keep_dc = 0;  // Hessian product: keep Lambda_0 (no projection)
+  int step = 0;     // subproblem step index
 };
 
 struct NFuncs {
@@ -131,7 +132,7 @@ template <typename T, int N> struct Impl {
   }
   static void cols_fwd_mul_inv(const PassArgs &a) {
     LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
-                       (const C2 *)a.tw, (C2 *)a.out, a.inv_n);
+                       (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc);
   }
   static void rows_r2c(const PassArgs &a, int mode) {
     if (mode == 1)
@@ -144,13 +145,13 @@ template <typename T, int N> struct Impl {
   static void rows_c2r(const PassArgs &a, int mode) {
     if (mode == 1)
       LB_LAUNCH((lbk::k_rows_c2r<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
-                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
+                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial, a.scale);
     else if (mode == 2)
       LB_LAUNCH((lbk::k_rows_c2r<T, N, 2>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
-                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
+                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial, a.scale);
     else
       LB_LAUNCH((lbk::k_rows_c2r<T, N, 0>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
-                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial);
+                         (const C2 *)a.tw, (const C2 *)a.in, (double *)a.out, a.psi, a.v, a.mpart, a.mbpi, a.partial, a.scale);
   }
   static void rows_inner(const PassArgs &a) {
     LB_LAUNCH((lbk::k_rows_inner<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, (const C2 *)a.tw,
@@ -176,7 +177,7 @@ template <typename T, int N> struct Impl {
   static void plane_inv_phys(const PassArgs &a, int n0) {
     if constexpr (lbk::PlaneCfg<T, N>::fits)
       LB_LAUNCH((lbk::k_plane_inv_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
-                a.g.nh, a.g.N, a.p, (const C2 *)a.tw, (const C2 *)a.in, a.psi, a.v, a.mpart, (double *)a.out);
+                a.g.nh, a.g.N, a.p, (const C2 *)a.tw, (const C2 *)a.in, a.psi, a.v, a.mpart, (double *)a.out, a.scale);
   }
 
   static NFuncs table() {

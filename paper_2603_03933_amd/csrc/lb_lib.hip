@@ -627,7 +627,7 @@ static void lincomb64(lb_plan *P, long n, double alpha, const double2 *x, double
 // After this call: GH holds g_hat (FP64), GHT its copy in the plan's precision,
 // gp64/gp32 hold Gamma'(psi), and P->sums holds per instance
 // [sum F, max |Gamma'|] at sums[0 .. 2B) and [G, ||g||^2, max |g|] at sums[32 ..).
-static void energy_grad_core(lb_plan *P, int batch, const Prm &p, const double *psi) {
+static void energy_grad_core(lb_plan *P, int batch, const Prm &p, const double *psi, int raw = 0) {
   PassArgs r = args_rows(P, LB_FP64, batch, p, false);
   r.psi = psi;
   r.out = P->SP;
@@ -666,14 +666,14 @@ static void energy_grad_core(lb_plan *P, int batch, const Prm &p, const double *
       KT kt_(P, "grad_assemble");
       LB_LAUNCH((lbk::k_grad_assemble<double>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
                          geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
-                         P->GH, (double2 *)nullptr, part2);
+                         P->GH, (double2 *)nullptr, part2, raw);
     }
   else
     {
       KT kt_(P, "grad_assemble");
       LB_LAUNCH((lbk::k_grad_assemble<float>), dim3(bpi * batch), dim3(lbk::EW_NT), 0, P->stream,
                          geo(P, batch), p, bpi, (const double2 *)P->SP, (const double2 *)(P->SP + (long)batch * P->nh),
-                         P->GH, (float2 *)P->GHT, part2);
+                         P->GH, (float2 *)P->GHT, part2, raw);
     }
   finalize(P, part2, bpi, 3, 0x4u, batch, P->sums + 32);
 }
@@ -696,11 +696,15 @@ extern "C" int lb_energy_grad(lb_plan *P, const lb_params *params, const double 
 // ---------------------------------------------------------------------------
 // Hessian-vector product on physical fields
 // ---------------------------------------------------------------------------
-extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi, const double *v, double *hv,
-                          int project) {
+// mode 0: P(L v + Gamma' v); 1: P L v + Gamma' v; 2: (L v + Gamma' v) / N (raw coordinates)
+static int hessvec_phys(lb_plan *P, const lb_params *params, const double *psi, const double *v, double *hv,
+                        int mode) {
   if (!P || !psi || !v || !hv) return fail(LB_ERR_ARG, "null argument");
   Prm p;
   LB_TRY(pack_params(P, params, P->batch, &p));
+  const int project = mode == 0;
+  const int keep_dc = mode == 2;
+  const double bscale = mode == 2 ? 1.0 / (double)P->N : 1.0;
   const int B = P->batch, prec = P->prec;
   void *work = P->WT;
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
@@ -717,7 +721,8 @@ extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi
     }
     PassArgs c0 = args_col(P, prec, B, p, 0);
     c0.out = work;
-    c0.inv_n = 1.0 / (double)P->N;
+    c0.inv_n = bscale / (double)P->N;
+    c0.keep_dc = keep_dc;
     {
       KT kt_(P, "col0_fwd_mul_inv");
       F(P, 0, prec)->cols_fwd_mul_inv(c0);
@@ -727,6 +732,7 @@ extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi
     o.out = hv;
     o.psi = psi;
     o.v = v;
+    o.scale = bscale;
     o.mpart = project ? P->partial : nullptr;
     {
       KT kt_(P, "plane_inv_phys");
@@ -754,7 +760,8 @@ extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi
   }
   PassArgs c0 = args_col(P, prec, B, p, 0);
   c0.out = work;
-  c0.inv_n = 1.0 / (double)P->N;
+  c0.inv_n = bscale / (double)P->N;
+  c0.keep_dc = keep_dc;
   {
     KT kt_(P, "col0_fwd_mul_inv");
     F(P, 0, prec)->cols_fwd_mul_inv(c0);
@@ -775,11 +782,54 @@ extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi
   o.v = v;
   o.mpart = project ? P->partial : nullptr;
   o.mbpi = r.rg.bpi;
+  o.scale = bscale;
   {
     KT kt_(P, "rows_c2r_hv");
     F(P, 2, prec)->rows_c2r(o, 1);
   }
   return check_launch("lb_hessvec");
+}
+
+extern "C" int lb_hessvec(lb_plan *P, const lb_params *params, const double *psi, const double *v, double *hv,
+                          int project) {
+  return hessvec_phys(P, params, psi, v, hv, project ? 0 : 1);
+}
+
+extern "C" int lb_hessvec_raw(lb_plan *P, const lb_params *params, const double *psi, const double *v, double *hv) {
+  return hessvec_phys(P, params, psi, v, hv, 2);
+}
+
+extern "C" int lb_energy_grad_raw(lb_plan *P, const lb_params *params, const double *psi, double *energy,
+                                  double *grad) {
+  if (!P || !psi || !energy || !grad) return fail(LB_ERR_ARG, "null argument");
+  Prm p;
+  LB_TRY(pack_params(P, params, P->batch, &p));
+  const int B = P->batch;
+  energy_grad_core(P, B, p, psi, 1);
+  {
+    KT kt_(P, "energy_out");
+    LB_LAUNCH(lbk::k_energy_out, dim3(1), dim3(64), 0, P->stream, (const double *)(P->sums + 32), 3,
+              (const double *)P->sums, 2, 1.0 / (double)P->N, B, energy);
+  }
+  inv_c2r(P, LB_FP64, B, p, P->GH, P->W64, grad, 0, nullptr, nullptr);
+  return check_launch("lb_energy_grad_raw");
+}
+
+extern "C" int lb_field_moments(lb_plan *P, const double *psi, const double *w, double *out) {
+  if (!P || !psi || !out) return fail(LB_ERR_ARG, "null argument");
+  const int B = P->batch;
+  const int bpi = (int)bpi_ew(P);
+  {
+    KT kt_(P, "field_moments");
+    LB_LAUNCH(lbk::k_field_moments, dim3(bpi * B), dim3(lbk::EW_NT), 0, P->stream, P->N, bpi, psi, w, P->partial);
+  }
+  finalize(P, P->partial, bpi, 4, 0u, B, P->sums);
+  {
+    KT kt_(P, "scale_out");
+    LB_LAUNCH(lbk::k_scale_out, dim3(1), dim3(64), 0, P->stream, (const double *)P->sums, 4 * B,
+              1.0 / (double)P->N, out);
+  }
+  return check_launch("lb_field_moments");
 }
 
 // spectral Hessian-vector product in FP64: out = Lambda x + P F_N(Gamma' F_N^{-1} x) + shift x

@@ -125,6 +125,9 @@ _SIGS = {
     "lb_plan_timing_entry": (_I, [_P, _I, C.c_char_p, _I, C.POINTER(C.c_long), C.POINTER(_D)]),
     "lb_energy_grad": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
     "lb_hessvec": (_I, [_P, C.POINTER(LbParams), _P, _P, _P, _I]),
+    "lb_energy_grad_raw": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
+    "lb_hessvec_raw": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
+    "lb_field_moments": (_I, [_P, _P, _P, _P]),
     "lb_tr_subproblem": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, C.POINTER(LbSubOpts), _P, _P, C.POINTER(LbSubInfo)]),
     "lb_imex_tr_solve": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo)]),
     "lb_shifted_solve": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, _D, _I, _P, C.POINTER(_I)]),
@@ -279,6 +282,32 @@ class Plan:
         if out is None:
             out = torch.empty_like(v)
         _check(lib().lb_hessvec(self._h, _params_array(params, self.batch), _ptr(psi, n, "psi"), _ptr(v, n, "v"), _ptr(out, n, "hv"), 1 if project else 0))
+        return out
+
+    def lb_energy_grad_raw(self, params, psi, energy=None, grad=None):
+        self._sync_stream()
+        n = self.N * self.batch
+        if energy is None:
+            energy = torch.empty(self.batch, dtype=torch.float64, device=psi.device)
+        if grad is None:
+            grad = torch.empty_like(psi)
+        _check(lib().lb_energy_grad_raw(self._h, _params_array(params, self.batch), _ptr(psi, n, "psi"), _ptr(energy, self.batch, "energy"), _ptr(grad, n, "grad")))
+        return energy, grad
+
+    def lb_hessvec_raw(self, params, psi, v, out=None):
+        self._sync_stream()
+        n = self.N * self.batch
+        if out is None:
+            out = torch.empty_like(v)
+        _check(lib().lb_hessvec_raw(self._h, _params_array(params, self.batch), _ptr(psi, n, "psi"), _ptr(v, n, "v"), _ptr(out, n, "hv")))
+        return out
+
+    def lb_field_moments(self, psi, w=None, out=None):
+        self._sync_stream()
+        n = self.N * self.batch
+        if out is None:
+            out = torch.empty(4 * self.batch, dtype=torch.float64, device=psi.device)
+        _check(lib().lb_field_moments(self._h, _ptr(psi, n, "psi"), _ptr(w, n, "w"), _ptr(out, 4 * self.batch, "out")))
         return out
 
     def lb_tr_subproblem(self, params, psi, grad, radius, opts: Optional[LbSubOpts] = None, d0=None, out=None):

@@ -203,6 +203,45 @@ def test_energy_derivatives_in_tau_and_gamma():
     assert abs(dgam + np.mean(psi**3) / 6) < 1e-13
 
 
+def test_raw_gradient_and_hessian_exact_central_differences():
+    """Coordinates of the N grid values, no mass constraint (mean kept): the
+    central differences of the quartic E and of its gradient are exact up to
+    the cubic/quartic terms, which are added back in closed form."""
+    g = O.Grid((6, 10), (5.0, 8.0))
+    m = O.Model(g, -0.15, 0.3, 1.1, 0.9)
+    psi = rand_field(g.n, 0.6, 31) + 0.4  # nonzero mean
+    e = rand_field(g.n, 1.0, 32) + 0.2
+    N = psi.size
+    for eps in (1e-2, 1e-3):
+        fd = (O.energy(m, psi + eps * e) - O.energy(m, psi - eps * e)) / (2 * eps)
+        exact = float(np.sum(O.gradient_raw(m, psi) * e)) + eps**2 / 6 * float(np.sum((psi - m.gamma) * e**3)) / N
+        assert abs(fd - exact) < 1e-12 * max(1.0, abs(fd))
+        gd = (O.gradient_raw(m, psi + eps * e) - O.gradient_raw(m, psi - eps * e)) / (2 * eps)
+        he = O.hessvec_raw(m, psi, e) + eps**2 / 6 * e**3 / N
+        assert np.max(np.abs(gd - he)) < 1e-12 * np.max(np.abs(gd))
+    # on zero-mean fields the raw gradient is the paper's projected one plus mean(F'(psi)), over N
+    psi0 = psi - psi.mean()
+    shift = np.mean(O.dF_bulk(psi0, m.tau, m.gamma))
+    assert np.max(np.abs(O.gradient_raw(m, psi0) * N - O.gradient_phys(m, psi0) - shift)) < 1e-12
+
+
+def test_field_moments_are_parameter_derivatives():
+    """tau and gamma derivatives of E and of <w, grad_raw E> (both affine in tau, gamma)."""
+    g = O.Grid((8, 6), (6.0, 5.0))
+    psi = rand_field(g.n, 0.8, 33) + 0.1
+    w = rand_field(g.n, 1.0, 34)
+    h = 0.41
+    M = O.field_moments(psi, w)
+
+    def gw(tau, gam):
+        return float(np.sum(w * O.gradient_raw(O.Model(g, tau, gam), psi)))
+
+    assert abs((O.energy(O.Model(g, 0.1 + h, 0.2), psi) - O.energy(O.Model(g, 0.1 - h, 0.2), psi)) / (2 * h) - M[0] / 2) < 1e-13
+    assert abs((O.energy(O.Model(g, 0.1, 0.2 + h), psi) - O.energy(O.Model(g, 0.1, 0.2 - h), psi)) / (2 * h) + M[1] / 6) < 1e-13
+    assert abs((gw(0.1 + h, 0.2) - gw(0.1 - h, 0.2)) / (2 * h) - M[2]) < 1e-13
+    assert abs((gw(0.1, 0.2 + h) - gw(0.1, 0.2 - h)) / (2 * h) + M[3] / 2) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Structure of the Hessian and invariants
 # ---------------------------------------------------------------------------

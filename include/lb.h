@@ -127,6 +127,17 @@ typedef struct lb_tr_opts {
   double cg_rtol;       /* CONTRACT: CG relative tolerance on (H + lambda I) s = -g */
   int cg_maxiter;
   int verbose;          /* 1: one line per outer iteration on stderr */
+  /* Nearly hard subproblems (Remark on the hard case, Section 3.2; Section 4.3):
+     with hard_case = 1, each outer iteration j estimates sigma_1 and its unit
+     eigenvector xi by hard_lanczos_steps Lanczos steps (preconditioner shift
+     hard_precond_shift, start lb_random_ball(1, seed, 2j + 1)); when sigma_1 < 0
+     and |<xi, g>| <= hard_tol, Algorithm 3 starts from lb_random_ball(r_j, seed,
+     2j) instead of -r g/||g||. */
+  int hard_case;              /* 0 (default): always the deterministic start */
+  double hard_tol;            /* 1e-12, the paper's threshold on |g^(1)| */
+  int hard_lanczos_steps;     /* 30 */
+  double hard_precond_shift;  /* 1.0 */
+  unsigned long long seed;    /* key of the random draws (0) */
 } lb_tr_opts;
 
 typedef struct lb_tr_info {
@@ -138,6 +149,7 @@ typedef struct lb_tr_info {
   int cg_total;      /* CG iterations spent in CONTRACT */
   int accepted, contracted, expanded;
   int status;        /* LB_OK or LB_NOT_CONVERGED */
+  int hard_cases;    /* subproblems started from a random point (hard_case = 1) */
 } lb_tr_info;
 
 typedef struct lb_plan lb_plan;
@@ -254,10 +266,24 @@ int lb_shifted_solve(lb_plan *plan, const lb_params *params, const double *psi, 
  *     clustered spectrum, so its lowest Ritz vector y converges in few steps;
  *     *ritz_min is the Rayleigh quotient of H at x = S y and *resid is
  *     ||Hx - ritz x|| / ||x||.
- * Either value bounds sigma_1 from above. batch must be 1. Host outputs.
+ * Either value bounds sigma_1 from above. batch must be 1. Host outputs;
+ * evec (device, N doubles, nullable) receives the unit Ritz vector (y, or
+ * x / ||x|| with preconditioning), mean zero.
  * Allocates steps + 1 spectral vectors on first use (kept by the plan). */
 int lb_lanczos_min(lb_plan *plan, const lb_params *params, const double *psi, const double *v0, int steps,
-                   double precond_shift, double *ritz_min, double *resid);
+                   double precond_shift, double *ritz_min, double *resid, double *evec);
+
+/* A random feasible initial point for nearly hard subproblems (Remark on the
+ * hard case, Section 3.2: a continuous distribution supported on the ball
+ * ||s|| <= r): d uniformly distributed in the ball of radius `radius` of the
+ * (N-1)-dimensional zero-mean subspace (||.|| = RMS). z_x is standard normal
+ * by the Box-Muller transform of the two first words of Philox4x64-10 (Salmon
+ * et al., SC'11) at counter (x, 0, 0, 0) and key (seed, draw) (x the C-order
+ * index, words mapped to (0, 1) by ((w >> 11) + 1/2) 2^-53); d = radius
+ * u^(1/(N-1)) (z - mean z) / rms(z - mean z) with u from word 0 at counter
+ * (0, 1, 0, 0). d_out: N doubles (device), written; batch must be 1.
+ * Asynchronous. */
+int lb_random_ball(lb_plan *plan, double radius, unsigned long long seed, unsigned long long draw, double *d_out);
 
 #ifdef __cplusplus
 }

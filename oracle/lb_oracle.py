@@ -631,7 +631,7 @@ def imex_tr_solve(
     psi0: np.ndarray,
     o: TROpts = TROpts(),
     record: bool = True,
-    d0_provider: Optional[Callable[[int, float, np.ndarray], Optional[np.ndarray]]] = None,
+    d0_provider: Optional[Callable[[int, float, np.ndarray, np.ndarray], Optional[np.ndarray]]] = None,
 ) -> TRResult:
     """Algorithm 1 (IMEX-TR): TRACE outer loop with Algorithm 3 as subproblem solver.
 
@@ -660,7 +660,7 @@ def imex_tr_solve(
             return TRResult(psi, E, gn2, gninf, j, inner_total, True, hist)
         eta = safe_eta(m, psi, o)
         sub_opts = SubOpts(eta=eta, eps_sub=o.eps_sub, max_inner=o.max_inner, max_newton=o.max_newton)
-        d0 = d0_provider(j, r, g) if d0_provider else None
+        d0 = d0_provider(j, r, g, psi) if d0_provider else None
         sub = imex_subproblem(m, psi, g, r, sub_opts, d0=d0)
         inner_total += sub.iters
         s_hat, lam = sub.d, sub.lam
@@ -702,7 +702,9 @@ def imex_tr_solve(
 # ---------------------------------------------------------------------------
 
 
-def lanczos_min(m: Model, psi: np.ndarray, v0_hat: np.ndarray, steps: int, precond_shift: float = 0.0) -> Tuple[float, float]:
+def lanczos_min(
+    m: Model, psi: np.ndarray, v0_hat: np.ndarray, steps: int, precond_shift: float = 0.0, want_vector: bool = False
+):
     """Smallest Ritz value of H after ``steps`` Lanczos steps with full reorthogonalisation.
 
     Returns (value, residual_norm). Without preconditioning (precond_shift <= 0)
@@ -713,6 +715,8 @@ def lanczos_min(m: Model, psi: np.ndarray, v0_hat: np.ndarray, steps: int, preco
     Ritz vector y of K converges quickly; the result is the Rayleigh quotient
     rho = <x, Hx>/<x, x> of H at x = S y and ||Hx - rho x|| / ||x||. Either
     value bounds sigma_1 from above; it is an estimate, not a certificate.
+    With want_vector the unit Ritz vector (x / ||x||, Psi_hat coordinates) is
+    returned as a third value.
     """
     if precond_shift > 0:
         Sd = np.where(np.arange(m.Lam.size).reshape(m.Lam.shape) == 0, 0.0, 1.0 / np.sqrt(m.Lam + precond_shift))
@@ -749,10 +753,91 @@ def lanczos_min(m: Model, psi: np.ndarray, v0_hat: np.ndarray, steps: int, preco
     k = len(alpha)
     Tm = np.diag(alpha) + np.diag(beta[: k - 1], 1) + np.diag(beta[: k - 1], -1)
     ev, evec = np.linalg.eigh(Tm)
-    if Sd is None:
-        return float(ev[0]), float(abs(beta[k - 1] * evec[k - 1, 0]))
     y = sum(evec[i, 0] * Qs[i] for i in range(k))
+    if Sd is None:
+        out = (float(ev[0]), float(abs(beta[k - 1] * evec[k - 1, 0])))
+        return out + (y / norm(y),) if want_vector else out
     x = Sd * y
     Hx = hessvec(m, psi, x)
     rho = dot(x, Hx) / dot(x, x)
-    return float(rho), float(norm(Hx - rho * x) / norm(x))
+    out = (float(rho), float(norm(Hx - rho * x) / norm(x)))
+    return out + (x / norm(x),) if want_vector else out
+
+
+# ---------------------------------------------------------------------------
+# Random initial point for nearly hard subproblems (Remark on the hard case,
+# Section 3.2; Section 4.3)
+# ---------------------------------------------------------------------------
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+_M32 = np.uint64(0xFFFFFFFF)
+
+
+def _mulhilo64(a: np.ndarray, b: int) -> Tuple[np.ndarray, np.ndarray]:
+    """High and low 64-bit words of a * b (a: uint64 array, b: constant), from 32-bit halves."""
+    s32 = np.uint64(32)
+    a_lo, a_hi = a & _M32, a >> s32
+    b_lo, b_hi = np.uint64(b & 0xFFFFFFFF), np.uint64(b >> 32)
+    ll, hl, lh, hh = a_lo * b_lo, a_hi * b_lo, a_lo * b_hi, a_hi * b_hi
+    cross = (ll >> s32) + (hl & _M32) + (lh & _M32)
+    lo = (ll & _M32) | ((cross & _M32) << s32)
+    hi = hh + (hl >> s32) + (lh >> s32) + (cross >> s32)
+    return hi, lo
+
+
+def philox4x64(counter: Sequence[np.ndarray], key: Tuple[int, int], rounds: int = 10) -> List[np.ndarray]:
+    """Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11): a counter-based
+    generator; each round multiplies words 0 and 2 by fixed constants, mixes the
+    high/low halves with words 1, 3 and the key, and bumps the key by Weyl
+    constants."""
+    c = [np.asarray(x, dtype=np.uint64) for x in counter]
+    n = max(x.size for x in c)
+    c = [np.broadcast_to(x, (n,)).copy() for x in c]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    with np.errstate(over="ignore"):
+        for _ in range(rounds):
+            hi0, lo0 = _mulhilo64(c[0], 0xD2E7470EE14C6C93)
+            hi1, lo1 = _mulhilo64(c[2], 0xCA5A826395121157)
+            c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+            k0 = k0 + np.uint64(0x9E3779B97F4A7C15)
+            k1 = k1 + np.uint64(0xBB67AE8584CAA73B)
+    return c
+
+
+def unit_open(w: np.ndarray) -> np.ndarray:
+    """Uniform in (0, 1) from the top 53 bits of a 64-bit word."""
+    return ((w >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0**-53
+
+
+def ball_point(shape: Tuple[int, ...], r: float, seed: int, draw: int) -> np.ndarray:
+    """A zero-mean field uniformly distributed in the ball ||d|| <= r of the
+    (N-1)-dimensional zero-mean subspace (||.|| = RMS): z_x standard normal
+    (Box-Muller from Philox4x64-10 at counter (x, 0, 0, 0), key (seed, draw)),
+    projected to zero mean and scaled to radius r u^(1/(N-1)), u uniform from
+    counter (0, 1, 0, 0)."""
+    N = int(np.prod(shape))
+    idx = np.arange(N, dtype=np.uint64)
+    w = philox4x64([idx, 0, 0, 0], (seed, draw))
+    z = np.sqrt(-2.0 * np.log(unit_open(w[0]))) * np.cos(2.0 * math.pi * unit_open(w[1]))
+    z = z - z.mean()
+    u = float(unit_open(philox4x64([0, 1, 0, 0], (seed, draw))[0])[0])
+    return (r * u ** (1.0 / (N - 1)) / math.sqrt(np.mean(z * z)) * z).reshape(shape)
+
+
+def hard_case_d0_provider(m: Model, seed: int = 0, tol: float = 1e-12, lanczos_steps: int = 30,
+                          precond_shift: float = 1.0, log: Optional[list] = None):
+    """d0 rule for Algorithm 3 inside Algorithm 1: when the subproblem is
+    nearly hard, i.e. H has a negative eigenvalue sigma_1 and its unit
+    eigenvector xi has |g^(1)| = |<xi, g>| <= tol, start from ball_point(r)
+    (draw 2j at outer iteration j) instead of -r g/||g||. sigma_1 and xi are
+    Lanczos estimates from the start vector ball_point(1) of draw 2j + 1."""
+
+    def provider(j: int, r: float, g_hat: np.ndarray, psi: np.ndarray) -> Optional[np.ndarray]:
+        v0 = fwd(ball_point(m.grid.n, 1.0, seed, 2 * j + 1))
+        sig, _, xi = lanczos_min(m, psi, v0, lanczos_steps, precond_shift, want_vector=True)
+        g1 = dot(g_hat, xi)
+        hard = sig < 0 and abs(g1) <= tol
+        if log is not None:
+            log.append(dict(j=j, sigma1=sig, g1=g1, hard=hard))
+        return fwd(ball_point(m.grid.n, r, seed, 2 * j)) if hard else None
+
+    return provider

@@ -13,6 +13,8 @@
 // write one partial per workgroup; a single workgroup sums them in a fixed
 // order, so every result is bitwise reproducible.
 #pragma once
+#include <cstdint>
+
 #include "fft.hpp"
 
 namespace lbk {
@@ -1172,6 +1174,77 @@ __global__ __launch_bounds__(EW_NT) void k_final_d(Geo g, Prm p, const c2<T> *__
 // Sum `nq` interleaved per-workgroup partials over the `bpi` workgroups of
 // each instance in a fixed order; q listed in `is_max` use max instead.
 // One workgroup per instance; out[b * nq + q].
+// ---------------------------------------------------------------------------
+// Random feasible initial point for nearly hard subproblems
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror and Shaw, SC'11), a counter-based
+// generator: ten rounds, each multiplying words 0 and 2 by fixed constants and
+// mixing the high/low halves with words 1, 3 and the key, which is bumped by
+// Weyl constants between rounds.
+struct Philox4 {
+  uint64_t w[4];
+};
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+__host__ __device__ inline Philox4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                              uint64_t k1) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = mulhi64(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = mulhi64(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  return Philox4{{c0, c1, c2, c3}};
+}
+// uniform in (0, 1) from the top 53 bits
+__host__ __device__ inline double unit_open(uint64_t w) { return ((double)(w >> 11) + 0.5) * 0x1p-53; }
+
+// z_x standard normal (Box-Muller on counter (x, 0, 0, 0), key (seed, draw));
+// per-workgroup partials [sum z, sum z^2] at partial[2 block + q]
+__global__ __launch_bounds__(EW_NT) void k_ball_normals(long N, uint64_t seed, uint64_t draw, double *__restrict__ z,
+                                                        double *partial) {
+  __shared__ double scratch[32];
+  double a = 0.0, b = 0.0;
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < N; i += (long)gridDim.x * EW_NT) {
+    const Philox4 w = philox4x64((uint64_t)i, 0, 0, 0, seed, draw);
+    const double v = sqrt(-2.0 * log(unit_open(w.w[0]))) * cos(6.283185307179586476925286766559 * unit_open(w.w[1]));
+    z[i] = v;
+    a += v;
+    b += v * v;
+  }
+  const double sa = block_sum<EW_NT>(a, scratch);
+  const double sb = block_sum<EW_NT>(b, scratch + 16);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sa;
+    partial[2 * blockIdx.x + 1] = sb;
+  }
+}
+// f = [r u^(1/(N-1)) / rms(z - mean z), mean z] with u from counter (0, 1, 0, 0)
+__global__ void k_ball_factor(long N, double r, uint64_t seed, uint64_t draw, const double *sums, double *f) {
+  if (threadIdx.x != 0) return;
+  const double zbar = sums[0] / (double)N;
+  const double var = sums[1] / (double)N - zbar * zbar;
+  const double u = unit_open(philox4x64(0, 1, 0, 0, seed, draw).w[0]);
+  f[0] = r * pow(u, 1.0 / (double)(N - 1)) / sqrt(var);
+  f[1] = zbar;
+}
+__global__ __launch_bounds__(EW_NT) void k_ball_scale(long N, const double *__restrict__ f, double *z) {
+  const double c = f[0], zbar = f[1];
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < N; i += (long)gridDim.x * EW_NT) z[i] = c * (z[i] - zbar);
+}
+
 // Per-workgroup partial sums [psi^2, psi^3, w psi, w psi^2] over instance b's
 // N points (w nullable: zeros); partial[(b * bpi + block) * 4 + q]
 __global__ __launch_bounds__(EW_NT) void k_field_moments(long N, int bpi, const double *__restrict__ psi,

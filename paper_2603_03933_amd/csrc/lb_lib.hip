@@ -1092,6 +1092,11 @@ extern "C" void lb_tr_opts_default(lb_tr_opts *o) {
   o->cg_rtol = 1e-12;
   o->cg_maxiter = 1000;
   o->verbose = 0;
+  o->hard_case = 0;
+  o->hard_tol = 1e-12;
+  o->hard_lanczos_steps = 30;
+  o->hard_precond_shift = 1.0;
+  o->seed = 0;
 }
 
 static int check_sub_opts(const lb_sub_opts &o) {
@@ -1248,7 +1253,9 @@ static void prec_scale(lb_plan *P, const Prm &p, const double2 *x, double c, dou
 // Lanczos with full reorthogonalisation on H, or with c > 0 on K = S H S,
 // S = (Lambda + c)^(-1/2) (congruent to H, same inertia, clustered spectrum);
 // then the Rayleigh quotient of H at x = S y for the lowest Ritz vector y.
-static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, double c, double *ritz, double *resid) {
+// vec_out (nullable, may alias v0): the unit Ritz vector (Psi_hat coordinates)
+static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, double c, double *ritz, double *resid,
+                        double2 *vec_out = nullptr) {
   if ((int)P->lz.size() < steps + 1) {
     while ((int)P->lz.size() < steps + 1) {
       void *q = nullptr;
@@ -1304,6 +1311,13 @@ static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, 
   if (!pc) {
     *ritz = A[(size_t)imin * m + imin];
     *resid = std::fabs(beta[m - 1] * V[(size_t)(m - 1) * m + imin]);
+    if (vec_out) {
+      lincomb64(P, n, 0.0, P->lz[0], 0.0, P->lz[0], P->R);
+      for (int i = 0; i < m; ++i) lincomb64(P, n, V[(size_t)i * m + imin], P->lz[i], 1.0, P->R, P->R);
+      double yy;
+      LB_TRY(spec_dot_host(P, p, P->R, P->R, &yy));
+      lincomb64(P, n, 1.0 / std::sqrt(yy), P->R, 0.0, P->R, vec_out);
+    }
     return 0;
   }
   // y = sum_i V[i, imin] q_i ; x = S y ; rho = <x, Hx> / <x, x>
@@ -1320,11 +1334,44 @@ static int lanczos_core(lb_plan *P, const Prm &p, const double2 *v0, int steps, 
   LB_TRY(spec_dot_host(P, p, P->AP, P->AP, &rr));
   *ritz = rho;
   *resid = std::sqrt(std::max(rr, 0.0) / xx);
+  if (vec_out) lincomb64(P, n, 1.0 / std::sqrt(xx), P->Pv, 0.0, P->Pv, vec_out);
   return 0;
 }
 
+// Uniform point of the ball ||d|| <= r in the zero-mean subspace (physical
+// field, batch 1): normals from Philox4x64-10 at counter (x, 0, 0, 0), key
+// (seed, draw), centred, scaled to radius r u^(1/(N-1)), u from counter
+// (0, 1, 0, 0).
+static int ball_point(lb_plan *P, double r, unsigned long long seed, unsigned long long draw, double *out) {
+  const int nb = (int)std::min<long>(cdiv(P->N, lbk::EW_NT), 1024);
+  {
+    KT kt_(P, "ball_normals");
+    LB_LAUNCH(lbk::k_ball_normals, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, (uint64_t)seed, (uint64_t)draw, out,
+              P->partial);
+  }
+  finalize(P, P->partial, nb, 2, 0u, 1, P->sums);
+  {
+    KT kt_(P, "ball_factor");
+    LB_LAUNCH(lbk::k_ball_factor, dim3(1), dim3(64), 0, P->stream, P->N, r, (uint64_t)seed, (uint64_t)draw,
+              (const double *)P->sums, P->sums + 8);
+  }
+  {
+    KT kt_(P, "ball_scale");
+    LB_LAUNCH(lbk::k_ball_scale, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, (const double *)(P->sums + 8), out);
+  }
+  return check_launch("ball_point");
+}
+
+extern "C" int lb_random_ball(lb_plan *P, double radius, unsigned long long seed, unsigned long long draw,
+                              double *d_out) {
+  if (!P || !d_out) return fail(LB_ERR_ARG, "null argument");
+  if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_random_ball needs a plan with batch 1");
+  if (!(radius > 0) || !std::isfinite(radius)) return fail(LB_ERR_ARG, "radius must be positive");
+  return ball_point(P, radius, seed, draw, d_out);
+}
+
 extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double *psi, const double *v0, int steps,
-                              double precond_shift, double *ritz_min, double *resid) {
+                              double precond_shift, double *ritz_min, double *resid, double *evec) {
   if (!P || !psi || !v0 || !ritz_min || !resid) return fail(LB_ERR_ARG, "null argument");
   if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_lanczos_min needs a plan with batch 1");
   if (steps < 1 || steps > 1000) return fail(LB_ERR_ARG, "steps must be in [1, 1000]");
@@ -1338,7 +1385,8 @@ extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double 
   fwd_r2c(P, LB_FP64, 1, p, v0, P->R, 1);
   if (!std::isfinite(precond_shift)) return fail(LB_ERR_ARG, "precond_shift must be finite");
   lincomb64(P, P->nh, 1.0, P->R, 0.0, P->R, P->SH);  // start vector out of the work buffers
-  LB_TRY(lanczos_core(P, p, P->SH, steps, precond_shift, ritz_min, resid));
+  LB_TRY(lanczos_core(P, p, P->SH, steps, precond_shift, ritz_min, resid, evec ? P->SH : nullptr));
+  if (evec) inv_c2r(P, LB_FP64, 1, p, P->SH, P->W64, evec, 0, nullptr, nullptr);
   return check_launch("lb_lanczos_min");
 }
 
@@ -1416,6 +1464,8 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
   if (!(o.theta > 0 && o.theta < 1) || !(o.gamma_c > 0 && o.gamma_c < 1) || !(o.gamma_e > 1) || !(o.gamma_lambda > 1) ||
       !(o.mu_lo > 0 && o.mu_lo <= o.mu_hi) || !(o.mu0 >= o.mu_lo) || !(o.r0 > 0 && o.r0 <= o.nu0) || !(o.eps > 0))
     return fail(LB_ERR_ARG, "bad trust-region options");
+  if (o.hard_case && (o.hard_lanczos_steps < 1 || o.hard_lanczos_steps > 1000 || !(o.hard_tol >= 0)))
+    return fail(LB_ERR_ARG, "bad hard-case options");
   Prm p;
   LB_TRY(pack_params(P, params, 1, &p));
   std::memset(info, 0, sizeof(*info));
@@ -1434,8 +1484,26 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
     }
     lb_sub_opts so = o.sub;
     so.eta = o.eta_safe && eg.gpmax > 0 ? std::min(o.eta, 0.9 / eg.gpmax) : o.eta;
+    // nearly hard subproblem (Remark on the hard case): sigma_1 < 0 and
+    // |<xi, g>| <= hard_tol -> start Algorithm 3 from a random point of the ball
+    const double2 *d0_spec = nullptr;
+    if (o.hard_case) {
+      LB_TRY(ball_point(P, 1.0, o.seed, 2ull * (unsigned long long)j + 1ull, P->sphys));
+      fwd_r2c(P, LB_FP64, 1, p, P->sphys, P->R, 1);
+      lincomb64(P, P->nh, 1.0, P->R, 0.0, P->R, P->SH);
+      double sig, res, g1;
+      LB_TRY(lanczos_core(P, p, P->SH, o.hard_lanczos_steps, o.hard_precond_shift, &sig, &res, P->SH));
+      LB_TRY(spec_dot_host(P, p, P->GH, P->SH, &g1));
+      if (sig < 0.0 && std::fabs(g1) <= o.hard_tol) {
+        LB_TRY(ball_point(P, r, o.seed, 2ull * (unsigned long long)j, P->sphys));
+        fwd_r2c(P, LB_FP64, 1, p, P->sphys, P->R, 1);
+        d0_spec = P->R;
+        info->hard_cases++;
+      }
+      if (o.verbose) std::fprintf(stderr, "[lb] j=%d sigma1~%.6e g1=%.3e%s\n", j, sig, g1, d0_spec ? " hard" : "");
+    }
     SubOut sub;
-    LB_TRY(run_subproblem(P, p, r, so, eg.gnorm, nullptr, &sub));
+    LB_TRY(run_subproblem(P, p, r, so, eg.gnorm, d0_spec, &sub));
     info->inner_total += sub.iters;
     const double lam = sub.lam, sn = sub.dnorm;
     if (!(sn > 0)) return fail(LB_ERR_NONFINITE, "zero trial step");

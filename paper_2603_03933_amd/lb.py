@@ -83,6 +83,11 @@ class LbTrOpts(C.Structure):
         ("cg_rtol", C.c_double),
         ("cg_maxiter", C.c_int),
         ("verbose", C.c_int),
+        ("hard_case", C.c_int),
+        ("hard_tol", C.c_double),
+        ("hard_lanczos_steps", C.c_int),
+        ("hard_precond_shift", C.c_double),
+        ("seed", C.c_ulonglong),
     ]
 
 
@@ -98,6 +103,7 @@ class LbTrInfo(C.Structure):
         ("contracted", C.c_int),
         ("expanded", C.c_int),
         ("status", C.c_int),
+        ("hard_cases", C.c_int),
     ]
 
 
@@ -131,7 +137,8 @@ _SIGS = {
     "lb_tr_subproblem": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, C.POINTER(LbSubOpts), _P, _P, C.POINTER(LbSubInfo)]),
     "lb_imex_tr_solve": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo)]),
     "lb_shifted_solve": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, _D, _I, _P, C.POINTER(_I)]),
-    "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, _D, C.POINTER(_D), C.POINTER(_D)]),
+    "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, _D, C.POINTER(_D), C.POINTER(_D), _P]),
+    "lb_random_ball": (_I, [_P, _D, C.c_ulonglong, C.c_ulonglong, _P]),
 }
 
 
@@ -337,12 +344,20 @@ class Plan:
         _check(lib().lb_shifted_solve(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(grad, self.N, "grad"), float(shift), float(rtol), int(maxiter), _ptr(out, self.N, "s_out"), C.byref(it)))
         return out, it.value
 
-    def lb_lanczos_min(self, params, psi, v0, steps, precond_shift=0.0):
+    def lb_lanczos_min(self, params, psi, v0, steps, precond_shift=0.0, evec=None):
+        """(ritz, residual); with evec (a device tensor) also the unit Ritz vector in it."""
         self._sync_stream()
         ritz = C.c_double()
         res = C.c_double()
-        _check(lib().lb_lanczos_min(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(v0, self.N, "v0"), int(steps), float(precond_shift), C.byref(ritz), C.byref(res)))
+        _check(lib().lb_lanczos_min(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(v0, self.N, "v0"), int(steps), float(precond_shift), C.byref(ritz), C.byref(res), _ptr(evec, self.N, "evec")))
         return ritz.value, res.value
+
+    def lb_random_ball(self, radius, seed, draw, out=None, device=None):
+        self._sync_stream()
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=device or torch.device("cuda"))
+        _check(lib().lb_random_ball(self._h, float(radius), int(seed), int(draw), _ptr(out, self.N, "d_out")))
+        return out
 
 
 def exported_symbols():

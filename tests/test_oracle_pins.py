@@ -148,6 +148,65 @@ def test_paper_hex_energies():
 
 
 # ---------------------------------------------------------------------------
+# Nearly hard subproblems: random feasible initial point
+# ---------------------------------------------------------------------------
+
+
+def test_philox_matches_numpy_generator():
+    """The oracle's Philox4x64-10 against numpy's implementation of the same
+    published generator (numpy emits the block of counter + 1 first)."""
+    for key in [(0, 0), (0x1234, 0x5678), (2**64 - 1, 12345)]:
+        ctr = np.arange(6, dtype=np.uint64)
+        w = np.stack(O.philox4x64([ctr, 0, 0, 0], key), 1)
+        bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array([2**64 - 1] * 4, dtype=np.uint64))
+        assert np.array_equal(w, bg.random_raw(24).reshape(6, 4))
+    # words 1..3 of the counter carry into the rounds too
+    bg = np.random.Philox(key=np.array([7, 9], dtype=np.uint64), counter=np.array([2**64 - 1, 4, 5, 6], dtype=np.uint64))
+    w = np.stack(O.philox4x64([np.array([0], dtype=np.uint64), 5, 5, 6], (7, 9)), 1)
+    assert np.array_equal(w, bg.random_raw(4).reshape(1, 4))
+
+
+def test_ball_point_is_uniform_in_the_zero_mean_ball():
+    """Feasible (||d|| <= r, mean 0) and uniform: in the (N-1)-dimensional ball the
+    radius fraction t = ||d|| / r has P(t <= s) = s^(N-1) (Kolmogorov-Smirnov),
+    and the direction has mean zero."""
+    shape, r = (2, 2), 0.7  # a 3-dimensional ball
+    ds = np.stack([O.ball_point(shape, r, 11, k).ravel() for k in range(800)])
+    assert np.max(np.abs(ds.mean(axis=1))) < 1e-15
+    t = np.sqrt(np.mean(ds**2, axis=1)) / r
+    assert np.all(t <= 1.0)
+    ts = np.sort(t ** 3)  # uniform on (0, 1) if the radius law is right
+    ks = np.max(np.abs(ts - (np.arange(1, 801) - 0.5) / 800))
+    assert ks < 1.63 / math.sqrt(800)  # 1 % level
+    assert np.linalg.norm(ds.mean(axis=0)) < 4 * r / math.sqrt(800)
+
+
+@pytest.mark.slow
+def test_hard_case_strategy_reproduces_section_4_3():
+    """Section 4.3: from the LAM state of Example 1's box at (tau, gamma) =
+    (-0.09, 0.34) the subproblems are nearly hard (|g^(1)| <= 1e-12). With the
+    deterministic start -r g/||g|| the solve ends at a state with a negative
+    Hessian eigenvalue; with the random feasible start it reaches the HEX
+    phase at the printed energy with a nonnegative spectrum (up to the zero
+    translation modes). 8^3 grid: the LAM and HEX modes are unaliased."""
+    gold = json.load(open(os.path.join(GOLDEN, "paper_energies.json")))["hard_case_experiment"]
+    M, L = 8, 2 * math.sqrt(2) * math.pi
+    g = O.Grid((M, M, M), (L, L, L))
+    m = O.Model(g, gold["tau"], gold["gamma"])
+    x = np.arange(M) * L / M
+    psi0 = 0.6 * np.cos(x[:, None, None] / math.sqrt(2)) + np.zeros((M, M, M))
+    opts = O.TROpts(eps=1e-10, max_outer=400, max_inner=20000)
+    det = O.imex_tr_solve(m, psi0, opts)
+    assert det.converged and O.hessian_eigs(m, det.psi)[0] < -1e-3  # not an SP-II
+    log = []
+    ran = O.imex_tr_solve(m, psi0, opts, d0_provider=O.hard_case_d0_provider(m, seed=1, tol=gold["hard_tol"], log=log))
+    assert ran.converged and any(e["hard"] for e in log)
+    assert all(abs(e["g1"]) <= gold["hard_tol"] for e in log if e["hard"])
+    assert abs(ran.energy - gold["randomized_energy"]) <= 0.5e-4  # printed to three figures
+    assert O.hessian_eigs(m, ran.psi)[0] >= -1e-8
+
+
+# ---------------------------------------------------------------------------
 # Derivatives: exact identities for a quartic energy
 # ---------------------------------------------------------------------------
 

@@ -119,6 +119,43 @@ def cpu_baseline(inst, inner_total: int, outer_total: int, cg_total: int, budget
     }
 
 
+SWEEP_CAPS = {"max_outer": 100, "max_inner": 2000, "eps_sub_rel": 1e-6}
+
+
+def phase_sweep(args, torch, I, lb, dev):
+    """64 independent 2D solves (n in {64..512}^2, (tau, gamma) on an 8 x 8 grid)
+    through lb_imex_tr_solve_many; aggregate solves/s. Capped (the tau = 0 row
+    has a degenerate quartic minimum and converges sublinearly)."""
+    insts = I.phase_sweep(64)
+    prec = args.sweep_precision
+    plans = [lb.Plan(i.grid.n, i.grid.box, precision=prec) for i in insts]
+    prms = [lb.Params(i.params.tau, i.params.gamma) for i in insts]
+    opts = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=SWEEP_CAPS["max_outer"],
+                      sub={"max_inner": SWEEP_CAPS["max_inner"], "poll_every": 64, "eps_sub_rel": SWEEP_CAPS["eps_sub_rel"]})
+    psis = [torch.from_numpy(i.psi0).to(dev) for i in insts]
+    order = sorted(range(len(insts)), key=lambda k: -insts[k].grid.n[0])
+    res = [None] * len(insts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c0 in range(0, len(order), 16):  # progress after every 16 solves
+        ids = order[c0:c0 + 16]
+        out = lb.lb_imex_tr_solve_many([plans[k] for k in ids], [prms[k] for k in ids], [psis[k] for k in ids], opts,
+                                       workers=args.sweep_workers)
+        for k, r in zip(ids, out):
+            res[k] = r
+        print(f"phase sweep: {c0 + len(ids)}/{len(order)} solves, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({
+        "metric": "IMEX-TR solves/s, 64-instance 2D phase sweep (concurrent)", "value": len(insts) / dt, "unit": "solves/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "phase_sweep 64 x 2D, n in {64,96,128,256,512}, box 8 pi n/64, tau x gamma 8 x 8",
+                   "caps": SWEEP_CAPS, "tol": TOL, "workers": args.sweep_workers},
+        "seconds": dt, "converged": sum(1 for _, rc in res if rc == 0),
+        "outer": sum(i.outer for i, _ in res), "inner": sum(i.inner_total for i, _ in res),
+    }), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -132,6 +169,10 @@ def main():
                     help="only run K iterations of Algorithm 3 on the workload (for counter collection) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales HBM counters) and exit")
+    ap.add_argument("--phase-sweep", action="store_true",
+                    help="only run the 64-instance 2D phase sweep (concurrent solves) and exit")
+    ap.add_argument("--sweep-precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--sweep-workers", type=int, default=4)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -151,6 +192,9 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"kernel": "torch.neg float64", "read_bytes": 8 << 27, "write_bytes": 8 << 27, "launches": 5}}))
+        return
+    if args.phase_sweep:
+        phase_sweep(args, torch, I, lb, dev)
         return
     inst = I.bcc_3d(args.size)
     n, box = inst.grid.n, inst.grid.box

@@ -285,6 +285,20 @@ int lb_lanczos_min(lb_plan *plan, const lb_params *params, const double *psi, co
  * Asynchronous. */
 int lb_random_ball(lb_plan *plan, double radius, unsigned long long seed, unsigned long long draw, double *d_out);
 
+/* `count` independent IMEX-TR solves (lb_imex_tr_solve each), e.g. a sweep of
+ * instances of different grid sizes and parameters, run concurrently: a pool
+ * of `workers` host threads, each with its own HIP stream, takes the jobs
+ * largest grid first. Job i solves on plans[i] (distinct plans of batch 1)
+ * with params[i] (host) and the field psi[i] (device, N_i doubles, updated);
+ * opts (nullable: defaults) apply to all. Each job starts after the work
+ * already enqueued on its plan's stream, and later work on that stream sees
+ * its result. infos[i] and status[i] (host, written) are the job's
+ * lb_tr_info and return code. Returns LB_OK when no job failed, else the first
+ * failing job's code (its message in lb_last_error). Blocks until all jobs
+ * are done. */
+int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double *const *psi, int count,
+                          const lb_tr_opts *opts, int workers, lb_tr_info *infos, int *status);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,11 +5,13 @@
 // every array operation runs in the kernels of kernels.hpp / fft.hpp.
 #define LB_MAIN_TU 1
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -1601,3 +1603,81 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
   info->status = status;
   return status;
 }
+
+// ---------------------------------------------------------------------------
+// Many independent solves at once (instances of different sizes and
+// parameters): a pool of host threads, each with its own HIP stream, takes
+// jobs largest first and runs the host-driven outer loop of each on its own
+// plan, so that the small, latency-bound launches of different instances
+// overlap on the GPU.
+// ---------------------------------------------------------------------------
+extern "C" int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double *const *psi, int count,
+                                     const lb_tr_opts *opts, int workers, lb_tr_info *infos, int *status) {
+  if (count < 0 || (count > 0 && (!plans || !params || !psi || !infos || !status)))
+    return fail(LB_ERR_ARG, "null argument");
+  if (count == 0) return LB_OK;
+  if (workers < 1) return fail(LB_ERR_ARG, "workers must be >= 1");
+  workers = std::min(workers, count);
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !psi[i]) return fail(LB_ERR_ARG, "null plan or field");
+    if (plans[i]->batch != 1) return fail(LB_ERR_MISMATCH, "lb_imex_tr_solve_many needs plans with batch 1");
+    for (int k = 0; k < i; ++k)
+      if (plans[k] == plans[i]) return fail(LB_ERR_ARG, "a plan appears in two jobs");
+  }
+  // the fields are ready on each plan's stream: the workers wait for that point
+  std::vector<hipEvent_t> ready(count, nullptr);
+  for (int i = 0; i < count; ++i) {
+    LB_HIP(hipEventCreateWithFlags(&ready[i], hipEventDisableTiming));
+    LB_HIP(hipEventRecord(ready[i], plans[i]->stream));
+  }
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plans[a]->N > plans[b]->N; });
+  std::atomic<int> next{0};
+  std::vector<std::string> errs(count);
+  auto work = [&]() {
+    hipStream_t ws = nullptr;
+    if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = nullptr;
+    for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) {
+      const int i = order[q];
+      lb_plan *P = plans[i];
+      std::memset(&infos[i], 0, sizeof(lb_tr_info));
+      if (!ws) {
+        status[i] = LB_ERR_HIP;
+        errs[i] = "hipStreamCreate failed";
+        continue;
+      }
+      const hipStream_t orig = P->stream;
+      int rc = hipStreamWaitEvent(ws, ready[i], 0) == hipSuccess ? LB_OK : LB_ERR_HIP;
+      if (rc == LB_OK) {
+        P->stream = ws;
+        rc = lb_imex_tr_solve(P, &params[i], psi[i], opts, &infos[i]);
+        if (rc < 0) errs[i] = g_last_error;
+        // later work on the plan's own stream sees the result
+        hipEvent_t done;
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess) {
+          (void)hipEventRecord(done, ws);
+          (void)hipStreamWaitEvent(orig, done, 0);
+          (void)hipEventDestroy(done);
+        }
+        P->stream = orig;
+      } else {
+        errs[i] = "hipStreamWaitEvent failed";
+      }
+      status[i] = rc;
+    }
+    if (ws) {
+      (void)hipStreamSynchronize(ws);
+      (void)hipStreamDestroy(ws);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < workers; ++w) pool.emplace_back(work);
+  work();
+  for (auto &t : pool) t.join();
+  for (int i = 0; i < count; ++i) (void)hipEventDestroy(ready[i]);
+  for (int i = 0; i < count; ++i)
+    if (status[i] < 0) return fail(status[i], "job " + std::to_string(i) + ": " + errs[i]);
+  return LB_OK;
+}
+

@@ -139,6 +139,7 @@ _SIGS = {
     "lb_shifted_solve": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, _D, _I, _P, C.POINTER(_I)]),
     "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, _D, C.POINTER(_D), C.POINTER(_D), _P]),
     "lb_random_ball": (_I, [_P, _D, C.c_ulonglong, C.c_ulonglong, _P]),
+    "lb_imex_tr_solve_many": (_I, [C.POINTER(_P), C.POINTER(LbParams), C.POINTER(_P), _I, C.POINTER(LbTrOpts), _I, C.POINTER(LbTrInfo), C.POINTER(_I)]),
 }
 
 
@@ -358,6 +359,24 @@ class Plan:
             out = torch.empty(self.n, dtype=torch.float64, device=device or torch.device("cuda"))
         _check(lib().lb_random_ball(self._h, float(radius), int(seed), int(draw), _ptr(out, self.N, "d_out")))
         return out
+
+
+def lb_imex_tr_solve_many(plans, params, psis, opts: Optional[LbTrOpts] = None, workers: int = 4):
+    """Concurrent independent solves (one per plan); returns [(info, rc)]."""
+    n = len(plans)
+    if len(params) != n or len(psis) != n:
+        raise ValueError("plans, params and psis must have the same length")
+    for pl in plans:
+        pl._sync_stream()
+    hp = (_P * n)(*[pl._h for pl in plans])
+    pa = (LbParams * n)()
+    for i, p in enumerate(params):
+        pa[i] = LbParams(float(p.tau), float(p.gamma), float(getattr(p, "xi", 1.0)), float(getattr(p, "q", 1.0)))
+    ps = (_P * n)(*[_ptr(x, pl.N, "psi") for x, pl in zip(psis, plans)])
+    infos = (LbTrInfo * n)()
+    st = (_I * n)()
+    _check(lib().lb_imex_tr_solve_many(hp, pa, ps, n, C.byref(opts) if opts is not None else None, int(workers), infos, st))
+    return [(infos[i], st[i]) for i in range(n)]
 
 
 def exported_symbols():

@@ -245,14 +245,27 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
   const int ml = lb * CC + c;
   const bool ok = ml < cg.cpi;
-  const int mo = ml / cg.inner;
-  const long base = b * cg.inst + (long)mo * cg.outer + (ml - mo * cg.inner);
+  // columns past the end (ragged last workgroup) address column 0; with
+  // Op::eager_loads they also load it and discard the values, so that every
+  // load is unconditional and all of a thread's loads are in flight together
+  // (one branch, and one memory latency, per element otherwise). Ops whose
+  // first pass holds many registers keep the branch (higher occupancy).
+  const int mls = ok ? ml : 0;
+  const int mo = mls / cg.inner;
+  const long base = b * cg.inst + (long)mo * cg.outer + (mls - mo * cg.inner);
   const auto bs = op.begin(b);
-  const auto cs = op.column(b, ok ? ml : 0);
+  const auto cs = op.column(b, mls);
   double acc = 0.0;
   fft_run<T, N, INV>(
       t, c, lds, [](int cc, int e) { return e * CC + cc; }, tw,
-      [&](int e) -> C { return ok ? op.load(bs, cs, base + e * cg.S, e) : C{T(0), T(0)}; },
+      [&](int e) -> C {
+        if constexpr (Op::eager_loads) {
+          const C v = op.load(bs, cs, base + e * cg.S, e);
+          return ok ? v : C{T(0), T(0)};
+        } else {
+          return ok ? op.load(bs, cs, base + e * cg.S, e) : C{T(0), T(0)};
+        }
+      },
       [&](int e) { return op.fetch(bs, cs, ok, base + e * cg.S, e); },
       [&](int e, C v, const auto &aux) {
         double *sq = reinterpret_cast<double *>(lds) + e * CC + c;
@@ -267,6 +280,7 @@ struct Empty {};
 // plain pass: out = scale * FFT(in); optional removal of the k = 0 mode
 // (zero_dc only on the final axis-0 pass)
 template <typename T> struct OpPlain {
+  static constexpr bool eager_loads = true;
   const c2<T> *in;
   c2<T> *out;
   T scale;
@@ -294,6 +308,7 @@ template <typename T> struct StepBlk {
 
 // step t of the subproblem, axis-0 inverse pass: d_t = b_{t-1} / (1 + eta (Lambda + lambda_t))
 template <typename T> struct OpInvScaleD {
+  static constexpr bool eager_loads = true;
   Geo g;
   Prm p;
   const c2<T> *b0, *b1;  // b buffers: b_{t-1} lives in (t - 1) & 1
@@ -313,10 +328,9 @@ template <typename T> struct OpInvScaleD {
   }
   __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
   __device__ c2<T> load(const StepBlk<T> &bs, const ColInfo &ci, long h, int e) const {
-    if (ci.dc && e == 0) return c2<T>{T(0), T(0)};
-    const double lam = lam_of(g.kk0[e] + ci.kkc, bs.xi, bs.q);
-    const double s = rcp64(1.0 + bs.eta * (lam + bs.lam_t));
     const c2<T> v = bs.bprev[h];
+    const double lam = lam_of(g.kk0[e] + ci.kkc, bs.xi, bs.q);
+    const double s = (ci.dc && e == 0) ? 0.0 : rcp64(1.0 + bs.eta * (lam + bs.lam_t));
     return c2<T>{T(double(v.x) * s), T(double(v.y) * s)};
   }
   __device__ Empty fetch(const StepBlk<T> &, const ColInfo &, bool, long, int) const { return Empty{}; }
@@ -335,6 +349,7 @@ template <typename T> struct UpdAux {
   double kk0;
 };
 template <typename T> struct OpFwdUpdate {
+  static constexpr bool eager_loads = false;
   Geo g;
   Prm p;
   const c2<T> *tmp;  // row/axis-1 transformed product Gamma' d_t
@@ -465,6 +480,7 @@ template <typename T> struct HessAux {
   double kk0;
 };
 template <typename T> struct OpFwdHess {
+  static constexpr bool eager_loads = false;
   Geo g;
   Prm p;
   const c2<T> *tmp;
@@ -477,7 +493,8 @@ template <typename T> struct OpFwdHess {
   __device__ c2<T> load(const HessBlk &, const ColInfo &, long h, int) const { return tmp[h]; }
   __device__ HessAux<T> fetch(const HessBlk &, const ColInfo &, bool ok, long h, int e) const {
     HessAux<T> a;
-    a.xv = ok ? x[h] : c2<T>{T(0), T(0)};
+    const c2<T> xv = x[h];  // h is a valid address for every thread
+    a.xv = ok ? xv : c2<T>{T(0), T(0)};
     a.kk0 = g.kk0[e];
     return a;
   }
@@ -506,12 +523,16 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
   const int ml = lb * CC + c;
   const bool ok = ml < cg.cpi;
-  const long base = b * cg.inst + ml;  // axis 0: every column starts in the first slab
+  const long base = b * cg.inst + (ok ? ml : 0);  // axis 0: every column starts in the first slab
   const ColInfo ci = col_info(g, ok ? ml : 0);
   const double xi = p.xi[b], q = p.q[b];
   auto lidx = [](int cc, int e) { return e * CC + cc; };
   fft_run<T, N, false>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return ok ? data[base + e * cg.S] : C{T(0), T(0)}; },
+      t, c, lds, lidx, tw,
+      [&](int e) -> C {
+        const C v = data[base + e * cg.S];
+        return ok ? v : C{T(0), T(0)};
+      },
       [&](int e) { return g.kk0[e]; },
       [&](int e, C v, double kk0) {
         double m = lam_of(kk0 + ci.kkc, xi, q) * inv_n;

@@ -94,7 +94,9 @@ constexpr int pow2_floor(int x) {
 }
 template <int N> struct Cfg {
   static constexpr int TPF = Shape<N>::TPF;
-  static constexpr int C0 = pow2_floor(256 / TPF);
+  // 256 threads, or 512 for long transforms so that a workgroup still spans
+  // 16 adjacent columns (>= 128 B runs per row in FP32)
+  static constexpr int C0 = pow2_floor((TPF >= 32 ? 512 : 256) / TPF);
   static constexpr int C = C0 > 64 ? 64 : (C0 < 1 ? 1 : C0);  // transforms per workgroup
   static constexpr int NT = C * TPF;                            // threads per workgroup
 };

@@ -1,0 +1,114 @@
+"""GPU: the largest configuration (256^3, FP64 and FP32) against the oracle,
+degenerate inputs (psi = 0, the interior and the tiny-radius subproblem), and
+limits of the plan."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lb_oracle as O
+from paper_2603_03933_amd import inputs as I
+from paper_2603_03933_amd import lb
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rms(a):
+    return math.sqrt(float(np.mean(a * a)))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_large_256_energy_gradient_hessvec(precision, tol):
+    """The 256^3 workload (N(0, 0.05^2) start) at full size, every element."""
+    inst = I.large_3d(256)
+    shape, box = inst.grid.n, inst.grid.box
+    m = O.Model(O.Grid(shape, box), inst.params.tau, inst.params.gamma)
+    v = I.hessvec_direction(shape, 1)
+    plan = lb.Plan(shape, box, precision=precision)
+    prm = lb.Params(m.tau, m.gamma)
+    E, g = plan.lb_energy_grad(prm, dev(inst.psi0))
+    hv = plan.lb_hessvec(prm, dev(inst.psi0), dev(v))
+    G, Fb = O.energy_parts(m, inst.psi0)
+    assert abs(host(E)[0] - (G + Fb)) <= 1e-12 * (abs(G) + float(np.mean(np.abs(O.F_bulk(inst.psi0, m.tau, m.gamma)))))
+    go = O.gradient_phys(m, inst.psi0)
+    gs = rms(O.inv(m.Lam * O.fwd(inst.psi0))) + rms(O.dF_bulk(inst.psi0, m.tau, m.gamma))
+    assert rms(host(g) - go) <= 1e-12 * gs  # energy and gradient are FP64 in both precisions
+    del go
+    ho = O.hessvec_phys(m, inst.psi0, v)
+    hs = rms(O.inv(m.Lam * O.fwd(v))) + rms(O.Gamma_p(inst.psi0, m.tau, m.gamma) * v)
+    assert rms(host(hv) - ho) <= tol * hs
+
+
+def test_large_256_subproblem_iterations_fp32():
+    """Five iterations of Algorithm 3 at 256^3 in FP32 against the oracle's five (FP64)."""
+    inst = I.large_3d(256)
+    shape, box = inst.grid.n, inst.grid.box
+    m = O.Model(O.Grid(shape, box), inst.params.tau, inst.params.gamma)
+    g_hat = O.gradient(m, inst.psi0)
+    r = 0.02
+    ref = O.imex_subproblem(m, inst.psi0, g_hat, r, O.SubOpts(eta=0.1, eps_sub=0.0, max_inner=5))
+    plan = lb.Plan(shape, box, precision="fp32")
+    d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(inst.psi0), dev(O.inv(g_hat)), r,
+                                        lb.sub_opts(eta=0.1, eps_sub=0.0, max_inner=5))
+    assert rc == lb.LB_NOT_CONVERGED and info.iters == 5
+    assert abs(info.lambda_ - ref.lam) <= 1e-5 * max(1.0, ref.lam)
+    assert rms(host(d) - O.inv(ref.d)) <= 1e-5 * rms(O.inv(ref.d))
+
+
+def test_psi_zero_is_a_stationary_point_with_hessian_lambda_plus_tau():
+    """psi = 0: E = 0, g = 0 (the solve returns at once) and H = Lambda + tau
+    in Fourier space (the psi = 0 spectrum)."""
+    shape, box = (32, 32, 32), (4 * math.sqrt(2) * math.pi,) * 3
+    m = O.Model(O.Grid(shape, box), -0.2, 0.3)
+    plan = lb.Plan(shape, box)
+    prm = lb.Params(m.tau, m.gamma)
+    z = torch.zeros(shape, dtype=torch.float64, device=DEV)
+    E, g = plan.lb_energy_grad(prm, z)
+    assert host(E)[0] == 0.0 and np.max(np.abs(host(g))) == 0.0
+    psi = z.clone()
+    info, rc = plan.lb_imex_tr_solve(prm, psi, lb.tr_opts())
+    assert rc == lb.LB_OK and info.outer == 0 and info.inner_total == 0
+    v = I.hessvec_direction(shape, 7)
+    hv = host(plan.lb_hessvec(prm, z, dev(v)))
+    ref = O.inv(O.project((m.Lam + m.tau) * O.fwd(v)))
+    assert np.max(np.abs(hv - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_tiny_radius_subproblem_is_a_scaled_steepest_descent_step():
+    """r -> 0: the minimiser tends to -r g/||g|| with lambda ~ ||g||/r (the linear term dominates)."""
+    shape, box = (16, 16), (2 * math.pi, 2 * math.pi)
+    m = O.Model(O.Grid(shape, box), -0.15, 0.25)
+    psi = I.zero_mean_noise(shape, 0.2, 3)
+    g_hat = O.gradient(m, psi)
+    r = 1e-7
+    plan = lb.Plan(shape, box)
+    d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), r, lb.sub_opts(eps_sub=1e-11))
+    ref = O.imex_subproblem(m, psi, g_hat, r, O.SubOpts(eps_sub=1e-11))
+    gphys = O.inv(g_hat)
+    assert rc == lb.LB_OK and ref.converged
+    assert abs(info.dnorm - r) <= 1e-12 * r
+    assert rms(host(d) + r * gphys / rms(gphys)) < 1e-5 * r
+    assert abs(info.lambda_ - ref.lam) < 1e-9 * ref.lam
+
+
+def test_plan_limits():
+    with pytest.raises(lb.LBError):
+        lb.Plan((16, 16), (1.0, 1.0), batch=9)  # at most 8 instances per plan
+    with pytest.raises(lb.LBError):
+        lb.Plan((16, 16), (1.0, 1.0), batch=0)
+    with pytest.raises(lb.LBError):
+        lb.Plan((16, 16, 1024), (1.0, 1.0, 1.0))  # longest transform is 512
+    plan = lb.Plan((16, 16), (1.0, 1.0), batch=2)
+    z = torch.zeros((2, 16, 16), dtype=torch.float64, device=DEV)
+    with pytest.raises(lb.LBError):  # the subproblem and the solve take one instance
+        plan.lb_imex_tr_solve(lb.Params(-0.1, 0.2), z[0].contiguous())

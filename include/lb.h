@@ -93,6 +93,9 @@ typedef struct lb_sub_opts {
                             printed; 0 (default): from power sums of |b|^2 taken once per
                             iteration (a truncated series with a rigorous tail bound far below
                             rounding), falling back to the full sum when the bound fails */
+  int single_workgroup;  /* 1 (default): on square 2D grids up to 64 x 64 one workgroup runs
+                            every iteration in a single launch (same arithmetic); 0: one
+                            launch sequence per iteration, as on every other grid */
 } lb_sub_opts;
 
 typedef struct lb_sub_info {

@@ -220,6 +220,92 @@ __device__ __forceinline__ double kk_pair(const Geo &g, int cpi, int i) {
   return g.kk0[e] + kk_col_part(g, i1, kl);
 }
 
+// Newton's method for the multiplier lambda_{t+1} (eq. lambda_update_rule)
+// from the power sums M (M[0] = phi(0), M[1 + m] = M_{m+2} around
+// mu0 = eta lambda_prev): the series with its tail bound where it holds,
+// else direct(lam, phi, dphi), a block-collective sum over the spectrum. Every
+// thread runs the same scalar iteration on the same values (uniform control
+// flow) and gets the same result. it / ndirect count steps / direct sums.
+struct NewtonPar {
+  double eta, r2, lam_prev, rtol, steptol;
+  int max_newton, form_phi, direct_only;
+};
+template <class Direct>
+__device__ double multiplier_newton(const double *M, const NewtonPar &np, const Direct &direct, int &it,
+                                    int &ndirect) {
+  const double eta = np.eta, r2 = np.r2, lam_prev = np.lam_prev;
+  const double mu0 = eta * lam_prev;
+  auto eval = [&](double lam, double &phi, double &dphi) {
+    const double D = eta * (lam - lam_prev);
+    const double rho = fabs(D) / (1.0 + mu0);
+    if (!np.direct_only && rho < 0.5) {
+      double rn = 1.0;
+#pragma unroll
+      for (int j = 0; j < NMOM; ++j) rn *= rho;
+      const double tail = M[1] * (NMOM + 1) * rn / ((1.0 - rho) * (1.0 - rho));
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int m = NMOM - 1; m >= 0; --m) a = fma(a, -D, (m + 1) * M[1 + m]);
+#pragma unroll
+      for (int m = NMOM - 2; m >= 0; --m) b = fma(b, -D, (double)((m + 1) * (m + 2)) * M[2 + m]);
+      if (tail <= 1e-17 * a) {
+        phi = a;
+        dphi = -eta * b;
+        return;
+      }
+    }
+    ++ndirect;
+    direct(lam, phi, dphi);
+  };
+  double lam = 0.0;
+  it = 0;
+  if (M[0] > r2) {  // phi(0) > r^2: the multiplier is the root of phi(lambda) = r^2
+    double phi, dphi;
+    if (np.form_phi || !(lam_prev > 0.0)) {
+      lam = 0.0;  // the printed iteration: Newton from lambda = 0
+      eval(0.0, phi, dphi);
+    } else {
+      lam = lam_prev;  // warm start at the previous multiplier
+      eval(lam, phi, dphi);
+    }
+    const double rr = sqrt(r2);
+    while (it < np.max_newton) {
+      if (phi >= r2 && phi - r2 <= np.rtol * r2) break;
+      double nl = np.form_phi ? lam - (phi - r2) / dphi : lam + 2.0 * phi * (1.0 - sqrt(phi) / rr) / dphi;
+      if (nl < 0.0) nl = 0.0;
+      ++it;
+      if (fabs(nl - lam) <= np.steptol * fmax(1.0, fabs(lam))) {
+        lam = nl;
+        break;
+      }
+      lam = nl;
+      eval(lam, phi, dphi);
+    }
+  }
+  return lam;
+}
+
+// sums of two values over a block of NT threads, returned to every thread
+template <int NT>
+__device__ __forceinline__ void block_sum2_nt(double &a, double &b, double *scratch /* >= 2 * NT / 64 */) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    scratch[w] = a;
+    scratch[NW + w] = b;
+  }
+  __syncthreads();
+  a = b = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    a += scratch[i];
+    b += scratch[NW + i];
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Column passes
 // ---------------------------------------------------------------------------
@@ -896,15 +982,19 @@ __device__ __forceinline__ void sk_lds_passes(c2<T> *buf, int fs, int es, const 
 // row passes pack half rows 2p, 2p+1 as one complex row Z_p of length N at
 // L[p 2 NH + x].
 
-// axis 1, inverse, first pass read from src (plane layout)
-template <typename T, int N, int NT>
-__device__ __forceinline__ void plane_cols_inv_from(c2<T> *L, const c2<T> *src, const c2<T> *__restrict__ tw) {
+// axis 1, inverse, first pass reading element (e, f) from load(f, e)
+template <typename T, int N, int NT, class Load>
+__device__ __forceinline__ void plane_cols_inv_load(c2<T> *L, const c2<T> *__restrict__ tw, const Load &load) {
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N);
-  sk_pass<T, N, true, NT, NH, true, 0, false>(
-      tw, [&](int f, int e) -> C { return src[e * NH + f]; }, [&](int f, int e, C v, int, int) { L[e * NH + f] = v; });
+  sk_pass<T, N, true, NT, NH, true, 0, false>(tw, load, [&](int f, int e, C v, int, int) { L[e * NH + f] = v; });
   __syncthreads();
   sk_lds_passes<T, N, true, NT, NH, true, 1, NP>(L, 1, NH, tw);
+}
+// ... from src (plane layout)
+template <typename T, int N, int NT>
+__device__ __forceinline__ void plane_cols_inv_from(c2<T> *L, const c2<T> *src, const c2<T> *__restrict__ tw) {
+  plane_cols_inv_load<T, N, NT>(L, tw, [&](int f, int e) -> c2<T> { return src[e * (N / 2 + 1) + f]; });
 }
 
 // rows, inverse: the first pass packs half rows 2p, 2p+1 into Z_p = A + i B;
@@ -937,9 +1027,9 @@ __device__ __forceinline__ void plane_rows_inv(c2<T> *L, const c2<T> *__restrict
 }
 
 // axis 1, forward: the first pass unpacks Z_p into half rows 2p, 2p+1; the
-// last pass writes to dst (plane layout)
-template <typename T, int N, int NT>
-__device__ __forceinline__ void plane_cols_fwd_to(c2<T> *L, c2<T> *dst, const c2<T> *__restrict__ tw) {
+// last pass hands element (e, f) to store_out(f, e, v, k, r)
+template <typename T, int N, int NT, class Store, bool LAST_MID = false>
+__device__ __forceinline__ void plane_cols_fwd_store(c2<T> *L, const c2<T> *__restrict__ tw, const Store &store_mem) {
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N);
   auto unpacked = [&](int k, int e) -> C {
@@ -948,7 +1038,6 @@ __device__ __forceinline__ void plane_cols_fwd_to(c2<T> *L, c2<T> *dst, const c2
     return (e & 1) ? C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)}
                    : C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
   };
-  auto store_mem = [&](int f, int e, C v, int, int) { dst[e * NH + f] = v; };
   auto store_lds = [&](int f, int e, C v, int, int) { L[e * NH + f] = v; };
   if constexpr (NP == 1) {
     sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_mem);
@@ -956,9 +1045,14 @@ __device__ __forceinline__ void plane_cols_fwd_to(c2<T> *L, c2<T> *dst, const c2
     sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_lds);
     __syncthreads();
     sk_lds_passes<T, N, false, NT, NH, true, 1, NP - 1>(L, 1, NH, tw);
-    sk_pass<T, N, false, NT, NH, true, NP - 1, false>(
+    sk_pass<T, N, false, NT, NH, true, NP - 1, LAST_MID>(
         tw, [&](int f, int e) -> C { return L[e * NH + f]; }, store_mem);
   }
+}
+// ... to dst (plane layout)
+template <typename T, int N, int NT>
+__device__ __forceinline__ void plane_cols_fwd_to(c2<T> *L, c2<T> *dst, const c2<T> *__restrict__ tw) {
+  plane_cols_fwd_store<T, N, NT>(L, tw, [&](int f, int e, c2<T> v, int, int) { dst[e * (N / 2 + 1) + f] = v; });
 }
 
 // Axes 1 and 2 of the inner iteration for one plane of fixed k0: inverse
@@ -1062,6 +1156,149 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np,
     hv[ia] = double(z.x) + bscale * ((tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean);
     hv[ib] = double(z.y) + bscale * ((tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean);
   });
+}
+
+// Algorithm 3 for one square 2D instance (N x N, the half spectrum held in
+// LDS like a plane) in a single workgroup that runs every iteration itself:
+//   d_t = b_{t-1} / (1 + eta (Lambda + lambda_t)), T d_t = P F_N(Gamma' F_N^{-1} d_t),
+//   residual of d_t, b_t = d_t - eta (g + T d_t), phi(0) and the power sums of
+//   w |b_t|^2, then the stop test and Newton for lambda_{t+1},
+// until the stop test holds or t reaches max_inner. b_t goes to b[t & 1]
+// (global memory, cached), so the result is read as for the multi-kernel
+// iteration; SubState is read at the start and written at the end.
+template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restrict__ tw, c2<T> *b0, c2<T> *b1,
+                                              const c2<T> *__restrict__ gh, const T *__restrict__ gp, SubState *st) {
+  using C = c2<T>;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  constexpr int NW = NT / 64, RS = MOM_NV + 1;
+  // the plane in LDS; after the last pass the same storage holds (w |b_t|^2, u) per element
+  __shared__ double2 Lraw[N * NH];
+  C *L = reinterpret_cast<C *>(Lraw);
+  __shared__ double M[RS];
+  __shared__ double scr[2 * NW];
+  if (st->done) return;
+  const double eta = st->eta, tol = st->tol;
+  const int max_inner = st->max_inner;
+  NewtonPar np{eta, st->r2, 0.0, st->newton_rtol, st->newton_steptol, st->max_newton, st->newton_phi,
+               st->newton_direct_only};
+  const double xi = p.xi[0], q = p.q[0];
+  const double inv_n = 1.0 / ((double)N * (double)N);
+  double lam_t = st->lam[0];
+  int newton_total = 0, newton_direct = 0;
+  for (int t = 0;; ++t) {
+    const C *bprev = ((t - 1) & 1) ? b1 : b0;
+    C *bnext = (t & 1) ? b1 : b0;
+    const double mu0 = eta * lam_t;
+    // d_t, axis 0 inverse
+    plane_cols_inv_load<T, N, NT>(L, tw, [&](int f, int e) -> C {
+      const C v = bprev[e * NH + f];
+      const double x = 1.0 + eta * lam_of(g.kk0[e] + g.kkl[f], xi, q) + mu0;
+      const double sc = (e == 0 && f == 0) ? 0.0 : rcp64(x);
+      return C{T(double(v.x) * sc), T(double(v.y) * sc)};
+    });
+    __syncthreads();
+    // rows inverse, x Gamma' (rows 2f, 2f + 1), rows forward
+    plane_rows_inv<T, N, NT>(L, tw, [&](int f, int e, C v, int, int) {
+      L[f * 2 * NH + e] = C{v.x * gp[(2 * f) * N + e], v.y * gp[(2 * f + 1) * N + e]};
+    });
+    __syncthreads();
+    sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, 2 * NH, 1, tw);
+    // axis 0 forward; per output element: residual of d_t, b_t, and (w |b_t|^2, u)
+    double res2 = 0.0;
+    auto upd = [&](int f, int e, C v, int, int) {
+      const int h = e * NH + f;
+      const bool dc = (e == 0 && f == 0);
+      const double lam = lam_of(g.kk0[e] + g.kkl[f], xi, q);
+      const double w = (f == 0 || 2 * f == N) ? 1.0 : 2.0;
+      const C bp = bprev[h], gg = gh[h];
+      const double u = rcp64(1.0 + eta * lam + mu0);
+      const double sc = dc ? 0.0 : u;
+      const double dx = double(bp.x) * sc, dy = double(bp.y) * sc;
+      const double tx = double(v.x) * inv_n, ty = double(v.y) * inv_n;
+      const double rx = double(gg.x) + (lam + lam_t) * dx + tx, ry = double(gg.y) + (lam + lam_t) * dy + ty;
+      const C bn = dc ? C{T(0), T(0)} : C{T(dx - eta * (double(gg.x) + tx)), T(dy - eta * (double(gg.y) + ty))};
+      bnext[h] = bn;
+      if (!dc) res2 += w * (rx * rx + ry * ry);
+      const double wb = dc ? 0.0 : w * (double(bn.x) * double(bn.x) + double(bn.y) * double(bn.y));
+      Lraw[h] = double2{wb, u};
+    };
+    plane_cols_fwd_store<T, N, NT, decltype(upd), true>(L, tw, upd);
+    __syncthreads();
+    // phi(0) and the power sums M_2 .. M_{NMOM+1} from the stored pairs
+    double acc[RS];
+#pragma unroll
+    for (int j = 0; j < RS; ++j) acc[j] = 0.0;
+    acc[MOM_NV] = res2;
+    for (int h = threadIdx.x; h < N * NH; h += NT) {
+      const double2 wu = Lraw[h];
+      const int e = h / NH, f = h - e * NH;
+      const double u0 = rcp64(1.0 + eta * lam_of(g.kk0[e] + g.kkl[f], xi, q));
+      acc[0] = fma(wu.x, u0 * u0, acc[0]);
+      double pw = wu.x * wu.y * wu.y;
+#pragma unroll
+      for (int j = 1; j < MOM_NV; ++j) {
+        acc[j] += pw;
+        pw *= wu.y;
+      }
+    }
+    __syncthreads();  // Lraw becomes the reduction scratch [NW][RS]
+    double *red = reinterpret_cast<double *>(Lraw);
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < RS; ++j) {
+      const double v = wave_sum(acc[j]);
+      if ((threadIdx.x & 63) == 0) red[wv * RS + j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < RS) {
+      double a = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) a += red[w * RS + threadIdx.x];
+      M[threadIdx.x] = a;
+    }
+    __syncthreads();
+    // stop test of d_t, then lambda_{t+1}
+    const double resid = sqrt(M[MOM_NV]);
+    const bool bad = !(resid == resid) || resid > 1e300;
+    if ((t >= 1 && resid < tol) || t >= max_inner || bad) {
+      if (threadIdx.x == 0) {
+        st->resid = resid;
+        st->done = (resid < tol) ? 1 : 2;
+        if (bad) st->nonfinite = 1;
+        st->final_step = t;
+        st->lam_final = lam_t;
+        st->lam[t & 1] = lam_t;
+        st->newton_total += newton_total;
+        st->newton_direct += newton_direct;
+        st->step = t;
+      }
+      break;
+    }
+    np.lam_prev = lam_t;
+    // direct sum of phi over the half spectrum of b_t (this workgroup wrote it)
+    auto direct = [&](double lam, double &phi, double &dphi) {
+      const double e2 = eta * lam;
+      double a = 0.0, b = 0.0;
+      for (int h = threadIdx.x + 1; h < N * NH; h += NT) {
+        const int e = h / NH, f = h - e * NH;
+        const C bn = bnext[h];
+        const double w = (f == 0 || 2 * f == N) ? 1.0 : 2.0;
+        const double wb = w * (double(bn.x) * double(bn.x) + double(bn.y) * double(bn.y));
+        const double r = rcp64(1.0 + eta * lam_of(g.kk0[e] + g.kkl[f], xi, q) + e2);
+        a = fma(wb, r * r, a);
+        b = fma(wb, r * r * r, b);
+      }
+      block_sum2_nt<NT>(a, b, scr);
+      phi = a;
+      dphi = -2.0 * eta * b;
+    };
+    int it = 0, nd = 0;
+    lam_t = multiplier_newton(M, np, direct, it, nd);
+    newton_total += it;
+    newton_direct += nd;
+    __syncthreads();  // M, the LDS and b_t are read again by the next iteration
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1392,32 +1629,11 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
     }
     return;
   }
-  const double eta = st->eta, r2 = st->r2;
-  const double mu0 = eta * lam_prev;
-  const bool direct_only = st->newton_direct_only != 0;
-  int ndirect = 0;
-  // phi and dphi/dlambda at lambda
-  auto eval = [&](double lam, double &phi, double &dphi) {
-    const double D = eta * (lam - lam_prev);
-    const double rho = fabs(D) / (1.0 + mu0);
-    if (!direct_only && rho < 0.5) {
-      double rn = 1.0;
-#pragma unroll
-      for (int j = 0; j < NMOM; ++j) rn *= rho;
-      const double tail = M[1] * (NMOM + 1) * rn / ((1.0 - rho) * (1.0 - rho));
-      double a = 0.0, b = 0.0;
-#pragma unroll
-      for (int m = NMOM - 1; m >= 0; --m) a = fma(a, -D, (m + 1) * M[1 + m]);
-#pragma unroll
-      for (int m = NMOM - 2; m >= 0; --m) b = fma(b, -D, (double)((m + 1) * (m + 2)) * M[2 + m]);
-      if (tail <= 1e-17 * a) {
-        phi = a;
-        dphi = -eta * b;
-        return;
-      }
-    }
-    // direct sum over the spectrum (pair entries)
-    ++ndirect;
+  const double eta = st->eta;
+  NewtonPar np{eta, st->r2, lam_prev, st->newton_rtol, st->newton_steptol, st->max_newton, st->newton_phi,
+               st->newton_direct_only};
+  // direct sum of phi over the spectrum (the pair entries)
+  auto direct = [&](double lam, double &phi, double &dphi) {
     const double xi = p.xi[0], q = p.q[0];
     const double e2 = eta * lam;
     const int cpi = npair / (g.n0 / 2 + 1);
@@ -1434,32 +1650,8 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
     phi = a;
     dphi = -2.0 * eta * b;
   };
-  double lam = 0.0;
-  int it = 0;
-  if (M[0] > r2) {  // phi(0) > r^2: the multiplier is the root of phi(lambda) = r^2
-    const bool form_phi = st->newton_phi != 0;
-    double phi, dphi;
-    if (form_phi || !(lam_prev > 0.0)) {
-      lam = 0.0;  // the printed iteration: Newton from lambda = 0
-      eval(0.0, phi, dphi);
-    } else {
-      lam = lam_prev;  // warm start at the previous multiplier
-      eval(lam, phi, dphi);
-    }
-    const double rr = sqrt(r2);
-    while (it < st->max_newton) {
-      if (phi >= r2 && phi - r2 <= st->newton_rtol * r2) break;
-      double nl = form_phi ? lam - (phi - r2) / dphi : lam + 2.0 * phi * (1.0 - sqrt(phi) / rr) / dphi;
-      if (nl < 0.0) nl = 0.0;
-      ++it;
-      if (fabs(nl - lam) <= st->newton_steptol * fmax(1.0, fabs(lam))) {
-        lam = nl;
-        break;
-      }
-      lam = nl;
-      eval(lam, phi, dphi);
-    }
-  }
+  int it = 0, ndirect = 0;
+  const double lam = multiplier_newton(M, np, direct, it, ndirect);
   if (threadIdx.x == 0) {
     st->resid = resid;
     st->lam[(t + 1) & 1] = lam;

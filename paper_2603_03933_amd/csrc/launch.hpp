@@ -73,6 +73,8 @@ struct NFuncs {
   void (*plane_inner)(const PassArgs &, int n0) = nullptr;
   void (*plane_fwd_phys)(const PassArgs &, int n0) = nullptr;  // v -> out (+ Gamma' v partials)
   void (*plane_inv_phys)(const PassArgs &, int n0) = nullptr;  // in -> hv
+  // whole subproblem of one square 2D instance in one workgroup (null when it does not fit)
+  void (*sub2d)(const PassArgs &) = nullptr;
 };
 
 template <typename T, int N> struct Impl {
@@ -180,6 +182,15 @@ template <typename T, int N> struct Impl {
                 a.g.nh, a.g.N, a.p, (const C2 *)a.tw, (const C2 *)a.in, a.psi, a.v, a.mpart, (double *)a.out, a.scale);
   }
 
+  // the whole subproblem in one workgroup: up to N = 64 (beyond, the butterflies
+  // and the update no longer fit in registers together)
+  static constexpr bool SUB2D = lbk::PlaneCfg<T, N>::fits && N <= 64;
+  static void sub2d(const PassArgs &a) {
+    if constexpr (SUB2D)
+      LB_LAUNCH((lbk::k_sub2d<T, N>), dim3(1), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, a.g, a.p, (const C2 *)a.tw,
+                (C2 *)a.b0, (C2 *)a.b1, (const C2 *)a.gh, (const T *)a.gp, a.st);
+  }
+
   static NFuncs table() {
     NFuncs f;
     f.C = lbk::Cfg<N>::C;
@@ -196,6 +207,7 @@ template <typename T, int N> struct Impl {
     f.plane_inner = lbk::PlaneCfg<T, N>::fits ? &plane_inner : nullptr;
     f.plane_fwd_phys = lbk::PlaneCfg<T, N>::fits ? &plane_fwd_phys : nullptr;
     f.plane_inv_phys = lbk::PlaneCfg<T, N>::fits ? &plane_inv_phys : nullptr;
+    f.sub2d = SUB2D ? &sub2d : nullptr;
     return f;
   }
 };

@@ -1020,7 +1020,25 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   const int chunk = std::max(1, o.poll_every);
   long launched = 0;
   const long max_steps = (long)o.max_inner + 1;
-  while (true) {
+  const NFuncs *f0 = F(P, 0, prec);
+  if (o.single_workgroup && P->dim == 2 && P->n0 == P->nl && f0->sub2d) {
+    // square 2D grid that fits one workgroup: every iteration in one launch
+    PassArgs a = args_col(P, prec, 1, p, 0);
+    a.b0 = P->B0;
+    a.b1 = P->B1;
+    a.gh = P->GHT;
+    a.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
+    a.st = P->st;
+    {
+      KT kt_(P, "sub2d");
+      f0->sub2d(a);
+    }
+    LB_TRY(check_launch("subproblem (one workgroup)"));
+    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
+    LB_HIP(hipStreamSynchronize(P->stream));
+    launched = max_steps;
+  }
+  while (launched < max_steps) {
     const int n = (int)std::min<long>(chunk, max_steps - launched);
     for (int i = 0; i < n; ++i) enqueue_step(P, p, (int)(launched + i));
     launched += n;
@@ -1028,7 +1046,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
     LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
     LB_HIP(hipStreamSynchronize(P->stream));
     if (!P->timing.pending.empty()) timing_flush(P);
-    if (P->st_h->done || launched >= max_steps) break;
+    if (P->st_h->done) break;
   }
   const SubState &f = *P->st_h;
   if (!f.done) return fail(LB_ERR_HIP, "subproblem loop ended without a stop decision");
@@ -1069,6 +1087,7 @@ extern "C" void lb_sub_opts_default(lb_sub_opts *o) {
   o->poll_every = 32;
   o->newton_phi = 0;
   o->newton_direct = 0;
+  o->single_workgroup = 1;
 }
 
 extern "C" void lb_tr_opts_default(lb_tr_opts *o) {

@@ -44,6 +44,7 @@ class LbSubOpts(C.Structure):
         ("poll_every", C.c_int),
         ("newton_phi", C.c_int),
         ("newton_direct", C.c_int),
+        ("single_workgroup", C.c_int),
     ]
 
 

@@ -380,3 +380,56 @@ def test_errors_are_reported():
         plan.lb_imex_tr_solve(lb.Params(-0.1, 0.2), bad, lb.tr_opts(max_outer=3))
     with pytest.raises(TypeError):
         plan.lb_hessvec(lb.Params(-0.1, 0.2), psi.cpu(), g.cpu())
+
+
+# ---------------------------------------------------------------------------
+# One-workgroup subproblem on small square 2D grids
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("n", [16, 64])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_workgroup_subproblem_equals_multi_kernel(n, precision):
+    """The one-launch subproblem (every iteration in one workgroup) against the
+    launch-per-iteration path and the oracle: same iteration count, multiplier
+    and step."""
+    shape, box = (n, n), (2 * math.pi * n / 16,) * 2
+    m = model_for(shape, box, -0.15, 0.25)
+    psi = I.zero_mean_noise(shape, 0.2, 5)
+    g_hat = O.gradient(m, psi)
+    r = 0.1
+    eps = 1e-10 if precision == "fp64" else 1e-4
+    plan = lb.Plan(shape, box, precision=precision)
+    prm = lb.Params(m.tau, m.gamma)
+    out = {}
+    for sw in (0, 1):
+        d, info, rc = plan.lb_tr_subproblem(prm, dev(psi), dev(O.inv(g_hat)), r, lb.sub_opts(eps_sub=eps, max_inner=20000, single_workgroup=sw))
+        out[sw] = (host(d), info, rc)
+    (d0, i0, rc0), (d1, i1, rc1) = out[0], out[1]
+    assert rc0 == rc1 == lb.LB_OK and i0.iters == i1.iters
+    # the power sums are added in another order (per mode here, per +-k0 pair
+    # there), so a Newton stop test can fall one step apart
+    assert abs(i0.newton_iters - i1.newton_iters) <= max(2, 0.05 * i0.newton_iters)
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert abs(i0.lambda_ - i1.lambda_) <= tol * max(1.0, i0.lambda_)
+    assert np.max(np.abs(d0 - d1)) <= tol * np.max(np.abs(d0))
+    ref = O.imex_subproblem(m, psi, g_hat, r, O.SubOpts(eta=0.1, eps_sub=eps, max_inner=20000))
+    if precision == "fp64":
+        assert abs(i1.iters - ref.iters) <= 1 and abs(i1.lambda_ - ref.lam) <= 1e-9 * max(1.0, ref.lam)
+
+
+def test_single_workgroup_full_solve_64():
+    """The 64^2 single-instance workload solved with and without the one-workgroup path."""
+    inst = I.single_2d(64)
+    shape, box = inst.grid.n, inst.grid.box
+    prm = lb.Params(inst.params.tau, inst.params.gamma)
+    res = {}
+    for sw in (0, 1):
+        plan = lb.Plan(shape, box)
+        psi = dev(inst.psi0)
+        info, rc = plan.lb_imex_tr_solve(prm, psi, lb.tr_opts(grad_norm_inf=0, eps=1e-8, sub={"max_inner": 10000, "single_workgroup": sw}))
+        res[sw] = (info, rc, host(psi))
+    (a, ra, pa), (b, rb, pb) = res[0], res[1]
+    assert ra == rb == lb.LB_OK
+    assert (a.outer, a.inner_total) == (b.outer, b.inner_total)
+    assert abs(a.energy - b.energy) <= 1e-12 * abs(a.energy)

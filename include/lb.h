@@ -96,6 +96,10 @@ typedef struct lb_sub_opts {
   int single_workgroup;  /* 1 (default): on square 2D grids up to 64 x 64 one workgroup runs
                             every iteration in a single launch (same arithmetic); 0: one
                             launch sequence per iteration, as on every other grid */
+  int graph;             /* 1: subproblems with max_inner >= 127 replay a captured HIP graph
+                            of two iterations' launches on a private stream (same kernels,
+                            same results); 0 (default, faster on the current runtime): direct
+                            launches. Not used while kernel timing is on. */
 } lb_sub_opts;
 
 typedef struct lb_sub_info {

@@ -1596,7 +1596,7 @@ __device__ __forceinline__ void block_sum2_all(double &a, double &b, double *scr
 
 __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__restrict__ mom, int nmb,
                                                   const double *__restrict__ rpart, int rbpi,
-                                                  const double *__restrict__ bsq2, int npair, SubState *st, int t) {
+                                                  const double *__restrict__ bsq2, int npair, SubState *st) {
   __shared__ double M[MOM_NV + 1];
   __shared__ double scratch[32];
   // wave v sums value v over the moment blocks (v = MOM_NV: residual partials)
@@ -1616,6 +1616,7 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
   }
   __syncthreads();
   if (st->done) return;
+  const int t = st->step;  // written by the previous step's Newton kernel
   const double resid = sqrt(M[MOM_NV]);
   const bool bad = !(resid == resid) || resid > 1e300;
   const double lam_prev = st->lam[t & 1];

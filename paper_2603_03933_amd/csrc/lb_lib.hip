@@ -122,6 +122,7 @@ struct lb_plan {
   int batch = 1;
   int prec = LB_FP64;
   hipStream_t stream = nullptr;
+  hipStream_t own = nullptr;  // private stream for captured launch sequences (created on first use)
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
   long npair = 0;         // (|k0|, column) entries per instance
   double *mom = nullptr;  // moment partials of the update pass, MOM_NV x its blocks
@@ -303,6 +304,7 @@ extern "C" int lb_plan_destroy(lb_plan *P) {
   for (hipEvent_t e : P->timing.pool) (void)hipEventDestroy(e);
   if (P->st_h) (void)hipHostFree(P->st_h);
   if (P->sums_h) (void)hipHostFree(P->sums_h);
+  if (P->own) (void)hipStreamDestroy(P->own);
   delete P;
   return LB_OK;
 }
@@ -893,8 +895,13 @@ struct SubOut {
   int iters = 0, newton = 0, newton_direct = 0, status = 0;
 };
 
+// One iteration of Algorithm 3 as a launch sequence. The kernels take only
+// the parity of the step (which b buffer and multiplier slot to use); the
+// Newton kernel reads the step number itself from SubState, so the same
+// two-step sequence serves every step pair and can be captured once.
 static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   const int prec = P->prec;
+  t &= 1;
   PassArgs a = args_col(P, prec, 1, p, 0);
   a.step = t;
   a.b0 = P->B0;
@@ -962,7 +969,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   {
     KT kt_(P, "newton");
     LB_LAUNCH(lbk::k_newton, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom, u.cg.bpi,
-                       (const double *)P->partial, u.cg.bpi, (const double *)P->bsq, (int)P->npair, P->st, t);
+                       (const double *)P->partial, u.cg.bpi, (const double *)P->bsq, (int)P->npair, P->st);
   }
 }
 
@@ -1038,16 +1045,64 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
     LB_HIP(hipStreamSynchronize(P->stream));
     launched = max_steps;
   }
+  // long subproblems replay a captured two-step launch sequence (no timing:
+  // its events are not captured)
+  // restores the caller's stream and frees the graph on every exit
+  struct GraphScope {
+    lb_plan *P;
+    hipStream_t user;
+    hipGraphExec_t exec = nullptr;
+    ~GraphScope() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      P->stream = user;
+    }
+  } gs{P, P->stream};
+  hipGraphExec_t &gexec = gs.exec;
+  const hipStream_t user = P->stream;
+  if (o.graph && !P->timing.on && launched < max_steps && max_steps >= 128) {
+    // capture and replay on the plan's own stream (the null stream cannot be
+    // captured), ordered after the work already on the caller's stream
+    if (!P->own) LB_HIP(hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking));
+    hipEvent_t ev;
+    LB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    LB_HIP(hipEventRecord(ev, user));
+    LB_HIP(hipStreamWaitEvent(P->own, ev, 0));
+    (void)hipEventDestroy(ev);
+    P->stream = P->own;
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal);
+    if (ce == hipSuccess) {
+      enqueue_step(P, p, 0);
+      enqueue_step(P, p, 1);
+      ce = hipStreamEndCapture(P->stream, &graph);
+    }
+    if (ce == hipSuccess) {
+      ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+    }
+    if (ce != hipSuccess) return fail(LB_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  }
   while (launched < max_steps) {
     const int n = (int)std::min<long>(chunk, max_steps - launched);
-    for (int i = 0; i < n; ++i) enqueue_step(P, p, (int)(launched + i));
-    launched += n;
+    if (gexec) {
+      for (int i = 0; i < n; i += 2) {
+        const hipError_t le = hipGraphLaunch(gexec, P->stream);
+        if (le != hipSuccess) return fail(LB_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(le));
+      }
+      launched += n + (n & 1);
+    } else {
+      for (int i = 0; i < n; ++i) enqueue_step(P, p, (int)(launched + i));
+      launched += n;
+    }
     LB_TRY(check_launch("subproblem step"));
     LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
     LB_HIP(hipStreamSynchronize(P->stream));
     if (!P->timing.pending.empty()) timing_flush(P);
     if (P->st_h->done) break;
   }
+  // the loop ended with a synchronisation of the stream it ran on, so the
+  // caller's stream may go on
+  P->stream = user;
   const SubState &f = *P->st_h;
   if (!f.done) return fail(LB_ERR_HIP, "subproblem loop ended without a stop decision");
   if (f.nonfinite) return fail(LB_ERR_NONFINITE, "non-finite residual in the subproblem");
@@ -1088,6 +1143,7 @@ extern "C" void lb_sub_opts_default(lb_sub_opts *o) {
   o->newton_phi = 0;
   o->newton_direct = 0;
   o->single_workgroup = 1;
+  o->graph = 0;
 }
 
 extern "C" void lb_tr_opts_default(lb_tr_opts *o) {

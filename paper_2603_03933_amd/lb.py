@@ -45,6 +45,7 @@ class LbSubOpts(C.Structure):
         ("newton_phi", C.c_int),
         ("newton_direct", C.c_int),
         ("single_workgroup", C.c_int),
+        ("graph", C.c_int),
     ]
 
 

@@ -433,3 +433,45 @@ def test_single_workgroup_full_solve_64():
     assert ra == rb == lb.LB_OK
     assert (a.outer, a.inner_total) == (b.outer, b.inner_total)
     assert abs(a.energy - b.energy) <= 1e-12 * abs(a.energy)
+
+
+# ---------------------------------------------------------------------------
+# Captured launch sequences (HIP graph replay of the inner iteration)
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize(
+    "shape,box,precision",
+    [((16, 16, 16), (2 * math.pi,) * 3, "fp64"), ((24, 16, 48), (3 * math.pi, 2 * math.pi, 6 * math.pi), "fp64"),
+     ((96, 96), (12 * math.pi,) * 2, "fp32"), ((32, 32), (4 * math.pi,) * 2, "fp64")],
+)
+def test_graph_replay_equals_direct_launches(shape, box, precision):
+    """The subproblem replaying a captured two-iteration graph (hundreds of
+    replays, host polls between chunks) gives the same bits as direct launches;
+    three subproblems in a row on the same plan, each capturing its own graph."""
+    m = model_for(shape, box, -0.15, 0.25)
+    plan = lb.Plan(shape, box, precision=precision)
+    prm = lb.Params(m.tau, m.gamma)
+    for k, r in enumerate((0.05, 0.2, 1.0)):
+        psi = I.zero_mean_noise(shape, 0.2, 30 + k)
+        g = dev(O.inv(O.gradient(m, psi)))
+        outs = []
+        for graph in (0, 1, 0, 1):
+            so = lb.sub_opts(eps_sub=1e-11 if precision == "fp64" else 1e-5, max_inner=3000, graph=graph, single_workgroup=0)
+            d, info, rc = plan.lb_tr_subproblem(prm, dev(psi), g, r, so)
+            outs.append((host(d), info.iters, info.lambda_, info.newton_iters, rc))
+        for o in outs[1:]:
+            assert np.array_equal(o[0], outs[0][0]) and o[1:] == outs[0][1:]
+
+
+def test_graph_replay_full_solve_equals_direct_launches():
+    shape, box = (16, 16, 16), (2 * math.pi,) * 3
+    m = model_for(shape, box, -0.15, 0.25)
+    psi0 = I.zero_mean_noise(shape, 0.1, 9)
+    res = []
+    for graph in (0, 1):
+        plan = lb.Plan(shape, box)
+        psi = dev(psi0)
+        info, rc = plan.lb_imex_tr_solve(lb.Params(m.tau, m.gamma), psi, lb.tr_opts(grad_norm_inf=0, eps=1e-8, sub={"max_inner": 3000, "graph": graph}))
+        res.append((host(psi), info.outer, info.inner_total, info.energy, rc))
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]

@@ -302,6 +302,45 @@ def main():
     for k in list(hv):
         hv[k + "_alg_hbm_frac"] = 24.0 * N * hv[k] / (HBM_PEAK_GBS * 1e9)
 
+    # the other single-GPU configurations, timed briefly: the 64^2 2D solve and Hv at 256^3
+    extra = {}
+    if not args.no_fp32:
+        c1 = I.single_2d(64)
+        p1 = lb.Plan(c1.grid.n, c1.grid.box)
+        prm1 = lb.Params(c1.params.tau, c1.params.gamma)
+        o1 = lb.tr_opts(grad_norm_inf=0, eps=TOL, sub={"max_inner": 10000})
+        psi1 = torch.from_numpy(c1.psi0).to(dev)
+        p1.lb_imex_tr_solve(prm1, psi1.clone(), o1)  # warm
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        i1, rc1 = p1.lb_imex_tr_solve(prm1, psi1, o1)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter() - s
+        v1 = torch.from_numpy(I.hessvec_direction(c1.grid.n, 3)).to(dev)
+        r1, _ = p1.lb_lanczos_min(prm1, psi1, v1, 60, precond_shift=1.0)
+        extra["solve_64x64_fp64"] = {"solves_per_s": 1.0 / d1, "status": "converged" if rc1 == 0 else "not_converged",
+                                     "energy": i1.energy, "gnorm": i1.gnorm, "outer": i1.outer, "inner": i1.inner_total,
+                                     "lambda_min_ritz": r1}
+        big = I.large_3d(256)
+        vb = torch.from_numpy(I.hessvec_direction(big.grid.n, 1)).to(dev)
+        pb = torch.from_numpy(big.psi0).to(dev)
+        prmb = lb.Params(big.params.tau, big.params.gamma)
+        hv256 = {}
+        for precision in ("fp64", "fp32"):
+            plb = lb.Plan(big.grid.n, big.grid.box, precision=precision)
+            ob = torch.empty_like(vb)
+            for _ in range(3):
+                plb.lb_hessvec(prmb, pb, vb, out=ob)
+            torch.cuda.synchronize()
+            s = time.perf_counter()
+            for _ in range(30):
+                plb.lb_hessvec(prmb, pb, vb, out=ob)
+            torch.cuda.synchronize()
+            hv256[precision] = 30 / (time.perf_counter() - s)
+            hv256[precision + "_alg_hbm_frac"] = 24.0 * big.grid.N * hv256[precision] / (HBM_PEAK_GBS * 1e9)
+            del plb, ob
+        extra["hessvec_256cubed_per_s"] = hv256
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, info.inner_total, info.outer, info.cg_total, args.cpu_budget)
@@ -343,6 +382,7 @@ def main():
         },
         "hessvec_per_s": hv,
         "solve_fp32_inner": fp32,
+        "other_configs": extra,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_share_warmup": {k: round(v[1] / total_ms, 4) for k, v in sorted(warm.items(), key=lambda kv: -kv[1][1])[:8]},

@@ -88,3 +88,36 @@ def test_version_and_error_string():
 
     assert lb.lib().lb_version() >= 100
     assert isinstance(lb.lib().lb_last_error(), bytes)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No CPU fallback: a missing library raises, and CPU tensors are rejected."""
+    import torch
+
+    from paper_2603_03933_amd import lb
+
+    monkeypatch.setattr(lb, "_lib", None)
+    monkeypatch.setattr(lb, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        lb.lib()
+    with pytest.raises(TypeError):
+        lb._ptr(torch.zeros(4, dtype=torch.float64), 4, "psi")
+
+
+def test_plan_rejects_bad_grids_without_touching_the_gpu():
+    """Argument errors are caught on the host before any device call."""
+    from paper_2603_03933_amd import lb
+
+    L = lb.lib()
+    h = ctypes.c_void_p()
+    g = lb.LbGrid()
+    g.dim = 4
+    assert L.lb_plan_create(ctypes.byref(h), ctypes.byref(g), 1, 0, None) == -1
+    assert "dim" in L.lb_last_error().decode()
+    g.dim = 2
+    g.n[0], g.n[1] = 10, 16  # 10 = 2 * 5: no radix-5 passes
+    g.box[0], g.box[1] = 1.0, 1.0
+    assert L.lb_plan_create(ctypes.byref(h), ctypes.byref(g), 1, 0, None) < 0
+    g.n[0] = 16
+    assert L.lb_plan_create(ctypes.byref(h), ctypes.byref(g), 9, 0, None) == -1  # batch limit
+    assert L.lb_plan_create(ctypes.byref(h), ctypes.byref(g), 1, 7, None) < 0  # no such precision

@@ -219,7 +219,9 @@ def main():
         print(json.dumps({"kernel_sample": {"iterations": sinfo.iters, "workload": f"bcc_3d {n[0]}^3 FP64, Algorithm 3 at psi0, r = 1"}}))
         return
 
-    # warmup, with every kernel timed to find the dominant one
+    # choose the plane-pass variant for this grid (autotuner), then warm up
+    # with every kernel timed to find the dominant one
+    tuned = plan.lb_plan_autotune(prm, psi0, reps=20)
     plan.lb_plan_set_timing(True, "")
     for _ in range(max(1, args.warmup)):
         info, rc, ritz, res = step(plan, opts)
@@ -283,6 +285,7 @@ def main():
         hv["fp32"] = hv_rate("fp32")
         hv["fp32_batch8"] = hv_rate("fp32", 8)
         p32 = lb.Plan(n, box, precision="fp32")
+        p32.lb_plan_autotune(prm, psi0, reps=20)
         o32 = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64, "eps_sub_rel": 1e-6})
         torch.cuda.synchronize()
         s = time.perf_counter()
@@ -382,6 +385,7 @@ def main():
         },
         "hessvec_per_s": hv,
         "solve_fp32_inner": fp32,
+        "autotune": {"plane_pass_threads": tuned},
         "other_configs": extra,
         "roofline": roofline,
         "cpu_baseline": cpu,

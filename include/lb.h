@@ -306,6 +306,14 @@ int lb_random_ball(lb_plan *plan, double radius, unsigned long long seed, unsign
 int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double *const *psi, int count,
                           const lb_tr_opts *opts, int workers, lb_tr_info *infos, int *status);
 
+/* Autotuner: on grids whose inner iteration uses the plane pass (3D with
+ * n1 = n2 >= 64), time that pass built with 256, 512 and 1024 threads on the
+ * plan's own buffers (Gamma' from psi, `reps` launches each) and use the
+ * fastest from then on. *threads receives the chosen thread count (0 when the
+ * plan has nothing to tune). Synchronises the stream; overwrites workspaces
+ * only. */
+int lb_plan_autotune(lb_plan *plan, const lb_params *params, const double *psi, int reps, int *threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1431,9 +1431,6 @@ __global__ __launch_bounds__(EW_NT) void k_final_d(Geo g, Prm p, const c2<T> *__
 
 // Non-template kernels: defined only in the library's main translation unit.
 #ifdef LB_MAIN_TU
-// Sum `nq` interleaved per-workgroup partials over the `bpi` workgroups of
-// each instance in a fixed order; q listed in `is_max` use max instead.
-// One workgroup per instance; out[b * nq + q].
 // ---------------------------------------------------------------------------
 // Random feasible initial point for nearly hard subproblems
 // ---------------------------------------------------------------------------
@@ -1536,6 +1533,9 @@ __global__ void k_scale_out(const double *sums, int count, double scale, double 
   if (i < count) out[i] = scale * sums[i];
 }
 
+// Sum `nq` interleaved per-workgroup partials over the `bpi` workgroups of
+// each instance in a fixed order; q listed in `is_max` use max instead.
+// One workgroup per instance; out[b * nq + q].
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int bpi, int nq,
                                                   unsigned is_max, double *__restrict__ out) {
   __shared__ double scratch[64];

@@ -71,6 +71,8 @@ struct NFuncs {
   void (*rows_energy)(const PassArgs &) = nullptr;  // FP64 tables only
   // plane passes for n1 = n_last = N (null when the plane does not fit in LDS)
   void (*plane_inner)(const PassArgs &, int n0) = nullptr;
+  // the same pass with 256, 512 and 1024 threads (autotuner candidates; null where not built)
+  void (*plane_inner_nt[3])(const PassArgs &, int n0) = {nullptr, nullptr, nullptr};
   void (*plane_fwd_phys)(const PassArgs &, int n0) = nullptr;  // v -> out (+ Gamma' v partials)
   void (*plane_inv_phys)(const PassArgs &, int n0) = nullptr;  // in -> hv
   // whole subproblem of one square 2D instance in one workgroup (null when it does not fit)
@@ -171,6 +173,11 @@ template <typename T, int N> struct Impl {
                          n0, a.g.nh, a.g.N, (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
   }
 
+  template <int NTV> static void plane_inner_nt(const PassArgs &a, int n0) {
+    if constexpr (lbk::PlaneCfg<T, N>::fits)
+      LB_LAUNCH((lbk::k_plane_inner<T, N, NTV>), dim3(n0 * a.g.batch), dim3(NTV), 0, a.stream, n0, a.g.nh, a.g.N,
+                (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
+  }
   static void plane_fwd_phys(const PassArgs &a, int n0) {
     if constexpr (lbk::PlaneCfg<T, N>::fits)
       LB_LAUNCH((lbk::k_plane_fwd_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
@@ -205,6 +212,11 @@ template <typename T, int N> struct Impl {
     f.rows_inner = &rows_inner;
     f.rows_energy = std::is_same<T, double>::value ? &rows_energy : nullptr;
     f.plane_inner = lbk::PlaneCfg<T, N>::fits ? &plane_inner : nullptr;
+    if constexpr (lbk::PlaneCfg<T, N>::fits && N >= 64) {
+      f.plane_inner_nt[0] = &plane_inner_nt<256>;
+      f.plane_inner_nt[1] = &plane_inner_nt<512>;
+      f.plane_inner_nt[2] = &plane_inner_nt<1024>;
+    }
     f.plane_fwd_phys = lbk::PlaneCfg<T, N>::fits ? &plane_fwd_phys : nullptr;
     f.plane_inv_phys = lbk::PlaneCfg<T, N>::fits ? &plane_inv_phys : nullptr;
     f.sub2d = SUB2D ? &sub2d : nullptr;

@@ -123,6 +123,7 @@ struct lb_plan {
   int prec = LB_FP64;
   hipStream_t stream = nullptr;
   hipStream_t own = nullptr;  // private stream for captured launch sequences (created on first use)
+  int plane_nt = -1;          // autotuned plane-pass variant (index into plane_inner_nt), -1: built-in choice
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
   long npair = 0;         // (|k0|, column) entries per instance
   double *mom = nullptr;  // moment partials of the update pass, MOM_NV x its blocks
@@ -836,6 +837,12 @@ extern "C" int lb_field_moments(lb_plan *P, const double *psi, const double *w, 
   return check_launch("lb_field_moments");
 }
 
+// the plane pass of the inner iteration, in the variant the autotuner chose
+static void plane_pass(lb_plan *P, const NFuncs *f1, const PassArgs &a) {
+  if (P->plane_nt >= 0 && f1->plane_inner_nt[P->plane_nt]) f1->plane_inner_nt[P->plane_nt](a, P->n0);
+  else f1->plane_inner(a, P->n0);
+}
+
 // spectral Hessian-vector product in FP64: out = Lambda x + P F_N(Gamma' F_N^{-1} x) + shift x
 static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out, double shift) {
   PassArgs c0 = args_col(P, LB_FP64, 1, p, 0);
@@ -851,7 +858,7 @@ static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out
     pl.out = P->W64;
     pl.gp = P->gp64;
     KT kt_(P, "plane_inner");
-    f1->plane_inner(pl, P->n0);
+    plane_pass(P, f1, pl);
   } else {
     if (P->dim == 3) {
       PassArgs c1 = args_col(P, LB_FP64, 1, p, 1);
@@ -920,7 +927,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
     pl.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
     pl.st = P->st;
     KT kt_(P, "plane_inner");
-    f1->plane_inner(pl, P->n0);
+    plane_pass(P, f1, pl);
   } else {
     if (P->dim == 3) {
       PassArgs c1 = args_col(P, prec, 1, p, 1);
@@ -1753,6 +1760,56 @@ extern "C" int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *par
   for (int i = 0; i < count; ++i) (void)hipEventDestroy(ready[i]);
   for (int i = 0; i < count; ++i)
     if (status[i] < 0) return fail(status[i], "job " + std::to_string(i) + ": " + errs[i]);
+  return LB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: the plane pass of the inner iteration (the dominant kernel on
+// cubic grids) is built with 256, 512 and 1024 threads; time each on this
+// plan's buffers and keep the fastest.
+// ---------------------------------------------------------------------------
+extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const double *psi, int reps, int *threads) {
+  if (!P || !psi || !threads) return fail(LB_ERR_ARG, "null argument");
+  if (reps < 1 || reps > 10000) return fail(LB_ERR_ARG, "reps must be in [1, 10000]");
+  *threads = 0;
+  const int prec = P->prec;
+  const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
+  if (!f1 || !f1->plane_inner || P->n1 != P->nl || !f1->plane_inner_nt[0]) return LB_OK;  // nothing to tune
+  Prm p;
+  LB_TRY(pack_params(P, params, P->batch, &p));
+  {
+    KT kt_(P, "gamma_p");
+    LB_LAUNCH(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N * P->batch, lbk::EW_NT), 4096)), dim3(lbk::EW_NT),
+              0, P->stream, P->N, P->batch, p, psi, P->gp64, P->gp32);
+  }
+  PassArgs pl = args_col(P, prec, 1, p, 1);
+  pl.out = P->WT;
+  pl.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
+  pl.st = nullptr;
+  hipEvent_t e0, e1;
+  LB_HIP(hipEventCreate(&e0));
+  LB_HIP(hipEventCreate(&e1));
+  const int nts[3] = {256, 512, 1024};
+  float best = 0.0f;
+  int pick = -1;
+  for (int v = 0; v < 3; ++v) {
+    f1->plane_inner_nt[v](pl, P->n0);  // warm
+    LB_HIP(hipEventRecord(e0, P->stream));
+    for (int r = 0; r < reps; ++r) f1->plane_inner_nt[v](pl, P->n0);
+    LB_HIP(hipEventRecord(e1, P->stream));
+    LB_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    LB_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (pick < 0 || ms < best) {
+      best = ms;
+      pick = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  LB_TRY(check_launch("lb_plan_autotune"));
+  P->plane_nt = pick;
+  *threads = nts[pick];
   return LB_OK;
 }
 

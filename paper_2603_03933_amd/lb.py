@@ -142,6 +142,7 @@ _SIGS = {
     "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, _D, C.POINTER(_D), C.POINTER(_D), _P]),
     "lb_random_ball": (_I, [_P, _D, C.c_ulonglong, C.c_ulonglong, _P]),
     "lb_imex_tr_solve_many": (_I, [C.POINTER(_P), C.POINTER(LbParams), C.POINTER(_P), _I, C.POINTER(LbTrOpts), _I, C.POINTER(LbTrInfo), C.POINTER(_I)]),
+    "lb_plan_autotune": (_I, [_P, C.POINTER(LbParams), _P, _I, C.POINTER(_I)]),
 }
 
 
@@ -275,6 +276,13 @@ class Plan:
             out[buf.value.decode()] = (cnt.value, ms.value)
             i += 1
         return out
+
+    def lb_plan_autotune(self, params, psi, reps=20):
+        """Time the plane-pass variants on this plan and keep the fastest; returns its thread count (0: none)."""
+        self._sync_stream()
+        nt = C.c_int()
+        _check(lib().lb_plan_autotune(self._h, _params_array(params, self.batch), _ptr(psi, self.N * self.batch, "psi"), int(reps), C.byref(nt)))
+        return nt.value
 
     def lb_energy_grad(self, params, psi, energy=None, grad=None, want_grad=True):
         self._sync_stream()

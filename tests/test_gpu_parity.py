@@ -475,3 +475,26 @@ def test_graph_replay_full_solve_equals_direct_launches():
         info, rc = plan.lb_imex_tr_solve(lb.Params(m.tau, m.gamma), psi, lb.tr_opts(grad_norm_inf=0, eps=1e-8, sub={"max_inner": 3000, "graph": graph}))
         res.append((host(psi), info.outer, info.inner_total, info.energy, rc))
     assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
+
+
+def test_autotuned_plan_gives_the_same_results():
+    """The autotuner only changes how many threads share a plane: the subproblem
+    iterates and the spectral Hessian products (CG, Lanczos) are bit-identical."""
+    shape, box = (64, 64, 64), (8 * math.sqrt(2) * math.pi,) * 3
+    m = model_for(shape, box, -0.2, 0.3)
+    psi = I.zero_mean_noise(shape, 0.3, 17)
+    g = dev(O.inv(O.gradient(m, psi)))
+    prm = lb.Params(m.tau, m.gamma)
+    res = []
+    for tune in (False, True):
+        plan = lb.Plan(shape, box)
+        if tune:
+            nt = plan.lb_plan_autotune(prm, dev(psi), reps=5)
+            assert nt in (256, 512, 1024)
+        d, info, rc = plan.lb_tr_subproblem(prm, dev(psi), g, 0.5, lb.sub_opts(eps_sub=1e-10, max_inner=500))
+        s, it = plan.lb_shifted_solve(prm, dev(psi), g, 0.3, 1e-10, 200)
+        res.append((host(d), info.iters, info.lambda_, host(s), it))
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1:3] == res[1][1:3]
+    assert np.array_equal(res[0][3], res[1][3]) and res[0][4] == res[1][4]
+    plan2d = lb.Plan((32, 32), (4 * math.pi,) * 2)
+    assert plan2d.lb_plan_autotune(prm, dev(I.zero_mean_noise((32, 32), 0.1, 1))) == 0  # nothing to tune

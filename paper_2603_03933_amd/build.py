@@ -81,7 +81,20 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     tmp = LIB + ".tmp"
     _run(["g++", "-shared", "-o", tmp, *objs, f"-L{tl}", "-l:libamdhip64.so", f"-Wl,-rpath,{tl}:/opt/rocm/lib", "-Wl,--no-undefined"])
     os.replace(tmp, LIB)
+    _build_c_client(tl)
     return LIB
+
+
+def _build_c_client(torch_lib: str) -> None:
+    """The plain-C test client of the ABI (tests/c/lb_client.c), if present,
+    linked against liblbtr.so and the same HIP runtime."""
+    root = os.path.dirname(HERE)
+    src = os.path.join(root, "tests", "c", "lb_client.c")
+    if not os.path.exists(src):
+        return
+    exe = os.path.join(root, "tests", "c", "lb_client")
+    _run(["gcc", "-O2", "-std=c11", f"-I{os.path.join(root, 'include')}", src, "-o", exe, f"-L{HERE}", "-llbtr",
+          f"-L{torch_lib}", "-l:libamdhip64.so", f"-Wl,-rpath,{HERE}:{torch_lib}:/opt/rocm/lib", "-lm"])
 
 
 if __name__ == "__main__":

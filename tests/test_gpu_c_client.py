@@ -1,0 +1,42 @@
+"""GPU: a plain C program using only include/lb.h and liblbtr.so (no Python
+in the process) gets the same energy, gradient, Hessian product and solve as
+the Python binding on the same field."""
+import json
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_03933_amd import lb
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CLIENT = os.path.join(ROOT, "tests", "c", "lb_client")
+
+
+@pytest.mark.skipif(not os.path.exists(CLIENT), reason="C client not built (run __graft_entry__.build())")
+def test_c_client_matches_python_binding():
+    out = subprocess.run([CLIENT], capture_output=True, text=True, timeout=240)
+    assert out.returncode == 0, out.stderr
+    c = json.loads(out.stdout.strip().splitlines()[-1])
+    n = 32
+    L = 4.0 * math.sqrt(2.0) * math.pi
+    i = np.arange(n)
+    psi0 = (0.3 * np.cos(2.0 * math.pi * (2.0 * i[:, None, None] + 2.0 * i[None, :, None]) / n)
+            + 0.01 * np.sin(2.0 * math.pi * i[None, None, :] / n)) + np.zeros((n, n, n))
+    plan = lb.Plan((n, n, n), (L, L, L))
+    prm = lb.Params(-0.2, 0.3)
+    psi = torch.from_numpy(psi0).cuda()
+    E, g = plan.lb_energy_grad(prm, psi)
+    hv = plan.lb_hessvec(prm, psi, g)
+    gf, hf = g.flatten().cpu().numpy(), hv.flatten().cpu().numpy()
+    assert abs(c["energy0"] - float(E[0])) <= 1e-13 * abs(c["energy0"])
+    assert np.allclose(c["grad0"], gf[:2], rtol=1e-12, atol=1e-15)
+    assert np.allclose(c["hv0"], hf[:2], rtol=1e-12, atol=1e-15)
+    info, rc = plan.lb_imex_tr_solve(prm, psi, lb.tr_opts(grad_norm_inf=0, eps=1e-8, sub={"max_inner": 5000}))
+    assert c["status"] == rc == lb.LB_OK
+    assert abs(c["energy"] - info.energy) <= 1e-10 * abs(info.energy)
+    assert c["gnorm"] < 1e-8

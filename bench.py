@@ -377,6 +377,8 @@ def main():
             "outer": info.outer,
             "inner": info.inner_total,
             "cg": info.cg_total,
+            "newton_steps": info.newton_total,
+            "newton_direct_evals": info.newton_direct,
             "accepted": info.accepted,
             "contracted": info.contracted,
             "lambda_min_ritz": ritz,

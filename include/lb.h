@@ -157,6 +157,8 @@ typedef struct lb_tr_info {
   int accepted, contracted, expanded;
   int status;        /* LB_OK or LB_NOT_CONVERGED */
   int hard_cases;    /* subproblems started from a random point (hard_case = 1) */
+  int newton_total;  /* Newton steps of the multiplier, summed over all subproblem iterations */
+  int newton_direct; /* of their evaluations, those that summed phi over the spectrum */
 } lb_tr_info;
 
 typedef struct lb_plan lb_plan;

@@ -208,18 +208,6 @@ struct SubState {
 constexpr int NMOM = 20;          // series terms
 constexpr int MOM_NV = NMOM + 1;  // phi(0) and M_2 .. M_{NMOM+1}
 
-// |Bk|^2 of pair entry i = e * cpi + ml (e = |k0|, ml = column of the instance)
-__device__ __forceinline__ double kk_pair(const Geo &g, int cpi, int i) {
-  const int e = i / cpi;
-  const int ml = i - e * cpi;
-  int i1 = 0, kl = ml;
-  if (g.dim == 3) {
-    i1 = ml / g.nhl;
-    kl = ml - i1 * g.nhl;
-  }
-  return g.kk0[e] + kk_col_part(g, i1, kl);
-}
-
 // Newton's method for the multiplier lambda_{t+1} (eq. lambda_update_rule)
 // from the power sums M (M[0] = phi(0), M[1 + m] = M_{m+2} around
 // mu0 = eta lambda_prev): the series with its tail bound where it holds,
@@ -980,7 +968,12 @@ __device__ __forceinline__ void sk_lds_passes(c2<T> *buf, int fs, int es, const 
 // Stages of the plane kernels. A plane of fixed i0 is held in LDS as the
 // half spectrum along the last axis: element (row e, column k) at L[e NH + k];
 // row passes pack half rows 2p, 2p+1 as one complex row Z_p of length N at
-// L[p 2 NH + x].
+// L[p PR + x]. Every pass reads all its elements into registers before it
+// writes, so Z may use its own stride: PR = N + 1 is odd, so the rows that
+// consecutive lanes hold start in distinct LDS banks (a stride of 2 NH, even,
+// put every other lane on the same banks), and N/2 rows of N + 1 still fit in
+// the N NH elements of the plane.
+template <int N> constexpr int plane_pr() { return N + 1; }
 
 // axis 1, inverse, first pass reading element (e, f) from load(f, e)
 template <typename T, int N, int NT, class Load>
@@ -1003,7 +996,7 @@ __device__ __forceinline__ void plane_cols_inv_from(c2<T> *L, const c2<T> *src, 
 template <typename T, int N, int NT, class Last>
 __device__ __forceinline__ void plane_rows_inv(c2<T> *L, const c2<T> *__restrict__ tw, const Last &last) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   auto packed = [&](int p, int e) -> C {
     const bool lo = 2 * e <= N;
     const int k = lo ? e : N - e;
@@ -1018,11 +1011,11 @@ __device__ __forceinline__ void plane_rows_inv(c2<T> *L, const c2<T> *__restrict
     sk_pass<T, N, true, NT, NR, false, 0, true>(tw, packed, last);
   } else {
     sk_pass<T, N, true, NT, NR, true, 0, true>(tw, packed,
-                                               [&](int f, int e, C v, int, int) { L[f * 2 * NH + e] = v; });
+                                               [&](int f, int e, C v, int, int) { L[f * PR + e] = v; });
     __syncthreads();
-    sk_lds_passes<T, N, true, NT, NR, true, 1, NP - 1>(L, 2 * NH, 1, tw);
+    sk_lds_passes<T, N, true, NT, NR, true, 1, NP - 1>(L, PR, 1, tw);
     sk_pass<T, N, true, NT, NR, false, NP - 1, true>(
-        tw, [&](int f, int e) -> C { return L[f * 2 * NH + e]; }, last);
+        tw, [&](int f, int e) -> C { return L[f * PR + e]; }, last);
   }
 }
 
@@ -1031,10 +1024,10 @@ __device__ __forceinline__ void plane_rows_inv(c2<T> *L, const c2<T> *__restrict
 template <typename T, int N, int NT, class Store, bool LAST_MID = false>
 __device__ __forceinline__ void plane_cols_fwd_store(c2<T> *L, const c2<T> *__restrict__ tw, const Store &store_mem) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N);
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), PR = plane_pr<N>();
   auto unpacked = [&](int k, int e) -> C {
     const int p = e >> 1;
-    const C zk = L[2 * p * NH + k], zm = L[2 * p * NH + ((N - k) % N)];
+    const C zk = L[p * PR + k], zm = L[p * PR + ((N - k) % N)];
     return (e & 1) ? C{T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x)}
                    : C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
   };
@@ -1063,7 +1056,7 @@ template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
 __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
                                                     c2<T> *data, const T *__restrict__ gp, const SubState *st) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   __shared__ C L[N * NH];
   if (st && st->done) return;
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
@@ -1087,10 +1080,10 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
     }
   }
   plane_rows_inv<T, N, NT>(L, tw, [&](int f, int e, C v, int k, int r) {
-    L[f * 2 * NH + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
+    L[f * PR + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
   });
   __syncthreads();
-  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, 2 * NH, 1, tw);  // rows, forward
+  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, tw);  // rows, forward
   plane_cols_fwd_to<T, N, NT>(L, plane, tw);
 }
 
@@ -1103,7 +1096,7 @@ __global__ __launch_bounds__(NT) void k_plane_fwd_phys(int n0, long nh, long Np,
                                                        const double *__restrict__ v, const double *__restrict__ psi,
                                                        c2<T> *out, double *partial) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   __shared__ C L[N * NH];
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
   const long off = b * Np + (long)i0 * (N * N);
@@ -1117,10 +1110,10 @@ __global__ __launch_bounds__(NT) void k_plane_fwd_phys(int n0, long nh, long Np,
       const double pa = psi[ia], pb = psi[ib];
       acc += (tau - gam * pa + 0.5 * pa * pa) * va + (tau - gam * pb + 0.5 * pb * pb) * vb;
     }
-    L[q * 2 * NH + x] = C{T(va), T(vb)};
+    L[q * PR + x] = C{T(va), T(vb)};
   }
   __syncthreads();
-  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, 2 * NH, 1, tw);
+  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, tw);
   plane_cols_fwd_to<T, N, NT>(L, out + b * nh + (long)i0 * (N * NH), tw);
   if (partial) {
     const double s = block_sum<NT>(acc, reinterpret_cast<double *>(L));
@@ -1170,7 +1163,7 @@ template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
 __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restrict__ tw, c2<T> *b0, c2<T> *b1,
                                               const c2<T> *__restrict__ gh, const T *__restrict__ gp, SubState *st) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   constexpr int NW = NT / 64, RS = MOM_NV + 1;
   // the plane in LDS; after the last pass the same storage holds (w |b_t|^2, u) per element
   __shared__ double2 Lraw[N * NH];
@@ -1200,10 +1193,10 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     __syncthreads();
     // rows inverse, x Gamma' (rows 2f, 2f + 1), rows forward
     plane_rows_inv<T, N, NT>(L, tw, [&](int f, int e, C v, int, int) {
-      L[f * 2 * NH + e] = C{v.x * gp[(2 * f) * N + e], v.y * gp[(2 * f + 1) * N + e]};
+      L[f * PR + e] = C{v.x * gp[(2 * f) * N + e], v.y * gp[(2 * f + 1) * N + e]};
     });
     __syncthreads();
-    sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, 2 * NH, 1, tw);
+    sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, tw);
     // axis 0 forward; per output element: residual of d_t, b_t, and (w |b_t|^2, u)
     double res2 = 0.0;
     auto upd = [&](int f, int e, C v, int, int) {
@@ -1633,19 +1626,52 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
   const double eta = st->eta;
   NewtonPar np{eta, st->r2, lam_prev, st->newton_rtol, st->newton_steptol, st->max_newton, st->newton_phi,
                st->newton_direct_only};
-  // direct sum of phi over the spectrum (the pair entries)
+  // direct sum of phi over the spectrum: the pair entries form rows e = |k0|
+  // of cpi columns. Each thread owns two columns at a time (|Bk|^2 of the
+  // column part formed once) and walks the rows in batches of DU with all
+  // 2 DU loads of a batch issued before the first is used (rows past the end
+  // re-read the last row and add nothing).
   auto direct = [&](double lam, double &phi, double &dphi) {
+    constexpr int DU = 16;
     const double xi = p.xi[0], q = p.q[0];
     const double e2 = eta * lam;
-    const int cpi = npair / (g.n0 / 2 + 1);
+    const int nrow = g.n0 / 2 + 1;
+    const int cpi = npair / nrow;
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < npair; i += NW_NT) {
-      if (i == 0) continue;
-      const double r = rcp64(1.0 + eta * lam_of(kk_pair(g, cpi, i), xi, q) + e2);
-      const double w = bsq2[i];
-      const double r2i = r * r;
-      a = fma(w, r2i, a);
-      b = fma(w, r2i * r, b);
+    for (int ml0 = 0; ml0 < cpi; ml0 += 2 * NW_NT) {
+      int mls[2];
+      bool okc[2];
+      double kkc[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int ml = ml0 + c * NW_NT + (int)threadIdx.x;
+        okc[c] = ml < cpi;
+        mls[c] = okc[c] ? ml : 0;
+        kkc[c] = col_info(g, mls[c]).kkc;
+      }
+      for (int e0 = 0; e0 < nrow; e0 += DU) {
+        double w[2][DU];
+#pragma unroll
+        for (int u = 0; u < DU; ++u) {
+          const long row = (long)(e0 + u < nrow ? e0 + u : nrow - 1) * cpi;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) w[c][u] = bsq2[row + mls[c]];
+        }
+#pragma unroll
+        for (int u = 0; u < DU; ++u) {
+          const int e = e0 + u;
+          if (e >= nrow) break;
+          const double kk0 = g.kk0[e];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            if (!okc[c] || (e == 0 && mls[c] == 0)) continue;
+            const double r = rcp64(1.0 + eta * lam_of(kk0 + kkc[c], xi, q) + e2);
+            const double r2i = r * r;
+            a = fma(w[c][u], r2i, a);
+            b = fma(w[c][u], r2i * r, b);
+          }
+        }
+      }
     }
     block_sum2_all(a, b, scratch);
     phi = a;

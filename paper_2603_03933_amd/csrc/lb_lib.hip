@@ -1589,6 +1589,8 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
     SubOut sub;
     LB_TRY(run_subproblem(P, p, r, so, eg.gnorm, d0_spec, &sub));
     info->inner_total += sub.iters;
+    info->newton_total += sub.newton;
+    info->newton_direct += sub.newton_direct;
     const double lam = sub.lam, sn = sub.dnorm;
     if (!(sn > 0)) return fail(LB_ERR_NONFINITE, "zero trial step");
     if (j > 0 && have_prev && rho_prev < o.theta) mu = std::max(mu, lam / sn);

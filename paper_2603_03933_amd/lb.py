@@ -106,6 +106,8 @@ class LbTrInfo(C.Structure):
         ("expanded", C.c_int),
         ("status", C.c_int),
         ("hard_cases", C.c_int),
+        ("newton_total", C.c_int),
+        ("newton_direct", C.c_int),
     ]
 
 

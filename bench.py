@@ -156,6 +156,48 @@ def phase_sweep(args, torch, I, lb, dev):
     }), flush=True)
 
 
+
+LARGE_CAPS = {"max_outer": 400, "max_inner": 2000, "eps_sub_rel": 1e-6}
+LARGE_TOL = 1e-7
+
+
+def large_solve(args, torch, I, lb, dev):
+    """The 256^3 mixed-precision workload (tau=-0.25, gamma=0.4, N(0, 0.05^2)
+    start): one IMEX-TR solve to ||g||_2 < 1e-7 (FP32 FFT and pointwise
+    stages, FP64 reductions and ratio; or FP64 throughout), then 30 steps of
+    preconditioned Lanczos from three random starts on the FP64 Hessian product
+    (the smallest Ritz value is an upper bound on lambda_min). Progress: one
+    line per outer iteration on stderr."""
+    inst = I.large_3d(256)
+    prec = args.large_precision
+    plan = lb.Plan(inst.grid.n, inst.grid.box, precision=prec)
+    prm = lb.Params(inst.params.tau, inst.params.gamma)
+    psi = torch.from_numpy(inst.psi0).to(dev)
+    opts = lb.tr_opts(grad_norm_inf=0, eps=LARGE_TOL, max_outer=LARGE_CAPS["max_outer"], verbose=1,
+                      sub={"max_inner": LARGE_CAPS["max_inner"], "poll_every": 64,
+                           "eps_sub_rel": LARGE_CAPS["eps_sub_rel"] if prec == "fp32" else 0.0})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info, rc = plan.lb_imex_tr_solve(prm, psi, opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    p64 = lb.Plan(inst.grid.n, inst.grid.box, precision="fp64")
+    ritz = []
+    for k in range(3):
+        v0 = torch.from_numpy(I.hessvec_direction(inst.grid.n, 100 + k)).to(dev)
+        ritz.append(p64.lb_lanczos_min(prm, psi, v0, 30, precond_shift=1.0))
+    print(json.dumps({
+        "metric": "IMEX-TR solves/s, 256^3 single solve", "value": 1.0 / dt, "unit": "solves/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "large_3d 256^3, box 16 pi, tau -0.25, gamma 0.4, psi0 N(0, 0.05^2) seed 0",
+                   "caps": LARGE_CAPS, "tol": LARGE_TOL},
+        "seconds": dt, "status": "converged" if rc == 0 else "not_converged", "energy": info.energy,
+        "gnorm": info.gnorm, "outer": info.outer, "inner": info.inner_total, "cg": info.cg_total,
+        "lanczos30": [{"ritz": r, "residual": e} for r, e in ritz],
+        "lambda_min_upper_bound": min(r for r, _ in ritz),
+        "sp2_check_passed": min(r for r, _ in ritz) >= -1e-7,
+    }), flush=True)
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +211,9 @@ def main():
                     help="only run K iterations of Algorithm 3 on the workload (for counter collection) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales HBM counters) and exit")
+    ap.add_argument("--large-solve", action="store_true",
+                    help="only run the 256^3 single solve (+ 30-step Lanczos, three starts) and exit")
+    ap.add_argument("--large-precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--phase-sweep", action="store_true",
                     help="only run the 64-instance 2D phase sweep (concurrent solves) and exit")
     ap.add_argument("--sweep-precision", default="fp32", choices=["fp32", "fp64"])
@@ -195,6 +240,9 @@ def main():
         return
     if args.phase_sweep:
         phase_sweep(args, torch, I, lb, dev)
+        return
+    if args.large_solve:
+        large_solve(args, torch, I, lb, dev)
         return
     inst = I.bcc_3d(args.size)
     n, box = inst.grid.n, inst.grid.box

@@ -64,11 +64,15 @@ def test_autograd_gradcheck_and_gradgradcheck():
     assert torch.autograd.gradgradcheck(f, (psi, tau, gam), eps=1e-6, atol=1e-8, rtol=1e-6)
 
 
-def test_autograd_exact_central_differences_on_the_differentiation_batch():
-    """8 instances of 24^3 ((tau, gamma) per instance): the central difference of
-    the quartic E along a direction e equals <dE/dpsi, e> + eps^2/6 sum (psi - gamma) e^3 / N,
-    and the same for the gradient with the Hessian; tau and gamma enter affinely."""
-    insts = I.diff_3d(24)
+@pytest.mark.parametrize("n,eps,tol", [(24, 1e-3, 1e-9), (96, 1e-6, 1e-7)])
+def test_autograd_exact_central_differences_on_the_differentiation_batch(n, eps, tol):
+    """8 instances of n^3 ((tau, gamma) per instance; 96^3 is the full
+    differentiation workload): the central difference of the quartic E along a
+    direction e equals <dE/dpsi, e> + eps^2/6 sum (psi - gamma) e^3 / N, and the
+    same for the gradient with the Hessian; tau and gamma enter affinely. At
+    eps = 1e-6 rounding (~ u |E| / eps) sets the tolerance, not the identity."""
+    print(f"differentiation batch 8 x {n}^3, eps {eps}", flush=True)
+    insts = I.diff_3d(n)
     shape, box = insts[0].grid.n, insts[0].grid.box
     B = len(insts)
     plan = lb.Plan(shape, box, batch=B)
@@ -80,7 +84,6 @@ def test_autograd_exact_central_differences_on_the_differentiation_batch():
     (gpsi,) = torch.autograd.grad(E.sum(), psi, create_graph=True)
     hv = torch.autograd.grad((gpsi * e).sum(), psi)[0]
     gt, gg = torch.autograd.grad(A.energy(plan, psi, tau, gam).sum(), (tau, gam))
-    eps = 1e-3
     N = math.prod(shape)
     with torch.no_grad():
         Ep = A.energy(plan, psi + eps * e, tau, gam)
@@ -88,11 +91,11 @@ def test_autograd_exact_central_differences_on_the_differentiation_batch():
         fd = host((Ep - Em) / (2 * eps))
         cub = host(((psi - gam.to(DEV).reshape(B, 1, 1, 1)) * e**3).sum(dim=(1, 2, 3))) / N
         lin = host((gpsi * e).sum(dim=(1, 2, 3)))
-        assert np.max(np.abs(fd - (lin + eps**2 / 6 * cub))) < 1e-9 * np.max(np.abs(lin))
+        assert np.max(np.abs(fd - (lin + eps**2 / 6 * cub))) < tol * np.max(np.abs(lin))
         gp = host(torch.autograd.functional.vjp(lambda p: A.energy(plan, p, tau, gam), psi + eps * e, torch.ones(B, dtype=torch.float64, device=DEV))[1])
         gm = host(torch.autograd.functional.vjp(lambda p: A.energy(plan, p, tau, gam), psi - eps * e, torch.ones(B, dtype=torch.float64, device=DEV))[1])
         hfd = (gp - gm) / (2 * eps) - eps**2 / 6 * host(e) ** 3 / N
-        assert np.max(np.abs(hfd - host(hv))) < 1e-9 * np.max(np.abs(host(hv)))
+        assert np.max(np.abs(hfd - host(hv))) < tol * np.max(np.abs(host(hv)))
         p_np = host(psi)
         assert np.allclose(host(gt), (p_np**2).mean(axis=(1, 2, 3)) / 2, rtol=1e-12)
         assert np.allclose(host(gg), -(p_np**3).mean(axis=(1, 2, 3)) / 6, rtol=1e-12)

@@ -145,6 +145,9 @@ typedef struct lb_tr_opts {
   int hard_lanczos_steps;     /* 30 */
   double hard_precond_shift;  /* 1.0 */
   unsigned long long seed;    /* key of the random draws (0) */
+  double cg_precond_shift;    /* CONTRACT's CG (the paper leaves the solver open): c > 0 (default 1)
+                                 preconditions (H + lambda~ I) by (Lambda + lambda~ + c)^-1, as in
+                                 lb_shifted_solve; 0: plain CG */
 } lb_tr_opts;
 
 typedef struct lb_tr_info {
@@ -259,10 +262,13 @@ int lb_imex_tr_solve(lb_plan *plan, const lb_params *params, double *psi, const 
 
 /* CONTRACT's linear system (Algorithm 2): conjugate gradients for
  * (H + shift I) s = -g on the zero-mean subspace (H + shift I must be
- * positive definite). grad, s_out: N doubles (device). batch must be 1.
- * *iters receives the CG iteration count. */
+ * positive definite), stopped when ||r|| <= rtol ||g|| or after maxiter steps.
+ * precond_shift = c > 0: preconditioned by the diagonal (Lambda_k + shift + c)^-1
+ * in Fourier space (same system, far fewer steps on stiff spectra); 0: plain
+ * CG; negative or non-finite: LB_ERR_ARG. grad, s_out: N doubles (device).
+ * batch must be 1. *iters receives the CG iteration count. */
 int lb_shifted_solve(lb_plan *plan, const lb_params *params, const double *psi, const double *grad, double shift,
-                     double rtol, int maxiter, double *s_out, int *iters);
+                     double rtol, int maxiter, double precond_shift, double *s_out, int *iters);
 
 /* Second-order check (the paper's SP-II test, Section 1 definition: grad = 0
  * and H >= 0): an estimate of sigma_1, the smallest eigenvalue of H on the

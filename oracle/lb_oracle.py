@@ -535,6 +535,7 @@ class TROpts:
     max_newton: int = 100
     cg_rtol: float = 1e-12
     cg_maxiter: int = 1000
+    cg_precond_shift: float = 1.0  # CONTRACT's CG preconditioned by (Lambda + lam~ + c)^-1; 0: plain CG
     nu_tol: float = 1e-12  # ||s_j|| = nu_j tested as | ||s_j|| - nu_j | <= nu_tol nu_j
 
 
@@ -565,23 +566,36 @@ def delta_energy_taylor(m: Model, psi: np.ndarray, g_hat: np.ndarray, s_hat: np.
     return -(dot(g_hat, s_hat) + quad + pw)
 
 
-def cg_shifted(m: Model, psi: np.ndarray, g_hat: np.ndarray, lam: float, rtol: float, maxiter: int) -> Tuple[np.ndarray, int]:
-    """Conjugate gradients for (H + lam I) s = -g (H + lam I positive definite)."""
+def cg_shifted(m: Model, psi: np.ndarray, g_hat: np.ndarray, lam: float, rtol: float, maxiter: int,
+               precond_shift: float = 0.0) -> Tuple[np.ndarray, int]:
+    """Conjugate gradients for (H + lam I) s = -g (H + lam I positive definite),
+    stopped when ||r|| <= rtol ||g|| or after maxiter steps.
+
+    With precond_shift c > 0 the textbook preconditioned form, with the
+    diagonal M = (Lambda + lam + c)^(-1): the interaction part of H + lam I,
+    which spans the stiff range of its spectrum (the bulk part is bounded by
+    max |Gamma'|). The system solved is the same; c = 0 is plain CG.
+    """
     b = -g_hat
     x = np.zeros_like(g_hat)
     res = b.copy()
-    p = res.copy()
+    Minv = project(1.0 / (m.Lam + lam + precond_shift)) if precond_shift > 0 else None
+    z = Minv * res if Minv is not None else res
+    p = z.copy()
+    rz = dot(res, z)
     rr = dot(res, res)
     bn = math.sqrt(rr)
     it = 0
     while it < maxiter and math.sqrt(rr) > rtol * bn:
         Ap = hessvec(m, psi, p) + lam * p
-        alpha = rr / dot(p, Ap)
+        alpha = rz / dot(p, Ap)
         x = x + alpha * p
         res = res - alpha * Ap
-        rr_new = dot(res, res)
-        p = res + (rr_new / rr) * p
-        rr = rr_new
+        rr = dot(res, res)
+        z = Minv * res if Minv is not None else res
+        rz_new = dot(res, z) if Minv is not None else rr
+        p = z + (rz_new / rz) * p
+        rz = rz_new
         it += 1
     return project(x), it
 
@@ -592,7 +606,7 @@ def contract(m: Model, psi: np.ndarray, g_hat: np.ndarray, r: float, mu: float, 
     info = {}
     if lam < o.mu_lo * sn:
         lam_hat = lam + math.sqrt(o.mu_lo * norm(g_hat))
-        s_new, it = cg_shifted(m, psi, g_hat, lam_hat, o.cg_rtol, o.cg_maxiter)
+        s_new, it = cg_shifted(m, psi, g_hat, lam_hat, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift)
         info.update(contract_branch="hat", cg=it)
         if lam_hat / norm(s_new) <= o.mu_hi:
             return norm(s_new), info
@@ -601,7 +615,7 @@ def contract(m: Model, psi: np.ndarray, g_hat: np.ndarray, r: float, mu: float, 
         lo, hi = lam, lam_hat
         for _ in range(200):
             mid = 0.5 * (lo + hi)
-            s_mid, it = cg_shifted(m, psi, g_hat, mid, o.cg_rtol, o.cg_maxiter)
+            s_mid, it = cg_shifted(m, psi, g_hat, mid, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift)
             ratio = mid / norm(s_mid)
             if ratio < o.mu_lo:
                 lo = mid
@@ -612,7 +626,7 @@ def contract(m: Model, psi: np.ndarray, g_hat: np.ndarray, r: float, mu: float, 
                 return norm(s_mid), info
         return norm(s_mid), info
     lam_t = o.gamma_lambda * lam
-    s_new, it = cg_shifted(m, psi, g_hat, lam_t, o.cg_rtol, o.cg_maxiter)
+    s_new, it = cg_shifted(m, psi, g_hat, lam_t, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift)
     info.update(contract_branch="gamma_lambda", cg=it)
     if norm(s_new) >= o.gamma_c * sn:
         return norm(s_new), info
@@ -676,7 +690,10 @@ def imex_tr_solve(
         rho = dE / sn**3
         rec = dict(j=j, E=E, gnorm=gn2, gnorm_inf=gninf, r=r, nu=nu, mu=mu, lam=lam, snorm=sn, rho=rho, eta=eta, inner=sub.iters, sub_resid=sub.resid)
         on_nu = abs(sn - nu) <= o.nu_tol * nu
-        if rho >= o.theta and (lam <= mu * sn or on_nu):
+        # lambda <= mu ||s|| tested as lambda / ||s|| <= mu: after a contraction mu
+        # was just raised to lambda / ||s||, and the two sides must then compare
+        # equal exactly, not by the rounding of (lambda / ||s||) ||s||
+        if rho >= o.theta and (lam / sn <= mu or on_nu):
             psi = psi + inv(s_hat)
             nu = max(nu, o.gamma_e * sn)
             r = min(nu, max(r, o.gamma_e * sn))

@@ -64,13 +64,14 @@ __global__ __launch_bounds__(EW_NT) void k_gamma_p(long N, int batch, Prm p, con
     if (g32) g32[i] = float(v);
   }
 }
-// out = x / sqrt(Lambda + c) over the half spectrum (k = 0 removed)
-__global__ __launch_bounds__(EW_NT) void k_prec_scale(Geo g, Prm p, const double2 *__restrict__ x, double c,
+// out = x / sqrt(Lambda + c) (root != 0) or x / (Lambda + c) over the half
+// spectrum (k = 0 removed)
+__global__ __launch_bounds__(EW_NT) void k_prec_scale(Geo g, Prm p, const double2 *__restrict__ x, double c, int root,
                                                       double2 *__restrict__ out) {
   for (long h = (long)blockIdx.x * EW_NT + threadIdx.x; h < g.nh; h += (long)gridDim.x * EW_NT) {
     int kl;
     const double lam = lam_of(kk_at(g, (int)h, kl), p.xi[0], p.q[0]);
-    const double s = (h == 0) ? 0.0 : 1.0 / sqrt(lam + c);
+    const double s = (h == 0) ? 0.0 : (root ? 1.0 / sqrt(lam + c) : 1.0 / (lam + c));
     const double2 v = x[h];
     out[h] = double2{v.x * s, v.y * s};
   }
@@ -1175,6 +1176,7 @@ extern "C" void lb_tr_opts_default(lb_tr_opts *o) {
   lb_sub_opts_default(&o->sub);
   o->cg_rtol = 1e-12;
   o->cg_maxiter = 1000;
+  o->cg_precond_shift = 1.0;
   o->verbose = 0;
   o->hard_case = 0;
   o->hard_tol = 1e-12;
@@ -1239,17 +1241,27 @@ extern "C" int lb_tr_subproblem(lb_plan *P, const lb_params *params, const doubl
   return so.status;
 }
 
+static void prec_scale(lb_plan *P, const Prm &p, const double2 *x, double c, double2 *out, int root);
+
 // ---------------------------------------------------------------------------
 // CG for (H + shift I) s = -g (Algorithm 2's linear systems), spectral FP64.
-// g_hat in GH; solution in X.
+// g_hat in GH; solution in X. Stops when ||r|| <= rtol ||g|| or after maxiter
+// steps. With pc > 0 the preconditioned form with the diagonal
+// M = (Lambda + shift + pc)^-1, the interaction part of H + shift I, which
+// spans the stiff range of the spectrum (z = M r lives in SP, free here);
+// pc = 0 is plain CG.
 // ---------------------------------------------------------------------------
-static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int maxiter, int *iters) {
+static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int maxiter, double pc, int *iters) {
   const long n = P->nh;
+  double2 *Z = pc > 0 ? P->SP : P->R;
   lincomb64(P, n, 0.0, P->GH, 0.0, P->GH, P->X);   // x = 0
   lincomb64(P, n, -1.0, P->GH, 0.0, P->GH, P->R);  // r = -g
-  lincomb64(P, n, 1.0, P->R, 0.0, P->R, P->Pv);    // p = r
-  double rr;
+  if (pc > 0) prec_scale(P, p, P->R, shift + pc, Z, 0);
+  lincomb64(P, n, 1.0, Z, 0.0, Z, P->Pv);  // p = z
+  double rr, rz;
   LB_TRY(spec_dot_host(P, p, P->R, P->R, &rr));
+  if (pc > 0) LB_TRY(spec_dot_host(P, p, P->R, Z, &rz));
+  else rz = rr;
   const double bn = std::sqrt(rr);
   int it = 0;
   while (it < maxiter && std::sqrt(rr) > rtol * bn) {
@@ -1257,13 +1269,17 @@ static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int m
     double pap;
     LB_TRY(spec_dot_host(P, p, P->Pv, P->AP, &pap));
     if (!(pap > 0)) return fail(LB_ERR_NONFINITE, "CG met a non-positive curvature; H + shift I is not positive definite");
-    const double alpha = rr / pap;
+    const double alpha = rz / pap;
     lincomb64(P, n, alpha, P->Pv, 1.0, P->X, P->X);
     lincomb64(P, n, -alpha, P->AP, 1.0, P->R, P->R);
-    double rn;
-    LB_TRY(spec_dot_host(P, p, P->R, P->R, &rn));
-    lincomb64(P, n, 1.0, P->R, rn / rr, P->Pv, P->Pv);
-    rr = rn;
+    LB_TRY(spec_dot_host(P, p, P->R, P->R, &rr));
+    double rzn = rr;
+    if (pc > 0) {
+      prec_scale(P, p, P->R, shift + pc, Z, 0);
+      LB_TRY(spec_dot_host(P, p, P->R, Z, &rzn));
+    }
+    lincomb64(P, n, 1.0, Z, rzn / rz, P->Pv, P->Pv);
+    rz = rzn;
     ++it;
   }
   *iters = it;
@@ -1271,8 +1287,10 @@ static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int m
 }
 
 extern "C" int lb_shifted_solve(lb_plan *P, const lb_params *params, const double *psi, const double *grad,
-                                double shift, double rtol, int maxiter, double *s_out, int *iters) {
+                                double shift, double rtol, int maxiter, double precond_shift, double *s_out,
+                                int *iters) {
   if (!P || !psi || !grad || !s_out || !iters) return fail(LB_ERR_ARG, "null argument");
+  if (!(precond_shift >= 0) || !std::isfinite(precond_shift)) return fail(LB_ERR_ARG, "precond_shift must be finite and >= 0");
   if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_shifted_solve needs a plan with batch 1");
   Prm p;
   LB_TRY(pack_params(P, params, 1, &p));
@@ -1282,7 +1300,7 @@ extern "C" int lb_shifted_solve(lb_plan *P, const lb_params *params, const doubl
                        P->stream, P->N, 1, p, psi, P->gp64, P->gp32);
   }
   fwd_r2c(P, LB_FP64, 1, p, grad, P->GH, 1);
-  LB_TRY(cg_shifted(P, p, shift, rtol, maxiter, iters));
+  LB_TRY(cg_shifted(P, p, shift, rtol, maxiter, precond_shift, iters));
   inv_c2r(P, LB_FP64, 1, p, P->X, P->W64, s_out, 0, nullptr, nullptr);
   LB_TRY(check_launch("lb_shifted_solve"));
   LB_HIP(hipStreamSynchronize(P->stream));
@@ -1328,10 +1346,10 @@ static void jacobi_eig(int m, std::vector<double> &A, std::vector<double> &V) {
   }
 }
 
-static void prec_scale(lb_plan *P, const Prm &p, const double2 *x, double c, double2 *out) {
+static void prec_scale(lb_plan *P, const Prm &p, const double2 *x, double c, double2 *out, int root = 1) {
   KT kt_(P, "prec_scale");
   LB_LAUNCH(lbk::k_prec_scale, dim3((unsigned)std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
-                     P->stream, geo(P, 1), p, x, c, out);
+                     P->stream, geo(P, 1), p, x, c, root, out);
 }
 
 // Lanczos with full reorthogonalisation on H, or with c > 0 on K = S H S,
@@ -1550,6 +1568,7 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
     return fail(LB_ERR_ARG, "bad trust-region options");
   if (o.hard_case && (o.hard_lanczos_steps < 1 || o.hard_lanczos_steps > 1000 || !(o.hard_tol >= 0)))
     return fail(LB_ERR_ARG, "bad hard-case options");
+  if (!(o.cg_precond_shift >= 0) || !std::isfinite(o.cg_precond_shift)) return fail(LB_ERR_ARG, "bad cg_precond_shift");
   Prm p;
   LB_TRY(pack_params(P, params, 1, &p));
   std::memset(info, 0, sizeof(*info));
@@ -1613,7 +1632,10 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
     const double rho = dE / (sn * sn * sn);
     const char *branch;
     const bool on_nu = std::fabs(sn - nu) <= o.nu_tol * nu;
-    if (rho >= o.theta && (lam <= mu * sn || on_nu)) {
+    // lambda <= mu ||s|| tested as lambda / ||s|| <= mu: after a contraction mu
+    // was just raised to lambda / ||s||, and the sides must then compare equal
+    // exactly, not by the rounding of (lambda / ||s||) ||s||
+    if (rho >= o.theta && (lam / sn <= mu || on_nu)) {
       const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
       {
         KT kt_(P, "axpy_real");
@@ -1631,7 +1653,7 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
       int it = 0;
       if (lam < o.mu_lo * sn) {
         const double lam_hat = lam + std::sqrt(o.mu_lo * eg.gnorm);
-        LB_TRY(cg_shifted(P, p, lam_hat, o.cg_rtol, o.cg_maxiter, &it));
+        LB_TRY(cg_shifted(P, p, lam_hat, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it));
         info->cg_total += it;
         double xx;
         LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
@@ -1642,7 +1664,7 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
           double lo = lam, hi = lam_hat;
           for (int k = 0; k < 200; ++k) {
             const double mid = 0.5 * (lo + hi);
-            LB_TRY(cg_shifted(P, p, mid, o.cg_rtol, o.cg_maxiter, &it));
+            LB_TRY(cg_shifted(P, p, mid, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it));
             info->cg_total += it;
             LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
             snew = std::sqrt(xx);
@@ -1655,7 +1677,7 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
         }
       } else {
         const double lt = o.gamma_lambda * lam;
-        LB_TRY(cg_shifted(P, p, lt, o.cg_rtol, o.cg_maxiter, &it));
+        LB_TRY(cg_shifted(P, p, lt, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it));
         info->cg_total += it;
         double xx;
         LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));

@@ -90,6 +90,7 @@ class LbTrOpts(C.Structure):
         ("hard_lanczos_steps", C.c_int),
         ("hard_precond_shift", C.c_double),
         ("seed", C.c_ulonglong),
+        ("cg_precond_shift", C.c_double),
     ]
 
 
@@ -140,7 +141,7 @@ _SIGS = {
     "lb_field_moments": (_I, [_P, _P, _P, _P]),
     "lb_tr_subproblem": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, C.POINTER(LbSubOpts), _P, _P, C.POINTER(LbSubInfo)]),
     "lb_imex_tr_solve": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo)]),
-    "lb_shifted_solve": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, _D, _I, _P, C.POINTER(_I)]),
+    "lb_shifted_solve": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, _D, _I, _D, _P, C.POINTER(_I)]),
     "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, _D, C.POINTER(_D), C.POINTER(_D), _P]),
     "lb_random_ball": (_I, [_P, _D, C.c_ulonglong, C.c_ulonglong, _P]),
     "lb_imex_tr_solve_many": (_I, [C.POINTER(_P), C.POINTER(LbParams), C.POINTER(_P), _I, C.POINTER(LbTrOpts), _I, C.POINTER(LbTrInfo), C.POINTER(_I)]),
@@ -349,12 +350,12 @@ class Plan:
         rc = _check(lib().lb_imex_tr_solve(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), C.byref(opts) if opts is not None else None, C.byref(info)))
         return info, rc
 
-    def lb_shifted_solve(self, params, psi, grad, shift, rtol=1e-12, maxiter=1000, out=None):
+    def lb_shifted_solve(self, params, psi, grad, shift, rtol=1e-12, maxiter=1000, out=None, precond_shift=0.0):
         self._sync_stream()
         if out is None:
             out = torch.empty_like(psi)
         it = C.c_int()
-        _check(lib().lb_shifted_solve(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(grad, self.N, "grad"), float(shift), float(rtol), int(maxiter), _ptr(out, self.N, "s_out"), C.byref(it)))
+        _check(lib().lb_shifted_solve(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), _ptr(grad, self.N, "grad"), float(shift), float(rtol), int(maxiter), float(precond_shift), _ptr(out, self.N, "s_out"), C.byref(it)))
         return out, it.value
 
     def lb_lanczos_min(self, params, psi, v0, steps, precond_shift=0.0, evec=None):

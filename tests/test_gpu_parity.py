@@ -256,18 +256,21 @@ def test_tr_subproblem_user_initial_point():
 # ---------------------------------------------------------------------------
 
 
-def test_shifted_solve_matches_oracle_cg():
+@pytest.mark.parametrize("pc", [0.0, 1.0])
+def test_shifted_solve_matches_oracle_cg(pc):
+    """Plain CG (pc = 0) and CG preconditioned by (Lambda + shift + pc)^-1."""
     shape, box = (16, 24), (2 * math.pi, 3 * math.pi)
     m = model_for(shape, box, -0.15, 0.25)
     psi = I.zero_mean_noise(shape, 0.2, 6)
     g_hat = O.gradient(m, psi)
     shift = 0.5
-    s_or, it_or = O.cg_shifted(m, psi, g_hat, shift, 1e-12, 1000)
+    s_or, it_or = O.cg_shifted(m, psi, g_hat, shift, 1e-12, 1000, pc)
     plan = lb.Plan(shape, box)
-    s, it = plan.lb_shifted_solve(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), shift)
-    # hundreds of CG steps on an ill-conditioned system: counts differ by rounding,
+    s, it = plan.lb_shifted_solve(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), shift, precond_shift=pc)
+    print(f"pc={pc}: {it} steps (oracle {it_or})")
+    # many CG steps on an ill-conditioned system: counts differ by rounding,
     # the solutions agree to the CG tolerance
-    assert abs(it - it_or) <= 0.1 * it_or
+    assert abs(it - it_or) <= max(1, 0.1 * it_or)
     assert np.max(np.abs(host(s) - O.inv(s_or))) < 1e-9 * np.max(np.abs(O.inv(s_or)))
     # and both solve the system: ||(H + shift) s + g|| small
     res = O.hessvec(m, psi, O.project(O.fwd(host(s)))) + shift * O.project(O.fwd(host(s))) + g_hat
@@ -431,7 +434,9 @@ def test_single_workgroup_full_solve_64():
         res[sw] = (info, rc, host(psi))
     (a, ra, pa), (b, rb, pb) = res[0], res[1]
     assert ra == rb == lb.LB_OK
-    assert (a.outer, a.inner_total) == (b.outer, b.inner_total)
+    # the two kernels sum in different orders: a subproblem whose stop test
+    # lands within rounding of eps_sub may take one iteration more in one of them
+    assert a.outer == b.outer and abs(a.inner_total - b.inner_total) <= a.outer
     assert abs(a.energy - b.energy) <= 1e-12 * abs(a.energy)
 
 

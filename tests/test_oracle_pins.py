@@ -361,6 +361,32 @@ def _to_coords(Q, d_hat, N):
     return Q.T @ O.inv(d_hat).reshape(-1) / math.sqrt(N)
 
 
+def test_cg_plain_and_preconditioned_solve_the_shifted_system():
+    """CONTRACT's system (H + lam I) s = -g (Algorithm 2): plain CG and CG
+    preconditioned by (Lambda + lam + c)^-1 both reach the dense solution in
+    an orthonormal basis of 1^perp; on a stiff spectrum the preconditioned form
+    needs far fewer steps and lands on the same s."""
+    m = _model2d(n=12)
+    psi = rand_field(m.grid.n, 0.3, 31)
+    g_hat = O.gradient(m, psi)
+    Hs, Q, gs = _dense_coords(m, psi, g_hat)
+    lam = 0.5 + max(0.0, -float(np.linalg.eigvalsh(Hs)[0]))
+    ref = -np.linalg.solve(Hs + lam * np.eye(len(gs)), gs)
+    for c in (0.0, 1.0):
+        s, it = O.cg_shifted(m, psi, g_hat, lam, 1e-13, 5000, c)
+        assert 0 < it < 5000
+        got = _to_coords(Q, s, m.grid.N)
+        assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+    # 64 x 64 on [0, 8 pi)^2: Lambda reaches ~2e4, H = Lambda + T with T ~ 0.3
+    ms = O.Model(O.Grid((64, 64), (8 * math.pi, 8 * math.pi)), 0.3, 0.25)
+    psi = rand_field(ms.grid.n, 0.05, 32)
+    g_hat = O.gradient(ms, psi)
+    s0, it0 = O.cg_shifted(ms, psi, g_hat, 0.01, 1e-12, 5000, 0.0)
+    s1, it1 = O.cg_shifted(ms, psi, g_hat, 0.01, 1e-12, 5000, 1.0)
+    assert it1 < it0 / 4 and it0 < 5000
+    assert O.norm(s1 - s0) < 1e-9 * O.norm(s0)
+
+
 def test_newton_lambda_finds_secular_root():
     from scipy.optimize import brentq
 
@@ -487,6 +513,11 @@ def test_outer_loop_invariants_and_saddle_escape():
         assert h1["E"] <= h0["E"] + 1e-15
         assert h0["r"] <= h0["nu"] * (1 + 1e-15)
     assert {"accept", "contract"} <= {h["branch"] for h in res.history}
+    # right after a contraction mu >= lambda / ||s||, so Algorithm 1 accepts
+    # whenever rho >= theta (the branch must not hang on a rounding)
+    for h0, h1 in zip(res.history, res.history[1:]):
+        if h0["branch"] == "contract" and h1["rho"] >= 1e-4:
+            assert h1["branch"] == "accept"
     ev = O.hessian_eigs(m, res.psi)
     assert ev[0] >= -1e-8
 

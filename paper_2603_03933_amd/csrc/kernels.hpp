@@ -896,8 +896,9 @@ template <typename T, int N> struct PlaneCfg {
   // the plane must fit in LDS, and the butterflies plus the prefetched Gamma'
   // in registers (beyond N = 128 they spill)
   static constexpr bool fits = (long)N * NH * sizeof(c2<T>) <= 160 * 1024 && N <= 128;
-  // FP64 butterflies need the registers of 512 threads; FP32 fits 1024
-  static constexpr int NT = sizeof(T) == 8 ? (N >= 48 ? 512 : 256) : (N >= 96 ? 1024 : (N >= 48 ? 512 : 256));
+  // 1024 threads from N = 96 (FP64 included: no spills with the odd packed-row
+  // stride; 4 waves per SIMD hide the LDS and memory latency of the passes)
+  static constexpr int NT = N >= 96 ? 1024 : (N >= 48 ? 512 : 256);
 };
 
 // One Stockham pass (radix plan 1) over NXF transforms of length N. Butterfly
@@ -1592,40 +1593,46 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
                                                   const double *__restrict__ bsq2, int npair, SubState *st) {
   __shared__ double M[MOM_NV + 1];
   __shared__ double scratch[32];
-  // wave v sums value v over the moment blocks (v = MOM_NV: residual partials)
+  // the state of this step, read before anything here writes it; its loads
+  // are in flight together with the partials' instead of after them
+  const SubState s0 = *st;
+  // wave v sums value v over the moment blocks (v = MOM_NV: residual partials),
+  // four loads in flight per lane (520 blocks: three memory round trips)
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int v = wv; v <= MOM_NV; v += NW_NT / 64) {
     const double *src = v < MOM_NV ? mom + (long)v * nmb : rpart;
     const int cnt = v < MOM_NV ? nmb : rbpi;
-    double a = 0.0, a2 = 0.0;
+    double a = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
     int i = lane;
-    for (; i + 64 < cnt; i += 128) {
+    for (; i + 192 < cnt; i += 256) {
       a += src[i];
       a2 += src[i + 64];
+      a3 += src[i + 128];
+      a4 += src[i + 192];
     }
-    if (i < cnt) a += src[i];
-    a = wave_sum(a + a2);
+    for (; i < cnt; i += 64) a += src[i];
+    a = wave_sum((a + a2) + (a3 + a4));
     if (lane == 0) M[v] = a;
   }
   __syncthreads();
-  if (st->done) return;
-  const int t = st->step;  // written by the previous step's Newton kernel
+  if (s0.done) return;
+  const int t = s0.step;  // written by the previous step's Newton kernel
   const double resid = sqrt(M[MOM_NV]);
   const bool bad = !(resid == resid) || resid > 1e300;
-  const double lam_prev = st->lam[t & 1];
-  if ((t >= 1 && resid < st->tol) || t >= st->max_inner || bad) {
+  const double lam_prev = (t & 1) ? s0.lam[1] : s0.lam[0];
+  if ((t >= 1 && resid < s0.tol) || t >= s0.max_inner || bad) {
     if (threadIdx.x == 0) {
       st->resid = resid;
-      st->done = (resid < st->tol) ? 1 : 2;
+      st->done = (resid < s0.tol) ? 1 : 2;
       if (bad) st->nonfinite = 1;
       st->final_step = t;
       st->lam_final = lam_prev;
     }
     return;
   }
-  const double eta = st->eta;
-  NewtonPar np{eta, st->r2, lam_prev, st->newton_rtol, st->newton_steptol, st->max_newton, st->newton_phi,
-               st->newton_direct_only};
+  const double eta = s0.eta;
+  NewtonPar np{eta, s0.r2, lam_prev, s0.newton_rtol, s0.newton_steptol, s0.max_newton, s0.newton_phi,
+               s0.newton_direct_only};
   // direct sum of phi over the spectrum: the pair entries form rows e = |k0|
   // of cpi columns. Each thread owns two columns at a time (|Bk|^2 of the
   // column part formed once) and walks the rows in batches of DU with all
@@ -1682,8 +1689,8 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
   if (threadIdx.x == 0) {
     st->resid = resid;
     st->lam[(t + 1) & 1] = lam;
-    st->newton_total += it;
-    st->newton_direct += ndirect;
+    st->newton_total = s0.newton_total + it;  // stores only: no read-modify-write round trip
+    st->newton_direct = s0.newton_direct + ndirect;
     st->step = t + 1;
   }
 }

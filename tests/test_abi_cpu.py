@@ -71,6 +71,50 @@ def test_struct_layouts_match_c():
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
+
+def header_prototypes():
+    """{name: (return type, [parameter declarations])} of every prototype in lb.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"^([a-z][\w ]*?\**)\s*\b(lb_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text, flags=re.M):
+        args = [a.strip() for a in " ".join(m.group(3).split()).split(",")]
+        out[m.group(2)] = (m.group(1).strip(), [a for a in args if a and a != "void"])
+    return out
+
+
+def _c_kind(decl):
+    if "*" in decl:
+        return "ptr"
+    words = decl.split()[:-1]  # drop the parameter name
+    return {("double",): "f64", ("int",): "i32", ("long",): "i64", ("size_t",): "u64",
+            ("unsigned", "long", "long"): "u64"}[tuple(words)]
+
+
+def _py_kind(ct):
+    if ct in (ctypes.c_void_p, ctypes.c_char_p) or issubclass(ct, ctypes._Pointer):
+        return "ptr"
+    return {ctypes.c_double: "f64", ctypes.c_int: "i32", ctypes.c_long: "i64", ctypes.c_size_t: "u64",
+            ctypes.c_ulonglong: "u64"}[ct]
+
+
+def test_binding_signatures_match_the_header():
+    """Every entry point's parameter list and return type in the ctypes
+    binding agree with its prototype in lb.h (count and kind of each
+    argument), so no call passes a value where the library reads another."""
+    from paper_2603_03933_amd import lb
+
+    protos = header_prototypes()
+    assert set(protos) == set(lb._SIGS)
+    for name, (ret, args) in protos.items():
+        pres, pargs = lb._SIGS[name]
+        assert [_c_kind(a) for a in args] == [_py_kind(t) for t in pargs], name
+        if ret == "void":
+            assert pres is None, name
+        elif "*" in ret:
+            assert pres is ctypes.c_char_p, name
+        else:
+            assert _py_kind(pres) == {"int": "i32", "size_t": "u64"}[ret], name
+
 def test_default_options_are_section4_values():
     from paper_2603_03933_amd import lb
 

@@ -242,6 +242,23 @@ __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &li
       }
     }
   }
+  // this pass's twiddles, loaded with its data (before the barrier, which a
+  // global load cannot cross)
+  C w[S][R];
+  if constexpr (NS > 1) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int j = t + s * TPF;
+      if (EXACT || j < NB) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          w[s][r] = tw[r * k * (N / (NS * R))];
+          if constexpr (INV) w[s][r].y = -w[s][r].y;
+        }
+      }
+    }
+  }
   if constexpr (P == NP - 1) {
     using Aux = decltype(fetch(0));
     Aux aux[S][R];
@@ -258,14 +275,9 @@ __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &li
     for (int s = 0; s < S; ++s) {
       const int j = t + s * TPF;
       if (EXACT || j < NB) {
-        const int k = j % NS;
         if constexpr (NS > 1) {
 #pragma unroll
-          for (int r = 1; r < R; ++r) {
-            C w = tw[r * k * (N / (NS * R))];
-            if constexpr (INV) w.y = -w.y;
-            v[s][r] = cmul(v[s][r], w);
-          }
+          for (int r = 1; r < R; ++r) v[s][r] = cmul(v[s][r], w[s][r]);
         }
         dft<T, R, INV>(v[s]);
       }
@@ -287,11 +299,7 @@ __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &li
         const int k = j % NS;
         if constexpr (NS > 1) {
 #pragma unroll
-          for (int r = 1; r < R; ++r) {
-            C w = tw[r * k * (N / (NS * R))];
-            if constexpr (INV) w.y = -w.y;
-            v[s][r] = cmul(v[s][r], w);
-          }
+          for (int r = 1; r < R; ++r) v[s][r] = cmul(v[s][r], w[s][r]);
         }
         dft<T, R, INV>(v[s]);
         const int base = (j / NS) * NS * R + k;
@@ -310,63 +318,6 @@ __device__ __forceinline__ void fft_lds(int t, int c, c2<T> *lds, const LIdx &li
   fft_run<T, N, INV>(
       t, c, lds, lidx, tw, [&](int e) -> c2<T> { return lds[lidx(c, e)]; }, NoFetch{},
       [&](int e, c2<T> v, NoAux) { lds[lidx(c, e)] = v; });
-}
-
-// ---------------------------------------------------------------------------
-// Batched transforms held entirely in LDS, shared by all NT threads of a
-// workgroup: NXF transforms of length N, element e of transform f at
-// buf[f * fs + e * es]. Each pass reads every butterfly of a thread into
-// registers, waits at a barrier, then writes, so the buffer is updated in
-// place. F_FAST puts consecutive threads on consecutive transforms (good when
-// fs is 1), otherwise on consecutive butterflies of one transform.
-// Ends with a barrier.
-// ---------------------------------------------------------------------------
-template <typename T, int N, bool INV, int NT, int NXF, bool F_FAST, int P = 0>
-__device__ __forceinline__ void fft_lds_batch(c2<T> *buf, int fs, int es, const c2<T> *__restrict__ tw) {
-  using C = c2<T>;
-  constexpr int NP = num_passes(N);
-  constexpr int R = radix_at(N, P);
-  constexpr int NS = span_before(N, P);
-  constexpr int NB = N / R;
-  constexpr int TOT = NXF * NB;
-  constexpr int K = (TOT + NT - 1) / NT;
-  C v[K][R];
-  int fj[K][2];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int bi = threadIdx.x + k * NT;
-    const int f = F_FAST ? bi % NXF : bi / NB;
-    const int j = F_FAST ? bi / NXF : bi % NB;
-    fj[k][0] = f;
-    fj[k][1] = j;
-    if (bi < TOT) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[k][r] = buf[f * fs + (j + r * NB) * es];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int bi = threadIdx.x + k * NT;
-    if (bi < TOT) {
-      const int f = fj[k][0], j = fj[k][1];
-      const int kk = j % NS;
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          C w = tw[r * kk * (N / (NS * R))];
-          if constexpr (INV) w.y = -w.y;
-          v[k][r] = cmul(v[k][r], w);
-        }
-      }
-      dft<T, R, INV>(v[k]);
-      const int base = (j / NS) * NS * R + kk;
-#pragma unroll
-      for (int r = 0; r < R; ++r) buf[f * fs + (base + r * NS) * es] = v[k][r];
-    }
-  }
-  __syncthreads();
-  if constexpr (P < NP - 1) fft_lds_batch<T, N, INV, NT, NXF, F_FAST, P + 1>(buf, fs, es, tw);
 }
 
 }  // namespace lbfft

@@ -204,7 +204,8 @@ template <typename T, int R, bool INV> __device__ __forceinline__ void dft(c2<T>
 }
 
 // ---------------------------------------------------------------------------
-// The pass loop. `t` in [0, TPF) is this thread's lane within the transform,
+// The pass loop (radix plan PLAN, TPF = N / its first radix threads per
+// transform). `t` in [0, TPF) is this thread's lane within the transform,
 // `c` the transform's slot in the workgroup, `lds` the workgroup's buffer and
 // lidx(c, e) the LDS position of element e of slot c. load(e) supplies the
 // first pass's inputs. For the last pass, fetch(e) is called for every output
@@ -218,14 +219,14 @@ struct NoFetch {
   __device__ NoAux operator()(int) const { return NoAux{}; }
 };
 
-template <typename T, int N, bool INV, int P = 0, class LIdx, class Load, class Fetch, class Store>
+template <typename T, int N, bool INV, int P = 0, int PLAN = 0, class LIdx, class Load, class Fetch, class Store>
 __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &lidx, const c2<T> *__restrict__ tw,
                                         const Load &load, const Fetch &fetch, const Store &store) {
   using C = c2<T>;
-  constexpr int NP = num_passes(N);
-  constexpr int R = radix_at(N, P);
-  constexpr int NS = span_before(N, P);
-  constexpr int TPF = Shape<N>::TPF;
+  constexpr int NP = npass_p<PLAN>(N);
+  constexpr int R = radix_p<PLAN>(N, P);
+  constexpr int NS = span_p<PLAN>(N, P);
+  constexpr int TPF = N / radix_p<PLAN>(N, 0);
   constexpr int NB = N / R;                // butterflies in this pass
   constexpr int S = (NB + TPF - 1) / TPF;  // butterflies per thread
   constexpr bool EXACT = (S * TPF == NB);
@@ -308,7 +309,7 @@ __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &li
       }
     }
     __syncthreads();
-    fft_run<T, N, INV, P + 1>(t, c, lds, lidx, tw, load, fetch, store);
+    fft_run<T, N, INV, P + 1, PLAN>(t, c, lds, lidx, tw, load, fetch, store);
   }
 }
 

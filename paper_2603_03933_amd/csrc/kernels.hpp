@@ -315,7 +315,9 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
   constexpr int CC = Cfg<N>::C;
   constexpr int NT = Cfg<N>::NT;
   __shared__ C lds[N * CC];
-  if (op.skip()) return;
+  // a stopped subproblem's steps must not write; the flag is applied at the
+  // stores, so that the data loads need not wait for it to arrive
+  const bool sk = op.skip();
   const int b = blockIdx.x / cg.bpi;
   const int lb = blockIdx.x - b * cg.bpi;
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
@@ -345,10 +347,10 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
       [&](int e) { return op.fetch(bs, cs, ok, base + e * cg.S, e); },
       [&](int e, C v, const auto &aux) {
         double *sq = reinterpret_cast<double *>(lds) + e * CC + c;
-        if (ok) op.store(bs, cs, base + e * cg.S, e, v, aux, acc, sq);
+        if (ok && !sk) op.store(bs, cs, base + e * cg.S, e, v, aux, acc, sq);
         else *sq = 0.0;
       });
-  op.template end<NT, N, CC>(bs, acc, reinterpret_cast<double *>(lds), b, lb, c);
+  if (!sk) op.template end<NT, N, CC>(bs, acc, reinterpret_cast<double *>(lds), b, lb, c);  // uniform
 }
 
 struct Empty {};
@@ -845,7 +847,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T
   using C = c2<T>;
   constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
   __shared__ C lds[CC * LD];
-  if (st && st->done) return;
+  const bool sk = st && st->done;  // applied at the stores (the loads need not wait for it)
   const int b = blockIdx.x / rg.bpi;
   const long pair0 = (long)(blockIdx.x % rg.bpi) * CC;
   const long ppi = rg.rpi / 2;
@@ -875,7 +877,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T
   for (int i = threadIdx.x; i < CC * NHL; i += NT) {
     const int cc = i / NHL, k = i % NHL;
     const long pr = pair0 + cc;
-    if (pr < ppi) {
+    if (pr < ppi && !sk) {
       const C zk = lds[cc * LD + k], zm = lds[cc * LD + ((N - k) % N)];
       const long oa = (rowbase + 2 * pr) * NHL + k;
       data[oa] = C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y)};
@@ -1059,7 +1061,7 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   __shared__ C L[N * NH];
-  if (st && st->done) return;
+  const bool sk = st && st->done;  // applied at the stores (the loads need not wait for it)
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
   C *plane = data + b * nh + (long)i0 * (N * NH);
   const T *g = gp + b * Np + (long)i0 * (N * N);
@@ -1085,7 +1087,9 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
   });
   __syncthreads();
   sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, tw);  // rows, forward
-  plane_cols_fwd_to<T, N, NT>(L, plane, tw);
+  plane_cols_fwd_store<T, N, NT>(L, tw, [&](int f, int e, C v, int, int) {
+    if (!sk) plane[e * NH + f] = v;
+  });
 }
 
 // Hessian-vector product, axes 2 and 1 forward from the physical field v:

@@ -33,8 +33,22 @@ struct Geo {
   long N;        // points per instance
   long nh;       // half-spectrum modes per instance
   int batch;
-  const double *kk0, *kk1, *kkl;  // (2 pi k / L)^2 per axis, index in storage order
+  double c0, c1, cl;  // 2 pi / L of the leading, middle (3D) and last axis
 };
+
+// |Bk|^2 along one axis, (c k)^2 with c = 2 pi / L, for storage index i of n
+// points (signed k, except along the halved last axis): two multiplies, no
+// table and so no memory round trip. Not contracted: the square is rounded
+// before callers add the other axes.
+__device__ __forceinline__ double kk_ax(int i, int n, double c, bool half) {
+#pragma clang fp contract(off)
+  const int k = (half || i < n / 2) ? i : i - n;
+  const double t = c * (double)k;
+  return t * t;
+}
+__device__ __forceinline__ double kk0_of(const Geo &g, int i0) { return kk_ax(i0, g.n0, g.c0, false); }
+__device__ __forceinline__ double kk1_of(const Geo &g, int i1) { return kk_ax(i1, g.n1, g.c1, false); }
+__device__ __forceinline__ double kkl_of(const Geo &g, int kl) { return kk_ax(kl, g.nl, g.cl, true); }
 
 __device__ __forceinline__ double lam_of(double kk, double xi, double q) {
   const double t = q * q - kk;
@@ -50,12 +64,12 @@ __device__ __forceinline__ void decode(const Geo &g, int h, int &i0, int &i1, in
 }
 // |Bk|^2 of a mode: kk0 + (kk_last + kk1)
 __device__ __forceinline__ double kk_col_part(const Geo &g, int i1, int kl) {
-  return g.dim == 3 ? g.kkl[kl] + g.kk1[i1] : g.kkl[kl];
+  return g.dim == 3 ? kkl_of(g, kl) + kk1_of(g, i1) : kkl_of(g, kl);
 }
 __device__ __forceinline__ double kk_at(const Geo &g, int h, int &kl) {
   int i0, i1;
   decode(g, h, i0, i1, kl);
-  return g.kk0[i0] + kk_col_part(g, i1, kl);
+  return kk0_of(g, i0) + kk_col_part(g, i1, kl);
 }
 __device__ __forceinline__ double herm_w(const Geo &g, int kl) { return (kl == 0 || 2 * kl == g.nl) ? 1.0 : 2.0; }
 
@@ -407,7 +421,7 @@ template <typename T> struct OpInvScaleD {
   __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
   __device__ c2<T> load(const StepBlk<T> &bs, const ColInfo &ci, long h, int e) const {
     const c2<T> v = bs.bprev[h];
-    const double lam = lam_of(g.kk0[e] + ci.kkc, bs.xi, bs.q);
+    const double lam = lam_of(kk0_of(g, e) + ci.kkc, bs.xi, bs.q);
     const double s = (ci.dc && e == 0) ? 0.0 : rcp64(1.0 + bs.eta * (lam + bs.lam_t));
     return c2<T>{T(double(v.x) * s), T(double(v.y) * s)};
   }
@@ -462,7 +476,7 @@ template <typename T> struct OpFwdUpdate {
       a.bp = c2<T>{T(0), T(0)};
       a.gg = a.bp;
     }
-    a.kk0 = g.kk0[e];
+    a.kk0 = kk0_of(g, e);
     return a;
   }
   // the LDS buffer is free once the last pass has read it: w |b_t|^2 goes to
@@ -509,7 +523,7 @@ template <typename T> struct OpFwdUpdate {
         if (e != 0 && 2 * e != N) v += sq[(N - e) * CC + cc];
         bsq2[((long)b * NH0 + e) * cpi + ml] = v;
         if (e != 0 || ml != 0) {
-          const double x = 1.0 + bs.eta * lam_of(g.kk0[e] + kkc, bs.xi, bs.q);
+          const double x = 1.0 + bs.eta * lam_of(kk0_of(g, e) + kkc, bs.xi, bs.q);
           const double u0 = rcp64(x);
           m[0] = fma(v, u0 * u0, m[0]);
           const double u = rcp64(x + mu0);
@@ -573,7 +587,7 @@ template <typename T> struct OpFwdHess {
     HessAux<T> a;
     const c2<T> xv = x[h];  // h is a valid address for every thread
     a.xv = ok ? xv : c2<T>{T(0), T(0)};
-    a.kk0 = g.kk0[e];
+    a.kk0 = kk0_of(g, e);
     return a;
   }
   __device__ void store(const HessBlk &hb, const ColInfo &ci, long h, int e, c2<T> v, const HessAux<T> &a,
@@ -611,7 +625,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
         const C v = data[base + e * cg.S];
         return ok ? v : C{T(0), T(0)};
       },
-      [&](int e) { return g.kk0[e]; },
+      [&](int e) { return kk0_of(g, e); },
       [&](int e, C v, double kk0) {
         double m = lam_of(kk0 + ci.kkc, xi, q) * inv_n;
         if (!ok || (ci.dc && e == 0 && !keep_dc)) m = 0.0;
@@ -1191,7 +1205,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     // d_t, axis 0 inverse
     plane_cols_inv_load<T, N, NT>(L, tw, [&](int f, int e) -> C {
       const C v = bprev[e * NH + f];
-      const double x = 1.0 + eta * lam_of(g.kk0[e] + g.kkl[f], xi, q) + mu0;
+      const double x = 1.0 + eta * lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q) + mu0;
       const double sc = (e == 0 && f == 0) ? 0.0 : rcp64(x);
       return C{T(double(v.x) * sc), T(double(v.y) * sc)};
     });
@@ -1207,7 +1221,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     auto upd = [&](int f, int e, C v, int, int) {
       const int h = e * NH + f;
       const bool dc = (e == 0 && f == 0);
-      const double lam = lam_of(g.kk0[e] + g.kkl[f], xi, q);
+      const double lam = lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q);
       const double w = (f == 0 || 2 * f == N) ? 1.0 : 2.0;
       const C bp = bprev[h], gg = gh[h];
       const double u = rcp64(1.0 + eta * lam + mu0);
@@ -1231,7 +1245,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     for (int h = threadIdx.x; h < N * NH; h += NT) {
       const double2 wu = Lraw[h];
       const int e = h / NH, f = h - e * NH;
-      const double u0 = rcp64(1.0 + eta * lam_of(g.kk0[e] + g.kkl[f], xi, q));
+      const double u0 = rcp64(1.0 + eta * lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q));
       acc[0] = fma(wu.x, u0 * u0, acc[0]);
       double pw = wu.x * wu.y * wu.y;
 #pragma unroll
@@ -1283,7 +1297,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
         const C bn = bnext[h];
         const double w = (f == 0 || 2 * f == N) ? 1.0 : 2.0;
         const double wb = w * (double(bn.x) * double(bn.x) + double(bn.y) * double(bn.y));
-        const double r = rcp64(1.0 + eta * lam_of(g.kk0[e] + g.kkl[f], xi, q) + e2);
+        const double r = rcp64(1.0 + eta * lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q) + e2);
         a = fma(wb, r * r, a);
         b = fma(wb, r * r * r, b);
       }
@@ -1672,7 +1686,7 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
         for (int u = 0; u < DU; ++u) {
           const int e = e0 + u;
           if (e >= nrow) break;
-          const double kk0 = g.kk0[e];
+          const double kk0 = kk0_of(g, e);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             if (!okc[c] || (e == 0 && mls[c] == 0)) continue;

@@ -113,7 +113,7 @@ struct AxisTab {
   const NFuncs *f64 = nullptr, *f32 = nullptr;
   double2 *tw64 = nullptr;
   float2 *tw32 = nullptr;
-  double *kk = nullptr;
+  double L = 1.0;  // box length along the axis
 };
 
 struct lb_plan {
@@ -199,11 +199,6 @@ static void twiddles(int n, std::vector<double2> &w64, std::vector<float2> &w32)
   }
 }
 
-static double kk_axis(int i, int n, double L, bool half) {
-  const int k = (half || i < n / 2) ? i : i - n;
-  const double t = 2.0 * M_PI * (double)k / L;
-  return t * t;
-}
 
 
 static hipEvent_t timing_event(lb_plan *P) {
@@ -371,11 +366,7 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
   for (int s = 0; s < 3; ++s) {
     const int a = axis_of[s];
     if (a < 0) {
-      // 2D: the middle-axis slot carries a single zero wavenumber
-      int rc = dalloc(P, &P->ax[1].kk, 1);
-      if (rc) return cleanup(rc);
-      const double z = 0.0;
-      if ((rc = upload(P, P->ax[1].kk, &z, sizeof(double)))) return cleanup(rc);
+      // 2D: the middle-axis slot is a single zero wavenumber
       P->ax[1].n = 1;
       continue;
     }
@@ -390,12 +381,7 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
     if ((rc = dalloc(P, &A.tw64, A.n)) || (rc = dalloc(P, &A.tw32, A.n))) return cleanup(rc);
     if ((rc = upload(P, A.tw64, w64.data(), A.n * sizeof(double2)))) return cleanup(rc);
     if ((rc = upload(P, A.tw32, w32.data(), A.n * sizeof(float2)))) return cleanup(rc);
-    const bool half = (s == 2);
-    const int cnt = half ? A.n / 2 + 1 : A.n;
-    std::vector<double> kk(cnt);
-    for (int i = 0; i < cnt; ++i) kk[i] = kk_axis(i, A.n, g->box[a], half);
-    if ((rc = dalloc(P, &A.kk, cnt))) return cleanup(rc);
-    if ((rc = upload(P, A.kk, kk.data(), cnt * sizeof(double)))) return cleanup(rc);
+    A.L = g->box[a];
   }
   // the update pass reduces w |b|^2 over the +-k0 pairs of each axis-0
   // column: entries p = |k0| * columns + column, per instance
@@ -465,9 +451,9 @@ static Geo geo(const lb_plan *P, int batch) {
   g.N = P->N;
   g.nh = P->nh;
   g.batch = batch;
-  g.kk0 = P->ax[0].kk;
-  g.kk1 = P->ax[1].kk;
-  g.kkl = P->ax[2].kk;
+  g.c0 = 2.0 * M_PI / P->ax[0].L;
+  g.c1 = 2.0 * M_PI / P->ax[1].L;
+  g.cl = 2.0 * M_PI / P->ax[2].L;
   return g;
 }
 

@@ -441,7 +441,7 @@ template <typename T> struct UpdAux {
   double kk0;
 };
 template <typename T> struct OpFwdUpdate {
-  static constexpr bool eager_loads = false;
+  static constexpr bool eager_loads = true;
   Geo g;
   Prm p;
   const c2<T> *tmp;  // row/axis-1 transformed product Gamma' d_t
@@ -518,7 +518,13 @@ template <typename T> struct OpFwdUpdate {
 #pragma unroll
     for (int j = 0; j < MOM_NV; ++j) m[j] = 0.0;
     if (okc) {
-      for (int e = threadIdx.x / CC; e < NH0; e += NT / CC) {
+      // constant trip count, unrolled: the rows' power chains interleave
+      constexpr int ES = NT / CC, NIT = (NH0 + ES - 1) / ES;
+      const int e0 = threadIdx.x / CC;
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int e = e0 + it * ES;
+        if (e >= NH0) break;
         double v = sq[e * CC + cc];
         if (e != 0 && 2 * e != N) v += sq[(N - e) * CC + cc];
         bsq2[((long)b * NH0 + e) * cpi + ml] = v;

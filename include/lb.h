@@ -53,7 +53,7 @@ extern "C" {
 #define LB_ERR_HIP (-2)         /* HIP runtime error                        */
 #define LB_ERR_MISMATCH (-3)    /* call does not fit the plan (batch, ...)  */
 #define LB_ERR_NONFINITE (-4)   /* NaN or Inf met in a reduction            */
-#define LB_ERR_UNSUPPORTED (-5) /* grid size or box the build cannot handle */
+#define LB_ERR_UNSUPPORTED (-5) /* grid size or box the library has no kernels for */
 
 /* Arithmetic of the FFT and pointwise stages of lb_hessvec and of the inner
  * subproblem iteration. Energies, gradients, norms, dot products, the

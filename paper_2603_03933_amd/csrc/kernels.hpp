@@ -132,11 +132,16 @@ __device__ __forceinline__ double lane63(double v) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
   return __hiloint2double(hi, lo);
 }
+// sum over each row of 16 lanes, left in the row's lane 15
+__device__ __forceinline__ double row_sum(double v) {
+  v += dpp_d<0x111, 0xf, true>(v);  // row_shr:1
+  v += dpp_d<0x112, 0xf, true>(v);  // row_shr:2
+  v += dpp_d<0x114, 0xf, true>(v);  // row_shr:4
+  v += dpp_d<0x118, 0xf, true>(v);  // row_shr:8
+  return v;
+}
 __device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<0x111, 0xf, true>(v);   // row_shr:1
-  v += dpp_d<0x112, 0xf, true>(v);   // row_shr:2
-  v += dpp_d<0x114, 0xf, true>(v);   // row_shr:4
-  v += dpp_d<0x118, 0xf, true>(v);   // row_shr:8
+  v = row_sum(v);
   v += dpp_d<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
   v += dpp_d<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
   return lane63(v);
@@ -542,24 +547,28 @@ template <typename T> struct OpFwdUpdate {
         }
       }
     }
-    constexpr int NW = NT / 64;
+    // each row of 16 lanes sums its 22 values (4 DPP steps each) and its lane
+    // 15 leaves them in LDS; threads 0..21 then add the NT / 16 row sums
+    constexpr int NROW = NT / 16;
     constexpr int RS = MOM_NV + 1;
-    const int wv = threadIdx.x >> 6;
-    __syncthreads();  // sq becomes the reduction scratch [NW][RS]
+    static_assert(N * CC >= NROW * RS, "LDS scratch of the row sums");
+    const int row = threadIdx.x >> 4;
+    const bool last = (threadIdx.x & 15) == 15;
+    __syncthreads();  // sq becomes the reduction scratch [NROW][RS]
     {
-      const double v = wave_sum(acc);
-      if ((threadIdx.x & 63) == 0) sq[wv * RS + MOM_NV] = v;
+      const double v = row_sum(acc);
+      if (last) sq[row * RS + MOM_NV] = v;
     }
 #pragma unroll
     for (int j = 0; j < MOM_NV; ++j) {
-      const double v = wave_sum(m[j]);
-      if ((threadIdx.x & 63) == 0) sq[wv * RS + j] = v;
+      const double v = row_sum(m[j]);
+      if (last) sq[row * RS + j] = v;
     }
     __syncthreads();
     if (threadIdx.x < RS) {
       double s = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) s += sq[w * RS + threadIdx.x];
+      for (int w = 0; w < NROW; ++w) s += sq[w * RS + threadIdx.x];
       if (threadIdx.x == MOM_NV)
         partial[blockIdx.x] = s;
       else

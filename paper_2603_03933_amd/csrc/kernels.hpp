@@ -1269,19 +1269,21 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
         pw *= wu.y;
       }
     }
-    __syncthreads();  // Lraw becomes the reduction scratch [NW][RS]
+    __syncthreads();  // Lraw becomes the reduction scratch [NT / 16][RS]
+    // sums over rows of 16 lanes (four DPP shifts each), row sums added in LDS
     double *red = reinterpret_cast<double *>(Lraw);
-    const int wv = threadIdx.x >> 6;
+    constexpr int NROW = NT / 16;
+    const int row = threadIdx.x >> 4;
 #pragma unroll
     for (int j = 0; j < RS; ++j) {
-      const double v = wave_sum(acc[j]);
-      if ((threadIdx.x & 63) == 0) red[wv * RS + j] = v;
+      const double v = row_sum(acc[j]);
+      if ((threadIdx.x & 15) == 15) red[row * RS + j] = v;
     }
     __syncthreads();
     if (threadIdx.x < RS) {
       double a = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) a += red[w * RS + threadIdx.x];
+      for (int w = 0; w < NROW; ++w) a += red[w * RS + threadIdx.x];
       M[threadIdx.x] = a;
     }
     __syncthreads();

@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--phase-sweep", action="store_true",
                     help="only run the 64-instance 2D phase sweep (concurrent solves) and exit")
     ap.add_argument("--sweep-precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--sweep-workers", type=int, default=4)
+    ap.add_argument("--sweep-workers", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

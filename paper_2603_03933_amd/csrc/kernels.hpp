@@ -1191,43 +1191,71 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np,
 //   residual of d_t, b_t = d_t - eta (g + T d_t), phi(0) and the power sums of
 //   w |b_t|^2, then the stop test and Newton for lambda_{t+1},
 // until the stop test holds or t reaches max_inner. b_t goes to b[t & 1]
-// (global memory, cached), so the result is read as for the multi-kernel
-// iteration; SubState is read at the start and written at the end.
+// (global memory), so the result is read as for the multi-kernel iteration;
+// SubState is read at the start and written at the end. b_t, g, Gamma',
+// Lambda and the twiddles stay in LDS for the whole launch, so an iteration
+// waits on no global load.
+template <typename T, int N> struct Sub2dCfg {
+  static constexpr int NH = N / 2 + 1;
+  static constexpr long LDS = (long)N * NH * (sizeof(double2) + 2 * sizeof(c2<T>) + sizeof(double)) +
+                              (long)N * N * sizeof(T) + (long)N * sizeof(c2<T>);
+  static constexpr bool fits = N <= 64 && LDS <= 150 * 1024;  // the rest: M, scratch of the sums
+};
 template <typename T, int N, int NT = PlaneCfg<T, N>::NT>
-__global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restrict__ tw, c2<T> *b0, c2<T> *b1,
+__global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restrict__ twg, c2<T> *b0, c2<T> *b1,
                                               const c2<T> *__restrict__ gh, const T *__restrict__ gp, SubState *st) {
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   constexpr int NW = NT / 64, RS = MOM_NV + 1;
+  static_assert(Sub2dCfg<T, N>::fits, "the LDS-resident subproblem");
   // the plane in LDS; after the last pass the same storage holds (w |b_t|^2, u) per element
   __shared__ double2 Lraw[N * NH];
   C *L = reinterpret_cast<C *>(Lraw);
+  __shared__ C Bs[N * NH];  // b_t (b_{-1} on entry)
+  __shared__ C Gs[N * NH];  // g
+  __shared__ T Gp[N * N];   // Gamma'(psi)
+  __shared__ double Lm[N * NH];  // Lambda
+  __shared__ C tw[N];
   __shared__ double M[RS];
   __shared__ double scr[2 * NW];
+  // row-sum scratch [NT / 16][RS]: the plane's storage where it is large
+  // enough (not for N <= 16), else an array of its own
+  constexpr int NROW = NT / 16;
+  constexpr bool RED_IN_PLANE = 2 * N * NH >= NROW * RS;
+  __shared__ double red_own[RED_IN_PLANE ? 1 : NROW * RS];
+  double *red = RED_IN_PLANE ? reinterpret_cast<double *>(Lraw) : red_own;
   if (st->done) return;
+  const double xi = p.xi[0], q = p.q[0];
+  for (int h = threadIdx.x; h < N * NH; h += NT) {
+    Bs[h] = b1[h];  // b_{t-1} of step 0 is b[1]
+    Gs[h] = gh[h];
+    const int e = h / NH, f = h - e * NH;
+    Lm[h] = lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q);
+  }
+  for (int i = threadIdx.x; i < N * N; i += NT) Gp[i] = gp[i];
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
+  __syncthreads();
   const double eta = st->eta, tol = st->tol;
   const int max_inner = st->max_inner;
   NewtonPar np{eta, st->r2, 0.0, st->newton_rtol, st->newton_steptol, st->max_newton, st->newton_phi,
                st->newton_direct_only};
-  const double xi = p.xi[0], q = p.q[0];
   const double inv_n = 1.0 / ((double)N * (double)N);
   double lam_t = st->lam[0];
   int newton_total = 0, newton_direct = 0;
   for (int t = 0;; ++t) {
-    const C *bprev = ((t - 1) & 1) ? b1 : b0;
     C *bnext = (t & 1) ? b1 : b0;
     const double mu0 = eta * lam_t;
     // d_t, axis 0 inverse
     plane_cols_inv_load<T, N, NT>(L, tw, [&](int f, int e) -> C {
-      const C v = bprev[e * NH + f];
-      const double x = 1.0 + eta * lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q) + mu0;
+      const C v = Bs[e * NH + f];
+      const double x = 1.0 + eta * Lm[e * NH + f] + mu0;
       const double sc = (e == 0 && f == 0) ? 0.0 : rcp64(x);
       return C{T(double(v.x) * sc), T(double(v.y) * sc)};
     });
     __syncthreads();
     // rows inverse, x Gamma' (rows 2f, 2f + 1), rows forward
     plane_rows_inv<T, N, NT>(L, tw, [&](int f, int e, C v, int, int) {
-      L[f * PR + e] = C{v.x * gp[(2 * f) * N + e], v.y * gp[(2 * f + 1) * N + e]};
+      L[f * PR + e] = C{v.x * Gp[(2 * f) * N + e], v.y * Gp[(2 * f + 1) * N + e]};
     });
     __syncthreads();
     sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, tw);
@@ -1236,9 +1264,9 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     auto upd = [&](int f, int e, C v, int, int) {
       const int h = e * NH + f;
       const bool dc = (e == 0 && f == 0);
-      const double lam = lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q);
+      const double lam = Lm[h];
       const double w = (f == 0 || 2 * f == N) ? 1.0 : 2.0;
-      const C bp = bprev[h], gg = gh[h];
+      const C bp = Bs[h], gg = Gs[h];  // each element is read and rewritten by one thread
       const double u = rcp64(1.0 + eta * lam + mu0);
       const double sc = dc ? 0.0 : u;
       const double dx = double(bp.x) * sc, dy = double(bp.y) * sc;
@@ -1246,6 +1274,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
       const double rx = double(gg.x) + (lam + lam_t) * dx + tx, ry = double(gg.y) + (lam + lam_t) * dy + ty;
       const C bn = dc ? C{T(0), T(0)} : C{T(dx - eta * (double(gg.x) + tx)), T(dy - eta * (double(gg.y) + ty))};
       bnext[h] = bn;
+      Bs[h] = bn;
       if (!dc) res2 += w * (rx * rx + ry * ry);
       const double wb = dc ? 0.0 : w * (double(bn.x) * double(bn.x) + double(bn.y) * double(bn.y));
       Lraw[h] = double2{wb, u};
@@ -1259,8 +1288,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     acc[MOM_NV] = res2;
     for (int h = threadIdx.x; h < N * NH; h += NT) {
       const double2 wu = Lraw[h];
-      const int e = h / NH, f = h - e * NH;
-      const double u0 = rcp64(1.0 + eta * lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q));
+      const double u0 = rcp64(1.0 + eta * Lm[h]);
       acc[0] = fma(wu.x, u0 * u0, acc[0]);
       double pw = wu.x * wu.y * wu.y;
 #pragma unroll
@@ -1269,10 +1297,8 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
         pw *= wu.y;
       }
     }
-    __syncthreads();  // Lraw becomes the reduction scratch [NT / 16][RS]
+    __syncthreads();  // Lraw may become the row-sum scratch
     // sums over rows of 16 lanes (four DPP shifts each), row sums added in LDS
-    double *red = reinterpret_cast<double *>(Lraw);
-    constexpr int NROW = NT / 16;
     const int row = threadIdx.x >> 4;
 #pragma unroll
     for (int j = 0; j < RS; ++j) {
@@ -1305,16 +1331,16 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
       break;
     }
     np.lam_prev = lam_t;
-    // direct sum of phi over the half spectrum of b_t (this workgroup wrote it)
+    // direct sum of phi over the half spectrum of b_t
     auto direct = [&](double lam, double &phi, double &dphi) {
       const double e2 = eta * lam;
       double a = 0.0, b = 0.0;
       for (int h = threadIdx.x + 1; h < N * NH; h += NT) {
         const int e = h / NH, f = h - e * NH;
-        const C bn = bnext[h];
+        const C bn = Bs[h];
         const double w = (f == 0 || 2 * f == N) ? 1.0 : 2.0;
         const double wb = w * (double(bn.x) * double(bn.x) + double(bn.y) * double(bn.y));
-        const double r = rcp64(1.0 + eta * lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q) + e2);
+        const double r = rcp64(1.0 + eta * Lm[h] + e2);
         a = fma(wb, r * r, a);
         b = fma(wb, r * r * r, b);
       }

@@ -190,8 +190,9 @@ template <typename T, int N> struct Impl {
   }
 
   // the whole subproblem in one workgroup: up to N = 64 (beyond, the butterflies
-  // and the update no longer fit in registers together)
-  static constexpr bool SUB2D = lbk::PlaneCfg<T, N>::fits && N <= 64;
+  // and the update no longer fit in registers together, nor b, g and Gamma' in
+  // LDS beside the plane)
+  static constexpr bool SUB2D = lbk::PlaneCfg<T, N>::fits && lbk::Sub2dCfg<T, N>::fits;
   static void sub2d(const PassArgs &a) {
     if constexpr (SUB2D)
       LB_LAUNCH((lbk::k_sub2d<T, N>), dim3(1), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, a.g, a.p, (const C2 *)a.tw,

@@ -392,7 +392,10 @@ def test_errors_are_reported():
 # ---------------------------------------------------------------------------
 
 
-@pytest.mark.parametrize("n", [16, 64])
+# every length the one-workgroup kernel takes: radix-16 single pass (16),
+# radix 3 (12, 24, 48), and the small grids whose row-sum scratch does not fit
+# in the plane's storage (8, 12, 16)
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_single_workgroup_subproblem_equals_multi_kernel(n, precision):
     """The one-launch subproblem (every iteration in one workgroup) against the

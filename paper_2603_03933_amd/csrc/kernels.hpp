@@ -1218,6 +1218,8 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
   __shared__ C tw[N];
   __shared__ double M[RS];
   __shared__ double scr[2 * NW];
+  __shared__ double nw_lam;  // wave 0's Newton result, steps, direct sums
+  __shared__ int nw_it[2];
   // row-sum scratch [NT / 16][RS]: the plane's storage where it is large
   // enough (not for N <= 16), else an array of its own
   constexpr int NROW = NT / 16;
@@ -1348,11 +1350,31 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
       phi = a;
       dphi = -2.0 * eta * b;
     };
-    int it = 0, nd = 0;
-    lam_t = multiplier_newton(M, np, direct, it, nd);
+    // Newton on the series in wave 0 alone; every thread runs it again with
+    // the direct sum where an evaluation needs one (as in the Newton kernel)
+    if (threadIdx.x < 64) {
+      auto stub = [&](double, double &phi, double &dphi) {
+        phi = np.r2;
+        dphi = -1.0;
+      };
+      int it1 = 0, nd1 = 0;
+      const double l1 = multiplier_newton(M, np, stub, it1, nd1);
+      if (threadIdx.x == 0) {
+        nw_lam = l1;
+        nw_it[0] = it1;
+        nw_it[1] = nd1;
+      }
+    }
+    __syncthreads();
+    int it = nw_it[0], nd = 0;
+    lam_t = nw_lam;
+    if (nw_it[1] != 0) {  // uniform
+      it = 0;
+      lam_t = multiplier_newton(M, np, direct, it, nd);
+    }
     newton_total += it;
     newton_direct += nd;
-    __syncthreads();  // M, the LDS and b_t are read again by the next iteration
+    __syncthreads();  // M, the LDS, b_t and the Newton result are read again by the next iteration
   }
 }
 
@@ -1745,8 +1767,32 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
     phi = a;
     dphi = -2.0 * eta * b;
   };
-  int it = 0, ndirect = 0;
-  const double lam = multiplier_newton(M, np, direct, it, ndirect);
+  // Newton on the series alone in one wave: the other waves would only repeat
+  // its dependent FP64 chain on the same SIMDs. An evaluation that needs the
+  // sum over the spectrum ends that run (a stub returns phi = r^2), and then
+  // every thread runs the iteration again with the block-collective sum.
+  __shared__ double lam_w;
+  __shared__ int it_w, nd_w;
+  if (threadIdx.x < 64) {
+    auto stub = [&](double, double &phi, double &dphi) {
+      phi = np.r2;
+      dphi = -1.0;
+    };
+    int it1 = 0, nd1 = 0;
+    const double l1 = multiplier_newton(M, np, stub, it1, nd1);
+    if (threadIdx.x == 0) {
+      lam_w = l1;
+      it_w = it1;
+      nd_w = nd1;
+    }
+  }
+  __syncthreads();
+  int it = it_w, ndirect = 0;
+  double lam = lam_w;
+  if (nd_w != 0) {  // uniform
+    it = 0;
+    lam = multiplier_newton(M, np, direct, it, ndirect);
+  }
   if (threadIdx.x == 0) {
     st->resid = resid;
     st->lam[(t + 1) & 1] = lam;

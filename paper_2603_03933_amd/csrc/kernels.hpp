@@ -1676,26 +1676,58 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
                                                   const double *__restrict__ bsq2, int npair, SubState *st) {
   __shared__ double M[MOM_NV + 1];
   __shared__ double scratch[32];
-  // the state of this step, read before anything here writes it; its loads
-  // are in flight together with the partials' instead of after them
-  const SubState s0 = *st;
-  // wave v sums value v over the moment blocks (v = MOM_NV: residual partials),
-  // four loads in flight per lane (520 blocks: three memory round trips)
+  // wave w sums values w and w + 16 (value MOM_NV: the residual partials)
+  // over the workgroups of the update pass. Both values' loads, KU per lane
+  // each (up to 64 KU workgroups), go out before the first add waits, and
+  // the step's state is read after them, so the two round trips overlap.
+  constexpr int WV = NW_NT / 64, KU = 9;
+  static_assert(2 * WV > MOM_NV, "two values per wave");
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int v = wv; v <= MOM_NV; v += NW_NT / 64) {
-    const double *src = v < MOM_NV ? mom + (long)v * nmb : rpart;
-    const int cnt = v < MOM_NV ? nmb : rbpi;
-    double a = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
-    int i = lane;
-    for (; i + 192 < cnt; i += 256) {
-      a += src[i];
-      a2 += src[i + 64];
-      a3 += src[i + 128];
-      a4 += src[i + 192];
+  const int va = wv, vb = wv + WV;
+  const bool hb = vb <= MOM_NV;  // uniform in the wave
+  const double *sa = va < MOM_NV ? mom + (long)va * nmb : rpart;
+  const double *sb = !hb ? sa : (vb < MOM_NV ? mom + (long)vb * nmb : rpart);  // !hb: loaded, not added
+  const int ca = va < MOM_NV ? nmb : rbpi, cb = !hb ? 0 : (vb < MOM_NV ? nmb : rbpi);
+  double xa[KU], xb[KU];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {  // unconditional (past the end: index 0, not added)
+    const int i = lane + 64 * k;
+    xa[k] = sa[i < ca ? i : 0];
+    xb[k] = sb[i < cb ? i : 0];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // the state of this step, read before anything here writes it
+  const SubState s0 = *st;
+  __builtin_amdgcn_sched_barrier(0);
+  {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      const int i = lane + 64 * k;
+      if (i < ca) a += xa[k];
+      if (i < cb) b += xb[k];
     }
-    for (; i < cnt; i += 64) a += src[i];
-    a = wave_sum((a + a2) + (a3 + a4));
-    if (lane == 0) M[v] = a;
+    for (int i0 = 64 * KU; i0 < ca || i0 < cb; i0 += 64 * KU) {  // more than 64 KU workgroups
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const int i = i0 + lane + 64 * k;
+        xa[k] = sa[i < ca ? i : 0];
+        xb[k] = sb[i < cb ? i : 0];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const int i = i0 + lane + 64 * k;
+        if (i < ca) a += xa[k];
+        if (i < cb) b += xb[k];
+      }
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+      M[va] = a;
+      if (hb) M[vb] = b;
+    }
   }
   __syncthreads();
   if (s0.done) return;

@@ -40,10 +40,9 @@ def kernel_bytes(name: str, prec: str, n) -> float | None:
     r = 8 if prec == "fp64" else 4
     N = math.prod(n)
     nh = N // n[-1] * (n[-1] // 2 + 1)
-    npair = (n[0] // 2 + 1) * (nh // n[0])  # (|k0|, column) pair sums, FP64
     table = {
-        # read T d, b_prev, g; write b_next and the pair sums of w|b|^2
-        "col0_fwd_update": nh * 4 * c + npair * 8,
+        # read T d, b_prev, g; write b_next (the moment partials are a few KB)
+        "col0_fwd_update": nh * 4 * c,
         "col0_inv_scale_d": nh * 2 * c,  # read b_prev, write the partial transform
         # read/write the partial transform, read Gamma' (one plane per workgroup)
         "plane_inner": nh * 2 * c + N * r,

@@ -440,7 +440,7 @@ template <typename T> struct OpInvScaleD {
 
 // step t, axis-0 forward pass of T d_t, then the diagonal update:
 //   Td = P F_N(Gamma' d_t),  r_t = g + (Lambda + lambda_t) d_t + Td  (residual of d_t),
-//   b_t = d_t - eta (g + Td),  bsq = w |b_t|^2 (for the secular function)
+//   b_t = d_t - eta (g + Td),  w |b_t|^2 (for the secular function)
 template <typename T> struct UpdAux {
   c2<T> bp, gg;
   double kk0;
@@ -452,7 +452,6 @@ template <typename T> struct OpFwdUpdate {
   const c2<T> *tmp;  // row/axis-1 transformed product Gamma' d_t
   c2<T> *b0, *b1;
   const c2<T> *gh;
-  double *bsq2;     // w (|b(k0)|^2 + |b(-k0)|^2) per (|k0|, column): [n0/2 + 1][columns]
   double *partial;  // one double per workgroup: sum w |r|^2
   double *mom;      // MOM_NV doubles per workgroup: phi(0), M_2 .. M_{NMOM+1}
   const SubState *st;
@@ -506,7 +505,7 @@ template <typename T> struct OpFwdUpdate {
     const double bxr = double(bn.x), byr = double(bn.y);
     *sq = ci.w * (bxr * bxr + byr * byr);
   }
-  // Pair sums w (|b(k0)|^2 + |b(-k0)|^2) go to bsq2; the block's shares of
+  // From the pair sums w (|b(k0)|^2 + |b(-k0)|^2), the block's shares of
   // phi(0) and of the power sums M_j around mu0 = eta lambda_t, and of the
   // squared residual, go to mom[j * blocks + block] and partial[block].
   template <int NT, int N, int CC>
@@ -532,7 +531,6 @@ template <typename T> struct OpFwdUpdate {
         if (e >= NH0) break;
         double v = sq[e * CC + cc];
         if (e != 0 && 2 * e != N) v += sq[(N - e) * CC + cc];
-        bsq2[((long)b * NH0 + e) * cpi + ml] = v;
         if (e != 0 || ml != 0) {
           const double x = 1.0 + bs.eta * lam_of(kk0_of(g, e) + kkc, bs.xi, bs.q);
           const double u0 = rcp64(x);
@@ -1671,9 +1669,11 @@ __device__ __forceinline__ void block_sum2_all(double &a, double &b, double *scr
   __syncthreads();
 }
 
+template <typename T>
 __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__restrict__ mom, int nmb,
                                                   const double *__restrict__ rpart, int rbpi,
-                                                  const double *__restrict__ bsq2, int npair, SubState *st) {
+                                                  const c2<T> *__restrict__ b0, const c2<T> *__restrict__ b1, int cpi,
+                                                  SubState *st) {
   __shared__ double M[MOM_NV + 1];
   __shared__ double scratch[32];
   // wave w sums values w and w + 16 (value MOM_NV: the residual partials)
@@ -1754,30 +1754,50 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
   // 2 DU loads of a batch issued before the first is used (rows past the end
   // re-read the last row and add nothing).
   auto direct = [&](double lam, double &phi, double &dphi) {
-    constexpr int DU = 16;
+    constexpr int DU = 4;
+    const c2<T> *bt = (t & 1) ? b1 : b0;  // b_t, written by this step's update pass
     const double xi = p.xi[0], q = p.q[0];
     const double e2 = eta * lam;
-    const int nrow = g.n0 / 2 + 1;
-    const int cpi = npair / nrow;
+    const int n0 = g.n0, nrow = n0 / 2 + 1;
     double a = 0.0, b = 0.0;
     for (int ml0 = 0; ml0 < cpi; ml0 += 2 * NW_NT) {
       int mls[2];
       bool okc[2];
-      double kkc[2];
+      double kkc[2], wc[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int ml = ml0 + c * NW_NT + (int)threadIdx.x;
         okc[c] = ml < cpi;
         mls[c] = okc[c] ? ml : 0;
-        kkc[c] = col_info(g, mls[c]).kkc;
+        const ColInfo ci = col_info(g, mls[c]);
+        kkc[c] = ci.kkc;
+        wc[c] = ci.w;
       }
       for (int e0 = 0; e0 < nrow; e0 += DU) {
+        // entries k0 and -k0 (rows e and n0 - e of column ml, at e cpi + ml)
+        c2<T> xp[2][DU], xm[2][DU];
+#pragma unroll
+        for (int u = 0; u < DU; ++u) {
+          const int e = e0 + u < nrow ? e0 + u : nrow - 1;
+          const int em = (e == 0 || 2 * e == n0) ? e : n0 - e;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            xp[c][u] = bt[(long)e * cpi + mls[c]];
+            xm[c][u] = bt[(long)em * cpi + mls[c]];
+          }
+        }
         double w[2][DU];
 #pragma unroll
         for (int u = 0; u < DU; ++u) {
-          const long row = (long)(e0 + u < nrow ? e0 + u : nrow - 1) * cpi;
+          const int e = e0 + u < nrow ? e0 + u : nrow - 1;
+          const bool paired = !(e == 0 || 2 * e == n0);
 #pragma unroll
-          for (int c = 0; c < 2; ++c) w[c][u] = bsq2[row + mls[c]];
+          for (int c = 0; c < 2; ++c) {
+            const double px = double(xp[c][u].x), py = double(xp[c][u].y);
+            const double mx = double(xm[c][u].x), my = double(xm[c][u].y);
+            const double sp = wc[c] * (px * px + py * py), sm = wc[c] * (mx * mx + my * my);
+            w[c][u] = paired ? sp + sm : sp;
+          }
         }
 #pragma unroll
         for (int u = 0; u < DU; ++u) {

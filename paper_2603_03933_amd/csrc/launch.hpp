@@ -47,7 +47,6 @@ struct PassArgs {
   void *b0 = nullptr;
   void *b1 = nullptr;
   const void *gh = nullptr;
-  double *bsq = nullptr;
   SubState *st = nullptr;
   const void *gp = nullptr;
   double *gp64 = nullptr;
@@ -112,7 +111,6 @@ template <typename T, int N> struct Impl {
     op.b0 = (C2 *)a.b0;
     op.b1 = (C2 *)a.b1;
     op.gh = (const C2 *)a.gh;
-    op.bsq2 = a.bsq;
     op.partial = a.partial;
     op.mom = a.mom;
     op.st = a.st;

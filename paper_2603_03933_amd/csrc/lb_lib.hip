@@ -126,7 +126,6 @@ struct lb_plan {
   hipStream_t own = nullptr;  // private stream for captured launch sequences (created on first use)
   int plane_nt = -1;          // autotuned plane-pass variant (index into plane_inner_nt), -1: built-in choice
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
-  long npair = 0;         // (|k0|, column) entries per instance
   double *mom = nullptr;  // moment partials of the update pass, MOM_NV x its blocks
   // FP64 spectral buffers (batch * nh complex each; SP holds 2 * batch)
   double2 *SP = nullptr, *GH = nullptr, *SH = nullptr, *W64 = nullptr;
@@ -136,7 +135,6 @@ struct lb_plan {
   // physical buffers (batch * N)
   double *gp64 = nullptr, *sphys = nullptr, *ptrial = nullptr;
   float *gp32 = nullptr;
-  double *bsq = nullptr;
   double *partial = nullptr;
   long partial_len = 0;
   double *sums = nullptr;  // small device scratch for finalised sums
@@ -385,7 +383,6 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
   }
   // the update pass reduces w |b|^2 over the +-k0 pairs of each axis-0
   // column: entries p = |k0| * columns + column, per instance
-  P->npair = (long)(P->n0 / 2 + 1) * (P->nh / P->n0);
   const long S = (long)batch * P->nh, Np = (long)batch * P->N;
   int rc;
   if ((rc = dalloc(P, &P->SP, 2 * S)) || (rc = dalloc(P, &P->GH, S)) || (rc = dalloc(P, &P->SH, S)) ||
@@ -410,7 +407,7 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
     if ((rc = dalloc(P, &P->gp32, Np))) return cleanup(rc);
   }
   if ((rc = dalloc(P, &P->gp64, Np)) || (rc = dalloc(P, &P->sphys, Np)) || (rc = dalloc(P, &P->ptrial, Np)) ||
-      (rc = dalloc(P, &P->bsq, (long)batch * P->npair)) || (rc = dalloc(P, &P->mom, (long)lbk::MOM_NV * bpi_col0(P))))
+      (rc = dalloc(P, &P->mom, (long)lbk::MOM_NV * bpi_col0(P))))
     return cleanup(rc);
   const long mb = std::max({bpi_pairs(P), bpi_rows(P), bpi_col0(P), P->dim == 3 ? bpi_col1(P) : 1L, bpi_ew(P)});
   P->partial_len = 8 * mb * batch + 64;
@@ -950,7 +947,6 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   u.b0 = P->B0;
   u.b1 = P->B1;
   u.gh = P->GHT;
-  u.bsq = P->bsq;
   u.partial = P->partial;
   u.mom = P->mom;
   u.st = P->st;
@@ -962,8 +958,14 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   }
   {
     KT kt_(P, "newton");
-    LB_LAUNCH(lbk::k_newton, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom, u.cg.bpi,
-                       (const double *)P->partial, u.cg.bpi, (const double *)P->bsq, (int)P->npair, P->st);
+    if (prec == LB_FP64)
+      LB_LAUNCH(lbk::k_newton<double>, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom,
+                u.cg.bpi, (const double *)P->partial, u.cg.bpi, (const double2 *)P->B0, (const double2 *)P->B1,
+                u.cg.cpi, P->st);
+    else
+      LB_LAUNCH(lbk::k_newton<float>, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom,
+                u.cg.bpi, (const double *)P->partial, u.cg.bpi, (const float2 *)P->B0, (const float2 *)P->B1,
+                u.cg.cpi, P->st);
   }
 }
 

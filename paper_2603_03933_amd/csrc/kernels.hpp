@@ -244,6 +244,13 @@ __device__ double multiplier_newton(const double *M, const NewtonPar &np, const 
   const double mu0 = eta * lam_prev;
   auto eval = [&](double lam, double &phi, double &dphi) {
     const double D = eta * (lam - lam_prev);
+    if (!np.direct_only && D == 0.0) {
+      // the series at its centre (the warm start): the same values as the
+      // Horner sums below with -D = 0, without their dependent chains
+      phi = M[1];
+      dphi = -eta * (2.0 * M[2]);
+      return;
+    }
     const double rho = fabs(D) / (1.0 + mu0);
     if (!np.direct_only && rho < 0.5) {
       double rn = 1.0;

@@ -199,18 +199,27 @@ static void twiddles(int n, std::vector<double2> &w64, std::vector<float2> &w32)
 
 
 
+// Kernel-timing events only carry timestamps (results are read after stream
+// synchronisation, never through them), so they are recorded without the
+// system-scope fence, whose cache writeback and invalidation would otherwise
+// slow every timed launch and the work after it.
 static hipEvent_t timing_event(lb_plan *P) {
   hipEvent_t e = nullptr;
   if (!P->timing.pool.empty()) {
     e = P->timing.pool.back();
     P->timing.pool.pop_back();
-  } else if (hipEventCreate(&e) != hipSuccess) {
+  } else if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
     e = nullptr;
   }
   return e;
 }
-static void timing_flush(lb_plan *P) {
-  for (const PendingTiming &q : P->timing.pending) {
+// Adds the first n pending kernel timings (all of them by default) to the
+// totals and returns their events to the pool.
+static void timing_flush(lb_plan *P, size_t n = (size_t)-1) {
+  std::vector<PendingTiming> &pend = P->timing.pending;
+  n = std::min(n, pend.size());
+  for (size_t i = 0; i < n; ++i) {
+    const PendingTiming &q = pend[i];
     float ms = 0.0f;
     if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
       P->timing.entries[q.idx].count += 1;
@@ -219,7 +228,7 @@ static void timing_flush(lb_plan *P) {
     P->timing.pool.push_back(q.a);
     P->timing.pool.push_back(q.b);
   }
-  P->timing.pending.clear();
+  pend.erase(pend.begin(), pend.begin() + (long)n);
 }
 namespace lb {
 thread_local hipEvent_t kt_ev[2] = {nullptr, nullptr};
@@ -1078,6 +1087,9 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
     }
     if (ce != hipSuccess) return fail(LB_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
   }
+  // timings of launches the last stop-flag read has seen complete: read while
+  // the GPU runs the next chunk, not while it waits for it
+  size_t timed_done = 0;
   while (launched < max_steps) {
     const int n = (int)std::min<long>(chunk, max_steps - launched);
     if (gexec) {
@@ -1091,9 +1103,13 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
       launched += n;
     }
     LB_TRY(check_launch("subproblem step"));
+    if (timed_done) {
+      timing_flush(P, timed_done);
+      timed_done = 0;
+    }
     LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
     LB_HIP(hipStreamSynchronize(P->stream));
-    if (!P->timing.pending.empty()) timing_flush(P);
+    timed_done = P->timing.pending.size();
     if (P->st_h->done) break;
   }
   // the loop ended with a synchronisation of the stream it ran on, so the

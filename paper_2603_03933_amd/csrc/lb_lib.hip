@@ -1796,6 +1796,21 @@ extern "C" int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *par
 // cubic grids) is built with 256, 512 and 1024 threads; time each on this
 // plan's buffers and keep the fastest.
 // ---------------------------------------------------------------------------
+extern "C" int lb_plan_set_plane_threads(lb_plan *P, int threads) {
+  if (!P) return fail(LB_ERR_ARG, "null plan");
+  if (threads == 0) {
+    P->plane_nt = -1;
+    return LB_OK;
+  }
+  const int v = threads == 256 ? 0 : threads == 512 ? 1 : threads == 1024 ? 2 : -1;
+  if (v < 0) return fail(LB_ERR_ARG, "plane threads must be 0, 256, 512 or 1024");
+  const NFuncs *f1 = P->dim == 3 ? F(P, 1, P->prec) : nullptr;
+  if (!f1 || !f1->plane_inner || P->n1 != P->nl || !f1->plane_inner_nt[v])
+    return fail(LB_ERR_UNSUPPORTED, "this grid has no plane pass");
+  P->plane_nt = v;
+  return LB_OK;
+}
+
 extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const double *psi, int reps, int *threads) {
   if (!P || !psi || !threads) return fail(LB_ERR_ARG, "null argument");
   if (reps < 1 || reps > 10000) return fail(LB_ERR_ARG, "reps must be in [1, 10000]");

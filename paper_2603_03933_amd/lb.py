@@ -146,6 +146,7 @@ _SIGS = {
     "lb_random_ball": (_I, [_P, _D, C.c_ulonglong, C.c_ulonglong, _P]),
     "lb_imex_tr_solve_many": (_I, [C.POINTER(_P), C.POINTER(LbParams), C.POINTER(_P), _I, C.POINTER(LbTrOpts), _I, C.POINTER(LbTrInfo), C.POINTER(_I)]),
     "lb_plan_autotune": (_I, [_P, C.POINTER(LbParams), _P, _I, C.POINTER(_I)]),
+    "lb_plan_set_plane_threads": (_I, [_P, _I]),
 }
 
 
@@ -286,6 +287,10 @@ class Plan:
         nt = C.c_int()
         _check(lib().lb_plan_autotune(self._h, _params_array(params, self.batch), _ptr(psi, self.N * self.batch, "psi"), int(reps), C.byref(nt)))
         return nt.value
+
+    def lb_plan_set_plane_threads(self, threads):
+        """Pin the plane-pass variant (256, 512 or 1024 threads; 0: the built-in choice)."""
+        _check(lib().lb_plan_set_plane_threads(self._h, int(threads)))
 
     def lb_energy_grad(self, params, psi, energy=None, grad=None, want_grad=True):
         self._sync_stream()

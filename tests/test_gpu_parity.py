@@ -426,6 +426,35 @@ def test_single_workgroup_subproblem_equals_multi_kernel(n, precision):
         assert abs(i1.iters - ref.iters) <= 1 and abs(i1.lambda_ - ref.lam) <= 1e-9 * max(1.0, ref.lam)
 
 
+def test_single_2d_64_solve_reaches_the_oracle_endpoint():
+    """The 64^2 single-instance workload (tau = -0.15, gamma = 0.25, noise
+    start) against the oracle's solve stored in tests/golden (written by
+    make_single_2d_64.py from the oracle alone): same outer and inner counts,
+    energy to 1e-12, the same lamellar field up to translation (extremes, RMS,
+    power at the leading modes), and a Lanczos lambda_min >= -1e-8 (the dense
+    oracle value is the translation mode, ~0)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "single_2d_64_oracle.json")))
+    inst = I.single_2d(64)
+    shape, box = inst.grid.n, inst.grid.box
+    prm = lb.Params(inst.params.tau, inst.params.gamma)
+    plan = lb.Plan(shape, box)
+    psi = dev(inst.psi0)
+    info, rc = plan.lb_imex_tr_solve(prm, psi, lb.tr_opts(grad_norm_inf=0, eps=1e-8, sub={"max_inner": 10000}))
+    out = host(psi)
+    assert rc == lb.LB_OK and info.gnorm < 1e-8
+    assert info.outer == gold["outer"] and abs(info.inner_total - gold["inner_total"]) <= info.outer
+    assert abs(info.energy - gold["energy"]) <= 1e-12 * abs(gold["energy"])
+    for k, v in (("psi_min", out.min()), ("psi_max", out.max()), ("psi_rms", np.sqrt(np.mean(out ** 2)))):
+        assert abs(v - gold[k]) <= 1e-8 * abs(gold[k]), k
+    power = np.abs(np.fft.fft2(out) / out.size) ** 2
+    for i, j, pw in gold["top_power"]:
+        assert abs(power[i, j] - pw) <= 1e-8 * gold["top_power"][0][2], (i, j)
+    ritz, _ = plan.lb_lanczos_min(prm, psi, dev(I.zero_mean_noise(shape, 1.0, 5)), 60, precond_shift=1.0)
+    assert ritz >= -1e-8 and gold["dense_lambda_min"] >= -1e-8
+
+
 def test_single_workgroup_full_solve_64():
     """The 64^2 single-instance workload solved with and without the one-workgroup path."""
     inst = I.single_2d(64)

@@ -323,10 +323,11 @@ int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double
 int lb_plan_autotune(lb_plan *plan, const lb_params *params, const double *psi, int reps, int *threads);
 
 /* Pins the plane-pass variant the autotuner would choose: threads = 256, 512
- * or 1024, or 0 for the built-in choice (1024 from n1 = 96, 512 from 48, else
- * 256). Only plans with a plane pass accept a nonzero value (LB_ERR_UNSUPPORTED
- * otherwise; LB_ERR_ARG for any other count). The variants differ only in how
- * many threads share a plane. */
+ * or 1024, or 0 for the built-in choice (1024 from n1 = 96, else 512). Only
+ * the plans lb_plan_autotune can tune (3D, n1 = n2 >= 64) accept a nonzero
+ * value (LB_ERR_UNSUPPORTED otherwise; LB_ERR_ARG for any other count). The
+ * variants differ only in how many threads share a plane; their results agree
+ * to rounding, and each variant is deterministic. */
 int lb_plan_set_plane_threads(lb_plan *plan, int threads);
 
 #ifdef __cplusplus

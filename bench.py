@@ -51,6 +51,11 @@ def kernel_bytes(name: str, prec: str, n) -> float | None:
         "col1_fwd": nh * 2 * c,
         "col0_inv": nh * 2 * c,
         "col0_fwd": nh * 2 * c,
+        # the three passes of one Hessian-vector product (24 N bytes at the
+        # method level: read psi and v, write the product)
+        "plane_fwd_phys": 2 * N * r + nh * c,  # read v and psi (mean partial), write the half spectrum
+        "col0_fwd_mul_inv": nh * 2 * c,
+        "plane_inv_phys": nh * c + 3 * N * r,  # read the spectrum, psi and v, write the product
     }
     return table.get(name)
 
@@ -208,6 +213,8 @@ def main():
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--kernel-sample", type=int, default=0, metavar="K",
                     help="only run K iterations of Algorithm 3 on the workload (for counter collection) and exit")
+    ap.add_argument("--hv-sample", type=int, default=0, metavar="K",
+                    help="only run K FP64 Hessian-vector products on the workload (for counter collection) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (scales HBM counters) and exit")
     ap.add_argument("--large-solve", action="store_true",
@@ -264,6 +271,13 @@ def main():
         d, sinfo, src = plan.lb_tr_subproblem(prm, psi0, g, 1.0, lb.sub_opts(eta=0.0132, max_inner=args.kernel_sample))
         torch.cuda.synchronize()
         print(json.dumps({"kernel_sample": {"iterations": sinfo.iters, "workload": f"bcc_3d {n[0]}^3 FP64, Algorithm 3 at psi0, r = 1"}}))
+        return
+    if args.hv_sample:
+        hv = torch.empty_like(psi0)
+        for _ in range(args.hv_sample):
+            plan.lb_hessvec(prm, psi0, v0, out=hv)
+        torch.cuda.synchronize()
+        print(json.dumps({"hv_sample": {"products": args.hv_sample, "workload": f"bcc_3d {n[0]}^3 FP64, H(psi0) v"}}))
         return
 
     # choose the plane-pass variant for this grid (autotuner), then warm up

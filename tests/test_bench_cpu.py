@@ -29,4 +29,9 @@ def test_kernel_bytes_at_128_cubed():
     # FP32 spectra and Gamma' halve every term
     for k in ("col0_inv_scale_d", "plane_inner", "col0_fwd_update"):
         assert bench.kernel_bytes(k, "fp32", n) * 2 == bench.kernel_bytes(k, "fp64", n)
+    # a Hessian-vector product's three passes move 40 N + 64 nh bytes in FP64,
+    # three times the 24 N its method-level definition touches
+    hv = sum(bench.kernel_bytes(k, "fp64", n) for k in ("plane_fwd_phys", "col0_fwd_mul_inv", "plane_inv_phys"))
+    assert hv == 40 * N + 64 * nh
+    assert abs(hv / (24 * N) - 3.02) < 0.01
     assert bench.kernel_bytes("not_a_kernel", "fp64", n) is None

@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--kernel-sample", type=int, default=0, metavar="K",
                     help="only run K iterations of Algorithm 3 on the workload (for counter collection) and exit")
+    ap.add_argument("--sample-precision", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the plan that --kernel-sample runs")
     ap.add_argument("--hv-sample", type=int, default=0, metavar="K",
                     help="only run K FP64 Hessian-vector products on the workload (for counter collection) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -267,10 +269,11 @@ def main():
         return info, rc, ritz, res
 
     if args.kernel_sample:
-        E, g = plan.lb_energy_grad(prm, psi0)
-        d, sinfo, src = plan.lb_tr_subproblem(prm, psi0, g, 1.0, lb.sub_opts(eta=0.0132, max_inner=args.kernel_sample))
+        sp = plan if args.sample_precision == "fp64" else lb.Plan(n, box, precision="fp32")
+        E, g = sp.lb_energy_grad(prm, psi0)
+        d, sinfo, src = sp.lb_tr_subproblem(prm, psi0, g, 1.0, lb.sub_opts(eta=0.0132, max_inner=args.kernel_sample))
         torch.cuda.synchronize()
-        print(json.dumps({"kernel_sample": {"iterations": sinfo.iters, "workload": f"bcc_3d {n[0]}^3 FP64, Algorithm 3 at psi0, r = 1"}}))
+        print(json.dumps({"kernel_sample": {"iterations": sinfo.iters, "workload": f"bcc_3d {n[0]}^3 {args.sample_precision.upper()}, Algorithm 3 at psi0, r = 1"}}))
         return
     if args.hv_sample:
         hv = torch.empty_like(psi0)

@@ -31,6 +31,12 @@ METRIC = "Hessian-vector products/s + IMEX-TR solves/s at 128³ (FP64 vs FP32+FP
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 TOL = 1e-8
 LANCZOS_STEPS = 60
+# Relative stop floor of FP32 inner loops (||r|| < 1e-5 ||g||): the absolute
+# 1e-13 of Section 4 lies below FP32 rounding, and the residual computed through
+# FP32 transforms carries a relative error of about eps_32 log2(N) (1.3e-6 at
+# 128^3), so a floor of 1e-6 sits on that noise and subproblems end only when
+# it happens to dip below; 1e-5 stays clear of it.
+FP32_SUB_REL = 1e-5
 
 
 def kernel_bytes(name: str, prec: str, n) -> float | None:
@@ -123,7 +129,7 @@ def cpu_baseline(inst, inner_total: int, outer_total: int, cg_total: int, budget
     }
 
 
-SWEEP_CAPS = {"max_outer": 100, "max_inner": 2000, "eps_sub_rel": 1e-6}
+SWEEP_CAPS = {"max_outer": 100, "max_inner": 2000, "eps_sub_rel": {"fp32": FP32_SUB_REL, "fp64": 1e-6}}
 
 
 def phase_sweep(args, torch, I, lb, dev):
@@ -135,7 +141,7 @@ def phase_sweep(args, torch, I, lb, dev):
     plans = [lb.Plan(i.grid.n, i.grid.box, precision=prec) for i in insts]
     prms = [lb.Params(i.params.tau, i.params.gamma) for i in insts]
     opts = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=SWEEP_CAPS["max_outer"],
-                      sub={"max_inner": SWEEP_CAPS["max_inner"], "poll_every": 64, "eps_sub_rel": SWEEP_CAPS["eps_sub_rel"]})
+                      sub={"max_inner": SWEEP_CAPS["max_inner"], "poll_every": 64, "eps_sub_rel": SWEEP_CAPS["eps_sub_rel"][prec]})
     psis = [torch.from_numpy(i.psi0).to(dev) for i in insts]
     order = sorted(range(len(insts)), key=lambda k: -insts[k].grid.n[0])
     res = [None] * len(insts)
@@ -161,7 +167,7 @@ def phase_sweep(args, torch, I, lb, dev):
 
 
 
-LARGE_CAPS = {"max_outer": 400, "max_inner": 2000, "eps_sub_rel": 1e-6}
+LARGE_CAPS = {"max_outer": 400, "max_inner": 2000, "eps_sub_rel": FP32_SUB_REL}  # relative floor: FP32 only
 LARGE_TOL = 1e-7
 
 
@@ -350,7 +356,7 @@ def main():
         hv["fp32_batch8"] = hv_rate("fp32", 8)
         p32 = lb.Plan(n, box, precision="fp32")
         p32.lb_plan_autotune(prm, psi0, reps=20)
-        o32 = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64, "eps_sub_rel": 1e-6})
+        o32 = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64, "eps_sub_rel": FP32_SUB_REL})
         torch.cuda.synchronize()
         s = time.perf_counter()
         i32, rc32, ritz32, _ = step(p32, o32)

@@ -370,6 +370,7 @@ def main():
             "outer": i32.outer,
             "inner": i32.inner_total,
             "lambda_min_ritz": ritz32,
+            "subproblem_stop": f"||r|| < max(1e-13, {FP32_SUB_REL:g} ||g||)",
         }
     # lb_hessvec reads psi and v and writes hv as FP64 arrays in either precision: 24 N bytes
     for k in list(hv):

@@ -392,6 +392,10 @@ def trs_global_dense(Hs: np.ndarray, gs: np.ndarray, r: float) -> DenseTRS:
 class SubOpts:
     eta: float = 0.1  # step size (Section 4 value)
     eps_sub: float = 1e-13  # stop when ||g + (H + lambda I) d|| < eps_sub
+    # ... or < eps_sub_rel * ||g||: a relative floor for iterations whose
+    # transforms run in single precision, where an absolute 1e-13 lies below
+    # rounding (0 disables it; the paper's test is the absolute one)
+    eps_sub_rel: float = 0.0
     max_inner: int = 10000
     max_newton: int = 100
     newton_rtol: float = 1e-14  # stop Newton when phi - r^2 <= newton_rtol * r^2
@@ -480,6 +484,7 @@ def imex_subproblem(
     resid = float("inf")
     k = 0
     converged = False
+    tol = max(opts.eps_sub, opts.eps_sub_rel * norm(g_hat))
     while k < opts.max_inner:
         Td = T_apply(m, psi, d)
         b = d - opts.eta * (g_hat + Td)
@@ -494,7 +499,7 @@ def imex_subproblem(
         if record:
             hist.append(dict(k=k, lam=lam, dnorm=norm(d_new), resid=resid, f=model_value(m, psi, g_hat, d_new), step=norm(d_new - d)))
         d = d_new
-        if resid < opts.eps_sub:
+        if resid < tol:
             converged = True
             break
     return SubResult(d, lam, k, newton_total, resid, converged, hist)
@@ -525,6 +530,7 @@ class TROpts:
     eps: float = 1e-10
     eta: float = 0.1
     eps_sub: float = 1e-13
+    eps_sub_rel: float = 0.0  # relative floor of the subproblem stop test (SubOpts.eps_sub_rel)
     # readings where the paper leaves a choice open
     grad_norm: str = "inf"  # "inf" (Algorithm 1) or "l2"
     eta_rule: str = "safe"  # "safe": min(eta, 0.9 / max|Gamma'|) per outer iteration; "fixed": eta
@@ -549,6 +555,7 @@ class TRResult:
     inner_total: int
     converged: bool
     history: List[dict] = field(default_factory=list)
+    sub_capped: int = 0  # subproblems that stopped at max_inner before their stop test held
 
 
 def delta_energy_taylor(m: Model, psi: np.ndarray, g_hat: np.ndarray, s_hat: np.ndarray) -> float:
@@ -640,6 +647,37 @@ def safe_eta(m: Model, psi: np.ndarray, o: TROpts) -> float:
     return min(o.eta, 0.9 / gmax) if gmax > 0 else o.eta
 
 
+def mu_before_ratio(o: TROpts, j: int, rho_prev: Optional[float], mu: float, lam: float, sn: float) -> float:
+    """Algorithm 1, after the subproblem: if j > 0 and rho_{j-1} < theta then
+    mu_j = max(mu_{j-1}, lambda_j / ||s_j||), else mu_j = mu_{j-1}."""
+    if j > 0 and rho_prev is not None and rho_prev < o.theta:
+        return max(mu, lam / sn)
+    return mu
+
+
+def outer_branch(o: TROpts, rho: float, lam: float, sn: float, r: float, nu: float, mu: float,
+                 contract_radius: Callable[[], float]) -> Tuple[str, float, float, float]:
+    """Algorithm 1 from the ratio rho_j on: returns (branch, r_{j+1}, nu_{j+1}, mu_{j+1}).
+
+    accept   if rho_j >= theta and (lambda_j <= mu_j ||s_j|| or ||s_j|| = nu_j):
+             nu_{j+1} = max(nu_j, gamma_E ||s_j||), r_{j+1} = min(nu_{j+1}, max(r_j, gamma_E ||s_j||)),
+             mu_{j+1} = max(mu_j, lambda_j / ||s_j||);
+    contract if rho_j < theta: r_{j+1} = CONTRACT(...) (Algorithm 2), nu and mu carried over;
+    expand   otherwise: r_{j+1} = min(nu_{j+1}, lambda_j / mu_j), nu and mu carried over.
+    The caller moves v to v + s_j on "accept". lambda_j <= mu_j ||s_j|| is tested
+    as lambda_j / ||s_j|| <= mu_j: right after a contraction mu_j was raised to
+    exactly lambda_j / ||s_j||, and the two sides must then compare equal, not
+    by the rounding of (lambda_j / ||s_j||) ||s_j||.
+    """
+    on_nu = abs(sn - nu) <= o.nu_tol * nu
+    if rho >= o.theta and (lam / sn <= mu or on_nu):
+        nu_new = max(nu, o.gamma_e * sn)
+        return "accept", min(nu_new, max(r, o.gamma_e * sn)), nu_new, max(mu, lam / sn)
+    if rho < o.theta:
+        return "contract", contract_radius(), nu, mu
+    return "expand", min(nu, lam / mu), nu, mu
+
+
 def imex_tr_solve(
     m: Model,
     psi0: np.ndarray,
@@ -652,66 +690,57 @@ def imex_tr_solve(
     The iterate is psi = P^T v (zero mean). Per iteration j:
       g_j = grad E_bar(v_j); return if ||g_j|| < eps;
       (s_j, lambda_j) from Algorithm 3 with radius r_j;
-      if j > 0 and rho_{j-1} < theta: mu_j = max(mu_{j-1}, lambda_j / ||s_j||);
+      mu_j from ``mu_before_ratio``;
       rho_j = (E_bar(v_j) - E_bar(v_j + s_j)) / ||s_j||^3;
-      accept  if rho_j >= theta and (lambda_j <= mu_j ||s_j|| or ||s_j|| = nu_j):
-              v += s, nu = max(nu, gamma_E ||s||), r = min(nu, max(r, gamma_E ||s||)),
-              mu = max(mu, lambda / ||s||);
-      contract if rho_j < theta: r = CONTRACT(...)  (mu carried over);
-      else    r = min(nu, lambda / mu).
+      the branch and r_{j+1}, nu_{j+1}, mu_{j+1} from ``outer_branch``.
     """
     psi = psi0 - psi0.mean()
     r, nu, mu = o.r0, o.nu0, o.mu0
     rho_prev = None
     hist = []
     inner_total = 0
+    sub_capped = 0
     E = energy(m, psi)
     g = gradient(m, psi)
     for j in range(o.max_outer):
         gn2, gninf = norm(g), norm_inf(g)
         gtest = gninf if o.grad_norm == "inf" else gn2
         if gtest < o.eps:
-            return TRResult(psi, E, gn2, gninf, j, inner_total, True, hist)
+            return TRResult(psi, E, gn2, gninf, j, inner_total, True, hist, sub_capped)
         eta = safe_eta(m, psi, o)
-        sub_opts = SubOpts(eta=eta, eps_sub=o.eps_sub, max_inner=o.max_inner, max_newton=o.max_newton)
+        sub_opts = SubOpts(eta=eta, eps_sub=o.eps_sub, eps_sub_rel=o.eps_sub_rel, max_inner=o.max_inner,
+                           max_newton=o.max_newton)
         d0 = d0_provider(j, r, g, psi) if d0_provider else None
         sub = imex_subproblem(m, psi, g, r, sub_opts, d0=d0)
         inner_total += sub.iters
+        sub_capped += 0 if sub.converged else 1
         s_hat, lam = sub.d, sub.lam
         sn = norm(s_hat)
-        if j > 0 and rho_prev is not None and rho_prev < o.theta:
-            mu = max(mu, lam / sn)
+        mu = mu_before_ratio(o, j, rho_prev, mu, lam, sn)
         if o.rho_numerator == "taylor":
             dE = delta_energy_taylor(m, psi, g, s_hat)
-            E_trial = None
         else:
-            E_trial = energy(m, psi + inv(s_hat))
-            dE = E - E_trial
+            dE = E - energy(m, psi + inv(s_hat))
         rho = dE / sn**3
         rec = dict(j=j, E=E, gnorm=gn2, gnorm_inf=gninf, r=r, nu=nu, mu=mu, lam=lam, snorm=sn, rho=rho, eta=eta, inner=sub.iters, sub_resid=sub.resid)
-        on_nu = abs(sn - nu) <= o.nu_tol * nu
-        # lambda <= mu ||s|| tested as lambda / ||s|| <= mu: after a contraction mu
-        # was just raised to lambda / ||s||, and the two sides must then compare
-        # equal exactly, not by the rounding of (lambda / ||s||) ||s||
-        if rho >= o.theta and (lam / sn <= mu or on_nu):
+        cinfo = {}
+
+        def contract_radius():
+            r_new, info = contract(m, psi, g, r, mu, s_hat, lam, o)
+            cinfo.update(info)
+            return r_new
+
+        branch, r, nu, mu = outer_branch(o, rho, lam, sn, r, nu, mu, contract_radius)
+        rec["branch"] = branch
+        rec.update(cinfo)
+        if branch == "accept":
             psi = psi + inv(s_hat)
-            nu = max(nu, o.gamma_e * sn)
-            r = min(nu, max(r, o.gamma_e * sn))
-            mu = max(mu, lam / sn)
             E = energy(m, psi)
             g = gradient(m, psi)
-            rec["branch"] = "accept"
-        elif rho < o.theta:
-            r, cinfo = contract(m, psi, g, r, mu, s_hat, lam, o)
-            rec["branch"] = "contract"
-            rec.update(cinfo)
-        else:
-            r = min(nu, lam / mu)
-            rec["branch"] = "expand"
         rho_prev = rho
         if record:
             hist.append(rec)
-    return TRResult(psi, E, norm(g), norm_inf(g), o.max_outer, inner_total, False, hist)
+    return TRResult(psi, E, norm(g), norm_inf(g), o.max_outer, inner_total, False, hist, sub_capped)
 
 
 # ---------------------------------------------------------------------------

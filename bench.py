@@ -37,6 +37,15 @@ LANCZOS_STEPS = 60
 # 128^3), so a floor of 1e-6 sits on that noise and subproblems end only when
 # it happens to dip below; 1e-5 stays clear of it.
 FP32_SUB_REL = 1e-5
+# kernels of one inner IMEX iteration (Algorithm 3): the unit whose method
+# bytes (32 N: read the iterate's spectrum, g and psi-dependent Gamma', write
+# b) the roofline figure is quoted on; cubic grids take the plane pass, the
+# others the axis-1 and row passes
+INNER_KERNELS = ("col0_inv_scale_d", "plane_inner", "col1_inv", "rows_inner", "col1_fwd", "col0_fwd_update", "newton")
+TIMING_EVERY = 8  # time one launch in 8 of each inner-iteration kernel during the timed steps
+# the default run also times the phase sweep and the 256^3 solve unless the
+# run has already taken this long (the whole bench must stay within minutes)
+EXTRA_CONFIG_BUDGET_S = 330.0
 
 
 def kernel_bytes(name: str, prec: str, n) -> float | None:
@@ -75,9 +84,7 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources (else None)."""
+def _pmc():
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -85,14 +92,63 @@ def traffic_from_profiles(kernel: str):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("source_hash") != source_hash():
+    return d if d.get("source_hash") == source_hash() else None
+
+
+def traffic_from_profiles(kernel: str, section: str = "kernels"):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources (else None)."""
+    d = _pmc()
+    if d is None:
         return None
-    k = d.get("kernels", {}).get(kernel)
+    k = d.get(section, {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _one_thread():
+    """Limit BLAS/OpenMP pools to one thread (numpy's FFT is single-threaded already)."""
+    try:
+        from threadpoolctl import threadpool_limits
+
+        return threadpool_limits(1)
+    except Exception:  # pragma: no cover - threadpoolctl missing
+        import contextlib
+
+        return contextlib.nullcontext()
+
+
+def oracle_endpoint(inst, psi_np, lanczos_steps: int = 12):
+    """The oracle's check of a GPU solve's endpoint: its gradient norm and energy
+    at the returned field and a preconditioned Lanczos estimate of sigma_1 (an
+    upper bound on it)."""
+    from oracle import lb_oracle as O
+    from paper_2603_03933_amd import inputs as I
+
+    with _one_thread():
+        m = O.Model(O.Grid(inst.grid.n, inst.grid.box), inst.params.tau, inst.params.gamma)
+        g = O.gradient(m, psi_np)
+        ritz, res = O.lanczos_min(m, psi_np, O.fwd(I.hessvec_direction(inst.grid.n, 9)), lanczos_steps, precond_shift=1.0)
+        return {"gnorm": O.norm(g), "energy": O.energy(m, psi_np), f"lanczos{lanczos_steps}_precond_ritz": ritz,
+                "ritz_residual": res}
 
 
 def cpu_baseline(inst, inner_total: int, outer_total: int, cg_total: int, budget_s: float):
     """Time the CPU oracle on a bounded sample of the same workload and scale to solves/s."""
+    with _one_thread():
+        return _cpu_baseline(inst, inner_total, outer_total, cg_total, budget_s)
+
+
+def _cpu_baseline(inst, inner_total: int, outer_total: int, cg_total: int, budget_s: float):
     import numpy as np
 
     from oracle import lb_oracle as O
@@ -120,9 +176,11 @@ def cpu_baseline(inst, inner_total: int, outer_total: int, cg_total: int, budget
         "value": 1.0 / t_solve,
         "unit": "solves/s",
         "cores": 1,
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": (
-            f"oracle (NumPy FP64, single-threaded pocketfft) on the 128^3 BCC input: {k} inner IMEX iterations "
+            f"oracle (NumPy FP64, pocketfft, BLAS limited to 1 thread) on the 128^3 BCC input: {k} inner IMEX iterations "
             f"({t_in:.3f} s each) and one energy+gradient ({t_eg:.3f} s); scaled by the GPU solve's counts "
             f"({inner_total} inner, {cg_total} CG, {outer_total} outer)"
         ),
@@ -132,12 +190,12 @@ def cpu_baseline(inst, inner_total: int, outer_total: int, cg_total: int, budget
 SWEEP_CAPS = {"max_outer": 100, "max_inner": 2000, "eps_sub_rel": {"fp32": FP32_SUB_REL, "fp64": 1e-6}}
 
 
-def phase_sweep(args, torch, I, lb, dev):
+def phase_sweep(torch, I, lb, dev, prec="fp32", workers=8, progress=True):
     """64 independent 2D solves (n in {64..512}^2, (tau, gamma) on an 8 x 8 grid)
-    through lb_imex_tr_solve_many; aggregate solves/s. Capped (the tau = 0 row
-    has a degenerate quartic minimum and converges sublinearly)."""
+    through lb_imex_tr_solve_many. Capped (the tau = 0 row has a degenerate
+    quartic minimum and converges sublinearly): the rate counts converged
+    solves only, and the capped ones are listed."""
     insts = I.phase_sweep(64)
-    prec = args.sweep_precision
     plans = [lb.Plan(i.grid.n, i.grid.box, precision=prec) for i in insts]
     prms = [lb.Params(i.params.tau, i.params.gamma) for i in insts]
     opts = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=SWEEP_CAPS["max_outer"],
@@ -150,28 +208,32 @@ def phase_sweep(args, torch, I, lb, dev):
     for c0 in range(0, len(order), 16):  # progress after every 16 solves
         ids = order[c0:c0 + 16]
         out = lb.lb_imex_tr_solve_many([plans[k] for k in ids], [prms[k] for k in ids], [psis[k] for k in ids], opts,
-                                       workers=args.sweep_workers)
+                                       workers=workers)
         for k, r in zip(ids, out):
             res[k] = r
-        print(f"phase sweep: {c0 + len(ids)}/{len(order)} solves, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        if progress:
+            print(f"phase sweep: {c0 + len(ids)}/{len(order)} solves, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    print(json.dumps({
-        "metric": "IMEX-TR solves/s, 64-instance 2D phase sweep (concurrent)", "value": len(insts) / dt, "unit": "solves/s",
-        "n_gpus": 1, "higher_is_better": True, "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
+    conv = [k for k in range(len(insts)) if res[k][1] == 0]
+    return {
+        "metric": "converged IMEX-TR solves/s, 64-instance 2D phase sweep (concurrent)",
+        "value": len(conv) / dt, "unit": "solves/s", "dtype": "f32" if prec == "fp32" else "f64",
         "config": {"workload": "phase_sweep 64 x 2D, n in {64,96,128,256,512}, box 8 pi n/64, tau x gamma 8 x 8",
-                   "caps": SWEEP_CAPS, "tol": TOL, "workers": args.sweep_workers},
-        "seconds": dt, "converged": sum(1 for _, rc in res if rc == 0),
+                   "caps": SWEEP_CAPS, "tol": TOL, "workers": workers},
+        "seconds": dt, "converged": len(conv), "all_instances_per_s": len(insts) / dt,
+        "capped": [{"i": k, "n": insts[k].grid.n[0], "tau": insts[k].params.tau, "gamma": insts[k].params.gamma,
+                    "outer": res[k][0].outer, "gnorm": res[k][0].gnorm} for k in range(len(insts)) if res[k][1] != 0],
         "outer": sum(i.outer for i, _ in res), "inner": sum(i.inner_total for i, _ in res),
-    }), flush=True)
-
+        "sub_capped": sum(i.sub_capped for i, _ in res),
+    }
 
 
 LARGE_CAPS = {"max_outer": 400, "max_inner": 2000, "eps_sub_rel": FP32_SUB_REL}  # relative floor: FP32 only
 LARGE_TOL = 1e-7
 
 
-def large_solve(args, torch, I, lb, dev):
+def large_solve(torch, I, lb, dev, prec="fp32", verbose=1):
     """The 256^3 mixed-precision workload (tau=-0.25, gamma=0.4, N(0, 0.05^2)
     start): one IMEX-TR solve to ||g||_2 < 1e-7 (FP32 FFT and pointwise
     stages, FP64 reductions and ratio; or FP64 throughout), then 30 steps of
@@ -179,11 +241,10 @@ def large_solve(args, torch, I, lb, dev):
     (the smallest Ritz value is an upper bound on lambda_min). Progress: one
     line per outer iteration on stderr."""
     inst = I.large_3d(256)
-    prec = args.large_precision
     plan = lb.Plan(inst.grid.n, inst.grid.box, precision=prec)
     prm = lb.Params(inst.params.tau, inst.params.gamma)
     psi = torch.from_numpy(inst.psi0).to(dev)
-    opts = lb.tr_opts(grad_norm_inf=0, eps=LARGE_TOL, max_outer=LARGE_CAPS["max_outer"], verbose=1,
+    opts = lb.tr_opts(grad_norm_inf=0, eps=LARGE_TOL, max_outer=LARGE_CAPS["max_outer"], verbose=verbose,
                       sub={"max_inner": LARGE_CAPS["max_inner"], "poll_every": 64,
                            "eps_sub_rel": LARGE_CAPS["eps_sub_rel"] if prec == "fp32" else 0.0})
     torch.cuda.synchronize()
@@ -191,24 +252,49 @@ def large_solve(args, torch, I, lb, dev):
     info, rc = plan.lb_imex_tr_solve(prm, psi, opts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    del plan
     p64 = lb.Plan(inst.grid.n, inst.grid.box, precision="fp64")
     ritz = []
     for k in range(3):
         v0 = torch.from_numpy(I.hessvec_direction(inst.grid.n, 100 + k)).to(dev)
         ritz.append(p64.lb_lanczos_min(prm, psi, v0, 30, precond_shift=1.0))
-    print(json.dumps({
+    return {
         "metric": "IMEX-TR solves/s, 256^3 single solve", "value": 1.0 / dt, "unit": "solves/s",
-        "n_gpus": 1, "higher_is_better": True, "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
+        "dtype": "f32" if prec == "fp32" else "f64",
         "config": {"workload": "large_3d 256^3, box 16 pi, tau -0.25, gamma 0.4, psi0 N(0, 0.05^2) seed 0",
                    "caps": LARGE_CAPS, "tol": LARGE_TOL},
         "seconds": dt, "status": "converged" if rc == 0 else "not_converged", "energy": info.energy,
         "gnorm": info.gnorm, "outer": info.outer, "inner": info.inner_total, "cg": info.cg_total,
+        "sub_capped": info.sub_capped,
         "lanczos30": [{"ritz": r, "residual": e} for r, e in ritz],
         "lambda_min_upper_bound": min(r for r, _ in ritz),
         "sp2_check_passed": min(r for r, _ in ritz) >= -1e-7,
-    }), flush=True)
+    }
+
+
+def fp32_floor_scan(torch, I, lb, dev, n=128):
+    """The residual floor of FP32 inner iterations: Algorithm 3 at the 128^3 BCC
+    input (r = 1) in FP32 and FP64 with stop floors eps_rel ||g|| from 1e-5 down
+    to 1e-8, capped at 4000 iterations; a floor below the FP32 transforms'
+    noise is never met (the cap is reached)."""
+    inst = I.bcc_3d(n)
+    prm = lb.Params(inst.params.tau, inst.params.gamma)
+    psi = torch.from_numpy(inst.psi0).to(dev)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        plan = lb.Plan(inst.grid.n, inst.grid.box, precision=prec)
+        E, g = plan.lb_energy_grad(prm, psi)
+        rows = []
+        for rel in (1e-5, 3e-6, 1e-6, 3e-7, 1e-7, 3e-8, 1e-8):
+            d, info, rc = plan.lb_tr_subproblem(prm, psi, g, 1.0, lb.sub_opts(eta=0.0132, eps_sub=0.0, eps_sub_rel=rel, max_inner=4000, poll_every=64))
+            rows.append({"eps_rel": rel, "iters": info.iters, "reached": rc == 0, "resid_rel": info.resid / info.gnorm})
+            print(f"floor scan {prec} {rel:g}: {info.iters} iterations, resid/|g| {info.resid / info.gnorm:.2e}", file=sys.stderr, flush=True)
+        out[prec] = rows
+    return {"fp32_floor_scan": {"workload": f"bcc_3d {n}^3, Algorithm 3 at psi0, r = 1, eta 0.0132, cap 4000", "rows": out}}
+
 
 def main():
+    t_start = time.perf_counter()
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -216,6 +302,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-extra-configs", action="store_true", help="skip the phase sweep and the 256^3 solve")
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--kernel-sample", type=int, default=0, metavar="K",
                     help="only run K iterations of Algorithm 3 on the workload (for counter collection) and exit")
@@ -232,6 +319,8 @@ def main():
                     help="only run the 64-instance 2D phase sweep (concurrent solves) and exit")
     ap.add_argument("--sweep-precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--sweep-workers", type=int, default=8)
+    ap.add_argument("--fp32-floor-scan", action="store_true",
+                    help="only run the FP32/FP64 subproblem stop-floor scan at 128^3 and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -253,10 +342,17 @@ def main():
         print(json.dumps({"copy_calibration": {"kernel": "torch.neg float64", "read_bytes": 8 << 27, "write_bytes": 8 << 27, "launches": 5}}))
         return
     if args.phase_sweep:
-        phase_sweep(args, torch, I, lb, dev)
+        r = phase_sweep(torch, I, lb, dev, args.sweep_precision, args.sweep_workers)
+        r.update({"n_gpus": 1, "higher_is_better": True, "data": "synthetic"})
+        print(json.dumps(r), flush=True)
         return
     if args.large_solve:
-        large_solve(args, torch, I, lb, dev)
+        r = large_solve(torch, I, lb, dev, args.large_precision)
+        r.update({"n_gpus": 1, "higher_is_better": True, "data": "synthetic"})
+        print(json.dumps(r), flush=True)
+        return
+    if args.fp32_floor_scan:
+        print(json.dumps(fp32_floor_scan(torch, I, lb, dev, args.size)), flush=True)
         return
     inst = I.bcc_3d(args.size)
     n, box = inst.grid.n, inst.grid.box
@@ -268,10 +364,10 @@ def main():
     plan = lb.Plan(n, box, precision="fp64")
     opts = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64})
 
-    def step(p, o):
-        psi.copy_(psi0)
-        info, rc = p.lb_imex_tr_solve(prm, psi, o)
-        ritz, res = p.lb_lanczos_min(prm, psi, v0, LANCZOS_STEPS, precond_shift=1.0)
+    def step(p, o, out=psi):
+        out.copy_(psi0)
+        info, rc = p.lb_imex_tr_solve(prm, out, o)
+        ritz, res = p.lb_lanczos_min(prm, out, v0, LANCZOS_STEPS, precond_shift=1.0)
         return info, rc, ritz, res
 
     if args.kernel_sample:
@@ -290,17 +386,17 @@ def main():
         return
 
     # choose the plane-pass variant for this grid (autotuner), then warm up
-    # with every kernel timed to find the dominant one
+    # with every kernel timed (the kernel shares)
     tuned = plan.lb_plan_autotune(prm, psi0, reps=20)
     plan.lb_plan_set_timing(True, "")
     for _ in range(max(1, args.warmup)):
         info, rc, ritz, res = step(plan, opts)
     warm = plan.timings()
-    dominant = max((k for k in warm if kernel_bytes(k, "fp64", n) is not None), key=lambda k: warm[k][1])
     total_ms = sum(v[1] for v in warm.values())
 
-    # timed steps: events only around the dominant kernel
-    plan.lb_plan_set_timing(True, dominant)
+    # timed steps: one launch in TIMING_EVERY of each inner-iteration kernel
+    # carries start/stop events (on the plan's stream)
+    plan.lb_plan_set_timing(True, ",".join(INNER_KERNELS), every=TIMING_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
@@ -312,22 +408,37 @@ def main():
     plan.lb_plan_set_timing(False, "")
     elapsed = t1 - t0
     info, rc, ritz, res = infos[-1]
-    launches, dom_ms = tm.get(dominant, (0, 0.0))
-    avg_s = dom_ms / max(1, launches) * 1e-3
-    alg = kernel_bytes(dominant, "fp64", n)
-    achieved = alg / avg_s / 1e9 if avg_s > 0 else None
+    psi_fp64_end = psi.detach().cpu().numpy()
+
+    # roofline of the benchmarked unit, one inner IMEX iteration: its method
+    # bytes (32 N, FP64) over the summed average durations of its kernels
+    per_kernel = {k: {"avg_us": tm[k][1] / tm[k][0] * 1e3, "launches_timed": tm[k][0]} for k in INNER_KERNELS if k in tm and tm[k][0]}
+    unit_s = sum(v["avg_us"] for v in per_kernel.values()) * 1e-6
+    unit_bytes = 32.0 * N
+    achieved = unit_bytes / unit_s / 1e9 if unit_s > 0 else None
+    counter = [traffic_from_profiles(k) for k in per_kernel if k != "newton"]
+    traffic = sum(counter) if counter and all(c is not None for c in counter) else None
+    dominant = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
+    dom_alg = kernel_bytes(dominant, "fp64", n)
+    dom_s = per_kernel[dominant]["avg_us"] * 1e-6
     roofline = {
-        "kernel": dominant,
+        "kernel": "inner IMEX iteration (" + " + ".join(per_kernel) + ")",
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS if achieved else None,
-        "traffic": traffic_from_profiles(dominant),
-        "alg_bytes_per_launch": alg,
-        "avg_launch_us": avg_s * 1e6,
-        "launches_timed": launches,
-        "share_of_kernel_time": warm[dominant][1] / total_ms if total_ms else None,
+        "traffic": traffic,
+        "traffic_over_alg": traffic / unit_bytes if traffic else None,
+        "alg_bytes_per_unit": unit_bytes,
+        "avg_unit_us": unit_s * 1e6,
+        "kernels": per_kernel,
+        "timing_sample_every": TIMING_EVERY,
+        "dominant_kernel_pass_bytes": {
+            "kernel": dominant, "alg_bytes_per_launch": dom_alg, "avg_launch_us": dom_s * 1e6,
+            "achieved": dom_alg / dom_s / 1e9, "frac": dom_alg / dom_s / 1e9 / HBM_PEAK_GBS,
+            "traffic": traffic_from_profiles(dominant)},
+        "wall_iteration_us": elapsed / max(1, sum(i[0].inner_total for i in infos)) * 1e6,
     }
 
     # Hessian-vector products/s (lb_hessvec, projected) in FP64 and FP32, one
@@ -350,33 +461,42 @@ def main():
         return batch * reps / (time.perf_counter() - s)
 
     hv = {"fp64": hv_rate("fp64"), "fp64_batch8": hv_rate("fp64", 8)}
-    fp32 = None
+    fp32 = fp64_floor = None
+    psi_fp32_end = None
     if not args.no_fp32:
         hv["fp32"] = hv_rate("fp32")
         hv["fp32_batch8"] = hv_rate("fp32", 8)
+
+        def timed_solve(p, o):
+            out = torch.empty_like(psi0)
+            torch.cuda.synchronize()
+            s = time.perf_counter()
+            i_, rc_, ritz_, _ = step(p, o, out)
+            torch.cuda.synchronize()
+            d = time.perf_counter() - s
+            return out, {
+                "solves_per_s": 1.0 / d, "status": "converged" if rc_ == 0 else "not_converged", "energy": i_.energy,
+                "gnorm": i_.gnorm, "outer": i_.outer, "inner": i_.inner_total, "cg": i_.cg_total,
+                "sub_capped": i_.sub_capped, "lambda_min_ritz": ritz_,
+                "inner_iteration_us": d / max(1, i_.inner_total) * 1e6,
+                "subproblem_stop": f"||r|| < max(1e-13, {FP32_SUB_REL:g} ||g||)",
+            }
+
         p32 = lb.Plan(n, box, precision="fp32")
         p32.lb_plan_autotune(prm, psi0, reps=20)
-        o32 = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub={"max_inner": 10000, "poll_every": 64, "eps_sub_rel": FP32_SUB_REL})
-        torch.cuda.synchronize()
-        s = time.perf_counter()
-        i32, rc32, ritz32, _ = step(p32, o32)
-        torch.cuda.synchronize()
-        d32 = time.perf_counter() - s
-        fp32 = {
-            "solves_per_s": 1.0 / d32,
-            "status": "converged" if rc32 == 0 else "not_converged",
-            "energy": i32.energy,
-            "gnorm": i32.gnorm,
-            "outer": i32.outer,
-            "inner": i32.inner_total,
-            "lambda_min_ritz": ritz32,
-            "subproblem_stop": f"||r|| < max(1e-13, {FP32_SUB_REL:g} ||g||)",
-        }
+        sub_rel = {"max_inner": 10000, "poll_every": 64, "eps_sub_rel": FP32_SUB_REL}
+        o_rel = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub=sub_rel)
+        out32, fp32 = timed_solve(p32, o_rel)
+        psi_fp32_end = out32.cpu().numpy()
+        # the same stop rule in FP64 throughout: the precisions compared like for like
+        _, fp64_floor = timed_solve(plan, o_rel)
+        del p32
     # lb_hessvec reads psi and v and writes hv as FP64 arrays in either precision: 24 N bytes
     for k in list(hv):
         hv[k + "_alg_hbm_frac"] = 24.0 * N * hv[k] / (HBM_PEAK_GBS * 1e9)
 
-    # the other single-GPU configurations, timed briefly: the 64^2 2D solve and Hv at 256^3
+    # the other single-GPU configurations: the 64^2 2D solve, Hv at 256^3,
+    # and (time permitting) the 64-instance phase sweep and the 256^3 solve
     extra = {}
     if not args.no_fp32:
         c1 = I.single_2d(64)
@@ -414,10 +534,23 @@ def main():
             hv256[precision + "_alg_hbm_frac"] = 24.0 * big.grid.N * hv256[precision] / (HBM_PEAK_GBS * 1e9)
             del plb, ob
         extra["hessvec_256cubed_per_s"] = hv256
+        del vb, pb
+        if not args.no_extra_configs:
+            for name, fn in (("phase_sweep_64x2d_fp32", lambda: phase_sweep(torch, I, lb, dev, "fp32", args.sweep_workers, progress=True)),
+                             ("solve_256cubed_fp32_inner", lambda: large_solve(torch, I, lb, dev, "fp32", verbose=0))):
+                if time.perf_counter() - t_start > EXTRA_CONFIG_BUDGET_S:
+                    extra[name] = {"skipped": f"the run had taken more than {EXTRA_CONFIG_BUDGET_S:g} s"}
+                    continue
+                print(f"bench: {name}", file=sys.stderr, flush=True)
+                extra[name] = fn()
 
     cpu = None
+    endpoint = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, info.inner_total, info.outer, info.cg_total, args.cpu_budget)
+        endpoint = {"fp64": oracle_endpoint(inst, psi_fp64_end)}
+        if psi_fp32_end is not None:
+            endpoint["fp32_inner"] = oracle_endpoint(inst, psi_fp32_end)
 
     inner_per_s = sum(i[0].inner_total for i in infos) / elapsed
     out = {
@@ -448,6 +581,7 @@ def main():
             "outer": info.outer,
             "inner": info.inner_total,
             "cg": info.cg_total,
+            "sub_capped": info.sub_capped,
             "newton_steps": info.newton_total,
             "newton_direct_evals": info.newton_direct,
             "accepted": info.accepted,
@@ -458,10 +592,12 @@ def main():
         },
         "hessvec_per_s": hv,
         "solve_fp32_inner": fp32,
+        "solve_fp64_same_floor": fp64_floor,
         "autotune": {"plane_pass_threads": tuned},
         "other_configs": extra,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "oracle_endpoint_check": endpoint,
         "kernel_share_warmup": {k: round(v[1] / total_ms, 4) for k, v in sorted(warm.items(), key=lambda kv: -kv[1][1])[:8]},
     }
     print(json.dumps(out), flush=True)

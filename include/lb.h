@@ -162,6 +162,10 @@ typedef struct lb_tr_info {
   int hard_cases;    /* subproblems started from a random point (hard_case = 1) */
   int newton_total;  /* Newton steps of the multiplier, summed over all subproblem iterations */
   int newton_direct; /* of their evaluations, those that summed phi over the spectrum */
+  int sub_capped;    /* outer iterations whose subproblem stopped at sub.max_inner before its
+                        stop test held; Algorithm 1 then takes that iterate as s_j although it
+                        need not satisfy the optimality conditions (eq.
+                        tr_subproblem_optimal_condition) */
 } lb_tr_info;
 
 typedef struct lb_plan lb_plan;
@@ -187,14 +191,19 @@ int lb_plan_set_stream(lb_plan *plan, void *stream);
 size_t lb_plan_workspace_bytes(const lb_plan *plan);
 
 /* Kernel timing, a measurement aid. When enabled, every kernel launch of the
- * plan whose name equals `filter` (all launches when filter is NULL or "")
- * is bracketed by HIP events on the plan's stream; durations accumulate per
- * kernel name until timing is set again. Names: rows_r2c, rows_c2r,
- * rows_c2r_hv, rows_energy, rows_inner, col1_fwd, col1_inv, col0_fwd,
- * col0_inv, col0_fwd_mul_inv, col0_inv_scale_d, col0_fwd_update,
- * col0_fwd_hess, bins, newton, grad_assemble, spec_reduce, finalize,
- * lincomb, init_b, final_d, gamma_p, energy_out, add_real, axpy_real. */
+ * plan whose name is listed in `filter` (comma-separated names; all launches
+ * when filter is NULL or "") is bracketed by HIP events on the plan's stream;
+ * durations accumulate per kernel name until timing is set again. Names
+ * include rows_r2c, rows_c2r, rows_c2r_hv, rows_energy, rows_inner, col1_fwd,
+ * col1_inv, col0_fwd, col0_inv, col0_fwd_mul_inv, col0_inv_scale_d,
+ * plane_inner, col0_fwd_update, col0_fwd_hess, plane_fwd_phys,
+ * plane_inv_phys, newton, sub2d, grad_assemble, spec_reduce, finalize,
+ * lincomb, init_b, final_d, gamma_p, energy_out, add_real, axpy_real.
+ * lb_plan_set_timing_sampled times only launches 0, every, 2 every, ... of
+ * each listed kernel (every >= 1), an unbiased sample of the durations at a
+ * fraction of the events' cost. */
 int lb_plan_set_timing(lb_plan *plan, int enable, const char *filter);
+int lb_plan_set_timing_sampled(lb_plan *plan, int enable, const char *filter, int every);
 /* Entry `index` (0-based) of the accumulated timings: kernel name, launches
  * and total milliseconds. Synchronises the stream. LB_ERR_ARG past the end. */
 int lb_plan_timing_entry(lb_plan *plan, int index, char *name, int name_len, long *count, double *total_ms);
@@ -241,6 +250,25 @@ int lb_hessvec_raw(lb_plan *plan, const lb_params *params, const double *psi, co
  *   psi, w : batch * N doubles (device; w nullable); out : 4 * batch doubles
  *   (device), written. FP64. Asynchronous. */
 int lb_field_moments(lb_plan *plan, const double *psi, const double *w, double *out);
+
+/* Parameter derivatives of E (eq. lb_energy), per instance b:
+ *   out[4 b + 0] = dE/dtau   = mean(psi^2) / 2
+ *   out[4 b + 1] = dE/dgamma = -mean(psi^3) / 6
+ *   out[4 b + 2] = d<w, grad_raw E>/dtau   = mean(w psi)
+ *   out[4 b + 3] = d<w, grad_raw E>/dgamma = -mean(w psi^2) / 2
+ * with grad_raw E the gradient with respect to the N grid values
+ * (lb_energy_grad_raw) and <w, .> the plain sum over grid points; entries 2
+ * and 3 are 0 when w is NULL.
+ *   psi, w : batch * N doubles (device; w nullable); out : 4 * batch doubles
+ *   (device), written. FP64. Asynchronous. */
+int lb_param_grad(lb_plan *plan, const double *psi, const double *w, double *out);
+
+/* Gradient with respect to the N grid values of
+ * ct[2 b] dE/dtau + ct[2 b + 1] dE/dgamma (eq. lb_energy), per instance b:
+ *   out[x] = (ct[2 b] psi_x - ct[2 b + 1] psi_x^2 / 2) / N.
+ *   psi : batch * N doubles (device); ct : 2 * batch doubles (device);
+ *   out : batch * N doubles (device), written. FP64. Asynchronous. */
+int lb_param_grad_vjp(lb_plan *plan, const double *psi, const double *ct, double *out);
 
 /* Trust-region subproblem min_{||d|| <= radius} <g,d> + <d,Hd>/2 by the
  * adaptive IMEX iteration (Section 3.2, Algorithm 3; eqs. imex-scheme and

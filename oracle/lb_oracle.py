@@ -256,6 +256,20 @@ def field_moments(psi: np.ndarray, w: Optional[np.ndarray] = None) -> np.ndarray
     return np.array([np.mean(psi**2), np.mean(psi**3), np.mean(z * psi), np.mean(z * psi**2)])
 
 
+def param_grad(psi: np.ndarray, w: Optional[np.ndarray] = None) -> np.ndarray:
+    """[dE/dtau, dE/dgamma, d<w, grad_raw E>/dtau, d<w, grad_raw E>/dgamma] for E of
+    eq. lb_energy (tau/2 psi^2 and -gamma/6 psi^3 are the only terms in tau and
+    gamma; grad_raw E has tau psi / N and -gamma psi^2 / (2 N)); <w, .> sums over
+    the grid points."""
+    z = np.zeros_like(psi) if w is None else w
+    return np.array([np.mean(psi**2) / 2.0, -np.mean(psi**3) / 6.0, np.mean(z * psi), -np.mean(z * psi**2) / 2.0])
+
+
+def param_grad_vjp(psi: np.ndarray, a: float, b: float) -> np.ndarray:
+    """Gradient with respect to the grid values of a dE/dtau + b dE/dgamma."""
+    return (a * psi - b * psi**2 / 2.0) / psi.size
+
+
 def hessvec_phys(m: Model, psi: np.ndarray, v: np.ndarray) -> np.ndarray:
     return inv(hessvec(m, psi, project(fwd(v))))
 

@@ -7,12 +7,11 @@ every k including k = 0 (on zero-mean fields it is the paper's E):
 
   dE/dpsi_x        = (F_N^{-1} Lambda psi_hat + F'(psi))_x / N   (lb_energy_grad_raw)
   d2E/dpsi^2 . v   = (F_N^{-1} Lambda F_N v + Gamma'(psi) v) / N  (lb_hessvec_raw)
-  dE/dtau = mean(psi^2)/2,   dE/dgamma = -mean(psi^3)/6             (lb_field_moments)
-  d(<G, dE/dpsi>)/dtau = mean(G psi), .../dgamma = -mean(G psi^2)/2 (lb_field_moments)
+  dE/dtau, dE/dgamma and d<G, dE/dpsi>/d(tau, gamma)            (lb_param_grad)
+  d(a dE/dtau + b dE/dgamma)/dpsi                                (lb_param_grad_vjp)
 
-Every derivative of E is computed by the library; the only torch arithmetic
-here is the chain rule (products with incoming gradients) and the psi
-derivative of the two moments above, which is pointwise (psi/N, psi^2/N).
+Every derivative is computed by the library; the only torch arithmetic here
+is the chain rule: products of those derivatives with incoming gradients.
 The paper's convention (projected gradient in Psi_hat coordinates, norms in
 RMS) is the library's lb_energy_grad; the two differ by the mean and a factor N.
 """
@@ -45,23 +44,19 @@ def _reduce_like(g: torch.Tensor, param: torch.Tensor):
     return g.sum().reshape(param.shape) if param.numel() == 1 else g.reshape(param.shape)
 
 
-class _Moments(torch.autograd.Function):
-    """(mean(psi^2)/2, -mean(psi^3)/6) per instance: dE/dtau, dE/dgamma."""
+class _ParamGrad(torch.autograd.Function):
+    """(dE/dtau, dE/dgamma) per instance; its psi-gradient comes from lb_param_grad_vjp."""
 
     @staticmethod
     def forward(ctx, psi, plan):
         ctx.save_for_backward(psi)
         ctx.plan = plan
-        m = plan.lb_field_moments(psi).reshape(plan.batch, 4)
-        return torch.stack([m[:, 0] / 2, -m[:, 1] / 6], dim=1)
+        return plan.lb_param_grad(psi).reshape(plan.batch, 4)[:, :2].contiguous()
 
     @staticmethod
     def backward(ctx, g2):
         (psi,) = ctx.saved_tensors
-        n = ctx.plan.N
-        a = _expand(g2[:, 0], psi)
-        b = _expand(g2[:, 1], psi)
-        return (a * psi - b * psi * psi / 2) / n, None
+        return ctx.plan.lb_param_grad_vjp(psi, g2.contiguous().reshape(-1)), None
 
 
 class _GradRaw(torch.autograd.Function):
@@ -80,9 +75,9 @@ class _GradRaw(torch.autograd.Function):
         plan = ctx.plan
         G = G.contiguous()
         dpsi = plan.lb_hessvec_raw(_params(tau, gamma, ctx.xi, ctx.q, plan.batch), psi, G)
-        m = plan.lb_field_moments(psi, G).reshape(plan.batch, 4)
+        m = plan.lb_param_grad(psi, G).reshape(plan.batch, 4)
         dtau = _reduce_like(m[:, 2], tau).to(tau.dtype)
-        dgamma = _reduce_like(-m[:, 3] / 2, gamma).to(gamma.dtype)
+        dgamma = _reduce_like(m[:, 3], gamma).to(gamma.dtype)
         return dpsi, dtau.to(tau.device), dgamma.to(gamma.device), None, None, None
 
 
@@ -102,7 +97,7 @@ class _Energy(torch.autograd.Function):
         if ctx.needs_input_grad[0]:
             dpsi = _expand(gE, psi) * _GradRaw.apply(psi, tau, gamma, plan, ctx.xi, ctx.q)
         if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
-            mg = _Moments.apply(psi, plan)
+            mg = _ParamGrad.apply(psi, plan)
             dtau = _reduce_like(gE * mg[:, 0].to(gE.device), tau).to(tau.device)
             dgamma = _reduce_like(gE * mg[:, 1].to(gE.device), gamma).to(gamma.device)
         return dpsi, dtau, dgamma, None, None, None

@@ -76,6 +76,26 @@ __global__ __launch_bounds__(EW_NT) void k_prec_scale(Geo g, Prm p, const double
     out[h] = double2{v.x * s, v.y * s};
   }
 }
+// parameter derivatives from the finalised sums [psi^2, psi^3, w psi, w psi^2]
+// per instance: out[4 b + q] = c_q sums[4 b + q] / N with c = (1/2, -1/6, 1, -1/2)
+__global__ void k_param_out(const double *sums, int batch, double inv_n, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 4 * batch) return;
+  const int q = i & 3;
+  const double c = q == 0 ? 0.5 : q == 1 ? -1.0 / 6.0 : q == 2 ? 1.0 : -0.5;
+  out[i] = c * sums[i] * inv_n;
+}
+// out = (ct[2 b] psi - ct[2 b + 1] psi^2 / 2) / N over instance b's points
+__global__ __launch_bounds__(EW_NT) void k_param_vjp(long N, int batch, const double *__restrict__ psi,
+                                                     const double *__restrict__ ct, double *__restrict__ out) {
+  const long total = N * batch;
+  const double inv_n = 1.0 / (double)N;
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < total; i += (long)gridDim.x * EW_NT) {
+    const int b = (int)(i / N);
+    const double x = psi[i];
+    out[i] = (ct[2 * b] * x - 0.5 * ct[2 * b + 1] * x * x) * inv_n;
+  }
+}
 // out = x + y (real)
 __global__ __launch_bounds__(EW_NT) void k_add_real(long n, const double *__restrict__ x, const double *__restrict__ y,
                                                     double *__restrict__ out) {
@@ -102,7 +122,9 @@ struct PendingTiming {
 };
 struct TimingState {
   bool on = false;
-  std::string filter;
+  std::vector<std::string> names;  // kernels to time (all when empty)
+  long every = 1;                  // time one launch in `every` of each kernel
+  std::vector<long> seen;          // launches per entry since timing was set
   std::vector<TimingEntry> entries;
   std::vector<PendingTiming> pending;
   std::vector<hipEvent_t> pool;
@@ -242,12 +264,18 @@ struct KT {
   hipEvent_t a = nullptr, b = nullptr;
   KT(lb_plan *P_, const char *name) : P(P_) {
     TimingState &T = P->timing;
-    if (!T.on || (!T.filter.empty() && T.filter != name)) return;
+    if (!T.on) return;
+    if (!T.names.empty() && std::find(T.names.begin(), T.names.end(), name) == T.names.end()) return;
     for (size_t i = 0; i < T.entries.size(); ++i)
       if (T.entries[i].name == name) idx = (int)i;
     if (idx < 0) {
       T.entries.push_back(TimingEntry{name, 0, 0.0});
+      T.seen.push_back(0);
       idx = (int)T.entries.size() - 1;
+    }
+    if (T.seen[idx]++ % T.every != 0) {  // not sampled
+      idx = -1;
+      return;
     }
     a = timing_event(P);
     b = timing_event(P);
@@ -274,12 +302,28 @@ struct KT {
 };
 
 extern "C" int lb_plan_set_timing(lb_plan *P, int enable, const char *filter) {
+  return lb_plan_set_timing_sampled(P, enable, filter, 1);
+}
+
+extern "C" int lb_plan_set_timing_sampled(lb_plan *P, int enable, const char *filter, int every) {
   if (!P) return fail(LB_ERR_ARG, "null plan");
+  if (every < 1) return fail(LB_ERR_ARG, "every must be >= 1");
   (void)hipStreamSynchronize(P->stream);
   timing_flush(P);
-  P->timing.on = enable != 0;
-  P->timing.filter = filter ? filter : "";
-  P->timing.entries.clear();
+  TimingState &T = P->timing;
+  T.on = enable != 0;
+  T.every = every;
+  T.names.clear();
+  const std::string f = filter ? filter : "";
+  size_t pos = 0;
+  while (pos < f.size()) {
+    size_t end = f.find(',', pos);
+    if (end == std::string::npos) end = f.size();
+    if (end > pos) T.names.push_back(f.substr(pos, end - pos));
+    pos = end + 1;
+  }
+  T.entries.clear();
+  T.seen.clear();
   return LB_OK;
 }
 
@@ -828,6 +872,33 @@ extern "C" int lb_field_moments(lb_plan *P, const double *psi, const double *w, 
               1.0 / (double)P->N, out);
   }
   return check_launch("lb_field_moments");
+}
+
+extern "C" int lb_param_grad(lb_plan *P, const double *psi, const double *w, double *out) {
+  if (!P || !psi || !out) return fail(LB_ERR_ARG, "null argument");
+  const int B = P->batch;
+  const int bpi = (int)bpi_ew(P);
+  {
+    KT kt_(P, "field_moments");
+    LB_LAUNCH(lbk::k_field_moments, dim3(bpi * B), dim3(lbk::EW_NT), 0, P->stream, P->N, bpi, psi, w, P->partial);
+  }
+  finalize(P, P->partial, bpi, 4, 0u, B, P->sums);
+  {
+    KT kt_(P, "param_out");
+    LB_LAUNCH(lbk::k_param_out, dim3(1), dim3(64), 0, P->stream, (const double *)P->sums, B, 1.0 / (double)P->N, out);
+  }
+  return check_launch("lb_param_grad");
+}
+
+extern "C" int lb_param_grad_vjp(lb_plan *P, const double *psi, const double *ct, double *out) {
+  if (!P || !psi || !ct || !out) return fail(LB_ERR_ARG, "null argument");
+  const long total = P->N * P->batch;
+  {
+    KT kt_(P, "param_vjp");
+    LB_LAUNCH(lbk::k_param_vjp, dim3((unsigned)std::min<long>(cdiv(total, lbk::EW_NT), 4096)), dim3(lbk::EW_NT), 0,
+              P->stream, P->N, P->batch, psi, ct, out);
+  }
+  return check_launch("lb_param_grad_vjp");
 }
 
 // the plane pass of the inner iteration, in the variant the autotuner chose
@@ -1612,6 +1683,7 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
     SubOut sub;
     LB_TRY(run_subproblem(P, p, r, so, eg.gnorm, d0_spec, &sub));
     info->inner_total += sub.iters;
+    if (sub.status != LB_OK) info->sub_capped++;
     info->newton_total += sub.newton;
     info->newton_direct += sub.newton_direct;
     const double lam = sub.lam, sn = sub.dnorm;

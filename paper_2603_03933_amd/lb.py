@@ -109,6 +109,7 @@ class LbTrInfo(C.Structure):
         ("hard_cases", C.c_int),
         ("newton_total", C.c_int),
         ("newton_direct", C.c_int),
+        ("sub_capped", C.c_int),
     ]
 
 
@@ -133,12 +134,15 @@ _SIGS = {
     "lb_plan_set_stream": (_I, [_P, _P]),
     "lb_plan_workspace_bytes": (C.c_size_t, [_P]),
     "lb_plan_set_timing": (_I, [_P, _I, C.c_char_p]),
+    "lb_plan_set_timing_sampled": (_I, [_P, _I, C.c_char_p, _I]),
     "lb_plan_timing_entry": (_I, [_P, _I, C.c_char_p, _I, C.POINTER(C.c_long), C.POINTER(_D)]),
     "lb_energy_grad": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
     "lb_hessvec": (_I, [_P, C.POINTER(LbParams), _P, _P, _P, _I]),
     "lb_energy_grad_raw": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
     "lb_hessvec_raw": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
     "lb_field_moments": (_I, [_P, _P, _P, _P]),
+    "lb_param_grad": (_I, [_P, _P, _P, _P]),
+    "lb_param_grad_vjp": (_I, [_P, _P, _P, _P]),
     "lb_tr_subproblem": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, C.POINTER(LbSubOpts), _P, _P, C.POINTER(LbSubInfo)]),
     "lb_imex_tr_solve": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo)]),
     "lb_shifted_solve": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, _D, _I, _D, _P, C.POINTER(_I)]),
@@ -265,9 +269,10 @@ class Plan:
     def workspace_bytes(self) -> int:
         return int(lib().lb_plan_workspace_bytes(self._h))
 
-    def lb_plan_set_timing(self, enable: bool, filter: str = ""):
+    def lb_plan_set_timing(self, enable: bool, filter: str = "", every: int = 1):
+        """Time the kernels named in `filter` (comma-separated; all when empty), one launch in `every`."""
         self._sync_stream()
-        _check(lib().lb_plan_set_timing(self._h, 1 if enable else 0, filter.encode()))
+        _check(lib().lb_plan_set_timing_sampled(self._h, 1 if enable else 0, filter.encode(), int(every)))
 
     def timings(self):
         """{kernel name: (launches, total ms)} accumulated since timing was set."""
@@ -334,6 +339,24 @@ class Plan:
         if out is None:
             out = torch.empty(4 * self.batch, dtype=torch.float64, device=psi.device)
         _check(lib().lb_field_moments(self._h, _ptr(psi, n, "psi"), _ptr(w, n, "w"), _ptr(out, 4 * self.batch, "out")))
+        return out
+
+    def lb_param_grad(self, psi, w=None, out=None):
+        """[dE/dtau, dE/dgamma, d<w, grad_raw E>/dtau, d<w, grad_raw E>/dgamma] per instance (4 * batch)."""
+        self._sync_stream()
+        n = self.N * self.batch
+        if out is None:
+            out = torch.empty(4 * self.batch, dtype=torch.float64, device=psi.device)
+        _check(lib().lb_param_grad(self._h, _ptr(psi, n, "psi"), _ptr(w, n, "w"), _ptr(out, 4 * self.batch, "out")))
+        return out
+
+    def lb_param_grad_vjp(self, psi, ct, out=None):
+        """Gradient in psi of ct[2b] dE/dtau + ct[2b+1] dE/dgamma (ct: 2 * batch doubles on the device)."""
+        self._sync_stream()
+        n = self.N * self.batch
+        if out is None:
+            out = torch.empty_like(psi)
+        _check(lib().lb_param_grad_vjp(self._h, _ptr(psi, n, "psi"), _ptr(ct, 2 * self.batch, "ct"), _ptr(out, n, "out")))
         return out
 
     def lb_tr_subproblem(self, params, psi, grad, radius, opts: Optional[LbSubOpts] = None, d0=None, out=None):

@@ -60,8 +60,8 @@ int main(void) {
   const int rc = lb_imex_tr_solve(plan, &prm, psi, &o, &info);
   CHECK(rc);
   printf("{\"energy0\": %.17g, \"grad0\": [%.17g, %.17g], \"hv0\": [%.17g, %.17g], \"status\": %d, "
-         "\"energy\": %.17g, \"gnorm\": %.17g, \"outer\": %d, \"inner\": %d}\n",
-         e0, g0[0], g0[1], hv0[0], hv0[1], rc, info.energy, info.gnorm, info.outer, info.inner_total);
+         "\"energy\": %.17g, \"gnorm\": %.17g, \"outer\": %d, \"inner\": %d, \"sub_capped\": %d}\n",
+         e0, g0[0], g0[1], hv0[0], hv0[1], rc, info.energy, info.gnorm, info.outer, info.inner_total, info.sub_capped);
   hipFree(psi);
   hipFree(grad);
   hipFree(hv);

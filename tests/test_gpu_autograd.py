@@ -48,6 +48,12 @@ def test_raw_gradient_hessvec_moments_match_oracle(shape, box, precision, tol):
     scale = (np.max(np.abs(O.inv(m.Lam * O.fwd(v)))) + np.max(np.abs(O.Gamma_p(psi, m.tau, m.gamma) * v))) / N
     assert np.max(np.abs(host(hv) - h_or)) < tol * scale
     assert np.allclose(host(mom), O.field_moments(psi, v), rtol=1e-13, atol=1e-15)
+    pg = plan.lb_param_grad(dev(psi), dev(v))
+    assert np.allclose(host(pg), O.param_grad(psi, v), rtol=1e-13, atol=1e-15)
+    ct = dev(np.array([0.7, -1.9]))
+    vjp = plan.lb_param_grad_vjp(dev(psi), ct)
+    ref = O.param_grad_vjp(psi, 0.7, -1.9)
+    assert np.max(np.abs(host(vjp) - ref)) < 1e-15 * np.max(np.abs(ref)) * 4
 
 
 def test_autograd_gradcheck_and_gradgradcheck():

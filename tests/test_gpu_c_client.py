@@ -40,3 +40,4 @@ def test_c_client_matches_python_binding():
     assert c["status"] == rc == lb.LB_OK
     assert abs(c["energy"] - info.energy) <= 1e-10 * abs(info.energy)
     assert c["gnorm"] < 1e-8
+    assert c["sub_capped"] == info.sub_capped

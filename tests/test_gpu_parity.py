@@ -131,10 +131,13 @@ def test_full_size_bcc_128_energy_grad_hessvec():
     clean = I.bcc_3d(128, noise=0.0).psi0
     E_clean, _ = plan.lb_energy_grad(prm, dev(clean), want_grad=False)
     assert abs(host(E_clean)[0] - 18.9) < 1e-12 * 18.9
+    # 1e-12 of the term scale (||Lambda psi_hat|| + ||F'(psi)||, resp. ||L v|| + ||Gamma' v||, RMS)
     go = O.gradient_phys(m, inst.psi0)
-    assert math.sqrt(np.mean((g - go) ** 2)) < 1e-12 * math.sqrt(np.mean(go**2)) * 10
+    g_scale = math.sqrt(np.mean(O.inv(m.Lam * O.fwd(inst.psi0)) ** 2)) + math.sqrt(np.mean(O.dF_bulk(inst.psi0, m.tau, m.gamma) ** 2))
+    assert math.sqrt(np.mean((g - go) ** 2)) <= 1e-12 * g_scale
     ho = O.hessvec_phys(m, inst.psi0, v)
-    assert math.sqrt(np.mean((hv - ho) ** 2)) < 1e-12 * math.sqrt(np.mean(ho**2)) * 10
+    h_scale = math.sqrt(np.mean(O.inv(m.Lam * O.fwd(v)) ** 2)) + math.sqrt(np.mean((O.Gamma_p(inst.psi0, m.tau, m.gamma) * v) ** 2))
+    assert math.sqrt(np.mean((hv - ho) ** 2)) <= 1e-12 * h_scale
 
 
 # ---------------------------------------------------------------------------
@@ -154,26 +157,34 @@ def test_full_size_bcc_128_energy_grad_hessvec():
 )
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_tr_subproblem_matches_oracle(shape, box, tau, r, amp, precision):
+    """FP64: both sides run Algorithm 3 to ||r|| < 1e-10 and agree to 1e-9
+    (the stop test's accuracy). FP32 transforms cannot reach that residual, so
+    both sides run the same 300 iterations (the oracle in FP64) and the FP32
+    iterate and multiplier agree with the oracle's to 1e-5 of their scale."""
     m = model_for(shape, box, tau, 0.25)
     psi = I.zero_mean_noise(shape, amp, 21)
     g_hat = O.gradient(m, psi)
-    eps_sub = 1e-10 if precision == "fp64" else 1e-4
-    opts_or = O.SubOpts(eta=0.1, eps_sub=eps_sub, max_inner=20000)
+    if precision == "fp64":
+        opts_or = O.SubOpts(eta=0.1, eps_sub=1e-10, max_inner=20000)
+        so = lb.sub_opts(eta=0.1, eps_sub=1e-10, max_inner=20000)
+    else:
+        opts_or = O.SubOpts(eta=0.1, eps_sub=0.0, max_inner=300)
+        so = lb.sub_opts(eta=0.1, eps_sub=0.0, max_inner=300)
     ref = O.imex_subproblem(m, psi, g_hat, r, opts_or)
     plan = lb.Plan(shape, box, precision=precision)
-    so = lb.sub_opts(eta=0.1, eps_sub=eps_sub, max_inner=20000)
     d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(psi), dev(O.inv(g_hat)), r, so)
     d = host(d)
     d_or = O.inv(ref.d)
-    assert ref.converged and rc == lb.LB_OK
     dn = math.sqrt(np.mean(d_or**2))
     if precision == "fp64":
+        assert ref.converged and rc == lb.LB_OK
         assert abs(info.iters - ref.iters) <= 1
         assert abs(info.lambda_ - ref.lam) <= 1e-9 * max(1.0, ref.lam)
         assert math.sqrt(np.mean((d - d_or) ** 2)) <= 1e-9 * max(dn, 1e-30)
     else:
-        assert abs(info.lambda_ - ref.lam) <= 1e-4 * max(1.0, ref.lam)
-        assert math.sqrt(np.mean((d - d_or) ** 2)) <= 1e-4 * max(dn, 1e-30)
+        assert info.iters == ref.iters == 300 and rc == lb.LB_NOT_CONVERGED
+        assert abs(info.lambda_ - ref.lam) <= 1e-5 * max(1.0, ref.lam)
+        assert math.sqrt(np.mean((d - d_or) ** 2)) <= 1e-5 * max(dn, 1e-30)
     assert info.dnorm <= r * (1 + 1e-12)
     assert abs(info.lambda_ * (info.dnorm - r)) <= 1e-8 * max(1.0, info.lambda_)
 

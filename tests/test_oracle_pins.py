@@ -301,6 +301,40 @@ def test_field_moments_are_parameter_derivatives():
     assert abs((gw(0.1, 0.2 + h) - gw(0.1, 0.2 - h)) / (2 * h) + M[3] / 2) < 1e-13
 
 
+def test_param_grad_and_its_psi_gradient_by_differences():
+    """param_grad: the tau and gamma derivatives of E and of <w, grad_raw E> by
+    central differences (exact: both are affine in tau and gamma);
+    param_grad_vjp: the psi-gradient of a dE/dtau + b dE/dgamma by central
+    differences along e (exact up to the cubic's eps^2 term, -b eps^2 mean(e^3) / 6)."""
+    g = O.Grid((6, 8), (5.0, 7.0))
+    psi = rand_field(g.n, 0.7, 35) + 0.2
+    w = rand_field(g.n, 1.0, 36)
+    e = rand_field(g.n, 1.0, 37)
+    h = 0.37
+    P = O.param_grad(psi, w)
+
+    def E(tau, gam, p=psi):
+        return O.energy(O.Model(g, tau, gam), p)
+
+    def gw(tau, gam):
+        return float(np.sum(w * O.gradient_raw(O.Model(g, tau, gam), psi)))
+
+    assert abs((E(0.1 + h, 0.2) - E(0.1 - h, 0.2)) / (2 * h) - P[0]) < 1e-13
+    assert abs((E(0.1, 0.2 + h) - E(0.1, 0.2 - h)) / (2 * h) - P[1]) < 1e-13
+    assert abs((gw(0.1 + h, 0.2) - gw(0.1 - h, 0.2)) / (2 * h) - P[2]) < 1e-13
+    assert abs((gw(0.1, 0.2 + h) - gw(0.1, 0.2 - h)) / (2 * h) - P[3]) < 1e-13
+    assert np.all(O.param_grad(psi)[2:] == 0.0)
+    a, b, eps = 0.8, -1.3, 1e-2
+
+    def f(p):
+        q = O.param_grad(p)
+        return a * q[0] + b * q[1]
+
+    fd = (f(psi + eps * e) - f(psi - eps * e)) / (2 * eps)
+    lin = float(np.sum(O.param_grad_vjp(psi, a, b) * e))
+    assert abs(fd - (lin - b * eps**2 * np.mean(e**3) / 6.0)) < 1e-14
+
+
 # ---------------------------------------------------------------------------
 # Structure of the Hessian and invariants
 # ---------------------------------------------------------------------------

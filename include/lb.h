@@ -229,6 +229,23 @@ int lb_energy_grad(lb_plan *plan, const lb_params *params, const double *psi, do
  * FFT arithmetic in the plan's precision. Asynchronous. */
 int lb_hessvec(lb_plan *plan, const lb_params *params, const double *psi, const double *v, double *hv, int project);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * Hessian-vector product of lb_hessvec for one FP64 instance of `grid`
+ * without a plan and without any allocation. Its workspace (twiddle tables,
+ * the partial sums of the projection's mean, the half spectrum) is a fixed
+ * 8 MiB device array of the library, one per GPU, held until the process
+ * ends; grids whose half spectrum exceeds about 520 000 modes (for example
+ * 128^3) are rejected with LB_ERR_ARG. Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (different streams, threads) race:
+ * serialise them. The twiddle tables are regenerated on the device in each
+ * call, so results agree with lb_hessvec to rounding, not bit for bit.
+ *   grid    : host; params : host, one entry; psi, v, hv : N doubles (device)
+ *   project : as for lb_hessvec; stream : hipStream_t (NULL: null stream)
+ * Asynchronous. Errors: LB_ERR_ARG, LB_ERR_UNSUPPORTED, LB_ERR_HIP. */
+int lb_hessvec_noalloc(const lb_grid *grid, const lb_params *params, const double *psi, const double *v, double *hv,
+                       int project, void *stream);
+
 /* Derivatives with respect to the N grid values (for automatic
  * differentiation frameworks), of E as printed in eq. lb_energy with the sum
  * over every k including k = 0 and no mass constraint (on zero-mean fields

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <thread>
@@ -872,6 +873,109 @@ extern "C" int lb_field_moments(lb_plan *P, const double *psi, const double *w, 
               1.0 / (double)P->N, out);
   }
   return check_launch("lb_field_moments");
+}
+
+// ---------------------------------------------------------------------------
+// Hessian-vector product without allocation: the workspace (twiddles, the
+// partial sums of the mean, the half spectrum) lives in a fixed device array,
+// one per GPU, located once per device with hipGetSymbolAddress; the plan is
+// a stack view onto it. Calls on one device share the array.
+// ---------------------------------------------------------------------------
+#define LB_NOALLOC_SCRATCH_BYTES (8u << 20)
+static __device__ __align__(256) unsigned char scratch[LB_NOALLOC_SCRATCH_BYTES];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+constexpr size_t kTwBytes = 3 * 512 * sizeof(double2);  // per-axis twiddles, n <= 512
+constexpr size_t kPartialDoubles = 4096;
+constexpr size_t kSpecOffset = kTwBytes + kPartialDoubles * sizeof(double);
+}  // namespace
+namespace lbk {
+// W[m] = exp(-2 pi i m / n) by quadrant (the axis points exact), as the plan's host tables
+__global__ void k_twiddles(int n, double2 *w) {
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < n; m += gridDim.x * blockDim.x) {
+    const long m4 = 4L * m;
+    const int quad = (int)(m4 / n);
+    const long rem = m4 % n;
+    double sn, cs;
+    sincospi(0.5 * (double)rem / (double)n, &sn, &cs);
+    double cc, ss;
+    switch (quad) {
+      case 0: cc = cs; ss = sn; break;
+      case 1: cc = -sn; ss = cs; break;
+      case 2: cc = -cs; ss = -sn; break;
+      default: cc = sn; ss = -cs; break;
+    }
+    w[m] = double2{cc, -ss};
+  }
+}
+}  // namespace lbk
+
+// the device address of this GPU's scratch array (looked up once per device)
+static int scratch_address(void **out) {
+  int d = 0;
+  LB_HIP(hipGetDevice(&d));
+  if (d < 0 || d >= kMaxDevices) return fail(LB_ERR_HIP, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[d]) {
+    void *ptr = nullptr;
+    LB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(LB_ERR_HIP, "hipGetSymbolAddress returned no address");
+    g_scratch_ptr[d] = ptr;
+  }
+  *out = g_scratch_ptr[d];
+  return 0;
+}
+
+extern "C" int lb_hessvec_noalloc(const lb_grid *g, const lb_params *params, const double *psi, const double *v,
+                                  double *hv, int project, void *stream) {
+  if (!g || !params || !psi || !v || !hv) return fail(LB_ERR_ARG, "null argument");
+  if (g->dim != 2 && g->dim != 3) return fail(LB_ERR_ARG, "dim must be 2 or 3");
+  for (int a = 0; a < g->dim; ++a) {
+    if (!(g->box[a] > 0.0) || !std::isfinite(g->box[a])) return fail(LB_ERR_ARG, "box sides must be positive");
+    if (!funcs_for(g->n[a], 0)) return fail(LB_ERR_UNSUPPORTED, "axis length not supported (2^a 3^b, 8..512)");
+  }
+  lb_plan V;  // a view: every buffer below points into the scratch array (no member allocates)
+  V.grid = *g;
+  V.dim = g->dim;
+  V.batch = 1;
+  V.prec = LB_FP64;
+  V.stream = (hipStream_t)stream;
+  V.n0 = g->n[0];
+  V.n1 = (g->dim == 3) ? g->n[1] : 1;
+  V.nl = g->n[g->dim - 1];
+  V.nhl = V.nl / 2 + 1;
+  V.N = (long)V.n0 * V.n1 * V.nl;
+  V.nh = (long)V.n0 * V.n1 * V.nhl;
+  if (kSpecOffset + (size_t)V.nh * sizeof(double2) > LB_NOALLOC_SCRATCH_BYTES)
+    return fail(LB_ERR_ARG, "grid too large for the fixed workspace of lb_hessvec_noalloc (8 MiB: half spectrum of "
+                            "at most 520 000 modes)");
+  void *base = nullptr;
+  LB_TRY(scratch_address(&base));
+  unsigned char *sb = (unsigned char *)base;
+  const int axis_of[3] = {0, g->dim == 3 ? 1 : -1, g->dim - 1};
+  for (int sl = 0; sl < 3; ++sl) {
+    AxisTab &A = V.ax[sl];
+    if (axis_of[sl] < 0) {
+      A.n = 1;
+      continue;
+    }
+    A.n = g->n[axis_of[sl]];
+    A.f64 = funcs_for(A.n, LB_FP64);
+    A.f32 = funcs_for(A.n, LB_FP32);
+    A.L = g->box[axis_of[sl]];
+    A.tw64 = (double2 *)(sb + (size_t)sl * 512 * sizeof(double2));
+    LB_LAUNCH(lbk::k_twiddles, dim3(2), dim3(256), 0, V.stream, A.n, A.tw64);
+  }
+  V.partial = (double *)(sb + kTwBytes);
+  V.partial_len = (long)kPartialDoubles;
+  const long need = std::max(bpi_pairs(&V), (long)V.n0);
+  if (need > (long)kPartialDoubles) return fail(LB_ERR_ARG, "grid needs more partial sums than the fixed workspace holds");
+  V.WT = (void *)(sb + kSpecOffset);
+  const int rc = hessvec_phys(&V, params, psi, v, hv, project ? 0 : 1);
+  V.ax[0].tw64 = V.ax[1].tw64 = V.ax[2].tw64 = nullptr;
+  return rc;
 }
 
 extern "C" int lb_param_grad(lb_plan *P, const double *psi, const double *w, double *out) {

@@ -142,6 +142,7 @@ _SIGS = {
     "lb_hessvec_raw": (_I, [_P, C.POINTER(LbParams), _P, _P, _P]),
     "lb_field_moments": (_I, [_P, _P, _P, _P]),
     "lb_param_grad": (_I, [_P, _P, _P, _P]),
+    "lb_hessvec_noalloc": (_I, [C.POINTER(LbGrid), C.POINTER(LbParams), _P, _P, _P, _I, _P]),
     "lb_param_grad_vjp": (_I, [_P, _P, _P, _P]),
     "lb_tr_subproblem": (_I, [_P, C.POINTER(LbParams), _P, _P, _D, C.POINTER(LbSubOpts), _P, _P, C.POINTER(LbSubInfo)]),
     "lb_imex_tr_solve": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo)]),
@@ -418,6 +419,23 @@ def lb_imex_tr_solve_many(plans, params, psis, opts: Optional[LbTrOpts] = None, 
     st = (_I * n)()
     _check(lib().lb_imex_tr_solve_many(hp, pa, ps, n, C.byref(opts) if opts is not None else None, int(workers), infos, st))
     return [(infos[i], st[i]) for i in range(n)]
+
+
+def lb_hessvec_noalloc(n: Sequence[int], box: Sequence[float], params, psi, v, out=None, project=True):
+    """Hessian-vector product of one FP64 instance with the library's fixed
+    workspace: no plan and no device allocation by the library (out is
+    allocated here by torch when not given)."""
+    g = LbGrid()
+    g.dim = len(n)
+    for a in range(g.dim):
+        g.n[a] = int(n[a])
+        g.box[a] = float(box[a])
+    N = math.prod(int(x) for x in n)
+    if out is None:
+        out = torch.empty_like(v)
+    _check(lib().lb_hessvec_noalloc(C.byref(g), _params_array(params, 1), _ptr(psi, N, "psi"), _ptr(v, N, "v"),
+                                    _ptr(out, N, "hv"), 1 if project else 0, _stream()))
+    return out
 
 
 def exported_symbols():

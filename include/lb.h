@@ -7,7 +7,8 @@
  * Grid (Section 2, grid set T_M^d): a periodic orthorhombic box
  * [0,box[0]) x ... with n[a] points per axis, x_j = j * box[a] / n[a];
  * reciprocal lattice B = diag(2 pi / box), reciprocal indices k_a in
- * [-n_a/2, n_a/2). Supported axis lengths: 2^a 3^b with 8 <= n <= 512.
+ * [-n_a/2, n_a/2); lb_plan_set_lattice replaces the box by a general
+ * Bravais lattice. Supported axis lengths: 2^a 3^b with 8 <= n <= 512.
  *
  * Fields are real arrays of N = prod(n) doubles in C order (last axis
  * fastest), `batch` instances back to back. Every array argument is a DEVICE
@@ -187,6 +188,19 @@ void lb_tr_opts_default(lb_tr_opts *opts);
 int lb_plan_create(lb_plan **out, const lb_grid *grid, int batch, int precision, void *stream);
 int lb_plan_destroy(lb_plan *plan);
 int lb_plan_set_stream(lb_plan *plan, void *stream);
+
+/* General Bravais lattice (Section 2: the grid T_M^d = {A (j / M)}, reciprocal
+ * matrix B with A B^T = 2 pi I). A: dim x dim doubles (host), row major, whose
+ * column a is the cell vector along grid axis a; grid point j is
+ * x = sum_a A[:, a] j_a / n_a. The interaction multiplier becomes
+ * Lambda_k = xi^2 (q^2 - |Bk|^2)^2 with |Bk|^2 = k^T B^T B k. A Nyquist index
+ * (-n_a/2) and its conjugate partner carry different |Bk|^2 when B has
+ * off-diagonal terms; both take their mean, so Lambda keeps real fields real.
+ * A diagonal A is the orthorhombic box diag(A) (the same results as a plan
+ * created with that box); A = NULL returns to the grid's box. Errors:
+ * LB_ERR_ARG (non-finite or singular A). Applies to every later call on the
+ * plan; lb_hessvec_noalloc takes orthorhombic boxes only. */
+int lb_plan_set_lattice(lb_plan *plan, const double *A);
 /* Device bytes held by the plan. */
 size_t lb_plan_workspace_bytes(const lb_plan *plan);
 
@@ -345,17 +359,32 @@ int lb_lanczos_min(lb_plan *plan, const lb_params *params, const double *psi, co
  * Asynchronous. */
 int lb_random_ball(lb_plan *plan, double radius, unsigned long long seed, unsigned long long draw, double *d_out);
 
-/* `count` independent IMEX-TR solves (lb_imex_tr_solve each), e.g. a sweep of
- * instances of different grid sizes and parameters, run concurrently: a pool
- * of `workers` host threads, each with its own HIP stream, takes the jobs
- * largest grid first. Job i solves on plans[i] (distinct plans of batch 1)
- * with params[i] (host) and the field psi[i] (device, N_i doubles, updated);
- * opts (nullable: defaults) apply to all. Each job starts after the work
- * already enqueued on its plan's stream, and later work on that stream sees
- * its result. infos[i] and status[i] (host, written) are the job's
- * lb_tr_info and return code. Returns LB_OK when no job failed, else the first
- * failing job's code (its message in lb_last_error). Blocks until all jobs
- * are done. */
+/* IMEX-TR solves of the plan's `batch` instances together (Algorithms 1-3 for
+ * each): every pass of the subproblem iteration and of the outer loop is one
+ * launch for all instances still iterating, with per-instance multipliers,
+ * stop flags, radii and branches; an instance leaves the launches when its
+ * gradient test holds. Each instance's result equals its lb_imex_tr_solve on
+ * a plan of batch 1, bit for bit.
+ *   params : batch entries (host); psi : batch * N doubles (device, zero-mean
+ *   fields, updated); infos, status : batch entries (host, written; status is
+ *   LB_OK, LB_NOT_CONVERGED or a negative error per instance).
+ * Nearly hard starts (hard_case) and the direct ratio numerator (rho_taylor = 0)
+ * need batch 1 (LB_ERR_UNSUPPORTED otherwise). Returns LB_OK, or the first
+ * instance's error. Synchronises the stream. */
+int lb_imex_tr_solve_batch(lb_plan *plan, const lb_params *params, double *psi, const lb_tr_opts *opts,
+                           lb_tr_info *infos, int *status);
+
+/* `count` independent jobs run concurrently, e.g. a sweep of instances of
+ * different grid sizes and parameters: a pool of `workers` host threads, each
+ * with its own HIP stream, takes the jobs largest first. Job i solves the
+ * plans[i]->batch instances of plans[i] (distinct plans) as
+ * lb_imex_tr_solve_batch does, with the fields psi[i] (device,
+ * batch_i * N_i doubles, updated). params, infos and status (host) hold one
+ * entry per instance, job after job (job i's first instance at
+ * sum_{k<i} batch_k). opts (nullable: defaults) apply to all. Each job starts
+ * after the work already enqueued on its plan's stream, and later work on that
+ * stream sees its result. Returns LB_OK when no instance failed, else the first
+ * failure's code (its message in lb_last_error). Blocks until all jobs are done. */
 int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double *const *psi, int count,
                           const lb_tr_opts *opts, int workers, lb_tr_info *infos, int *status);
 

@@ -43,21 +43,64 @@ import numpy as np
 
 
 class Grid:
-    """Periodic orthorhombic grid with n[a] points on [0, box[a])."""
+    """Periodic grid T_M^d (Section 2) with n[a] points per axis.
 
-    def __init__(self, n: Sequence[int], box: Sequence[float]):
+    Either an orthorhombic box (``box``: sides L_a, lattice A = diag(L)) or a
+    general Bravais lattice (``lattice``: the d x d matrix A whose column a is
+    the cell vector along grid axis a; grid points x_j = A (j / n)). The
+    reciprocal matrix is B = 2 pi A^{-T} (A B^T = 2 pi I), so the Fourier mode
+    of index k is exp(i (Bk).x) with Bk = sum_a k_a B[:, a], and
+    |Bk|^2 = k^T B^T B k.
+    """
+
+    def __init__(self, n: Sequence[int], box: Optional[Sequence[float]] = None, lattice=None):
         self.n = tuple(int(m) for m in n)
-        self.box = tuple(float(L) for L in box)
-        if len(self.n) != len(self.box) or len(self.n) not in (1, 2, 3):
-            raise ValueError("dimension mismatch")
         self.dim = len(self.n)
+        if self.dim not in (1, 2, 3):
+            raise ValueError("dimension must be 1, 2 or 3")
+        if lattice is None:
+            if box is None or len(box) != self.dim:
+                raise ValueError("dimension mismatch")
+            self.box = tuple(float(L) for L in box)
+            self.A = np.diag(self.box)
+        else:
+            self.A = np.array(lattice, dtype=float).reshape(self.dim, self.dim)
+            self.box = None
+        self.B = 2.0 * math.pi * np.linalg.inv(self.A).T
         self.N = int(np.prod(self.n))
         # signed reciprocal index per axis, K_M: -n/2 <= k < n/2
         self.kidx = [signed_index(m) for m in self.n]
         mesh = np.meshgrid(*self.kidx, indexing="ij")
-        # |Bk|^2 with B = diag(2 pi / L)
-        self.kk = sum((2.0 * math.pi * mesh[a] / self.box[a]) ** 2 for a in range(self.dim))
+        if lattice is None:
+            # |Bk|^2 with B = diag(2 pi / L)
+            self.kk = sum((2.0 * math.pi * mesh[a] / self.box[a]) ** 2 for a in range(self.dim))
+        else:
+            self.kk = kk_general(self.B, self.n, mesh)
         self.zero = (0,) * self.dim
+
+
+def kk_general(B: np.ndarray, n: Sequence[int], mesh) -> np.ndarray:
+    """|Bk|^2 = sum_ab G_ab k_a k_b, G = B^T B, over the signed index set K_M.
+
+    An index k_a = -n_a/2 (Nyquist) stands for the same DFT entry as +n_a/2,
+    so the conjugate partner of entry k, which a real field fixes to the
+    complex conjugate, is k with every Nyquist coordinate negated. With
+    off-diagonal G the two carry different |Bk|^2; both take their mean, so
+    that the multiplier maps real fields to real fields: the cross term
+    k_a k_b is kept when axes a and b are both at Nyquist or both not, and
+    dropped when exactly one is (the mean of the two signs).
+    """
+    G = B.T @ B
+    d = len(n)
+    nyq = [mesh[a] == -(n[a] // 2) if n[a] % 2 == 0 else np.zeros_like(mesh[a], dtype=bool) for a in range(d)]
+    out = np.zeros(mesh[0].shape)
+    for a in range(d):
+        out = out + G[a, a] * mesh[a].astype(float) ** 2
+    for a in range(d):
+        for b in range(a + 1, d):
+            keep = nyq[a] == nyq[b]
+            out = out + np.where(keep, 2.0 * G[a, b] * mesh[a].astype(float) * mesh[b].astype(float), 0.0)
+    return out
 
 
 def signed_index(n: int) -> np.ndarray:

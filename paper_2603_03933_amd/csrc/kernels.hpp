@@ -33,7 +33,13 @@ struct Geo {
   long N;        // points per instance
   long nh;       // half-spectrum modes per instance
   int batch;
-  double c0, c1, cl;  // 2 pi / L of the leading, middle (3D) and last axis
+  // |Bk|^2 = sum_ab G_ab k_a k_b with G = B^T B (Section 2, A B^T = 2 pi I):
+  // c_a = sqrt(G_aa) (2 pi / L_a for an orthorhombic box) and the cross
+  // coefficients 2 G_ab of the leading, middle (3D) and last axes, all 0 for
+  // an orthorhombic box
+  double c0, c1, cl;
+  double x01, x0l, x1l;
+  int general;  // some cross coefficient is nonzero (uniform branch for the paired sums)
 };
 
 // |Bk|^2 along one axis, (c k)^2 with c = 2 pi / L, for storage index i of n
@@ -62,14 +68,39 @@ __device__ __forceinline__ void decode(const Geo &g, int h, int &i0, int &i1, in
   i0 = r / g.n1;
   i1 = r - i0 * g.n1;
 }
-// |Bk|^2 of a mode: kk0 + (kk_last + kk1)
-__device__ __forceinline__ double kk_col_part(const Geo &g, int i1, int kl) {
-  return g.dim == 3 ? kkl_of(g, kl) + kk1_of(g, i1) : kkl_of(g, kl);
+
+// The column part of |Bk|^2 for (k1, k_last) and the coefficients of k0 in
+// the cross terms. The signed index set puts a Nyquist entry at -n/2; its
+// conjugate partner is the entry with every Nyquist coordinate negated, and
+// with cross terms the two would carry different |Bk|^2, so both take their
+// mean: a cross term k_a k_b counts when axes a and b are both at Nyquist or
+// both not. lin applies when k0 is not at Nyquist, lin_nyq when it is. On an
+// orthorhombic box every cross coefficient is 0 and the sums below add zeros.
+struct ColK {
+  double kkc, lin, lin_nyq;
+};
+__device__ __forceinline__ ColK col_k(const Geo &g, int i1, int kl) {
+  ColK c;
+  c.kkc = g.dim == 3 ? kkl_of(g, kl) + kk1_of(g, i1) : kkl_of(g, kl);
+  const bool n1q = g.dim == 3 && 2 * i1 == g.n1;
+  const bool nlq = 2 * kl == g.nl;  // stored as +nl/2, signed -nl/2
+  const double k1 = g.dim == 3 ? (double)(i1 < g.n1 / 2 ? i1 : i1 - g.n1) : 0.0;
+  const double kls = nlq ? -(double)kl : (double)kl;
+  c.kkc += (n1q == nlq) ? g.x1l * (k1 * kls) : 0.0;
+  c.lin = (n1q ? 0.0 : g.x01 * k1) + (nlq ? 0.0 : g.x0l * kls);
+  c.lin_nyq = (n1q ? g.x01 * k1 : 0.0) + (nlq ? g.x0l * kls : 0.0);
+  return c;
+}
+// |Bk|^2 of axis-0 element e of a column: (kk0 + kkc) + k0 lin
+__device__ __forceinline__ double kk_elem(const Geo &g, int e, double kkc, double lin, double lin_nyq) {
+  const int k0 = e < g.n0 / 2 ? e : e - g.n0;
+  return (kk0_of(g, e) + kkc) + (double)k0 * (2 * e == g.n0 ? lin_nyq : lin);
 }
 __device__ __forceinline__ double kk_at(const Geo &g, int h, int &kl) {
   int i0, i1;
   decode(g, h, i0, i1, kl);
-  return kk0_of(g, i0) + kk_col_part(g, i1, kl);
+  const ColK c = col_k(g, i1, kl);
+  return kk_elem(g, i0, c.kkc, c.lin, c.lin_nyq);
 }
 __device__ __forceinline__ double herm_w(const Geo &g, int kl) { return (kl == 0 || 2 * kl == g.nl) ? 1.0 : 2.0; }
 
@@ -84,21 +115,36 @@ __device__ __forceinline__ double rcp64(double x) {
 
 // Reciprocal-space data shared by all elements of one axis-0 column
 struct ColInfo {
-  double kkc;  // |Bk|^2 contribution of the column's (k1, k_last)
-  double w;    // Hermitian weight of the column
-  int dc;      // the column holds k = 0 at element 0
+  double kkc;           // |Bk|^2 contribution of the column's (k1, k_last)
+  double lin, lin_nyq;  // coefficients of k0 in the cross terms (0 on an orthorhombic box)
+  double w;             // Hermitian weight of the column
+  int dc;               // the column holds k = 0 at element 0
 };
-__device__ __forceinline__ ColInfo col_info(const Geo &g, int ml) {
+// GEN: the grid may have cross terms (general lattice); the orthorhombic
+// instantiations keep |Bk|^2 = kk0 + kkc without them
+template <bool GEN = true> __device__ __forceinline__ ColInfo col_info(const Geo &g, int ml) {
   int i1 = 0, kl = ml;
   if (g.dim == 3) {
     i1 = ml / g.nhl;
     kl = ml - i1 * g.nhl;
   }
   ColInfo c;
-  c.kkc = kk_col_part(g, i1, kl);
+  if constexpr (GEN) {
+    const ColK k = col_k(g, i1, kl);
+    c.kkc = k.kkc;
+    c.lin = k.lin;
+    c.lin_nyq = k.lin_nyq;
+  } else {
+    c.kkc = g.dim == 3 ? kkl_of(g, kl) + kk1_of(g, i1) : kkl_of(g, kl);
+    c.lin = c.lin_nyq = 0.0;
+  }
   c.w = herm_w(g, kl);
   c.dc = (ml == 0);
   return c;
+}
+template <bool GEN = true> __device__ __forceinline__ double kk_e(const Geo &g, int e, const ColInfo &c) {
+  if constexpr (GEN) return kk_elem(g, e, c.kkc, c.lin, c.lin_nyq);
+  else return kk0_of(g, e) + c.kkc;
 }
 
 constexpr int pow2_floor(int x) {
@@ -343,8 +389,8 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
   __shared__ C lds[N * CC];
   // a stopped subproblem's steps must not write; the flag is applied at the
   // stores, so that the data loads need not wait for it to arrive
-  const bool sk = op.skip();
   const int b = blockIdx.x / cg.bpi;
+  const bool sk = op.skip(b);
   const int lb = blockIdx.x - b * cg.bpi;
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
   const int ml = lb * CC + c;
@@ -391,7 +437,7 @@ template <typename T> struct OpPlain {
   int zero_dc;
   long nh;
   const SubState *st;  // non-null: skip once the subproblem has stopped
-  __device__ bool skip() const { return st && st->done; }
+  __device__ bool skip(int b) const { return st && st[b].done; }
   __device__ Empty begin(int) const { return Empty{}; }
   __device__ int column(int, int ml) const { return zero_dc && ml == 0; }
   __device__ c2<T> load(const Empty &, int, long h, int) const { return in[h]; }
@@ -411,7 +457,7 @@ template <typename T> struct StepBlk {
 };
 
 // step t of the subproblem, axis-0 inverse pass: d_t = b_{t-1} / (1 + eta (Lambda + lambda_t))
-template <typename T> struct OpInvScaleD {
+template <typename T, bool GEN> struct OpInvScaleD {
   static constexpr bool eager_loads = true;
   Geo g;
   Prm p;
@@ -419,21 +465,21 @@ template <typename T> struct OpInvScaleD {
   c2<T> *out;
   const SubState *st;
   int t;  // step index (known to the host when it enqueues the step)
-  __device__ bool skip() const { return st->done != 0; }
+  __device__ bool skip(int b) const { return st[b].done != 0; }
   __device__ StepBlk<T> begin(int b) const {
     StepBlk<T> s;
     s.bprev = ((t - 1) & 1) ? b1 : b0;
     s.bnext = nullptr;
-    s.lam_t = st->lam[t & 1];
-    s.eta = st->eta;
+    s.lam_t = st[b].lam[t & 1];
+    s.eta = st[b].eta;
     s.xi = p.xi[b];
     s.q = p.q[b];
     return s;
   }
-  __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
+  __device__ ColInfo column(int, int ml) const { return col_info<GEN>(g, ml); }
   __device__ c2<T> load(const StepBlk<T> &bs, const ColInfo &ci, long h, int e) const {
     const c2<T> v = bs.bprev[h];
-    const double lam = lam_of(kk0_of(g, e) + ci.kkc, bs.xi, bs.q);
+    const double lam = lam_of(kk_e<GEN>(g, e, ci), bs.xi, bs.q);
     const double s = (ci.dc && e == 0) ? 0.0 : rcp64(1.0 + bs.eta * (lam + bs.lam_t));
     return c2<T>{T(double(v.x) * s), T(double(v.y) * s)};
   }
@@ -450,9 +496,9 @@ template <typename T> struct OpInvScaleD {
 //   b_t = d_t - eta (g + Td),  w |b_t|^2 (for the secular function)
 template <typename T> struct UpdAux {
   c2<T> bp, gg;
-  double kk0;
+  double kk;  // |Bk|^2 of the element
 };
-template <typename T> struct OpFwdUpdate {
+template <typename T, bool GEN> struct OpFwdUpdate {
   static constexpr bool eager_loads = true;
   Geo g;
   Prm p;
@@ -465,20 +511,20 @@ template <typename T> struct OpFwdUpdate {
   double inv_n;
   int cpi;          // columns per instance
   int t;            // step index
-  __device__ bool skip() const { return st->done != 0; }
+  __device__ bool skip(int b) const { return st[b].done != 0; }
   __device__ StepBlk<T> begin(int b) const {
     StepBlk<T> s;
     s.bprev = ((t - 1) & 1) ? b1 : b0;
     s.bnext = (t & 1) ? b1 : b0;
-    s.lam_t = st->lam[t & 1];
-    s.eta = st->eta;
+    s.lam_t = st[b].lam[t & 1];
+    s.eta = st[b].eta;
     s.xi = p.xi[b];
     s.q = p.q[b];
     return s;
   }
-  __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
+  __device__ ColInfo column(int, int ml) const { return col_info<GEN>(g, ml); }
   __device__ c2<T> load(const StepBlk<T> &, const ColInfo &, long h, int) const { return tmp[h]; }
-  __device__ UpdAux<T> fetch(const StepBlk<T> &bs, const ColInfo &, bool ok, long h, int e) const {
+  __device__ UpdAux<T> fetch(const StepBlk<T> &bs, const ColInfo &ci, bool ok, long h, int e) const {
     UpdAux<T> a;
     if (ok) {
       a.bp = bs.bprev[h];
@@ -487,7 +533,7 @@ template <typename T> struct OpFwdUpdate {
       a.bp = c2<T>{T(0), T(0)};
       a.gg = a.bp;
     }
-    a.kk0 = kk0_of(g, e);
+    a.kk = kk_e<GEN>(g, e, ci);
     return a;
   }
   // the LDS buffer is free once the last pass has read it: w |b_t|^2 goes to
@@ -499,7 +545,7 @@ template <typename T> struct OpFwdUpdate {
       *sq = 0.0;
       return;
     }
-    const double lam = lam_of(a.kk0 + ci.kkc, bs.xi, bs.q);
+    const double lam = lam_of(a.kk, bs.xi, bs.q);
     const double s = rcp64(1.0 + bs.eta * (lam + bs.lam_t));
     const double dx = double(a.bp.x) * s, dy = double(a.bp.y) * s;
     const double tx = double(v.x) * inv_n, ty = double(v.y) * inv_n;
@@ -523,32 +569,48 @@ template <typename T> struct OpFwdUpdate {
     const int cc = threadIdx.x % CC;
     const int ml = lb * CC + cc;
     const bool okc = ml < cpi;
-    const double kkc = col_info(g, okc ? ml : 0).kkc;
+    const double kkc = col_info<GEN>(g, okc ? ml : 0).kkc;
     const double mu0 = bs.eta * bs.lam_t;
     double m[MOM_NV];
 #pragma unroll
     for (int j = 0; j < MOM_NV; ++j) m[j] = 0.0;
-    if (okc) {
-      // constant trip count, unrolled: the rows' power chains interleave
-      constexpr int ES = NT / CC, NIT = (NH0 + ES - 1) / ES;
-      const int e0 = threadIdx.x / CC;
+    auto add_moments = [&](double v, double kk) {
+      const double x = 1.0 + bs.eta * lam_of(kk, bs.xi, bs.q);
+      const double u0 = rcp64(x);
+      m[0] = fma(v, u0 * u0, m[0]);
+      const double u = rcp64(x + mu0);
+      double pw = v * u * u;
 #pragma unroll
-      for (int it = 0; it < NIT; ++it) {
-        const int e = e0 + it * ES;
-        if (e >= NH0) break;
-        double v = sq[e * CC + cc];
-        if (e != 0 && 2 * e != N) v += sq[(N - e) * CC + cc];
-        if (e != 0 || ml != 0) {
-          const double x = 1.0 + bs.eta * lam_of(kk0_of(g, e) + kkc, bs.xi, bs.q);
-          const double u0 = rcp64(x);
-          m[0] = fma(v, u0 * u0, m[0]);
-          const double u = rcp64(x + mu0);
-          double pw = v * u * u;
+      for (int j = 1; j < MOM_NV; ++j) {
+        m[j] += pw;
+        pw *= u;
+      }
+    };
+    if constexpr (!GEN) {
+      if (okc) {
+        // +-k0 share Lambda on an orthorhombic box: one term per pair of rows.
+        // Constant trip count, unrolled: the rows' power chains interleave
+        constexpr int ES = NT / CC, NIT = (NH0 + ES - 1) / ES;
+        const int e0 = threadIdx.x / CC;
 #pragma unroll
-          for (int j = 1; j < MOM_NV; ++j) {
-            m[j] += pw;
-            pw *= u;
-          }
+        for (int it = 0; it < NIT; ++it) {
+          const int e = e0 + it * ES;
+          if (e >= NH0) break;
+          double v = sq[e * CC + cc];
+          if (e != 0 && 2 * e != N) v += sq[(N - e) * CC + cc];
+          if (e != 0 || ml != 0) add_moments(v, kk0_of(g, e) + kkc);
+        }
+      }
+    } else {
+      if (okc) {
+        // cross terms: every row with its own Lambda
+        const ColInfo ci = col_info<true>(g, ml);
+        constexpr int ES = NT / CC, NIT = (N + ES - 1) / ES;
+        const int e0 = threadIdx.x / CC;
+        for (int it = 0; it < NIT; ++it) {
+          const int e = e0 + it * ES;
+          if (e >= N) break;
+          if (e != 0 || ml != 0) add_moments(sq[e * CC + cc], kk_e<true>(g, e, ci));
         }
       }
     }
@@ -589,9 +651,9 @@ struct HessBlk {
 };
 template <typename T> struct HessAux {
   c2<T> xv;
-  double kk0;
+  double kk;
 };
-template <typename T> struct OpFwdHess {
+template <typename T, bool GEN> struct OpFwdHess {
   static constexpr bool eager_loads = false;
   Geo g;
   Prm p;
@@ -599,15 +661,15 @@ template <typename T> struct OpFwdHess {
   const c2<T> *x;
   c2<T> *out;
   double inv_n, shift;
-  __device__ bool skip() const { return false; }
+  __device__ bool skip(int) const { return false; }
   __device__ HessBlk begin(int b) const { return HessBlk{p.xi[b], p.q[b]}; }
-  __device__ ColInfo column(int, int ml) const { return col_info(g, ml); }
+  __device__ ColInfo column(int, int ml) const { return col_info<GEN>(g, ml); }
   __device__ c2<T> load(const HessBlk &, const ColInfo &, long h, int) const { return tmp[h]; }
-  __device__ HessAux<T> fetch(const HessBlk &, const ColInfo &, bool ok, long h, int e) const {
+  __device__ HessAux<T> fetch(const HessBlk &, const ColInfo &ci, bool ok, long h, int e) const {
     HessAux<T> a;
     const c2<T> xv = x[h];  // h is a valid address for every thread
     a.xv = ok ? xv : c2<T>{T(0), T(0)};
-    a.kk0 = kk0_of(g, e);
+    a.kk = kk_e<GEN>(g, e, ci);
     return a;
   }
   __device__ void store(const HessBlk &hb, const ColInfo &ci, long h, int e, c2<T> v, const HessAux<T> &a,
@@ -616,7 +678,7 @@ template <typename T> struct OpFwdHess {
       out[h] = c2<T>{T(0), T(0)};
       return;
     }
-    const double lam = lam_of(a.kk0 + ci.kkc, hb.xi, hb.q) + shift;
+    const double lam = lam_of(a.kk, hb.xi, hb.q) + shift;
     out[h] = c2<T>{T(lam * double(a.xv.x) + double(v.x) * inv_n), T(lam * double(a.xv.y) + double(v.y) * inv_n)};
   }
   template <int NT, int N, int CC, class B> __device__ void end(const B &, double, double *, int, int, int) const {}
@@ -624,7 +686,7 @@ template <typename T> struct OpFwdHess {
 
 // Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
 // (k = 0 removed unless keep_dc), inverse transform, all in one workgroup pass.
-template <typename T, int N>
+template <typename T, int N, bool GEN>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo g, Prm p, const c2<T> *__restrict__ tw,
                                                                   c2<T> *data, double inv_n, int keep_dc) {
   using C = c2<T>;
@@ -636,7 +698,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   const int ml = lb * CC + c;
   const bool ok = ml < cg.cpi;
   const long base = b * cg.inst + (ok ? ml : 0);  // axis 0: every column starts in the first slab
-  const ColInfo ci = col_info(g, ok ? ml : 0);
+  const ColInfo ci = col_info<GEN>(g, ok ? ml : 0);
   const double xi = p.xi[b], q = p.q[b];
   auto lidx = [](int cc, int e) { return e * CC + cc; };
   fft_run<T, N, false>(
@@ -645,9 +707,9 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
         const C v = data[base + e * cg.S];
         return ok ? v : C{T(0), T(0)};
       },
-      [&](int e) { return kk0_of(g, e); },
-      [&](int e, C v, double kk0) {
-        double m = lam_of(kk0 + ci.kkc, xi, q) * inv_n;
+      [&](int e) { return kk_e<GEN>(g, e, ci); },
+      [&](int e, C v, double kk) {
+        double m = lam_of(kk, xi, q) * inv_n;
         if (!ok || (ci.dc && e == 0 && !keep_dc)) m = 0.0;
         lds[lidx(c, e)] = C{T(double(v.x) * m), T(double(v.y) * m)};
       });
@@ -881,8 +943,8 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_rows_inner(RowGeo rg, const c2<T
   using C = c2<T>;
   constexpr int CC = Cfg<N>::C, NT = Cfg<N>::NT, LD = RowLds<N>::LD, NHL = N / 2 + 1;
   __shared__ C lds[CC * LD];
-  const bool sk = st && st->done;  // applied at the stores (the loads need not wait for it)
   const int b = blockIdx.x / rg.bpi;
+  const bool sk = st && st[b].done;  // applied at the stores (the loads need not wait for it)
   const long pair0 = (long)(blockIdx.x % rg.bpi) * CC;
   const long ppi = rg.rpi / 2;
   const long rowbase = (long)b * rg.rpi;
@@ -1095,8 +1157,8 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   __shared__ C L[N * NH];
-  const bool sk = st && st->done;  // applied at the stores (the loads need not wait for it)
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
+  const bool sk = st && st[b].done;  // applied at the stores (the loads need not wait for it)
   C *plane = data + b * nh + (long)i0 * (N * NH);
   const T *g = gp + b * Np + (long)i0 * (N * N);
   plane_cols_inv_from<T, N, NT>(L, plane, tw);
@@ -1231,13 +1293,21 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
   constexpr bool RED_IN_PLANE = 2 * N * NH >= NROW * RS;
   __shared__ double red_own[RED_IN_PLANE ? 1 : NROW * RS];
   double *red = RED_IN_PLANE ? reinterpret_cast<double *>(Lraw) : red_own;
+  // one workgroup per instance of the batch
+  const int inst = blockIdx.x;
+  st += inst;
+  b0 += (long)inst * N * NH;
+  b1 += (long)inst * N * NH;
+  gh += (long)inst * N * NH;
+  gp += (long)inst * N * N;
   if (st->done) return;
-  const double xi = p.xi[0], q = p.q[0];
+  const double xi = p.xi[inst], q = p.q[inst];
   for (int h = threadIdx.x; h < N * NH; h += NT) {
     Bs[h] = b1[h];  // b_{t-1} of step 0 is b[1]
     Gs[h] = gh[h];
     const int e = h / NH, f = h - e * NH;
-    Lm[h] = lam_of(kk0_of(g, e) + kkl_of(g, f), xi, q);
+    const ColK ck = col_k(g, 0, f);
+    Lm[h] = lam_of(kk_elem(g, e, ck.kkc, ck.lin, ck.lin_nyq), xi, q);
   }
   for (int i = threadIdx.x; i < N * N; i += NT) Gp[i] = gp[i];
   for (int i = threadIdx.x; i < N; i += NT) tw[i] = twg[i];
@@ -1478,10 +1548,13 @@ __global__ __launch_bounds__(EW_NT) void k_lincomb(long n, double alpha, const c
 }
 
 // Initial point of the subproblem, stored as b_{-1} = d_0 (1 + eta Lambda) so
-// that step 0 recovers d_0 with lambda_0 = 0:
-//   d_0 = coef * src (coef = -r / ||g|| with src = g, or 1 with src = user d0)
+// that step 0 recovers d_0 with lambda_0 = 0, per instance b:
+//   d_0 = coef_b * src (coef_b = -r_b / ||g_b|| with src = g, or 1 with src = user d0)
+struct InitCoef {
+  double coef[MAXB], eta[MAXB];
+};
 template <typename T, typename TS>
-__global__ __launch_bounds__(EW_NT) void k_init_b(Geo g, Prm p, const c2<TS> *__restrict__ src, double coef, double eta,
+__global__ __launch_bounds__(EW_NT) void k_init_b(Geo g, Prm p, const c2<TS> *__restrict__ src, InitCoef ic,
                                                   c2<T> *__restrict__ bm1) {
   const long total = (long)g.batch * g.nh;
   for (long h = (long)blockIdx.x * EW_NT + threadIdx.x; h < total; h += (long)gridDim.x * EW_NT) {
@@ -1490,24 +1563,27 @@ __global__ __launch_bounds__(EW_NT) void k_init_b(Geo g, Prm p, const c2<TS> *__
     int kl;
     const double lam = lam_of(kk_at(g, (int)hl, kl), p.xi[b], p.q[b]);
     const c2<TS> s = src[h];
-    const double f = (hl == 0) ? 0.0 : coef * (1.0 + eta * lam);
+    const double f = (hl == 0) ? 0.0 : ic.coef[b] * (1.0 + ic.eta[b] * lam);
     bm1[h] = c2<T>{T(f * double(s.x)), T(f * double(s.y))};
   }
 }
 
-// Final step of the subproblem: d = b_{t*-1} / (1 + eta (Lambda + lambda_{t*})) in FP64
+// Final step of the subproblem: d = b_{t*-1} / (1 + eta (Lambda + lambda_{t*})) in FP64, per instance
 template <typename T>
 __global__ __launch_bounds__(EW_NT) void k_final_d(Geo g, Prm p, const c2<T> *__restrict__ b0, const c2<T> *__restrict__ b1,
                                                    const SubState *st, double2 *__restrict__ d) {
-  const int t = st->final_step;
-  const c2<T> *src = ((t - 1) & 1) ? b1 : b0;
-  const double lamf = st->lam_final, eta = st->eta;
-  for (long h = (long)blockIdx.x * EW_NT + threadIdx.x; h < g.nh; h += (long)gridDim.x * EW_NT) {
+  const long total = (long)g.batch * g.nh;
+  for (long hh = (long)blockIdx.x * EW_NT + threadIdx.x; hh < total; hh += (long)gridDim.x * EW_NT) {
+    const int b = (int)(hh / g.nh);
+    const long h = hh - (long)b * g.nh;
+    const int t = st[b].final_step;
+    const c2<T> *src = ((t - 1) & 1) ? b1 : b0;
+    const double lamf = st[b].lam_final, eta = st[b].eta;
     int kl;
-    const double lam = lam_of(kk_at(g, (int)h, kl), p.xi[0], p.q[0]);
+    const double lam = lam_of(kk_at(g, (int)h, kl), p.xi[b], p.q[b]);
     const double s = (h == 0) ? 0.0 : 1.0 / (1.0 + eta * (lam + lamf));
-    const c2<T> v = src[h];
-    d[h] = double2{double(v.x) * s, double(v.y) * s};
+    const c2<T> v = src[hh];
+    d[hh] = double2{double(v.x) * s, double(v.y) * s};
   }
 }
 
@@ -1676,13 +1752,22 @@ __device__ __forceinline__ void block_sum2_all(double &a, double &b, double *scr
   __syncthreads();
 }
 
-template <typename T>
-__global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__restrict__ mom, int nmb,
+template <typename T, bool GEN>
+__global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__restrict__ mom, int nmb, long mstride,
                                                   const double *__restrict__ rpart, int rbpi,
                                                   const c2<T> *__restrict__ b0, const c2<T> *__restrict__ b1, int cpi,
                                                   SubState *st) {
   __shared__ double M[MOM_NV + 1];
   __shared__ double scratch[32];
+  // one workgroup per instance of the batch: its nmb update workgroups' moment
+  // partials at mom[j * mstride + inst * nmb + i], residual partials at
+  // rpart[inst * rbpi + i]
+  const int inst = blockIdx.x;
+  st += inst;
+  mom += (long)inst * nmb;
+  rpart += (long)inst * rbpi;
+  b0 += (long)inst * g.nh;
+  b1 += (long)inst * g.nh;
   // wave w sums values w and w + 16 (value MOM_NV: the residual partials)
   // over the workgroups of the update pass. Both values' loads, KU per lane
   // each (up to 64 KU workgroups), go out before the first add waits, and
@@ -1692,8 +1777,8 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int va = wv, vb = wv + WV;
   const bool hb = vb <= MOM_NV;  // uniform in the wave
-  const double *sa = va < MOM_NV ? mom + (long)va * nmb : rpart;
-  const double *sb = !hb ? sa : (vb < MOM_NV ? mom + (long)vb * nmb : rpart);  // !hb: loaded, not added
+  const double *sa = va < MOM_NV ? mom + (long)va * mstride : rpart;
+  const double *sb = !hb ? sa : (vb < MOM_NV ? mom + (long)vb * mstride : rpart);  // !hb: loaded, not added
   const int ca = va < MOM_NV ? nmb : rbpi, cb = !hb ? 0 : (vb < MOM_NV ? nmb : rbpi);
   double xa[KU], xb[KU];
 #pragma unroll
@@ -1763,22 +1848,24 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
   auto direct = [&](double lam, double &phi, double &dphi) {
     constexpr int DU = 4;
     const c2<T> *bt = (t & 1) ? b1 : b0;  // b_t, written by this step's update pass
-    const double xi = p.xi[0], q = p.q[0];
+    const double xi = p.xi[inst], q = p.q[inst];
     const double e2 = eta * lam;
     const int n0 = g.n0, nrow = n0 / 2 + 1;
     double a = 0.0, b = 0.0;
     for (int ml0 = 0; ml0 < cpi; ml0 += 2 * NW_NT) {
       int mls[2];
       bool okc[2];
-      double kkc[2], wc[2];
+      double kkc[2], wc[2], lin[2], linq[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int ml = ml0 + c * NW_NT + (int)threadIdx.x;
         okc[c] = ml < cpi;
         mls[c] = okc[c] ? ml : 0;
-        const ColInfo ci = col_info(g, mls[c]);
+        const ColInfo ci = col_info<GEN>(g, mls[c]);
         kkc[c] = ci.kkc;
         wc[c] = ci.w;
+        lin[c] = ci.lin;
+        linq[c] = ci.lin_nyq;
       }
       for (int e0 = 0; e0 < nrow; e0 += DU) {
         // entries k0 and -k0 (rows e and n0 - e of column ml, at e cpi + ml)
@@ -1793,7 +1880,7 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
             xm[c][u] = bt[(long)em * cpi + mls[c]];
           }
         }
-        double w[2][DU];
+        double wp[2][DU], wm[2][DU];
 #pragma unroll
         for (int u = 0; u < DU; ++u) {
           const int e = e0 + u < nrow ? e0 + u : nrow - 1;
@@ -1802,8 +1889,8 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
           for (int c = 0; c < 2; ++c) {
             const double px = double(xp[c][u].x), py = double(xp[c][u].y);
             const double mx = double(xm[c][u].x), my = double(xm[c][u].y);
-            const double sp = wc[c] * (px * px + py * py), sm = wc[c] * (mx * mx + my * my);
-            w[c][u] = paired ? sp + sm : sp;
+            wp[c][u] = wc[c] * (px * px + py * py);
+            wm[c][u] = paired ? wc[c] * (mx * mx + my * my) : 0.0;
           }
         }
 #pragma unroll
@@ -1814,10 +1901,21 @@ __global__ __launch_bounds__(NW_NT) void k_newton(Geo g, Prm p, const double *__
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             if (!okc[c] || (e == 0 && mls[c] == 0)) continue;
-            const double r = rcp64(1.0 + eta * lam_of(kk0 + kkc[c], xi, q) + e2);
-            const double r2i = r * r;
-            a = fma(w[c][u], r2i, a);
-            b = fma(w[c][u], r2i * r, b);
+            if constexpr (!GEN) {  // +-k0 share Lambda
+              const double w = wp[c][u] + wm[c][u];
+              const double r = rcp64(1.0 + eta * lam_of(kk0 + kkc[c], xi, q) + e2);
+              const double r2i = r * r;
+              a = fma(w, r2i, a);
+              b = fma(w, r2i * r, b);
+            } else {
+              const int em = (e == 0 || 2 * e == n0) ? e : n0 - e;
+              const double rp = rcp64(1.0 + eta * lam_of(kk_elem(g, e, kkc[c], lin[c], linq[c]), xi, q) + e2);
+              const double rm = rcp64(1.0 + eta * lam_of(kk_elem(g, em, kkc[c], lin[c], linq[c]), xi, q) + e2);
+              a = fma(wp[c][u], rp * rp, a);
+              b = fma(wp[c][u], rp * rp * rp, b);
+              a = fma(wm[c][u], rm * rm, a);
+              b = fma(wm[c][u], rm * rm * rm, b);
+            }
           }
         }
       }

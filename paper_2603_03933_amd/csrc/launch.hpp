@@ -91,8 +91,10 @@ template <typename T, int N> struct Impl {
       LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpPlain<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
                          (const C2 *)a.tw, op);
   }
-  static void cols_inv_scale_d(const PassArgs &a) {
-    lbk::OpInvScaleD<T> op{};
+  // the ops below come in two forms: orthorhombic (|Bk|^2 without cross
+  // terms, the benchmark's) and general lattice; a.g.general picks one
+  template <bool GEN> static void cols_inv_scale_d_t(const PassArgs &a) {
+    lbk::OpInvScaleD<T, GEN> op{};
     op.g = a.g;
     op.p = a.p;
     op.b0 = (const C2 *)a.b0;
@@ -100,11 +102,15 @@ template <typename T, int N> struct Impl {
     op.out = (C2 *)a.out;
     op.st = a.st;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
-                       (const C2 *)a.tw, op);
+    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+              (const C2 *)a.tw, op);
   }
-  static void cols_fwd_update(const PassArgs &a) {
-    lbk::OpFwdUpdate<T> op{};
+  static void cols_inv_scale_d(const PassArgs &a) {
+    if (a.g.general) cols_inv_scale_d_t<true>(a);
+    else cols_inv_scale_d_t<false>(a);
+  }
+  template <bool GEN> static void cols_fwd_update_t(const PassArgs &a) {
+    lbk::OpFwdUpdate<T, GEN> op{};
     op.g = a.g;
     op.p = a.p;
     op.tmp = (const C2 *)a.in;
@@ -117,11 +123,15 @@ template <typename T, int N> struct Impl {
     op.inv_n = a.inv_n;
     op.cpi = a.cg.cpi;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
-                       (const C2 *)a.tw, op);
+    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T, GEN>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+              (const C2 *)a.tw, op);
   }
-  static void cols_fwd_hess(const PassArgs &a) {
-    lbk::OpFwdHess<T> op{};
+  static void cols_fwd_update(const PassArgs &a) {
+    if (a.g.general) cols_fwd_update_t<true>(a);
+    else cols_fwd_update_t<false>(a);
+  }
+  template <bool GEN> static void cols_fwd_hess_t(const PassArgs &a) {
+    lbk::OpFwdHess<T, GEN> op{};
     op.g = a.g;
     op.p = a.p;
     op.tmp = (const C2 *)a.in;
@@ -129,12 +139,20 @@ template <typename T, int N> struct Impl {
     op.out = (C2 *)a.out;
     op.inv_n = a.inv_n;
     op.shift = a.shift;
-    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdHess<T>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
-                       (const C2 *)a.tw, op);
+    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdHess<T, GEN>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
+              (const C2 *)a.tw, op);
+  }
+  static void cols_fwd_hess(const PassArgs &a) {
+    if (a.g.general) cols_fwd_hess_t<true>(a);
+    else cols_fwd_hess_t<false>(a);
   }
   static void cols_fwd_mul_inv(const PassArgs &a) {
-    LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
-                       (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc);
+    if (a.g.general)
+      LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N, true>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
+                (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc);
+    else
+      LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N, false>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
+                (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc);
   }
   static void rows_r2c(const PassArgs &a, int mode) {
     if (mode == 1)
@@ -193,7 +211,7 @@ template <typename T, int N> struct Impl {
   static constexpr bool SUB2D = lbk::PlaneCfg<T, N>::fits && lbk::Sub2dCfg<T, N>::fits;
   static void sub2d(const PassArgs &a) {
     if constexpr (SUB2D)
-      LB_LAUNCH((lbk::k_sub2d<T, N>), dim3(1), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, a.g, a.p, (const C2 *)a.tw,
+      LB_LAUNCH((lbk::k_sub2d<T, N>), dim3(a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, a.g, a.p, (const C2 *)a.tw,
                 (C2 *)a.b0, (C2 *)a.b1, (const C2 *)a.gh, (const T *)a.gp, a.st);
   }
 

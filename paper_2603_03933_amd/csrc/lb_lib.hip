@@ -149,6 +149,10 @@ struct lb_plan {
   hipStream_t own = nullptr;  // private stream for captured launch sequences (created on first use)
   int plane_nt = -1;          // autotuned plane-pass variant (index into plane_inner_nt), -1: built-in choice
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
+  // general Bravais lattice (lb_plan_set_lattice): the reciprocal metric
+  // G = B^T B by axis slot (0 leading, 1 middle, 2 last); unused when 0
+  int general = 0;
+  double G[3][3] = {};
   double *mom = nullptr;  // moment partials of the update pass, MOM_NV x its blocks
   // FP64 spectral buffers (batch * nh complex each; SP holds 2 * batch)
   double2 *SP = nullptr, *GH = nullptr, *SH = nullptr, *W64 = nullptr;
@@ -358,6 +362,61 @@ extern "C" int lb_plan_destroy(lb_plan *P) {
   return LB_OK;
 }
 
+extern "C" int lb_plan_set_lattice(lb_plan *P, const double *A) {
+  if (!P) return fail(LB_ERR_ARG, "null plan");
+  const int d = P->dim;
+  const int slot_of[3] = {0, d == 3 ? 1 : 2, 2};  // grid axis -> slot
+  if (!A) {  // back to the grid's box
+    P->general = 0;
+    const int axis_of[3] = {0, d == 3 ? 1 : -1, d - 1};
+    for (int s = 0; s < 3; ++s)
+      if (axis_of[s] >= 0) P->ax[s].L = P->grid.box[axis_of[s]];
+    return LB_OK;
+  }
+  for (int i = 0; i < d * d; ++i)
+    if (!std::isfinite(A[i])) return fail(LB_ERR_ARG, "non-finite lattice matrix");
+  bool diag = true;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      if (i != j && A[i * d + j] != 0.0) diag = false;
+  if (diag) {  // orthorhombic: the box path, bit for bit
+    for (int a = 0; a < d; ++a)
+      if (!(A[a * d + a] > 0.0)) return fail(LB_ERR_ARG, "lattice vectors must be nonzero");
+    P->general = 0;
+    for (int a = 0; a < d; ++a) P->ax[slot_of[a]].L = A[a * d + a];
+    return LB_OK;
+  }
+  // reciprocal metric G = B^T B = 4 pi^2 (A^T A)^-1 (A B^T = 2 pi I)
+  long double M[3][3] = {}, Inv[3][3] = {};
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      for (int k = 0; k < d; ++k) M[i][j] += (long double)A[k * d + i] * (long double)A[k * d + j];
+  long double det;
+  if (d == 2) {
+    det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    if (!(std::fabs((double)det) > 0.0)) return fail(LB_ERR_ARG, "singular lattice matrix");
+    Inv[0][0] = M[1][1] / det;
+    Inv[1][1] = M[0][0] / det;
+    Inv[0][1] = Inv[1][0] = -M[0][1] / det;
+  } else {
+    det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+          M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+    if (!(std::fabs((double)det) > 0.0)) return fail(LB_ERR_ARG, "singular lattice matrix");
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+        Inv[i][j] = (M[i1][j1] * M[i2][j2] - M[i1][j2] * M[i2][j1]) / det;
+      }
+  }
+  const long double fp2 = 4.0L * 3.141592653589793238462643383279502884L * 3.141592653589793238462643383279502884L;
+  for (int s = 0; s < 3; ++s)
+    for (int t = 0; t < 3; ++t) P->G[s][t] = 0.0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) P->G[slot_of[i]][slot_of[j]] = (double)(fp2 * Inv[i][j]);
+  P->general = 1;
+  return LB_OK;
+}
+
 extern "C" int lb_plan_set_stream(lb_plan *P, void *stream) {
   if (!P) return fail(LB_ERR_ARG, "null plan");
   P->stream = (hipStream_t)stream;
@@ -461,7 +520,7 @@ extern "C" int lb_plan_create(lb_plan **out, const lb_grid *g, int batch, int pr
     if ((rc = dalloc(P, &P->gp32, Np))) return cleanup(rc);
   }
   if ((rc = dalloc(P, &P->gp64, Np)) || (rc = dalloc(P, &P->sphys, Np)) || (rc = dalloc(P, &P->ptrial, Np)) ||
-      (rc = dalloc(P, &P->mom, (long)lbk::MOM_NV * bpi_col0(P))))
+      (rc = dalloc(P, &P->mom, (long)lbk::MOM_NV * bpi_col0(P) * batch)))
     return cleanup(rc);
   const long mb = std::max({bpi_pairs(P), bpi_rows(P), bpi_col0(P), P->dim == 3 ? bpi_col1(P) : 1L, bpi_ew(P)});
   P->partial_len = 8 * mb * batch + 64;
@@ -502,9 +561,21 @@ static Geo geo(const lb_plan *P, int batch) {
   g.N = P->N;
   g.nh = P->nh;
   g.batch = batch;
-  g.c0 = 2.0 * M_PI / P->ax[0].L;
-  g.c1 = 2.0 * M_PI / P->ax[1].L;
-  g.cl = 2.0 * M_PI / P->ax[2].L;
+  if (!P->general) {
+    g.c0 = 2.0 * M_PI / P->ax[0].L;
+    g.c1 = 2.0 * M_PI / P->ax[1].L;
+    g.cl = 2.0 * M_PI / P->ax[2].L;
+    g.x01 = g.x0l = g.x1l = 0.0;
+    g.general = 0;
+  } else {
+    g.c0 = std::sqrt(P->G[0][0]);
+    g.c1 = P->dim == 3 ? std::sqrt(P->G[1][1]) : 2.0 * M_PI;
+    g.cl = std::sqrt(P->G[2][2]);
+    g.x01 = 2.0 * P->G[0][1];
+    g.x0l = 2.0 * P->G[0][2];
+    g.x1l = 2.0 * P->G[1][2];
+    g.general = 1;
+  }
   return g;
 }
 
@@ -1012,7 +1083,9 @@ static void plane_pass(lb_plan *P, const NFuncs *f1, const PassArgs &a) {
 }
 
 // spectral Hessian-vector product in FP64: out = Lambda x + P F_N(Gamma' F_N^{-1} x) + shift x
-static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out, double shift) {
+static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out, double shift,
+                        const double *gp = nullptr) {
+  if (!gp) gp = P->gp64;
   PassArgs c0 = args_col(P, LB_FP64, 1, p, 0);
   c0.in = x;
   c0.out = P->W64;
@@ -1024,7 +1097,7 @@ static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out
   if (f1 && f1->plane_inner && P->n1 == P->nl) {
     PassArgs pl = args_col(P, LB_FP64, 1, p, 1);
     pl.out = P->W64;
-    pl.gp = P->gp64;
+    pl.gp = gp;
     KT kt_(P, "plane_inner");
     plane_pass(P, f1, pl);
   } else {
@@ -1037,7 +1110,7 @@ static void hess_spec64(lb_plan *P, const Prm &p, const double2 *x, double2 *out
     }
     PassArgs r = args_rows(P, LB_FP64, 1, p, true);
     r.out = P->W64;
-    r.gp = P->gp64;
+    r.gp = gp;
     {
       KT kt_(P, "rows_inner");
       F(P, 2, LB_FP64)->rows_inner(r);
@@ -1070,14 +1143,22 @@ struct SubOut {
   int iters = 0, newton = 0, newton_direct = 0, status = 0;
 };
 
-// One iteration of Algorithm 3 as a launch sequence. The kernels take only
-// the parity of the step (which b buffer and multiplier slot to use); the
-// Newton kernel reads the step number itself from SubState, so the same
-// two-step sequence serves every step pair and can be captured once.
-static void enqueue_step(lb_plan *P, const Prm &p, int t) {
+// One iteration of Algorithm 3 for the B instances at the front of the plan's
+// batch, as a launch sequence. The kernels take only the parity of the step
+// (which b buffer and multiplier slot to use); the Newton kernel reads the
+// step number itself from SubState, so the same two-step sequence serves
+// every step pair and can be captured once.
+template <typename T, bool GEN>
+static void launch_newton(lb_plan *P, const PassArgs &u, const Prm &p, int B) {
+  using C2 = lbfft::c2<T>;
+  LB_LAUNCH((lbk::k_newton<T, GEN>), dim3(B), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom,
+            u.cg.bpi, (long)u.cg.bpi * B, (const double *)P->partial, u.cg.bpi, (const C2 *)P->B0, (const C2 *)P->B1,
+            u.cg.cpi, P->st);
+}
+static void enqueue_step(lb_plan *P, const Prm &p, int t, int B = 1) {
   const int prec = P->prec;
   t &= 1;
-  PassArgs a = args_col(P, prec, 1, p, 0);
+  PassArgs a = args_col(P, prec, B, p, 0);
   a.step = t;
   a.b0 = P->B0;
   a.b1 = P->B1;
@@ -1090,7 +1171,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
   if (f1 && f1->plane_inner && P->n1 == P->nl) {
     // axis-1 inverse, rows with Gamma', axis-1 forward: one plane pass in LDS
-    PassArgs pl = args_col(P, prec, 1, p, 1);
+    PassArgs pl = args_col(P, prec, B, p, 1);
     pl.out = P->WT;
     pl.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
     pl.st = P->st;
@@ -1098,7 +1179,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
     plane_pass(P, f1, pl);
   } else {
     if (P->dim == 3) {
-      PassArgs c1 = args_col(P, prec, 1, p, 1);
+      PassArgs c1 = args_col(P, prec, B, p, 1);
       c1.in = P->WT;
       c1.out = P->WT;
       c1.st = P->st;
@@ -1107,7 +1188,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
         F(P, 1, prec)->cols_plain(c1, true);
       }
     }
-    PassArgs r = args_rows(P, prec, 1, p, true);
+    PassArgs r = args_rows(P, prec, B, p, true);
     r.out = P->WT;
     r.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
     r.st = P->st;
@@ -1116,7 +1197,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
       F(P, 2, prec)->rows_inner(r);
     }
     if (P->dim == 3) {
-      PassArgs c1 = args_col(P, prec, 1, p, 1);
+      PassArgs c1 = args_col(P, prec, B, p, 1);
       c1.in = P->WT;
       c1.out = P->WT;
       c1.st = P->st;
@@ -1126,7 +1207,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
       }
     }
   }
-  PassArgs u = args_col(P, prec, 1, p, 0);
+  PassArgs u = args_col(P, prec, B, p, 0);
   u.in = P->WT;
   u.b0 = P->B0;
   u.b1 = P->B1;
@@ -1142,75 +1223,70 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t) {
   }
   {
     KT kt_(P, "newton");
-    if (prec == LB_FP64)
-      LB_LAUNCH(lbk::k_newton<double>, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom,
-                u.cg.bpi, (const double *)P->partial, u.cg.bpi, (const double2 *)P->B0, (const double2 *)P->B1,
-                u.cg.cpi, P->st);
-    else
-      LB_LAUNCH(lbk::k_newton<float>, dim3(1), dim3(lbk::NW_NT), 0, P->stream, u.g, p, (const double *)P->mom,
-                u.cg.bpi, (const double *)P->partial, u.cg.bpi, (const float2 *)P->B0, (const float2 *)P->B1,
-                u.cg.cpi, P->st);
+    const bool gen = u.g.general != 0;
+    if (prec == LB_FP64) {
+      if (gen) launch_newton<double, true>(P, u, p, B);
+      else launch_newton<double, false>(P, u, p, B);
+    } else {
+      if (gen) launch_newton<float, true>(P, u, p, B);
+      else launch_newton<float, false>(P, u, p, B);
+    }
   }
 }
 
-// Runs Algorithm 3 with g_hat in GH/GHT and Gamma' in gp64/gp32; the initial
-// point is -r g/||g|| or d0_spec (FP64 spectral, nullable). Leaves d in SH.
-static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts &o, double gnorm,
-                          const double2 *d0_spec, SubOut *out) {
+// Runs Algorithm 3 for the B instances at the front of the batch (radius r[b],
+// step size eta[b], ||g_b|| = gnorm[b]) with g_hat in GH/GHT and Gamma' in
+// gp64/gp32; the initial point is -r g/||g|| or d0_spec (FP64 spectral,
+// nullable, B = 1 only). Leaves d in SH; out[b] per instance. The launches
+// continue until every instance's stop test or cap has ended it (a stopped
+// instance's passes compute but store nothing).
+static int run_subproblem(lb_plan *P, const Prm &p, int B, const double *r, const lb_sub_opts &o, const double *eta,
+                          const double *gnorm, const double2 *d0_spec, SubOut *out) {
   const int prec = P->prec;
-  const long nb = std::min<long>(cdiv(P->nh, lbk::EW_NT), 4096);
-  const Geo g1 = geo(P, 1);
-  if (d0_spec) {
-    if (prec == LB_FP64)
-      {
-        KT kt_(P, "init_b");
-        LB_LAUNCH((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
-                           o.eta, (double2 *)P->B1);
-      }
-    else
-      {
-        KT kt_(P, "init_b");
-        LB_LAUNCH((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, d0_spec, 1.0,
-                           o.eta, (float2 *)P->B1);
-      }
-  } else {
-    if (prec == LB_FP64)
-      {
-        KT kt_(P, "init_b");
-        LB_LAUNCH((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
-                           (const double2 *)P->GH, -r / gnorm, o.eta, (double2 *)P->B1);
-      }
-    else
-      {
-        KT kt_(P, "init_b");
-        LB_LAUNCH((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
-                           (const double2 *)P->GH, -r / gnorm, o.eta, (float2 *)P->B1);
-      }
+  const long nb = std::min<long>(cdiv((long)B * P->nh, lbk::EW_NT), 4096);
+  const Geo gB = geo(P, B);
+  lbk::InitCoef ic{};
+  for (int b = 0; b < B; ++b) {
+    ic.coef[b] = d0_spec ? 1.0 : -r[b] / gnorm[b];
+    ic.eta[b] = eta[b];
   }
-  SubState s{};
-  s.lam[0] = 0.0;
-  s.lam[1] = 0.0;
-  s.eta = o.eta;
-  s.r2 = r * r;
-  s.tol = std::max(o.eps_sub, o.eps_sub_rel * gnorm);
-  s.newton_rtol = o.newton_rtol;
-  s.newton_steptol = o.newton_steptol;
-  s.step = 0;
-  s.done = 0;
-  s.max_inner = o.max_inner;
-  s.max_newton = o.max_newton;
-  s.newton_phi = o.newton_phi;
-  s.newton_direct_only = o.newton_direct;
+  const void *src = d0_spec ? (const void *)d0_spec : (const void *)P->GH;
+  if (prec == LB_FP64) {
+    KT kt_(P, "init_b");
+    LB_LAUNCH((lbk::k_init_b<double, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, gB, p, (const double2 *)src,
+              ic, (double2 *)P->B1);
+  } else {
+    KT kt_(P, "init_b");
+    LB_LAUNCH((lbk::k_init_b<float, double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, gB, p, (const double2 *)src,
+              ic, (float2 *)P->B1);
+  }
   LB_HIP(hipStreamSynchronize(P->stream));  // the pinned mirror may still feed an earlier copy
-  *P->st_h = s;
-  LB_HIP(hipMemcpyAsync(P->st, P->st_h, sizeof(SubState), hipMemcpyHostToDevice, P->stream));
+  for (int b = 0; b < B; ++b) {
+    SubState s{};
+    s.lam[0] = 0.0;
+    s.lam[1] = 0.0;
+    s.eta = eta[b];
+    s.r2 = r[b] * r[b];
+    s.tol = std::max(o.eps_sub, o.eps_sub_rel * gnorm[b]);
+    s.newton_rtol = o.newton_rtol;
+    s.newton_steptol = o.newton_steptol;
+    s.step = 0;
+    s.done = 0;
+    s.max_inner = o.max_inner;
+    s.max_newton = o.max_newton;
+    s.newton_phi = o.newton_phi;
+    s.newton_direct_only = o.newton_direct;
+    P->st_h[b] = s;
+  }
+  LB_HIP(hipMemcpyAsync(P->st, P->st_h, sizeof(SubState) * B, hipMemcpyHostToDevice, P->stream));
   const int chunk = std::max(1, o.poll_every);
   long launched = 0;
   const long max_steps = (long)o.max_inner + 1;
   const NFuncs *f0 = F(P, 0, prec);
   if (o.single_workgroup && P->dim == 2 && P->n0 == P->nl && f0->sub2d) {
-    // square 2D grid that fits one workgroup: every iteration in one launch
-    PassArgs a = args_col(P, prec, 1, p, 0);
+    // square 2D grid that fits one workgroup: every iteration in one launch,
+    // one workgroup per instance
+    PassArgs a = args_col(P, prec, B, p, 0);
     a.b0 = P->B0;
     a.b1 = P->B1;
     a.gh = P->GHT;
@@ -1221,7 +1297,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
       f0->sub2d(a);
     }
     LB_TRY(check_launch("subproblem (one workgroup)"));
-    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
+    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState) * B, hipMemcpyDeviceToHost, P->stream));
     LB_HIP(hipStreamSynchronize(P->stream));
     launched = max_steps;
   }
@@ -1252,8 +1328,8 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal);
     if (ce == hipSuccess) {
-      enqueue_step(P, p, 0);
-      enqueue_step(P, p, 1);
+      enqueue_step(P, p, 0, B);
+      enqueue_step(P, p, 1, B);
       ce = hipStreamEndCapture(P->stream, &graph);
     }
     if (ce == hipSuccess) {
@@ -1265,6 +1341,11 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
   // timings of launches the last stop-flag read has seen complete: read while
   // the GPU runs the next chunk, not while it waits for it
   size_t timed_done = 0;
+  auto all_done = [&]() {
+    for (int b = 0; b < B; ++b)
+      if (!P->st_h[b].done) return false;
+    return true;
+  };
   while (launched < max_steps) {
     const int n = (int)std::min<long>(chunk, max_steps - launched);
     if (gexec) {
@@ -1274,7 +1355,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
       }
       launched += n + (n & 1);
     } else {
-      for (int i = 0; i < n; ++i) enqueue_step(P, p, (int)(launched + i));
+      for (int i = 0; i < n; ++i) enqueue_step(P, p, (int)(launched + i), B);
       launched += n;
     }
     LB_TRY(check_launch("subproblem step"));
@@ -1282,38 +1363,39 @@ static int run_subproblem(lb_plan *P, const Prm &p, double r, const lb_sub_opts 
       timing_flush(P, timed_done);
       timed_done = 0;
     }
-    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState), hipMemcpyDeviceToHost, P->stream));
+    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState) * B, hipMemcpyDeviceToHost, P->stream));
     LB_HIP(hipStreamSynchronize(P->stream));
     timed_done = P->timing.pending.size();
-    if (P->st_h->done) break;
+    if (all_done()) break;
   }
   // the loop ended with a synchronisation of the stream it ran on, so the
   // caller's stream may go on
   P->stream = user;
-  const SubState &f = *P->st_h;
-  if (!f.done) return fail(LB_ERR_HIP, "subproblem loop ended without a stop decision");
-  if (f.nonfinite) return fail(LB_ERR_NONFINITE, "non-finite residual in the subproblem");
-  if (prec == LB_FP64)
-    {
-      KT kt_(P, "final_d");
-      LB_LAUNCH((lbk::k_final_d<double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p,
-                         (const double2 *)P->B0, (const double2 *)P->B1, (const SubState *)P->st, P->SH);
-    }
-  else
-    {
-      KT kt_(P, "final_d");
-      LB_LAUNCH((lbk::k_final_d<float>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, g1, p, (const float2 *)P->B0,
-                         (const float2 *)P->B1, (const SubState *)P->st, P->SH);
-    }
-  double dd = 0.0;
-  LB_TRY(spec_dot_host(P, p, P->SH, P->SH, &dd));
-  out->lam = f.lam_final;
-  out->resid = f.resid;
-  out->dnorm = std::sqrt(std::max(dd, 0.0));
-  out->iters = f.final_step;
-  out->newton = f.newton_total;
-  out->newton_direct = f.newton_direct;
-  out->status = (f.done == 1) ? LB_OK : LB_NOT_CONVERGED;
+  for (int b = 0; b < B; ++b) {
+    if (!P->st_h[b].done) return fail(LB_ERR_HIP, "subproblem loop ended without a stop decision");
+    if (P->st_h[b].nonfinite) return fail(LB_ERR_NONFINITE, "non-finite residual in the subproblem");
+  }
+  if (prec == LB_FP64) {
+    KT kt_(P, "final_d");
+    LB_LAUNCH((lbk::k_final_d<double>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, gB, p, (const double2 *)P->B0,
+              (const double2 *)P->B1, (const SubState *)P->st, P->SH);
+  } else {
+    KT kt_(P, "final_d");
+    LB_LAUNCH((lbk::k_final_d<float>), dim3(nb), dim3(lbk::EW_NT), 0, P->stream, gB, p, (const float2 *)P->B0,
+              (const float2 *)P->B1, (const SubState *)P->st, P->SH);
+  }
+  spec_reduce<double, 0>(P, B, p, P->SH, P->SH, P->sums);
+  LB_TRY(read_sums(P, P->sums, B));
+  for (int b = 0; b < B; ++b) {
+    const SubState &f = P->st_h[b];
+    out[b].lam = f.lam_final;
+    out[b].resid = f.resid;
+    out[b].dnorm = std::sqrt(std::max(P->sums_h[b], 0.0));
+    out[b].iters = f.final_step;
+    out[b].newton = f.newton_total;
+    out[b].newton_direct = f.newton_direct;
+    out[b].status = (f.done == 1) ? LB_OK : LB_NOT_CONVERGED;
+  }
   return 0;
 }
 
@@ -1405,7 +1487,7 @@ extern "C" int lb_tr_subproblem(lb_plan *P, const lb_params *params, const doubl
     d0s = P->X;
   }
   SubOut so;
-  LB_TRY(run_subproblem(P, p, radius, o, gnorm, d0s, &so));
+  LB_TRY(run_subproblem(P, p, 1, &radius, o, &o.eta, &gnorm, d0s, &so));
   inv_c2r(P, LB_FP64, 1, p, P->SH, P->W64, d_out, 0, nullptr, nullptr);
   LB_TRY(check_launch("lb_tr_subproblem"));
   LB_HIP(hipStreamSynchronize(P->stream));
@@ -1430,11 +1512,16 @@ static void prec_scale(lb_plan *P, const Prm &p, const double2 *x, double c, dou
 // spans the stiff range of the spectrum (z = M r lives in SP, free here);
 // pc = 0 is plain CG.
 // ---------------------------------------------------------------------------
-static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int maxiter, double pc, int *iters) {
+static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int maxiter, double pc, int *iters,
+                      int inst = 0) {
+  // instance `inst` of the batch: its g_hat and Gamma' (p holds its parameters
+  // in entry 0); the CG vectors live in the first instance's workspace
+  const double2 *GHi = P->GH + (long)inst * P->nh;
+  const double *gpi = P->gp64 + (long)inst * P->N;
   const long n = P->nh;
   double2 *Z = pc > 0 ? P->SP : P->R;
-  lincomb64(P, n, 0.0, P->GH, 0.0, P->GH, P->X);   // x = 0
-  lincomb64(P, n, -1.0, P->GH, 0.0, P->GH, P->R);  // r = -g
+  lincomb64(P, n, 0.0, GHi, 0.0, GHi, P->X);   // x = 0
+  lincomb64(P, n, -1.0, GHi, 0.0, GHi, P->R);  // r = -g
   if (pc > 0) prec_scale(P, p, P->R, shift + pc, Z, 0);
   lincomb64(P, n, 1.0, Z, 0.0, Z, P->Pv);  // p = z
   double rr, rz;
@@ -1444,7 +1531,7 @@ static int cg_shifted(lb_plan *P, const Prm &p, double shift, double rtol, int m
   const double bn = std::sqrt(rr);
   int it = 0;
   while (it < maxiter && std::sqrt(rr) > rtol * bn) {
-    hess_spec64(P, p, P->Pv, P->AP, shift);
+    hess_spec64(P, p, P->Pv, P->AP, shift, gpi);
     double pap;
     LB_TRY(spec_dot_host(P, p, P->Pv, P->AP, &pap));
     if (!(pap > 0)) return fail(LB_ERR_NONFINITE, "CG met a non-positive curvature; H + shift I is not positive definite");
@@ -1677,19 +1764,6 @@ extern "C" int lb_lanczos_min(lb_plan *P, const lb_params *params, const double 
 struct EG {
   double E, gnorm, gninf, gpmax;
 };
-static int energy_grad_host(lb_plan *P, const Prm &p, const double *psi, EG *eg) {
-  energy_grad_core(P, 1, p, psi);
-  LB_TRY(check_launch("energy"));
-  LB_TRY(read_sums(P, P->sums, 40));
-  const double *s = P->sums_h;
-  eg->E = s[32] + s[0] / (double)P->N;
-  eg->gnorm = std::sqrt(std::max(s[33], 0.0));
-  eg->gninf = s[34];
-  eg->gpmax = s[1];
-  if (!std::isfinite(eg->E) || !std::isfinite(eg->gnorm)) return fail(LB_ERR_NONFINITE, "non-finite energy or gradient");
-  return 0;
-}
-
 // energy only at psi + s (s in sphys), for the direct ratio numerator; leaves
 // the current iterate's g_hat and Gamma' untouched
 static int energy_at_trial(lb_plan *P, const Prm &p, const double *psi, double *E) {
@@ -1734,13 +1808,7 @@ static int energy_at_trial(lb_plan *P, const Prm &p, const double *psi, double *
   return 0;
 }
 
-extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi, const lb_tr_opts *opts,
-                                lb_tr_info *info) {
-  if (!P || !psi || !info) return fail(LB_ERR_ARG, "null argument");
-  if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_imex_tr_solve needs a plan with batch 1");
-  lb_tr_opts o;
-  if (opts) o = *opts;
-  else lb_tr_opts_default(&o);
+static int check_tr_opts(const lb_tr_opts &o) {
   LB_TRY(check_sub_opts(o.sub));
   if (!(o.theta > 0 && o.theta < 1) || !(o.gamma_c > 0 && o.gamma_c < 1) || !(o.gamma_e > 1) || !(o.gamma_lambda > 1) ||
       !(o.mu_lo > 0 && o.mu_lo <= o.mu_hi) || !(o.mu0 >= o.mu_lo) || !(o.r0 > 0 && o.r0 <= o.nu0) || !(o.eps > 0))
@@ -1748,146 +1816,341 @@ extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi
   if (o.hard_case && (o.hard_lanczos_steps < 1 || o.hard_lanczos_steps > 1000 || !(o.hard_tol >= 0)))
     return fail(LB_ERR_ARG, "bad hard-case options");
   if (!(o.cg_precond_shift >= 0) || !std::isfinite(o.cg_precond_shift)) return fail(LB_ERR_ARG, "bad cg_precond_shift");
-  Prm p;
-  LB_TRY(pack_params(P, params, 1, &p));
-  std::memset(info, 0, sizeof(*info));
-  double r = o.r0, nu = o.nu0, mu = o.mu0;
-  double rho_prev = 0.0;
-  bool have_prev = false;
-  EG eg;
-  LB_TRY(energy_grad_host(P, p, psi, &eg));
+  return 0;
+}
+
+// Prm whose entry 0 is entry s of q (one instance's view)
+static Prm prm_one(const Prm &q, int s) {
+  Prm p{};
+  p.tau[0] = q.tau[s];
+  p.gamma[0] = q.gamma[s];
+  p.xi[0] = q.xi[s];
+  p.q[0] = q.q[s];
+  return p;
+}
+
+// Algorithm 2 (CONTRACT) for instance `inst` of the batch, whose g_j and
+// Gamma'(psi_j) are in GH / gp64 (p: its parameters in entry 0): the new radius.
+static int contract_radius(lb_plan *P, const Prm &p, int inst, const lb_tr_opts &o, double lam, double sn, double gnorm,
+                           double *r_out, int *cg_total) {
+  int it = 0;
+  double xx;
+  if (lam < o.mu_lo * sn) {
+    const double lam_hat = lam + std::sqrt(o.mu_lo * gnorm);
+    LB_TRY(cg_shifted(P, p, lam_hat, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it, inst));
+    *cg_total += it;
+    LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
+    double snew = std::sqrt(xx);
+    if (lam_hat / snew > o.mu_hi) {
+      // lambda~ / ||s(lambda~)|| increases with lambda~: bisect on (lambda_j, lambda_hat)
+      double lo = lam, hi = lam_hat;
+      for (int k = 0; k < 200; ++k) {
+        const double mid = 0.5 * (lo + hi);
+        LB_TRY(cg_shifted(P, p, mid, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it, inst));
+        *cg_total += it;
+        LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
+        snew = std::sqrt(xx);
+        const double ratio = mid / snew;
+        if (ratio < o.mu_lo) lo = mid;
+        else if (ratio > o.mu_hi) hi = mid;
+        else break;
+      }
+    }
+    *r_out = snew;
+    return 0;
+  }
+  const double lt = o.gamma_lambda * lam;
+  LB_TRY(cg_shifted(P, p, lt, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it, inst));
+  *cg_total += it;
+  LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
+  const double snew = std::sqrt(xx);
+  if (snew >= o.gamma_c * sn) *r_out = snew;
+  else *r_out = o.contract_else_old_step ? o.gamma_c * sn : o.gamma_c * snew;
+  return 0;
+}
+
+// real rows of instances: y[s] += coef[s] x[s] (coef by value, one per instance)
+struct RowCoef {
+  double c[lbk::MAXB];
+};
+namespace lbk {
+__global__ __launch_bounds__(EW_NT) void k_axpy_rows(long N, int B, RowCoef a, const double *__restrict__ x, double *y) {
+  const long total = N * B;
+  for (long i = (long)blockIdx.x * EW_NT + threadIdx.x; i < total; i += (long)gridDim.x * EW_NT) {
+    const double c = a.c[i / N];
+    if (c != 0.0) y[i] += c * x[i];
+  }
+}
+}  // namespace lbk
+
+// swap the fields of batch slots s and t (device rows of N doubles; sphys is scratch)
+static int swap_rows(lb_plan *P, double *psi, int s, int t) {
+  if (s == t) return 0;
+  const size_t bytes = sizeof(double) * P->N;
+  double *a = psi + (long)s * P->N, *b = psi + (long)t * P->N, *tmp = P->sphys;
+  LB_HIP(hipMemcpyAsync(tmp, a, bytes, hipMemcpyDeviceToDevice, P->stream));
+  LB_HIP(hipMemcpyAsync(a, b, bytes, hipMemcpyDeviceToDevice, P->stream));
+  LB_HIP(hipMemcpyAsync(b, tmp, bytes, hipMemcpyDeviceToDevice, P->stream));
+  return 0;
+}
+
+// Algorithms 1 and 2 (host-driven outer loop) for the plan's `batch`
+// instances together: every pass of every outer iteration is one launch for
+// all instances still iterating (they are kept at the front of the batch;
+// an instance that has converged or failed is swapped to the back and its
+// field restored to its slot at the end). The scalar logic runs per instance
+// exactly as for one instance, so each result equals its one-instance solve
+// bit for bit. Nearly hard subproblems and the direct ratio numerator are
+// supported for a batch of one.
+static int solve_core(lb_plan *P, const lb_params *params, double *psi, const lb_tr_opts &o, lb_tr_info *infos,
+                      int *status) {
+  const int B = P->batch;
+  LB_TRY(check_tr_opts(o));
+  if (B > 1 && (o.hard_case || !o.rho_taylor))
+    return fail(LB_ERR_UNSUPPORTED, "batched solves take the Taylor ratio numerator and no hard-case starts");
+  Prm pall;
+  LB_TRY(pack_params(P, params, B, &pall));
+  struct Inst {
+    double r, nu, mu, rho_prev = 0.0;
+    bool have_prev = false;
+    EG eg{};
+  };
+  std::vector<Inst> S(B);
+  std::vector<int> slot_inst(B);  // instance held by each batch slot
+  for (int b = 0; b < B; ++b) {
+    S[b].r = o.r0;
+    S[b].nu = o.nu0;
+    S[b].mu = o.mu0;
+    slot_inst[b] = b;
+    std::memset(&infos[b], 0, sizeof(lb_tr_info));
+    status[b] = LB_NOT_CONVERGED;
+  }
+  int nA = B;  // active slots [0, nA)
+  Prm pA = pall;
+  auto rebuild_params = [&]() {
+    for (int s2 = 0; s2 < nA; ++s2) {
+      const int i2 = slot_inst[s2];
+      pA.tau[s2] = pall.tau[i2];
+      pA.gamma[s2] = pall.gamma[i2];
+      pA.xi[s2] = pall.xi[i2];
+      pA.q[s2] = pall.q[i2];
+    }
+  };
+  auto finish = [&](int slot, int st_code, int outer) {
+    const int i2 = slot_inst[slot];
+    lb_tr_info &inf = infos[i2];
+    inf.energy = S[i2].eg.E;
+    inf.gnorm = S[i2].eg.gnorm;
+    inf.gnorm_inf = S[i2].eg.gninf;
+    inf.outer = outer;
+    inf.status = st_code;
+    status[i2] = st_code;
+  };
+  // energy and gradient of the active slots, per instance
+  auto energy_grads = [&]() -> int {
+    energy_grad_core(P, nA, pA, psi);
+    LB_TRY(check_launch("energy"));
+    LB_TRY(read_sums(P, P->sums, 64));
+    const double *sm = P->sums_h;
+    for (int s2 = 0; s2 < nA; ++s2) {
+      EG &eg = S[slot_inst[s2]].eg;
+      eg.E = sm[32 + 3 * s2] + sm[2 * s2] / (double)P->N;
+      eg.gnorm = std::sqrt(std::max(sm[33 + 3 * s2], 0.0));
+      eg.gninf = sm[34 + 3 * s2];
+      eg.gpmax = sm[2 * s2 + 1];
+    }
+    return 0;
+  };
+  // moves the slots flagged in `out` to the back of the active range
+  std::vector<char> out(B, 0);
+  auto compact = [&]() -> int {
+    int s2 = 0;
+    while (s2 < nA) {
+      if (!out[s2]) {
+        ++s2;
+        continue;
+      }
+      const int last = nA - 1;
+      LB_TRY(swap_rows(P, psi, s2, last));
+      std::swap(slot_inst[s2], slot_inst[last]);
+      std::swap(out[s2], out[last]);
+      out[last] = 0;
+      --nA;
+    }
+    rebuild_params();
+    return 0;
+  };
+  int first_err = 0;
+  std::string first_msg;
   int j = 0;
-  int status = LB_NOT_CONVERGED;
-  for (; j < o.max_outer; ++j) {
-    const double gtest = o.grad_norm_inf ? eg.gninf : eg.gnorm;
-    if (gtest < o.eps) {
-      status = LB_OK;
-      break;
+  bool eg_fresh = false;
+  for (; j < o.max_outer && nA > 0; ++j) {
+    // g_j of every active instance; those within the tolerance (or non-finite) leave
+    if (!eg_fresh) LB_TRY(energy_grads());
+    eg_fresh = false;
+    bool any = false;
+    for (int s2 = 0; s2 < nA; ++s2) {
+      const EG &eg = S[slot_inst[s2]].eg;
+      if (!std::isfinite(eg.E) || !std::isfinite(eg.gnorm)) {
+        finish(s2, LB_ERR_NONFINITE, j);
+        if (!first_err) {
+          first_err = LB_ERR_NONFINITE;
+          first_msg = "non-finite energy or gradient";
+        }
+        out[s2] = any = true;
+      } else if ((o.grad_norm_inf ? eg.gninf : eg.gnorm) < o.eps) {
+        finish(s2, LB_OK, j);
+        out[s2] = any = true;
+      }
+    }
+    if (any) {
+      LB_TRY(compact());
+      if (nA == 0) break;
+      LB_TRY(energy_grads());  // the compacted slots' g_j and Gamma'
+    }
+    std::vector<double> r(nA), eta(nA), gn(nA);
+    for (int s2 = 0; s2 < nA; ++s2) {
+      const Inst &I = S[slot_inst[s2]];
+      r[s2] = I.r;
+      eta[s2] = o.eta_safe && I.eg.gpmax > 0 ? std::min(o.eta, 0.9 / I.eg.gpmax) : o.eta;
+      gn[s2] = I.eg.gnorm;
     }
     lb_sub_opts so = o.sub;
-    so.eta = o.eta_safe && eg.gpmax > 0 ? std::min(o.eta, 0.9 / eg.gpmax) : o.eta;
-    // nearly hard subproblem (Remark on the hard case): sigma_1 < 0 and
-    // |<xi, g>| <= hard_tol -> start Algorithm 3 from a random point of the ball
+    so.eta = eta[0];
+    // nearly hard subproblem (Remark on the hard case; one instance): sigma_1 < 0
+    // and |<xi, g>| <= hard_tol -> start Algorithm 3 from a random point of the ball
     const double2 *d0_spec = nullptr;
     if (o.hard_case) {
       LB_TRY(ball_point(P, 1.0, o.seed, 2ull * (unsigned long long)j + 1ull, P->sphys));
-      fwd_r2c(P, LB_FP64, 1, p, P->sphys, P->R, 1);
+      fwd_r2c(P, LB_FP64, 1, pA, P->sphys, P->R, 1);
       lincomb64(P, P->nh, 1.0, P->R, 0.0, P->R, P->SH);
       double sig, res, g1;
-      LB_TRY(lanczos_core(P, p, P->SH, o.hard_lanczos_steps, o.hard_precond_shift, &sig, &res, P->SH));
-      LB_TRY(spec_dot_host(P, p, P->GH, P->SH, &g1));
+      LB_TRY(lanczos_core(P, pA, P->SH, o.hard_lanczos_steps, o.hard_precond_shift, &sig, &res, P->SH));
+      LB_TRY(spec_dot_host(P, pA, P->GH, P->SH, &g1));
       if (sig < 0.0 && std::fabs(g1) <= o.hard_tol) {
-        LB_TRY(ball_point(P, r, o.seed, 2ull * (unsigned long long)j, P->sphys));
-        fwd_r2c(P, LB_FP64, 1, p, P->sphys, P->R, 1);
+        LB_TRY(ball_point(P, r[0], o.seed, 2ull * (unsigned long long)j, P->sphys));
+        fwd_r2c(P, LB_FP64, 1, pA, P->sphys, P->R, 1);
         d0_spec = P->R;
-        info->hard_cases++;
+        infos[slot_inst[0]].hard_cases++;
       }
       if (o.verbose) std::fprintf(stderr, "[lb] j=%d sigma1~%.6e g1=%.3e%s\n", j, sig, g1, d0_spec ? " hard" : "");
     }
-    SubOut sub;
-    LB_TRY(run_subproblem(P, p, r, so, eg.gnorm, d0_spec, &sub));
-    info->inner_total += sub.iters;
-    if (sub.status != LB_OK) info->sub_capped++;
-    info->newton_total += sub.newton;
-    info->newton_direct += sub.newton_direct;
-    const double lam = sub.lam, sn = sub.dnorm;
-    if (!(sn > 0)) return fail(LB_ERR_NONFINITE, "zero trial step");
-    if (j > 0 && have_prev && rho_prev < o.theta) mu = std::max(mu, lam / sn);
-    double dE;
+    std::vector<SubOut> sub(nA);
+    LB_TRY(run_subproblem(P, pA, nA, r.data(), so, eta.data(), gn.data(), d0_spec, sub.data()));
+    // the ratio numerator E(v) - E(v + s) of every active instance
+    std::vector<double> dE(nA);
     if (o.rho_taylor) {
-      double gs, quad;
-      LB_TRY(spec_dot_host(P, p, P->GH, P->SH, &gs));
-      LB_TRY(spec_lam_host(P, p, P->SH, &quad));
-      inv_c2r(P, LB_FP64, 1, p, P->SH, P->W64, P->sphys, 2, psi, P->partial);
-      finalize(P, P->partial, (int)bpi_pairs(P), 1, 0u, 1, P->sums);
-      LB_TRY(read_sums(P, P->sums, 1));
-      const double pw = P->sums_h[0] / (double)P->N;
-      dE = -(gs + 0.5 * quad + pw);
-    } else {
-      inv_c2r(P, LB_FP64, 1, p, P->SH, P->W64, P->sphys, 0, nullptr, nullptr);
+      spec_reduce<double, 0>(P, nA, pA, P->GH, P->SH, P->sums);
+      spec_reduce<double, 1>(P, nA, pA, P->SH, P->SH, P->sums + 16);
+      inv_c2r(P, LB_FP64, nA, pA, P->SH, P->W64, P->sphys, 2, psi, P->partial);
+      finalize(P, P->partial, (int)bpi_pairs(P), 1, 0u, nA, P->sums + 32);
+      LB_TRY(read_sums(P, P->sums, 48));
+      for (int s2 = 0; s2 < nA; ++s2) {
+        const double gs = P->sums_h[s2], quad = P->sums_h[16 + s2], pw = P->sums_h[32 + s2] / (double)P->N;
+        dE[s2] = -(gs + 0.5 * quad + pw);
+      }
+    } else {  // one instance
+      inv_c2r(P, LB_FP64, 1, pA, P->SH, P->W64, P->sphys, 0, nullptr, nullptr);
       double Et;
-      LB_TRY(energy_at_trial(P, p, psi, &Et));
-      dE = eg.E - Et;
+      LB_TRY(energy_at_trial(P, pA, psi, &Et));
+      dE[0] = S[slot_inst[0]].eg.E - Et;
     }
-    const double rho = dE / (sn * sn * sn);
-    const char *branch;
-    const bool on_nu = std::fabs(sn - nu) <= o.nu_tol * nu;
-    // lambda <= mu ||s|| tested as lambda / ||s|| <= mu: after a contraction mu
-    // was just raised to lambda / ||s||, and the sides must then compare equal
-    // exactly, not by the rounding of (lambda / ||s||) ||s||
-    if (rho >= o.theta && (lam / sn <= mu || on_nu)) {
-      const long nb = std::min<long>(cdiv(P->N, lbk::EW_NT), 4096);
-      {
-        KT kt_(P, "axpy_real");
-        LB_LAUNCH(lbk::k_axpy_real, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, 1.0, (const double *)P->sphys,
-                           psi);
-      }
-      nu = std::max(nu, o.gamma_e * sn);
-      r = std::min(nu, std::max(r, o.gamma_e * sn));
-      mu = std::max(mu, lam / sn);
-      LB_TRY(energy_grad_host(P, p, psi, &eg));
-      info->accepted++;
-      branch = "accept";
-    } else if (rho < o.theta) {
-      // Algorithm 2 (CONTRACT); needs Gamma'(psi_j) and g_j, still in gp64 / GH
-      int it = 0;
-      if (lam < o.mu_lo * sn) {
-        const double lam_hat = lam + std::sqrt(o.mu_lo * eg.gnorm);
-        LB_TRY(cg_shifted(P, p, lam_hat, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it));
-        info->cg_total += it;
-        double xx;
-        LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
-        double snew = std::sqrt(xx);
-        if (lam_hat / snew <= o.mu_hi) {
-          r = snew;
-        } else {
-          double lo = lam, hi = lam_hat;
-          for (int k = 0; k < 200; ++k) {
-            const double mid = 0.5 * (lo + hi);
-            LB_TRY(cg_shifted(P, p, mid, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it));
-            info->cg_total += it;
-            LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
-            snew = std::sqrt(xx);
-            const double ratio = mid / snew;
-            if (ratio < o.mu_lo) lo = mid;
-            else if (ratio > o.mu_hi) hi = mid;
-            else break;
-          }
-          r = snew;
-        }
+    RowCoef acc{};
+    bool any_accept = false;
+    for (int s2 = 0; s2 < nA; ++s2) {
+      const int i2 = slot_inst[s2];
+      Inst &I = S[i2];
+      lb_tr_info &inf = infos[i2];
+      const SubOut &su = sub[s2];
+      inf.inner_total += su.iters;
+      inf.newton_total += su.newton;
+      inf.newton_direct += su.newton_direct;
+      if (su.status != LB_OK) inf.sub_capped++;
+      const double lam = su.lam, sn = su.dnorm;
+      if (!(sn > 0)) return fail(LB_ERR_NONFINITE, "zero trial step");
+      if (j > 0 && I.have_prev && I.rho_prev < o.theta) I.mu = std::max(I.mu, lam / sn);
+      const double rho = dE[s2] / (sn * sn * sn);
+      const char *branch;
+      const bool on_nu = std::fabs(sn - I.nu) <= o.nu_tol * I.nu;
+      // lambda <= mu ||s|| tested as lambda / ||s|| <= mu: after a contraction mu
+      // was just raised to lambda / ||s||, and the sides must then compare equal
+      // exactly, not by the rounding of (lambda / ||s||) ||s||
+      if (rho >= o.theta && (lam / sn <= I.mu || on_nu)) {
+        acc.c[s2] = 1.0;
+        any_accept = true;
+        I.nu = std::max(I.nu, o.gamma_e * sn);
+        I.r = std::min(I.nu, std::max(I.r, o.gamma_e * sn));
+        I.mu = std::max(I.mu, lam / sn);
+        inf.accepted++;
+        branch = "accept";
+      } else if (rho < o.theta) {
+        // Algorithm 2 (CONTRACT); needs Gamma'(psi_j) and g_j of this instance
+        LB_TRY(contract_radius(P, prm_one(pA, s2), s2, o, lam, sn, I.eg.gnorm, &I.r, &inf.cg_total));
+        inf.contracted++;
+        branch = "contract";
       } else {
-        const double lt = o.gamma_lambda * lam;
-        LB_TRY(cg_shifted(P, p, lt, o.cg_rtol, o.cg_maxiter, o.cg_precond_shift, &it));
-        info->cg_total += it;
-        double xx;
-        LB_TRY(spec_dot_host(P, p, P->X, P->X, &xx));
-        const double snew = std::sqrt(xx);
-        if (snew >= o.gamma_c * sn) r = snew;
-        else r = o.contract_else_old_step ? o.gamma_c * sn : o.gamma_c * snew;
+        I.r = std::min(I.nu, lam / I.mu);
+        inf.expanded++;
+        branch = "expand";
       }
-      info->contracted++;
-      branch = "contract";
-    } else {
-      r = std::min(nu, lam / mu);
-      info->expanded++;
-      branch = "expand";
+      if (o.verbose)
+        std::fprintf(stderr,
+                     "[lb] i=%d j=%d E=%.15e |g|=%.3e |g|inf=%.3e r=%.3e nu=%.3e mu=%.3e lam=%.6e |s|=%.3e rho=%.6e "
+                     "eta=%.4f inner=%d resid=%.2e %s\n",
+                     i2, j, I.eg.E, I.eg.gnorm, I.eg.gninf, I.r, I.nu, I.mu, lam, sn, rho, eta[s2], su.iters, su.resid,
+                     branch);
+      I.rho_prev = rho;
+      I.have_prev = true;
     }
-    if (o.verbose)
-      std::fprintf(stderr,
-                   "[lb] j=%d E=%.15e |g|=%.3e |g|inf=%.3e r=%.3e nu=%.3e mu=%.3e lam=%.6e |s|=%.3e rho=%.6e eta=%.4f "
-                   "inner=%d resid=%.2e %s\n",
-                   j, eg.E, eg.gnorm, eg.gninf, r, nu, mu, lam, sn, rho, so.eta, sub.iters, sub.resid, branch);
-    rho_prev = rho;
-    have_prev = true;
+    if (any_accept) {
+      // v_{j+1} = v_j + s_j for the accepted instances (s_j in sphys)
+      const long nb = std::min<long>(cdiv((long)nA * P->N, lbk::EW_NT), 4096);
+      KT kt_(P, "axpy_real");
+      LB_LAUNCH(lbk::k_axpy_rows, dim3(nb), dim3(lbk::EW_NT), 0, P->stream, P->N, nA, acc, (const double *)P->sphys,
+                psi);
+    } else if (!o.hard_case) {
+      eg_fresh = true;  // no field moved: g_j and Gamma' still hold
+    }
+  }
+  // instances still iterating at the cap: E and g at their last iterate
+  if (nA > 0 && !eg_fresh) LB_TRY(energy_grads());
+  for (int s2 = 0; s2 < nA; ++s2) finish(s2, LB_NOT_CONVERGED, j);
+  // every field back to its own slot
+  for (int s2 = 0; s2 < B; ++s2) {
+    while (slot_inst[s2] != s2) {
+      const int t = slot_inst[s2];
+      LB_TRY(swap_rows(P, psi, s2, t));
+      std::swap(slot_inst[s2], slot_inst[t]);
+    }
   }
   LB_TRY(check_launch("lb_imex_tr_solve"));
   LB_HIP(hipStreamSynchronize(P->stream));
-  info->energy = eg.E;
-  info->gnorm = eg.gnorm;
-  info->gnorm_inf = eg.gninf;
-  info->outer = j;
-  info->status = status;
-  return status;
+  if (first_err) return fail(first_err, first_msg);
+  return 0;
+}
+
+extern "C" int lb_imex_tr_solve(lb_plan *P, const lb_params *params, double *psi, const lb_tr_opts *opts,
+                                lb_tr_info *info) {
+  if (!P || !psi || !info) return fail(LB_ERR_ARG, "null argument");
+  if (P->batch != 1) return fail(LB_ERR_MISMATCH, "lb_imex_tr_solve needs a plan with batch 1");
+  lb_tr_opts o;
+  if (opts) o = *opts;
+  else lb_tr_opts_default(&o);
+  int st = 0;
+  LB_TRY(solve_core(P, params, psi, o, info, &st));
+  return st;
+}
+
+extern "C" int lb_imex_tr_solve_batch(lb_plan *P, const lb_params *params, double *psi, const lb_tr_opts *opts,
+                                      lb_tr_info *infos, int *status) {
+  if (!P || !params || !psi || !infos || !status) return fail(LB_ERR_ARG, "null argument");
+  lb_tr_opts o;
+  if (opts) o = *opts;
+  else lb_tr_opts_default(&o);
+  LB_TRY(solve_core(P, params, psi, o, infos, status));
+  for (int b = 0; b < P->batch; ++b)
+    if (status[b] < 0) return status[b];
+  return LB_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1904,12 +2167,17 @@ extern "C" int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *par
   if (count == 0) return LB_OK;
   if (workers < 1) return fail(LB_ERR_ARG, "workers must be >= 1");
   workers = std::min(workers, count);
+  // job i solves the plans[i]->batch instances starting at instance off[i]
+  std::vector<long> off(count + 1, 0);
   for (int i = 0; i < count; ++i) {
     if (!plans[i] || !psi[i]) return fail(LB_ERR_ARG, "null plan or field");
-    if (plans[i]->batch != 1) return fail(LB_ERR_MISMATCH, "lb_imex_tr_solve_many needs plans with batch 1");
     for (int k = 0; k < i; ++k)
       if (plans[k] == plans[i]) return fail(LB_ERR_ARG, "a plan appears in two jobs");
+    off[i + 1] = off[i] + plans[i]->batch;
   }
+  lb_tr_opts o;
+  if (opts) o = *opts;
+  else lb_tr_opts_default(&o);
   // the fields are ready on each plan's stream: the workers wait for that point
   std::vector<hipEvent_t> ready(count, nullptr);
   for (int i = 0; i < count; ++i) {
@@ -1918,27 +2186,33 @@ extern "C" int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *par
   }
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return plans[a]->N > plans[b]->N; });
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return plans[a]->N * plans[a]->batch > plans[b]->N * plans[b]->batch; });
   std::atomic<int> next{0};
   std::vector<std::string> errs(count);
+  std::vector<int> job_rc(count, LB_OK);
   auto work = [&]() {
     hipStream_t ws = nullptr;
     if (hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = nullptr;
     for (int q = next.fetch_add(1); q < count; q = next.fetch_add(1)) {
       const int i = order[q];
       lb_plan *P = plans[i];
-      std::memset(&infos[i], 0, sizeof(lb_tr_info));
       if (!ws) {
-        status[i] = LB_ERR_HIP;
+        job_rc[i] = LB_ERR_HIP;
         errs[i] = "hipStreamCreate failed";
+        for (long k = off[i]; k < off[i + 1]; ++k) status[k] = LB_ERR_HIP;
         continue;
       }
       const hipStream_t orig = P->stream;
       int rc = hipStreamWaitEvent(ws, ready[i], 0) == hipSuccess ? LB_OK : LB_ERR_HIP;
       if (rc == LB_OK) {
         P->stream = ws;
-        rc = lb_imex_tr_solve(P, &params[i], psi[i], opts, &infos[i]);
-        if (rc < 0) errs[i] = g_last_error;
+        rc = solve_core(P, &params[off[i]], psi[i], o, &infos[off[i]], &status[off[i]]);
+        if (rc < 0) {
+          errs[i] = g_last_error;
+          for (long k = off[i]; k < off[i + 1]; ++k)
+            if (status[k] >= 0) status[k] = rc;
+        }
         // later work on the plan's own stream sees the result
         hipEvent_t done;
         if (hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess) {
@@ -1949,8 +2223,9 @@ extern "C" int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *par
         P->stream = orig;
       } else {
         errs[i] = "hipStreamWaitEvent failed";
+        for (long k = off[i]; k < off[i + 1]; ++k) status[k] = rc;
       }
-      status[i] = rc;
+      job_rc[i] = rc;
     }
     if (ws) {
       (void)hipStreamSynchronize(ws);
@@ -1962,8 +2237,11 @@ extern "C" int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *par
   work();
   for (auto &t : pool) t.join();
   for (int i = 0; i < count; ++i) (void)hipEventDestroy(ready[i]);
-  for (int i = 0; i < count; ++i)
-    if (status[i] < 0) return fail(status[i], "job " + std::to_string(i) + ": " + errs[i]);
+  for (int i = 0; i < count; ++i) {
+    if (job_rc[i] < 0) return fail(job_rc[i], "job " + std::to_string(i) + ": " + errs[i]);
+    for (long k = off[i]; k < off[i + 1]; ++k)
+      if (status[k] < 0) return fail(status[k], "job " + std::to_string(i) + ": an instance failed");
+  }
   return LB_OK;
 }
 

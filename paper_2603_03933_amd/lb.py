@@ -132,6 +132,7 @@ _SIGS = {
     "lb_plan_create": (_I, [C.POINTER(_P), C.POINTER(LbGrid), _I, _I, _P]),
     "lb_plan_destroy": (_I, [_P]),
     "lb_plan_set_stream": (_I, [_P, _P]),
+    "lb_plan_set_lattice": (_I, [_P, C.POINTER(_D)]),
     "lb_plan_workspace_bytes": (C.c_size_t, [_P]),
     "lb_plan_set_timing": (_I, [_P, _I, C.c_char_p]),
     "lb_plan_set_timing_sampled": (_I, [_P, _I, C.c_char_p, _I]),
@@ -150,6 +151,7 @@ _SIGS = {
     "lb_lanczos_min": (_I, [_P, C.POINTER(LbParams), _P, _P, _I, _D, C.POINTER(_D), C.POINTER(_D), _P]),
     "lb_random_ball": (_I, [_P, _D, C.c_ulonglong, C.c_ulonglong, _P]),
     "lb_imex_tr_solve_many": (_I, [C.POINTER(_P), C.POINTER(LbParams), C.POINTER(_P), _I, C.POINTER(LbTrOpts), _I, C.POINTER(LbTrInfo), C.POINTER(_I)]),
+    "lb_imex_tr_solve_batch": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo), C.POINTER(_I)]),
     "lb_plan_autotune": (_I, [_P, C.POINTER(LbParams), _P, _I, C.POINTER(_I)]),
     "lb_plan_set_plane_threads": (_I, [_P, _I]),
 }
@@ -266,6 +268,17 @@ class Plan:
     def _sync_stream(self):
         _check(lib().lb_plan_set_stream(self._h, _stream()))
 
+    def lb_plan_set_lattice(self, A=None):
+        """General Bravais lattice: A (dim x dim, column a = cell vector along grid axis a); None: the box."""
+        if A is None:
+            _check(lib().lb_plan_set_lattice(self._h, None))
+            return
+        rows = [[float(x) for x in r] for r in A]
+        if len(rows) != self.dim or any(len(r) != self.dim for r in rows):
+            raise ValueError(f"lattice matrix must be {self.dim} x {self.dim}")
+        arr = (_D * (self.dim * self.dim))(*[x for r in rows for x in r])
+        _check(lib().lb_plan_set_lattice(self._h, arr))
+
     @property
     def workspace_bytes(self) -> int:
         return int(lib().lb_plan_workspace_bytes(self._h))
@@ -379,6 +392,19 @@ class Plan:
         rc = _check(lib().lb_imex_tr_solve(self._h, _params_array(params, 1), _ptr(psi, self.N, "psi"), C.byref(opts) if opts is not None else None, C.byref(info)))
         return info, rc
 
+    def lb_imex_tr_solve_batch(self, params, psi, opts: Optional[LbTrOpts] = None):
+        """Solves of the plan's batch instances together; psi [batch, *grid] updated; returns [(info, status)]."""
+        self._sync_stream()
+        B = self.batch
+        infos = (LbTrInfo * B)()
+        st = (_I * B)()
+        lib().lb_imex_tr_solve_batch(self._h, _params_array(params, B), _ptr(psi, self.N * B, "psi"),
+                                     C.byref(opts) if opts is not None else None, infos, st)
+        for k in range(B):
+            if st[k] < 0:
+                raise LBError(st[k], lib().lb_last_error().decode())
+        return [(infos[k], st[k]) for k in range(B)]
+
     def lb_shifted_solve(self, params, psi, grad, shift, rtol=1e-12, maxiter=1000, out=None, precond_shift=0.0):
         self._sync_stream()
         if out is None:
@@ -404,21 +430,25 @@ class Plan:
 
 
 def lb_imex_tr_solve_many(plans, params, psis, opts: Optional[LbTrOpts] = None, workers: int = 4):
-    """Concurrent independent solves (one per plan); returns [(info, rc)]."""
+    """Concurrent independent jobs (one per plan, each solving its plan's batch);
+    params: one entry per instance, job after job; returns [(info, rc)] per instance."""
     n = len(plans)
-    if len(params) != n or len(psis) != n:
-        raise ValueError("plans, params and psis must have the same length")
+    if len(psis) != n:
+        raise ValueError("plans and psis must have the same length")
+    total = sum(pl.batch for pl in plans)
+    if len(params) != total:
+        raise ValueError(f"need {total} parameter sets (one per instance)")
     for pl in plans:
         pl._sync_stream()
     hp = (_P * n)(*[pl._h for pl in plans])
-    pa = (LbParams * n)()
+    pa = (LbParams * total)()
     for i, p in enumerate(params):
         pa[i] = LbParams(float(p.tau), float(p.gamma), float(getattr(p, "xi", 1.0)), float(getattr(p, "q", 1.0)))
-    ps = (_P * n)(*[_ptr(x, pl.N, "psi") for x, pl in zip(psis, plans)])
-    infos = (LbTrInfo * n)()
-    st = (_I * n)()
+    ps = (_P * n)(*[_ptr(x, pl.N * pl.batch, "psi") for x, pl in zip(psis, plans)])
+    infos = (LbTrInfo * total)()
+    st = (_I * total)()
     _check(lib().lb_imex_tr_solve_many(hp, pa, ps, n, C.byref(opts) if opts is not None else None, int(workers), infos, st))
-    return [(infos[i], st[i]) for i in range(n)]
+    return [(infos[i], st[i]) for i in range(total)]
 
 
 def lb_hessvec_noalloc(n: Sequence[int], box: Sequence[float], params, psi, v, out=None, project=True):

@@ -1,6 +1,7 @@
-"""GPU: concurrent independent solves (lb_imex_tr_solve_many) give the same
-results, bit for bit, as the same solves run one at a time, and the oracle's
-endpoint; misuse is rejected."""
+"""GPU: concurrent independent solves (lb_imex_tr_solve_many) and batched
+solves (lb_imex_tr_solve_batch: several instances of one grid in one launch
+per pass) give the same results, bit for bit, as the same solves run one at a
+time, and the oracle's endpoint; misuse is rejected."""
 import math
 
 import numpy as np
@@ -49,12 +50,89 @@ def test_solve_many_matches_sequential_and_oracle():
     assert abs(res[0][0].energy - ref.energy) < 1e-10 * max(1.0, abs(ref.energy))
 
 
-def test_solve_many_rejects_shared_plan_and_batched_plans():
+def test_solve_many_rejects_shared_plan_and_mismatched_params():
     shape, box, prm, psi0 = _jobs()[0]
     plan = lb.Plan(shape, box)
     psis = [torch.from_numpy(psi0).to(DEV) for _ in range(2)]
     with pytest.raises(lb.LBError):
         lb.lb_imex_tr_solve_many([plan, plan], [prm, prm], psis)
     bplan = lb.Plan(shape, box, batch=2)
-    with pytest.raises(lb.LBError):
-        lb.lb_imex_tr_solve_many([bplan], [prm], [torch.zeros(psi0.size, dtype=torch.float64, device=DEV)])
+    with pytest.raises(ValueError):  # a batch-2 plan needs two parameter sets
+        lb.lb_imex_tr_solve_many([bplan], [prm], [torch.zeros(2 * psi0.size, dtype=torch.float64, device=DEV)])
+
+
+# (grid, box, precision): the multi-kernel 2D path, the one-workgroup 2D path
+# (one workgroup per instance), the 3D plane path, a 3D grid with axis-1 and
+# row passes
+BATCH_CASES = [
+    ((48, 96), (6 * math.pi, 12 * math.pi), "fp64"),
+    ((48, 96), (6 * math.pi, 12 * math.pi), "fp32"),
+    ((32, 32), (4 * math.pi, 4 * math.pi), "fp64"),
+    ((32, 32, 32), (4 * math.sqrt(2) * math.pi,) * 3, "fp64"),
+    ((16, 24, 32), (2 * math.pi, 3 * math.pi, 4 * math.pi), "fp32"),
+]
+
+
+@pytest.mark.parametrize("shape,box,precision", BATCH_CASES)
+def test_batched_solve_equals_single_solves_bit_for_bit(shape, box, precision):
+    """Five instances ((tau, gamma) and noise per instance; they converge after
+    different numbers of outer iterations and leave the batch at different
+    times) solved in one batch against five single-instance solves: identical
+    fields, iteration counts and energies."""
+    print(f"batched solve {shape} {precision}", flush=True)
+    B = 5
+    prms = [lb.Params(-0.15 - 0.03 * k, 0.2 + 0.05 * k) for k in range(B)]
+    psi0 = np.stack([I.zero_mean_noise(shape, 0.1, 90 + k) for k in range(B)])
+    sub = {"max_inner": 3000, "poll_every": 16}
+    if precision == "fp32":
+        sub["eps_sub_rel"] = 1e-5
+    opts = lb.tr_opts(grad_norm_inf=0, eps=1e-8, max_outer=60, sub=sub)
+    single = []
+    p1 = lb.Plan(shape, box, precision=precision)
+    for k in range(B):
+        psi = torch.from_numpy(psi0[k]).to(DEV)
+        info, rc = p1.lb_imex_tr_solve(prms[k], psi, opts)
+        single.append((info, rc, psi.cpu().numpy()))
+    pb = lb.Plan(shape, box, batch=B, precision=precision)
+    psi = torch.from_numpy(psi0).to(DEV)
+    res = pb.lb_imex_tr_solve_batch(prms, psi, opts)
+    out = psi.cpu().numpy()
+    outers = []
+    for k, ((info, rc), (sinfo, src, spsi)) in enumerate(zip(res, single)):
+        outers.append(info.outer)
+        assert rc == src, k
+        assert (info.outer, info.inner_total, info.cg_total, info.accepted, info.contracted, info.sub_capped) == \
+            (sinfo.outer, sinfo.inner_total, sinfo.cg_total, sinfo.accepted, sinfo.contracted, sinfo.sub_capped), k
+        assert info.energy == sinfo.energy and info.gnorm == sinfo.gnorm, k
+        assert np.array_equal(out[k], spsi), k
+    print(f"  outer iterations per instance: {outers}")
+    # one endpoint against the oracle (FP64 plans)
+    if precision == "fp64":
+        m = O.Model(O.Grid(shape, box), prms[1].tau, prms[1].gamma)
+        ref = O.imex_tr_solve(m, psi0[1], O.TROpts(grad_norm="l2", eps=1e-8, max_outer=60, max_inner=3000))
+        if ref.converged and res[1][1] == lb.LB_OK:
+            assert abs(res[1][0].energy - ref.energy) < 1e-10 * max(1.0, abs(ref.energy))
+
+
+def test_solve_many_with_batched_plans():
+    """Jobs of batch-3 plans of two grid sizes through the worker pool equal the
+    same instances solved one at a time."""
+    opts = lb.tr_opts(grad_norm_inf=0, eps=1e-8, max_outer=60, sub={"max_inner": 3000})
+    jobs = [((32, 32), (4 * math.pi,) * 2), ((48, 48), (6 * math.pi,) * 2)]
+    plans, psis, prms, ref = [], [], [], []
+    for j, (shape, box) in enumerate(jobs):
+        p3 = [lb.Params(-0.1 - 0.05 * k, 0.25) for k in range(3)]
+        f = np.stack([I.zero_mean_noise(shape, 0.1, 100 + 10 * j + k) for k in range(3)])
+        plans.append(lb.Plan(shape, box, batch=3))
+        psis.append(torch.from_numpy(f).to(DEV))
+        prms += p3
+        p1 = lb.Plan(shape, box)
+        for k in range(3):
+            x = torch.from_numpy(f[k]).to(DEV)
+            info, rc = p1.lb_imex_tr_solve(p3[k], x, opts)
+            ref.append((info, rc, x.cpu().numpy()))
+    res = lb.lb_imex_tr_solve_many(plans, prms, psis, opts, workers=2)
+    outs = [x for ps in psis for x in ps.cpu().numpy()]
+    for (info, rc), (sinfo, src, sp), o in zip(res, ref, outs):
+        assert rc == src and info.outer == sinfo.outer and info.inner_total == sinfo.inner_total
+        assert info.energy == sinfo.energy and np.array_equal(o, sp)

@@ -76,6 +76,140 @@ def test_lambda_multiplier_values():
     assert abs(lam[4, 0] - 4.0 * (2.25 - 16.0) ** 2) < 1e-12
 
 
+def _hex_primitive(a=4 * math.pi / math.sqrt(3)):
+    """Primitive cell of the 2D hexagonal lattice: cell vectors (a, 0) and (a/2, a sqrt(3)/2)."""
+    return np.array([[a, a / 2], [0.0, a * math.sqrt(3) / 2]])
+
+
+def test_general_lattice_reduces_to_the_box():
+    n, box = (8, 12), (3.0, 5.0)
+    g1, g2 = O.Grid(n, box), O.Grid(n, lattice=np.diag(box))
+    assert np.allclose(g2.B, np.diag([2 * math.pi / 3.0, 2 * math.pi / 5.0]), rtol=1e-15)
+    assert np.max(np.abs(g1.kk - g2.kk)) < 1e-13 * np.max(g1.kk)
+    A = _hex_primitive()
+    g = O.Grid((8, 8), lattice=A)
+    assert np.allclose(A @ g.B.T, 2 * math.pi * np.eye(2), atol=1e-14)  # A B^T = 2 pi I (Section 2)
+
+
+def test_hexagonal_primitive_cell_closed_form():
+    """The hexagonal phase on its primitive (non-orthogonal) cell, side 4 pi / sqrt(3): the six
+    indices +-(1,0), +-(0,1), +-(1,1) have |Bk| = 1, so E(a) = 3 tau a^2 - 2 gamma a^3 + 15 a^4 / 4,
+    the same closed form as on the orthorhombic cell (4 pi, 4 pi / sqrt(3)) with twice the points."""
+    g = O.Grid((16, 16), lattice=_hex_primitive())
+    modes = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1)]
+    for k in modes:
+        assert abs(g.kk[k[0] % 16, k[1] % 16] - 1.0) < 1e-14
+    assert abs(g.kk[1, 15] - 3.0) < 1e-13  # (1, -1): |b1 - b2|^2 = 3
+    tau, gamma = -0.28, 0.32
+    m = O.Model(g, tau, gamma)
+    m_rect = O.Model(O.Grid((16, 12), (4 * math.pi, 4 * math.pi / math.sqrt(3))), tau, gamma)
+    for a in (0.1, 0.3, 0.7):
+        e = O.energy(m, I.cosine_modes(g.n, modes, a))
+        closed = 3 * tau * a * a - 2 * gamma * a**3 + 15 * a**4 / 4
+        assert abs(e - closed) < 1e-13 * max(1.0, abs(closed))
+        e_rect = O.energy(m_rect, I.cosine_modes(m_rect.grid.n, I.hex_2d_modes(1), a))
+        assert abs(e - e_rect) < 1e-13 * max(1.0, abs(closed))
+
+
+def test_hexagonal_solve_on_the_primitive_cell_equals_the_two_cell_box():
+    """The oracle's IMEX-TR solve of the hexagonal phase at (tau, gamma) =
+    (-0.28, 0.32) on its primitive cell (24 x 24 points) and on the
+    orthorhombic box holding two cells (24 x 16 points, the same point density)
+    reaches the same energy per volume, the paper's printed -8.02e-2."""
+    tau, gamma = -0.28, 0.32
+    m = O.Model(O.Grid((24, 24), lattice=_hex_primitive()), tau, gamma)
+    modes = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, -1)]
+    prim = O.imex_tr_solve(m, I.cosine_modes((24, 24), modes, 0.3), O.TROpts(grad_norm="l2", eps=1e-9, max_inner=3000))
+    rect = O.imex_tr_solve(O.Model(O.Grid((24, 16), (4 * math.pi, 4 * math.pi / math.sqrt(3))), tau, gamma),
+                           I.cosine_modes((24, 16), I.hex_2d_modes(1), 0.3), O.TROpts(grad_norm="l2", eps=1e-9, max_inner=3000))
+    assert prim.converged and rect.converged
+    assert abs(prim.energy - rect.energy) < 1e-10 * abs(rect.energy)
+    assert abs(prim.energy - (-8.02e-2)) <= 0.5e-4
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_equivalent_cells_give_the_same_energy(dim):
+    """Two cells of one lattice, A and A U (U unimodular), sample the same points
+    of a periodic field (x = A j/n and A U j'/n cover the same set): the mode of
+    index k in the first is index U^T k in the second, with the same |Bk|^2, and
+    a band-limited field has the same energy, gradient norm and Hessian product
+    norm in both descriptions."""
+    if dim == 2:
+        A = _hex_primitive(5.0)
+        U = np.array([[1, 1], [0, 1]])
+        n = (12, 12)
+    else:
+        A = np.array([[4.0, 1.0, 0.5], [0.0, 3.5, 0.8], [0.0, 0.0, 4.2]])
+        U = np.array([[1, 0, 1], [0, 1, -1], [0, 0, 1]])
+        n = (8, 8, 8)
+    g1, g2 = O.Grid(n, lattice=A), O.Grid(n, lattice=A @ U)
+    # band limit: the indices U^T k stay inside K_M (below Nyquist) on the second grid
+    band = 2 if dim == 2 else 1
+    ks = [k for k in itertools.product(range(-band, band + 1), repeat=dim) if any(k)]
+
+    def coefficients(seed):
+        r = np.random.default_rng(seed)
+        coef = {}
+        for k in ks:
+            if tuple(-c for c in k) in coef:
+                continue
+            z = complex(r.standard_normal(), r.standard_normal()) * 0.2
+            coef[k] = z
+            coef[tuple(-c for c in k)] = z.conjugate()
+        return coef
+
+    def field(coef, Ut):
+        h = np.zeros(n, dtype=complex)
+        for k, z in coef.items():
+            kk = tuple(int(c) % m for c, m in zip(Ut @ np.array(k), n))
+            h[kk] += z
+        return O.inv(h)
+
+    I_ = np.eye(dim, dtype=int)
+    c_psi, c_v = coefficients(3), coefficients(4)
+    psi1, psi2 = field(c_psi, I_), field(c_psi, U.T)
+    v1, v2 = field(c_v, I_), field(c_v, U.T)
+    for k in ks:
+        i1 = tuple(c % m for c, m in zip(k, n))
+        i2 = tuple(int(c) % m for c, m in zip(U.T @ np.array(k), n))
+        assert abs(g1.kk[i1] - g2.kk[i2]) < 1e-12 * max(1.0, g1.kk[i1])
+    m1, m2 = O.Model(g1, -0.2, 0.3), O.Model(g2, -0.2, 0.3)
+    e1, e2 = O.energy(m1, psi1), O.energy(m2, psi2)
+    assert abs(e1 - e2) < 1e-13 * max(1.0, abs(e1))
+    assert abs(O.norm(O.gradient(m1, psi1)) - O.norm(O.gradient(m2, psi2))) < 1e-12
+    # the products are pointwise on the same points, the band-limited v's interaction part agrees
+    h1 = O.norm(O.hessvec(m1, psi1, O.project(O.fwd(v1))))
+    h2 = O.norm(O.hessvec(m2, psi2, O.project(O.fwd(v2))))
+    assert abs(h1 - h2) < 1e-12 * h1
+    # a wrong reciprocal matrix (B instead of B^T in |Bk|^2) breaks the equality
+    Bw = g2.B.T
+    kk_w = O.kk_general(Bw, n, np.meshgrid(*g2.kidx, indexing="ij"))
+    bad = max(abs(g1.kk[tuple(c % m for c, m in zip(k, n))] - kk_w[tuple(int(c) % m for c, m in zip(U.T @ np.array(k), n))]) for k in ks)
+    assert bad > 1e-3
+
+
+def test_general_lattice_hessian_is_symmetric_and_real():
+    """With off-diagonal B the Nyquist entries' mean multiplier keeps the
+    interaction operator real and symmetric (dense matrix from the DFT)."""
+    A = np.array([[3.0, 0.9], [0.4, 2.5]])
+    g = O.Grid((6, 8), lattice=A)
+    m = O.Model(g, -0.2, 0.3)
+    N = g.N
+    L = np.zeros((N, N))
+    for j in range(N):
+        e = np.zeros(N)
+        e[j] = 1.0
+        h = np.fft.ifftn(g.kk.reshape(g.n) * 0 + (1.0 - g.kk) ** 2 * np.fft.fftn(e.reshape(g.n)))
+        assert np.max(np.abs(h.imag)) < 1e-12
+        L[:, j] = h.real.ravel()
+    assert np.max(np.abs(L - L.T)) < 1e-12 * np.max(np.abs(L))
+    psi = rand_field(g.n, 0.3, 8)
+    u, w = rand_field(g.n, 1.0, 9), rand_field(g.n, 1.0, 10)
+    Hu = O.inv(O.hessvec(m, psi, O.project(O.fwd(u))))
+    Hw = O.inv(O.hessvec(m, psi, O.project(O.fwd(w))))
+    assert abs(np.mean(Hu * w) - np.mean(u * Hw)) < 1e-13 * np.sqrt(np.mean(Hu**2) * np.mean(w**2))
+
+
 # ---------------------------------------------------------------------------
 # Closed forms: trial functions and the paper's printed energies
 # ---------------------------------------------------------------------------
@@ -198,6 +332,13 @@ def test_hard_case_strategy_reproduces_section_4_3():
     opts = O.TROpts(eps=1e-10, max_outer=400, max_inner=20000)
     det = O.imex_tr_solve(m, psi0, opts)
     assert det.converged and O.hessian_eigs(m, det.psi)[0] < -1e-3  # not an SP-II
+    # the lamellar start keeps every iterate a function of x alone (the gradient
+    # and Hessian products of such fields are too); in that subspace the
+    # deterministic solve ends at the psi = 0 saddle: E = 0 and sigma_1 = tau
+    # (H = Lambda + tau with the shell on the grid), not at the paper's BCC state
+    assert np.max(np.abs(det.psi - det.psi[:, :1, :1])) == 0.0
+    assert abs(det.energy) < 1e-15 and math.sqrt(np.mean(det.psi**2)) < 1e-8
+    assert abs(O.hessian_eigs(m, det.psi)[0] - gold["tau"]) < 1e-9  # Gamma' = tau - gamma psi + ..., psi ~ 1e-10
     log = []
     ran = O.imex_tr_solve(m, psi0, opts, d0_provider=O.hard_case_d0_provider(m, seed=1, tol=gold["hard_tol"], log=log))
     assert ran.converged and any(e["hard"] for e in log)

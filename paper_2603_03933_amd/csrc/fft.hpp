@@ -218,10 +218,18 @@ struct NoAux {};
 struct NoFetch {
   __device__ NoAux operator()(int) const { return NoAux{}; }
 };
+struct NoPre {
+  __device__ void operator()() const {}
+};
 
-template <typename T, int N, bool INV, int P = 0, int PLAN = 0, class LIdx, class Load, class Fetch, class Store>
+// pre() runs once, in the first pass after its loads are issued and before its
+// first barrier (callers use it to fill an LDS twiddle table that later passes
+// read through `tw`: the first pass reads no twiddles)
+template <typename T, int N, bool INV, int P = 0, int PLAN = 0, class LIdx, class Load, class Fetch, class Store,
+          class Pre = NoPre>
 __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &lidx, const c2<T> *__restrict__ tw,
-                                        const Load &load, const Fetch &fetch, const Store &store) {
+                                        const Load &load, const Fetch &fetch, const Store &store,
+                                        const Pre &pre = Pre{}) {
   using C = c2<T>;
   constexpr int NP = npass_p<PLAN>(N);
   constexpr int R = radix_p<PLAN>(N, P);
@@ -271,6 +279,7 @@ __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &li
         for (int r = 0; r < R; ++r) aux[s][r] = fetch(j + r * NB);
       }
     }
+    if constexpr (P == 0) pre();
     __syncthreads();  // all reads of the buffer finish before it is rewritten
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -292,6 +301,7 @@ __device__ __forceinline__ void fft_run(int t, int c, c2<T> *lds, const LIdx &li
       }
     }
   } else {
+    if constexpr (P == 0) pre();
     __syncthreads();  // all reads of the buffer finish before it is rewritten
 #pragma unroll
     for (int s = 0; s < S; ++s) {

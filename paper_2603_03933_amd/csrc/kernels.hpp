@@ -378,6 +378,31 @@ struct ColGeo {
   long inst;  // instance stride
 };
 
+// A twiddle table of N entries staged into LDS: load() reads it with a
+// kernel's first loads, one scalar (real or imaginary part) per thread, and
+// store() writes it to LDS before the first barrier (half the registers of
+// holding whole complex entries in N threads)
+template <typename T, int N, int NT> struct TwStage {
+  static constexpr int PER = (2 * N + NT - 1) / NT;
+  T v[PER];
+  __device__ __forceinline__ void load(const c2<T> *__restrict__ tw) {
+    const T *s = reinterpret_cast<const T *>(tw);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = threadIdx.x + u * NT;
+      v[u] = s[i < 2 * N ? i : 0];
+    }
+  }
+  __device__ __forceinline__ void store(c2<T> *twl) const {
+    T *d = reinterpret_cast<T *>(twl);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < 2 * N) d[i] = v[u];
+    }
+  }
+};
+
 // Ops are stateless: begin(b) returns per-workgroup state and column(...)
 // per-column state by value; fetch(...) returns what the final store needs
 // besides the transform output (loaded ahead of the last pass).
@@ -387,6 +412,11 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
   constexpr int CC = Cfg<N>::C;
   constexpr int NT = Cfg<N>::NT;
   __shared__ C lds[N * CC];
+  // the twiddle table in LDS: loaded with the first pass (which needs none),
+  // stored before its barrier, so later passes read it without a memory round trip
+  __shared__ C twl[N];
+  TwStage<T, N, NT> tv;
+  tv.load(tw);
   // a stopped subproblem's steps must not write; the flag is applied at the
   // stores, so that the data loads need not wait for it to arrive
   const int b = blockIdx.x / cg.bpi;
@@ -407,7 +437,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
   const auto cs = op.column(b, mls);
   double acc = 0.0;
   fft_run<T, N, INV>(
-      t, c, lds, [](int cc, int e) { return e * CC + cc; }, tw,
+      t, c, lds, [](int cc, int e) { return e * CC + cc; }, twl,
       [&](int e) -> C {
         if constexpr (Op::eager_loads) {
           const C v = op.load(bs, cs, base + e * cg.S, e);
@@ -421,6 +451,9 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
         double *sq = reinterpret_cast<double *>(lds) + e * CC + c;
         if (ok && !sk) op.store(bs, cs, base + e * cg.S, e, v, aux, acc, sq);
         else *sq = 0.0;
+      },
+      [&]() {
+        tv.store(twl);
       });
   if (!sk) op.template end<NT, N, CC>(bs, acc, reinterpret_cast<double *>(lds), b, lb, c);  // uniform
 }
@@ -692,6 +725,9 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   using C = c2<T>;
   constexpr int CC = Cfg<N>::C;
   __shared__ C lds[N * CC];
+  __shared__ C twl[N];  // the twiddle table, stored during the first pass
+  TwStage<T, N, Cfg<N>::NT> tv;
+  tv.load(tw);
   const int b = blockIdx.x / cg.bpi;
   const int lb = blockIdx.x - b * cg.bpi;
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
@@ -702,7 +738,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   const double xi = p.xi[b], q = p.q[b];
   auto lidx = [](int cc, int e) { return e * CC + cc; };
   fft_run<T, N, false>(
-      t, c, lds, lidx, tw,
+      t, c, lds, lidx, twl,
       [&](int e) -> C {
         const C v = data[base + e * cg.S];
         return ok ? v : C{T(0), T(0)};
@@ -712,10 +748,13 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
         double m = lam_of(kk, xi, q) * inv_n;
         if (!ok || (ci.dc && e == 0 && !keep_dc)) m = 0.0;
         lds[lidx(c, e)] = C{T(double(v.x) * m), T(double(v.y) * m)};
+      },
+      [&]() {
+        tv.store(twl);
       });
   __syncthreads();
   fft_run<T, N, true>(
-      t, c, lds, lidx, tw, [&](int e) -> C { return lds[lidx(c, e)]; }, NoFetch{},
+      t, c, lds, lidx, twl, [&](int e) -> C { return lds[lidx(c, e)]; }, NoFetch{},
       [&](int e, C v, NoAux) {
         if (ok) data[base + e * cg.S] = v;
       });
@@ -1075,18 +1114,24 @@ __device__ __forceinline__ void sk_lds_passes(c2<T> *buf, int fs, int es, const 
 template <int N> constexpr int plane_pr() { return N + 1; }
 
 // axis 1, inverse, first pass reading element (e, f) from load(f, e)
-template <typename T, int N, int NT, class Load>
-__device__ __forceinline__ void plane_cols_inv_load(c2<T> *L, const c2<T> *__restrict__ tw, const Load &load) {
+// (pre() runs after the first pass, before its barrier: the first pass reads
+// no twiddles, so an LDS twiddle table stored there serves the later passes)
+template <typename T, int N, int NT, class Load, class Pre = lbfft::NoPre>
+__device__ __forceinline__ void plane_cols_inv_load(c2<T> *L, const c2<T> *__restrict__ tw, const Load &load,
+                                                    const Pre &pre = Pre{}) {
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N);
   sk_pass<T, N, true, NT, NH, true, 0, false>(tw, load, [&](int f, int e, C v, int, int) { L[e * NH + f] = v; });
+  pre();
   __syncthreads();
   sk_lds_passes<T, N, true, NT, NH, true, 1, NP>(L, 1, NH, tw);
 }
 // ... from src (plane layout)
-template <typename T, int N, int NT>
-__device__ __forceinline__ void plane_cols_inv_from(c2<T> *L, const c2<T> *src, const c2<T> *__restrict__ tw) {
-  plane_cols_inv_load<T, N, NT>(L, tw, [&](int f, int e) -> c2<T> { return src[e * (N / 2 + 1) + f]; });
+template <typename T, int N, int NT, class Pre = lbfft::NoPre>
+__device__ __forceinline__ void plane_cols_inv_from(c2<T> *L, const c2<T> *src, const c2<T> *__restrict__ tw,
+                                                    const Pre &pre = Pre{}) {
+  plane_cols_inv_load<T, N, NT>(
+      L, tw, [&](int f, int e) -> c2<T> { return src[e * (N / 2 + 1) + f]; }, pre);
 }
 
 // rows, inverse: the first pass packs half rows 2p, 2p+1 into Z_p = A + i B;
@@ -1157,11 +1202,16 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   __shared__ C L[N * NH];
+  __shared__ C twl[N];  // the twiddle table, stored during the first pass (which reads none)
+  TwStage<T, N, NT> tv;
+  tv.load(tw);
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
   const bool sk = st && st[b].done;  // applied at the stores (the loads need not wait for it)
   C *plane = data + b * nh + (long)i0 * (N * NH);
   const T *g = gp + b * Np + (long)i0 * (N * N);
-  plane_cols_inv_from<T, N, NT>(L, plane, tw);
+  plane_cols_inv_from<T, N, NT>(L, plane, twl, [&]() {
+    tv.store(twl);
+  });
   __syncthreads();
   using LastS = PassShape<T, N, true, NT, NR, false, NP - 1>;
   T g0[LastS::K][LastS::R], g1[LastS::K][LastS::R];
@@ -1178,12 +1228,12 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
       }
     }
   }
-  plane_rows_inv<T, N, NT>(L, tw, [&](int f, int e, C v, int k, int r) {
+  plane_rows_inv<T, N, NT>(L, twl, [&](int f, int e, C v, int k, int r) {
     L[f * PR + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
   });
   __syncthreads();
-  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, tw);  // rows, forward
-  plane_cols_fwd_store<T, N, NT>(L, tw, [&](int f, int e, C v, int, int) {
+  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, twl);  // rows, forward
+  plane_cols_fwd_store<T, N, NT>(L, twl, [&](int f, int e, C v, int, int) {
     if (!sk) plane[e * NH + f] = v;
   });
 }
@@ -1199,9 +1249,13 @@ __global__ __launch_bounds__(NT) void k_plane_fwd_phys(int n0, long nh, long Np,
   using C = c2<T>;
   constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
   __shared__ C L[N * NH];
+  __shared__ C twl[N];  // the twiddle table, stored before the first pass
+  TwStage<T, N, NT> tv;
+  tv.load(tw);
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
   const long off = b * Np + (long)i0 * (N * N);
   const double tau = p.tau[b], gam = p.gamma[b];
+  __shared__ double red[NT / 64];  // wave sums of the mean partial
   double acc = 0.0;
   for (int i = threadIdx.x; i < NR * N; i += NT) {
     const int q = i / N, x = i - q * N;
@@ -1213,12 +1267,18 @@ __global__ __launch_bounds__(NT) void k_plane_fwd_phys(int n0, long nh, long Np,
     }
     L[q * PR + x] = C{T(va), T(vb)};
   }
+  tv.store(twl);
+  if (partial) {  // the wave sums now; the passes' barriers order them before thread 0 adds them
+    const double ws = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
+  }
   __syncthreads();
-  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, tw);
-  plane_cols_fwd_to<T, N, NT>(L, out + b * nh + (long)i0 * (N * NH), tw);
-  if (partial) {
-    const double s = block_sum<NT>(acc, reinterpret_cast<double *>(L));
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  sk_lds_passes<T, N, false, NT, NR, true, 0, NP>(L, PR, 1, twl);
+  plane_cols_fwd_to<T, N, NT>(L, out + b * nh + (long)i0 * (N * NH), twl);
+  if (partial && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    partial[blockIdx.x] = s;
   }
 }
 
@@ -1231,24 +1291,70 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np,
                                                        const double *__restrict__ v, const double *__restrict__ mpart,
                                                        double *hv, double bscale) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1;
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2;
+  constexpr int NW = NT / 64;
   __shared__ C L[N * NH];
+  __shared__ C twl[N];      // the twiddle table, stored during the first pass (which reads none)
+  __shared__ double red[NW];  // wave sums of the mean
+  TwStage<T, N, NT> tv;
+  tv.load(tw);
   const int b = blockIdx.x / n0, i0 = blockIdx.x - b * n0;
-  double mean = 0.0;
-  if (mpart) {
-    double a = 0.0;
-    for (int i = threadIdx.x; i < n0; i += NT) a += mpart[(long)b * n0 + i];
-    mean = block_sum_all<NT>(a, reinterpret_cast<double *>(L)) / (double)Np;
-  }
-  plane_cols_inv_from<T, N, NT>(L, in + b * nh + (long)i0 * (N * NH), tw);
-  __syncthreads();
   const long off = b * Np + (long)i0 * (N * N);
   const double tau = p.tau[b], gam = p.gamma[b];
-  plane_rows_inv<T, N, NT>(L, tw, [&](int f, int x, C z, int, int) {
+  // the mean's partials (n0 <= 512 <= 4 NT) are loaded up front, and in FP32
+  // also Gamma'(psi) v at this thread's outputs of the last row pass; the
+  // plane's passes hide them (FP64 has no registers to spare: it loads them
+  // at the stores)
+  constexpr bool PREF = sizeof(T) == 4;
+  double mv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = threadIdx.x + u * NT;
+    mv[u] = (mpart && i < n0) ? mpart[(long)b * n0 + i] : 0.0;
+  }
+  using LastS = PassShape<T, N, true, NT, NR, false, NP - 1>;
+  constexpr int KP = PREF ? LastS::K : 1, RP = PREF ? LastS::R : 1;
+  double wa[KP][RP], wb[KP][RP];
+  auto gpv = [&](long i) {
+    const double ps = psi[i];
+    return (tau - gam * ps + 0.5 * ps * ps) * v[i];
+  };
+  if constexpr (PREF) {
+#pragma unroll
+    for (int k = 0; k < LastS::K; ++k) {
+      const int bi = threadIdx.x + k * NT;
+      if (bi < LastS::TOT) {
+        const int f = LastS::f_of(bi), j = LastS::j_of(bi);
+#pragma unroll
+        for (int r = 0; r < LastS::R; ++r) {
+          const long ia = off + (long)(2 * f) * N + j + r * LastS::NS;
+          wa[k][r] = gpv(ia);
+          wb[k][r] = gpv(ia + N);
+        }
+      }
+    }
+  }
+  plane_cols_inv_from<T, N, NT>(L, in + b * nh + (long)i0 * (N * NH), twl, [&]() {
+    tv.store(twl);
+  });
+  {
+    const double ws = wave_sum(mv[0] + mv[1] + mv[2] + mv[3]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
+  }
+  __syncthreads();
+  double msum = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) msum += red[w];
+  const double mean = mpart ? msum / (double)Np : 0.0;
+  plane_rows_inv<T, N, NT>(L, twl, [&](int f, int x, C z, int k, int r) {
     const long ia = off + (long)(2 * f) * N + x, ib = ia + N;
-    const double pa = psi[ia], pb = psi[ib];
-    hv[ia] = double(z.x) + bscale * ((tau - gam * pa + 0.5 * pa * pa) * v[ia] - mean);
-    hv[ib] = double(z.y) + bscale * ((tau - gam * pb + 0.5 * pb * pb) * v[ib] - mean);
+    if constexpr (PREF) {
+      hv[ia] = double(z.x) + bscale * (wa[k][r] - mean);
+      hv[ib] = double(z.y) + bscale * (wb[k][r] - mean);
+    } else {
+      hv[ia] = double(z.x) + bscale * (gpv(ia) - mean);
+      hv[ib] = double(z.y) + bscale * (gpv(ib) - mean);
+    }
   });
 }
 

@@ -335,6 +335,9 @@ def main():
     ap.add_argument("--sweep-precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--sweep-workers", type=int, default=8)
     ap.add_argument("--sweep-batch", type=int, default=8, help="instances per batched plan in the phase sweep (1: no batching)")
+    ap.add_argument("--plane-split", choices=["auto", "0", "1"], default="auto",
+                    help="inner-iteration order of the 128^3 plans: autotuned (default), one workgroup per plane (0), "
+                         "or pair-split with the half-plane pass (1)")
     ap.add_argument("--fp32-floor-scan", action="store_true",
                     help="only run the FP32/FP64 subproblem stop-floor scan at 128^3 and exit")
     args = ap.parse_args()
@@ -386,8 +389,18 @@ def main():
         ritz, res = p.lb_lanczos_min(prm, out, v0, LANCZOS_STEPS, precond_shift=1.0)
         return info, rc, ritz, res
 
+    def choose_variant(p):
+        """The inner iteration's plane stage: autotuned, or pinned by --plane-split."""
+        if args.plane_split == "auto":
+            p.lb_plan_autotune(prm, psi0, reps=20)
+        else:
+            p.lb_plan_set_plane_split(int(args.plane_split), 0)
+        split, threads = p.lb_plan_get_plane_variant()
+        return {"pair_split": split, "plane_pass_threads": threads, "chosen_by": "autotuner" if args.plane_split == "auto" else "pinned"}
+
     if args.kernel_sample:
         sp = plan if args.sample_precision == "fp64" else lb.Plan(n, box, precision="fp32")
+        choose_variant(sp)
         E, g = sp.lb_energy_grad(prm, psi0)
         d, sinfo, src = sp.lb_tr_subproblem(prm, psi0, g, 1.0, lb.sub_opts(eta=0.0132, max_inner=args.kernel_sample))
         torch.cuda.synchronize()
@@ -403,7 +416,7 @@ def main():
 
     # choose the plane-pass variant for this grid (autotuner), then warm up
     # with every kernel timed (the kernel shares)
-    tuned = plan.lb_plan_autotune(prm, psi0, reps=20)
+    tuned = choose_variant(plan)
     plan.lb_plan_set_timing(True, "")
     for _ in range(max(1, args.warmup)):
         info, rc, ritz, res = step(plan, opts)
@@ -481,7 +494,7 @@ def main():
         return batch * reps / (time.perf_counter() - s)
 
     hv = {"fp64": hv_rate("fp64"), "fp64_batch8": hv_rate("fp64", 8)}
-    fp32 = fp64_floor = None
+    fp32 = fp64_floor = tuned32 = None
     psi_fp32_end = None
     if not args.no_fp32:
         hv["fp32"] = hv_rate("fp32")
@@ -503,7 +516,7 @@ def main():
             }
 
         p32 = lb.Plan(n, box, precision="fp32")
-        p32.lb_plan_autotune(prm, psi0, reps=20)
+        tuned32 = choose_variant(p32)
         sub_rel = {"max_inner": 10000, "poll_every": 64, "eps_sub_rel": FP32_SUB_REL}
         o_rel = lb.tr_opts(grad_norm_inf=0, eps=TOL, max_outer=500, sub=sub_rel)
         out32, fp32 = timed_solve(p32, o_rel)
@@ -613,7 +626,7 @@ def main():
         "hessvec_per_s": hv,
         "solve_fp32_inner": fp32,
         "solve_fp64_same_floor": fp64_floor,
-        "autotune": {"plane_pass_threads": tuned},
+        "autotune": {"fp64": tuned, "fp32": tuned32},
         "other_configs": extra,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -389,11 +389,15 @@ int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double
                           const lb_tr_opts *opts, int workers, lb_tr_info *infos, int *status);
 
 /* Autotuner: on grids whose inner iteration uses the plane pass (3D with
- * n1 = n2 >= 64), time that pass built with 256, 512 and 1024 threads on the
- * plan's own buffers (Gamma' from psi, `reps` launches each) and use the
- * fastest from then on. *threads receives the chosen thread count (0 when the
- * plan has nothing to tune). Synchronises the stream; overwrites workspaces
- * only. */
+ * n1 = n2 >= 64), time the inner iteration's three passes (Section 3.2: the
+ * scaled inverse, the product with Gamma', the forward update) in each built
+ * variant: one workgroup per plane with 256, 512 or 1024 threads, and the
+ * pair-split order (lb_plan_set_plane_split) with 256, 512 or 1024 threads per
+ * half-plane workgroup, `reps` iterations each on the plan's own buffers
+ * (Gamma' from psi), and use the fastest from then on. *threads receives the
+ * chosen variant's thread count (0 when the plan has nothing to tune;
+ * lb_plan_get_plane_variant tells the order). Synchronises the stream;
+ * overwrites workspaces only. */
 int lb_plan_autotune(lb_plan *plan, const lb_params *params, const double *psi, int reps, int *threads);
 
 /* Pins the plane-pass variant the autotuner would choose: threads = 256, 512
@@ -403,6 +407,27 @@ int lb_plan_autotune(lb_plan *plan, const lb_params *params, const double *psi, 
  * variants differ only in how many threads share a plane; their results agree
  * to rounding, and each variant is deterministic. */
 int lb_plan_set_plane_threads(lb_plan *plan, int threads);
+
+/* Order of the inner iteration on grids with the plane pass (3D, n1 = n2; the
+ * product T d of Section 3.2 by pointwise products and FFTs). split = 1 splits
+ * the axis-1 transform by the parity of x1 = 2m + p: the axis-0 inverse pass
+ * does its first radix-2 step across the column pairs (k1, k1 + n1/2) and the
+ * forward update pass its last, and a half-plane pass with two workgroups per
+ * plane does the rest (twice the workgroups of the plane pass, half the LDS
+ * each). split = 0 keeps one workgroup per plane. threads = 256, 512 or 1024
+ * pins the half-plane pass's thread count, 0 keeps the built-in one (with
+ * split = 0 a nonzero count pins the plane pass's, as
+ * lb_plan_set_plane_threads). LB_ERR_UNSUPPORTED when split = 1 and the grid
+ * has no such order (the (n1/2)(n2/2 + 1) columns with k1 < n1/2 must fill
+ * whole column workgroups); LB_ERR_ARG for other values. Both orders compute
+ * the same iteration: results agree to rounding, and each is deterministic.
+ * The Hessian products of CONTRACT and Lanczos keep one workgroup per plane. */
+int lb_plan_set_plane_split(lb_plan *plan, int split, int threads);
+
+/* The inner iteration's order in use: *split = 1 for the pair-split order,
+ * and *threads the plane or half-plane pass's thread count (both 0 when the
+ * grid has no plane pass). */
+int lb_plan_get_plane_variant(lb_plan *plan, int *split, int *threads);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@
 // order, so every result is bitwise reproducible.
 #pragma once
 #include <cstdint>
+#include <type_traits>
 
 #include "fft.hpp"
 
@@ -376,13 +377,47 @@ struct ColGeo {
   long outer;
   long S;     // element stride along the transformed axis
   long inst;  // instance stride
+  int hsplit = 0;  // > 0: pair-split column order (col_of), hsplit = (n1/2) n_half columns
+};
+
+// Column of lane c in workgroup lb of an instance. Plain order: lb CC + c.
+// Pair-split order: lanes c < CC/2 take column lb CC/2 + c (k1 < n1/2) and
+// lanes c >= CC/2 the partner of lane c - CC/2, hsplit columns further on
+// (k1 + n1/2), so that a pair sits in lanes c and c ^ CC/2 of one wave.
+template <int CC> __device__ __forceinline__ int col_of(const ColGeo &cg, int lb, int c) {
+  if (cg.hsplit == 0) return lb * CC + c;
+  constexpr int HC = CC / 2;
+  return c < HC ? lb * HC + c : cg.hsplit + lb * HC + (c - HC);
+}
+// the value lane ^ M holds (M = 8: row_ror:8 within rows of 16 lanes;
+// otherwise a lane permute)
+template <int M> __device__ __forceinline__ double lane_xor(double x) {
+  if constexpr (M == 8) return dpp_d<0x128, 0xf, false>(x);
+  else return __shfl_xor(x, M);
+}
+template <int M> __device__ __forceinline__ float lane_xor(float x) {
+  if constexpr (M == 8)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));
+  else return __shfl_xor(x, M);
+}
+template <int M, typename T> __device__ __forceinline__ c2<T> lane_xor2(c2<T> v) {
+  return c2<T>{lane_xor<M>(v.x), lane_xor<M>(v.y)};
+}
+// pair butterfly of an axis-0 pass on the pair-split order: PAIR = 1 at the
+// loads, 2 at the stores (Op::PAIR; 0 or absent: none)
+template <class Op, class = void> struct OpPair {
+  static constexpr int value = 0;
+};
+template <class Op> struct OpPair<Op, std::void_t<decltype(Op::PAIR)>> {
+  static constexpr int value = Op::PAIR;
 };
 
 // A twiddle table of N entries staged into LDS: load() reads it with a
 // kernel's first loads, one scalar (real or imaginary part) per thread, and
 // store() writes it to LDS before the first barrier (half the registers of
-// holding whole complex entries in N threads)
-template <typename T, int N, int NT> struct TwStage {
+// holding whole complex entries in N threads). STRIDE 2 takes every other
+// entry of a table of 2N (the twiddles of a half-length transform).
+template <typename T, int N, int NT, int STRIDE = 1> struct TwStage {
   static constexpr int PER = (2 * N + NT - 1) / NT;
   T v[PER];
   __device__ __forceinline__ void load(const c2<T> *__restrict__ tw) {
@@ -390,7 +425,7 @@ template <typename T, int N, int NT> struct TwStage {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = threadIdx.x + u * NT;
-      v[u] = s[i < 2 * N ? i : 0];
+      v[u] = s[i < 2 * N ? 2 * STRIDE * (i >> 1) + (i & 1) : 0];
     }
   }
   __device__ __forceinline__ void store(c2<T> *twl) const {
@@ -423,7 +458,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
   const bool sk = op.skip(b);
   const int lb = blockIdx.x - b * cg.bpi;
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
-  const int ml = lb * CC + c;
+  const int ml = col_of<CC>(cg, lb, c);
   const bool ok = ml < cg.cpi;
   // columns past the end (ragged last workgroup) address column 0; with
   // Op::eager_loads they also load it and discard the values, so that every
@@ -440,7 +475,8 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
       t, c, lds, [](int cc, int e) { return e * CC + cc; }, twl,
       [&](int e) -> C {
         if constexpr (Op::eager_loads) {
-          const C v = op.load(bs, cs, base + e * cg.S, e);
+          C v = op.load(bs, cs, base + e * cg.S, e);
+          if constexpr (OpPair<Op>::value == 1) v = op.template pair_in<CC>(c, v);
           return ok ? v : C{T(0), T(0)};
         } else {
           return ok ? op.load(bs, cs, base + e * cg.S, e) : C{T(0), T(0)};
@@ -448,6 +484,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
       },
       [&](int e) { return op.fetch(bs, cs, ok, base + e * cg.S, e); },
       [&](int e, C v, const auto &aux) {
+        if constexpr (OpPair<Op>::value == 2) v = op.template pair_out<CC>(cs, c, v);
         double *sq = reinterpret_cast<double *>(lds) + e * CC + c;
         if (ok && !sk) op.store(bs, cs, base + e * cg.S, e, v, aux, acc, sq);
         else *sq = 0.0;
@@ -455,7 +492,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
       [&]() {
         tv.store(twl);
       });
-  if (!sk) op.template end<NT, N, CC>(bs, acc, reinterpret_cast<double *>(lds), b, lb, c);  // uniform
+  if (!sk) op.template end<NT, N, CC>(bs, acc, reinterpret_cast<double *>(lds), b, ml, c);  // uniform
 }
 
 struct Empty {};
@@ -489,15 +526,28 @@ template <typename T> struct StepBlk {
   double lam_t, eta, xi, q;
 };
 
-// step t of the subproblem, axis-0 inverse pass: d_t = b_{t-1} / (1 + eta (Lambda + lambda_t))
-template <typename T, bool GEN> struct OpInvScaleD {
+// column information plus the pair twiddle e^{-2 pi i k'/n1} of a
+// pair-split partner column (k1 = k' + n1/2)
+template <typename T> struct ColTw : ColInfo {
+  c2<T> tw;
+};
+
+// step t of the subproblem, axis-0 inverse pass: d_t = b_{t-1} / (1 + eta (Lambda + lambda_t)).
+// SPLIT (pair-split order, for the half-plane pass): the stores leave
+// s_0(k') = a(k') + a(k' + n1/2) in row k' and s_1(k') = (a(k') - a(k' + n1/2))
+// e^{+2 pi i k'/n1} in row k' + n1/2 (a: the axis-0 inverse of d_t), the
+// first radix-2 step of the axis-1 inverse transform split by the parity of x1
+template <typename T, bool GEN, bool SPLIT = false> struct OpInvScaleD {
   static constexpr bool eager_loads = true;
+  static constexpr int PAIR = SPLIT ? 2 : 0;
   Geo g;
   Prm p;
   const c2<T> *b0, *b1;  // b buffers: b_{t-1} lives in (t - 1) & 1
   c2<T> *out;
   const SubState *st;
+  const c2<T> *twn;  // SPLIT: the axis-1 twiddle table (e^{-2 pi i k/n1})
   int t;  // step index (known to the host when it enqueues the step)
+  using CI = std::conditional_t<SPLIT, ColTw<T>, ColInfo>;
   __device__ bool skip(int b) const { return st[b].done != 0; }
   __device__ StepBlk<T> begin(int b) const {
     StepBlk<T> s;
@@ -509,7 +559,26 @@ template <typename T, bool GEN> struct OpInvScaleD {
     s.q = p.q[b];
     return s;
   }
-  __device__ ColInfo column(int, int ml) const { return col_info<GEN>(g, ml); }
+  __device__ CI column(int, int ml) const {
+    CI ci;
+    static_cast<ColInfo &>(ci) = col_info<GEN>(g, ml);
+    if constexpr (SPLIT) {
+      const int k1 = ml / g.nhl, h1 = g.n1 / 2;
+      ci.tw = twn[k1 >= h1 ? k1 - h1 : 0];
+    }
+    return ci;
+  }
+  // lane c holds a(k1) of its column, lane c ^ CC/2 that of the partner
+  template <int CC> __device__ c2<T> pair_out(const CI &ci, int c, c2<T> v) const {
+    const c2<T> u = lane_xor2<CC / 2, T>(v);
+    if (c < CC / 2) return c2<T>{v.x + u.x, v.y + u.y};
+    if constexpr (SPLIT) {
+      const c2<T> d{u.x - v.x, u.y - v.y};
+      return c2<T>{d.x * ci.tw.x + d.y * ci.tw.y, d.y * ci.tw.x - d.x * ci.tw.y};  // d conj(tw)
+    } else {
+      return v;
+    }
+  }
   __device__ c2<T> load(const StepBlk<T> &bs, const ColInfo &ci, long h, int e) const {
     const c2<T> v = bs.bprev[h];
     const double lam = lam_of(kk_e<GEN>(g, e, ci), bs.xi, bs.q);
@@ -531,8 +600,13 @@ template <typename T> struct UpdAux {
   c2<T> bp, gg;
   double kk;  // |Bk|^2 of the element
 };
-template <typename T, bool GEN> struct OpFwdUpdate {
+// SPLIT (pair-split order, after the half-plane pass): the loads form
+// Y(k'') = Z_0(k'') + Z_1(k'') in row k'' and Y(k'' + n1/2) = Z_0(k'') - Z_1(k'')
+// from Z_0 in row k'' and Z_1 in row k'' + n1/2, the last radix-2 step of the
+// axis-1 forward transform split by the parity of x1
+template <typename T, bool GEN, bool SPLIT = false> struct OpFwdUpdate {
   static constexpr bool eager_loads = true;
+  static constexpr int PAIR = SPLIT ? 1 : 0;
   Geo g;
   Prm p;
   const c2<T> *tmp;  // row/axis-1 transformed product Gamma' d_t
@@ -557,6 +631,11 @@ template <typename T, bool GEN> struct OpFwdUpdate {
   }
   __device__ ColInfo column(int, int ml) const { return col_info<GEN>(g, ml); }
   __device__ c2<T> load(const StepBlk<T> &, const ColInfo &, long h, int) const { return tmp[h]; }
+  // lane c holds Z_0 (c < CC/2) or Z_1 of its column pair, lane c ^ CC/2 the other
+  template <int CC> __device__ c2<T> pair_in(int c, c2<T> v) const {
+    const c2<T> u = lane_xor2<CC / 2, T>(v);
+    return c < CC / 2 ? c2<T>{v.x + u.x, v.y + u.y} : c2<T>{u.x - v.x, u.y - v.y};
+  }
   __device__ UpdAux<T> fetch(const StepBlk<T> &bs, const ColInfo &ci, bool ok, long h, int e) const {
     UpdAux<T> a;
     if (ok) {
@@ -595,12 +674,11 @@ template <typename T, bool GEN> struct OpFwdUpdate {
   // phi(0) and of the power sums M_j around mu0 = eta lambda_t, and of the
   // squared residual, go to mom[j * blocks + block] and partial[block].
   template <int NT, int N, int CC>
-  __device__ void end(const StepBlk<T> &bs, double acc, double *sq, int b, int lb, int) const {
+  __device__ void end(const StepBlk<T> &bs, double acc, double *sq, int b, int ml, int) const {
     static_assert(NT % CC == 0, "each thread keeps one column");
     __syncthreads();
     constexpr int NH0 = N / 2 + 1;
     const int cc = threadIdx.x % CC;
-    const int ml = lb * CC + cc;
     const bool okc = ml < cpi;
     const double kkc = col_info<GEN>(g, okc ? ml : 0).kkc;
     const double mu0 = bs.eta * bs.lam_t;
@@ -1116,31 +1194,34 @@ template <int N> constexpr int plane_pr() { return N + 1; }
 // axis 1, inverse, first pass reading element (e, f) from load(f, e)
 // (pre() runs after the first pass, before its barrier: the first pass reads
 // no twiddles, so an LDS twiddle table stored there serves the later passes)
-template <typename T, int N, int NT, class Load, class Pre = lbfft::NoPre>
+// (LEN: the axis-1 transform length, N or N/2 for the half-plane pass; tw
+// is that length's table)
+template <typename T, int N, int NT, int LEN, class Load, class Pre = lbfft::NoPre>
 __device__ __forceinline__ void plane_cols_inv_load(c2<T> *L, const c2<T> *__restrict__ tw, const Load &load,
                                                     const Pre &pre = Pre{}) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N);
-  sk_pass<T, N, true, NT, NH, true, 0, false>(tw, load, [&](int f, int e, C v, int, int) { L[e * NH + f] = v; });
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(LEN);
+  sk_pass<T, LEN, true, NT, NH, true, 0, false>(tw, load, [&](int f, int e, C v, int, int) { L[e * NH + f] = v; });
   pre();
   __syncthreads();
-  sk_lds_passes<T, N, true, NT, NH, true, 1, NP>(L, 1, NH, tw);
+  sk_lds_passes<T, LEN, true, NT, NH, true, 1, NP>(L, 1, NH, tw);
 }
 // ... from src (plane layout)
 template <typename T, int N, int NT, class Pre = lbfft::NoPre>
 __device__ __forceinline__ void plane_cols_inv_from(c2<T> *L, const c2<T> *src, const c2<T> *__restrict__ tw,
                                                     const Pre &pre = Pre{}) {
-  plane_cols_inv_load<T, N, NT>(
+  plane_cols_inv_load<T, N, NT, N>(
       L, tw, [&](int f, int e) -> c2<T> { return src[e * (N / 2 + 1) + f]; }, pre);
 }
 
 // rows, inverse: the first pass packs half rows 2p, 2p+1 into Z_p = A + i B;
 // the last pass (consecutive threads on consecutive outputs x = j + r NS of
 // one row) hands its outputs to last(p, x, z, k, r)
-template <typename T, int N, int NT, class Last>
+// (NR packed rows: N/2, or N/4 in the half-plane pass)
+template <typename T, int N, int NT, int NR, class Last>
 __device__ __forceinline__ void plane_rows_inv(c2<T> *L, const c2<T> *__restrict__ tw, const Last &last) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NR = N / 2, PR = plane_pr<N>();
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), PR = plane_pr<N>();
   auto packed = [&](int p, int e) -> C {
     const bool lo = 2 * e <= N;
     const int k = lo ? e : N - e;
@@ -1165,10 +1246,11 @@ __device__ __forceinline__ void plane_rows_inv(c2<T> *L, const c2<T> *__restrict
 
 // axis 1, forward: the first pass unpacks Z_p into half rows 2p, 2p+1; the
 // last pass hands element (e, f) to store_out(f, e, v, k, r)
-template <typename T, int N, int NT, class Store, bool LAST_MID = false>
+// (LEN: the axis-1 transform length, as for plane_cols_inv_load)
+template <typename T, int N, int NT, class Store, bool LAST_MID = false, int LEN = N>
 __device__ __forceinline__ void plane_cols_fwd_store(c2<T> *L, const c2<T> *__restrict__ tw, const Store &store_mem) {
   using C = c2<T>;
-  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), PR = plane_pr<N>();
+  constexpr int NH = N / 2 + 1, NP = lbfft::npass_p<1>(LEN), PR = plane_pr<N>();
   auto unpacked = [&](int k, int e) -> C {
     const int p = e >> 1;
     const C zk = L[p * PR + k], zm = L[p * PR + ((N - k) % N)];
@@ -1177,12 +1259,12 @@ __device__ __forceinline__ void plane_cols_fwd_store(c2<T> *L, const c2<T> *__re
   };
   auto store_lds = [&](int f, int e, C v, int, int) { L[e * NH + f] = v; };
   if constexpr (NP == 1) {
-    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_mem);
+    sk_pass<T, LEN, false, NT, NH, true, 0, true>(tw, unpacked, store_mem);
   } else {
-    sk_pass<T, N, false, NT, NH, true, 0, true>(tw, unpacked, store_lds);
+    sk_pass<T, LEN, false, NT, NH, true, 0, true>(tw, unpacked, store_lds);
     __syncthreads();
-    sk_lds_passes<T, N, false, NT, NH, true, 1, NP - 1>(L, 1, NH, tw);
-    sk_pass<T, N, false, NT, NH, true, NP - 1, LAST_MID>(
+    sk_lds_passes<T, LEN, false, NT, NH, true, 1, NP - 1>(L, 1, NH, tw);
+    sk_pass<T, LEN, false, NT, NH, true, NP - 1, LAST_MID>(
         tw, [&](int f, int e) -> C { return L[e * NH + f]; }, store_mem);
   }
 }
@@ -1228,7 +1310,7 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
       }
     }
   }
-  plane_rows_inv<T, N, NT>(L, twl, [&](int f, int e, C v, int k, int r) {
+  plane_rows_inv<T, N, NT, N / 2>(L, twl, [&](int f, int e, C v, int k, int r) {
     L[f * PR + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
   });
   __syncthreads();
@@ -1236,6 +1318,76 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
   plane_cols_fwd_store<T, N, NT>(L, twl, [&](int f, int e, C v, int, int) {
     if (!sk) plane[e * NH + f] = v;
   });
+}
+
+// Half-plane pass of the inner iteration (pair-split order, n1 = n_last = N):
+// the axis-1 transform of length N split by the parity p of x1 = 2m + p. The
+// axis-0 inverse pass leaves s_0 in rows 0 .. N/2 - 1 of each plane and s_1
+// in rows N/2 .. N - 1 (OpInvScaleD with SPLIT); values at x1 = 2m + p are the
+// length-N/2 inverse transform of s_p. Workgroup (i0, p) transforms its half,
+// does the row transforms with the product with Gamma' on rows x1 = 2m + p,
+// transforms back over m (length N/2) into Y_p and stores
+// Z_p(k'') = e^{-2 pi i p k''/N} Y_p(k'') in the same rows (OpFwdUpdate with
+// SPLIT combines Z_0 and Z_1). Each workgroup touches only its own rows, and
+// holds half a plane in LDS: two workgroups per plane.
+template <typename T, int N> struct HalfCfg {
+  static constexpr int H = N / 2, NH = N / 2 + 1;
+  static constexpr bool fits =
+      PlaneCfg<T, N>::fits && N >= 32 && N % 4 == 0 && (H * NH) % 8 == 0 && lbfft::npass_p<1>(H) > 0;
+  static constexpr int NT = N >= 96 ? 512 : 256;
+};
+template <typename T, int N, int NT = HalfCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_plane_inner_half(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
+                                                         c2<T> *data, const T *__restrict__ gp, const SubState *st) {
+  using C = c2<T>;
+  constexpr int H = N / 2, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = H / 2, PR = plane_pr<N>();
+  static_assert(NRW * PR <= H * NH, "packed rows fit in the half plane");
+  __shared__ C L[H * NH];
+  __shared__ C twl[N];  // length-N twiddles (rows, and Z_1's factor), stored during the first pass
+  __shared__ C twh[H];  // length-N/2 twiddles (axis 1)
+  TwStage<T, N, NT> tv;
+  TwStage<T, H, NT, 2> th;
+  tv.load(tw);
+  th.load(tw);
+  const int pl = blockIdx.x >> 1, par = blockIdx.x & 1;
+  const int b = pl / n0, i0 = pl - b * n0;
+  const bool sk = st && st[b].done;  // applied at the stores
+  C *half = data + b * nh + (long)i0 * (N * NH) + (long)par * (H * NH);
+  const T *g = gp + b * Np + (long)i0 * (N * N);
+  plane_cols_inv_load<T, N, NT, H>(
+      L, twh, [&](int f, int e) -> C { return half[e * NH + f]; },
+      [&]() {
+        tv.store(twl);
+        th.store(twh);
+      });
+  __syncthreads();
+  // Gamma' for the last inverse row pass: packed row f holds the local rows
+  // 2f and 2f + 1, i.e. x1 = 4f + p and 4f + 2 + p
+  using LastS = PassShape<T, N, true, NT, NRW, false, NP - 1>;
+  T g0[LastS::K][LastS::R], g1[LastS::K][LastS::R];
+#pragma unroll
+  for (int k = 0; k < LastS::K; ++k) {
+    const int bi = threadIdx.x + k * NT;
+    if (bi < LastS::TOT) {
+      const int f = LastS::f_of(bi), j = LastS::j_of(bi);
+#pragma unroll
+      for (int r = 0; r < LastS::R; ++r) {
+        const int e = j + r * LastS::NS;
+        g0[k][r] = g[(4 * f + par) * N + e];
+        g1[k][r] = g[(4 * f + 2 + par) * N + e];
+      }
+    }
+  }
+  plane_rows_inv<T, N, NT, NRW>(L, twl, [&](int f, int e, C v, int k, int r) {
+    L[f * PR + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
+  });
+  __syncthreads();
+  sk_lds_passes<T, N, false, NT, NRW, true, 0, NP>(L, PR, 1, twl);  // rows, forward
+  auto store = [&](int f, int e, C v, int, int) {
+    if (par) v = cmul(v, twl[e]);
+    if (!sk) half[e * NH + f] = v;
+  };
+  plane_cols_fwd_store<T, N, NT, decltype(store), false, H>(L, twh, store);
 }
 
 // Hessian-vector product, axes 2 and 1 forward from the physical field v:
@@ -1346,7 +1498,7 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np,
 #pragma unroll
   for (int w = 0; w < NW; ++w) msum += red[w];
   const double mean = mpart ? msum / (double)Np : 0.0;
-  plane_rows_inv<T, N, NT>(L, twl, [&](int f, int x, C z, int k, int r) {
+  plane_rows_inv<T, N, NT, N / 2>(L, twl, [&](int f, int x, C z, int k, int r) {
     const long ia = off + (long)(2 * f) * N + x, ib = ia + N;
     if constexpr (PREF) {
       hv[ia] = double(z.x) + bscale * (wa[k][r] - mean);
@@ -1429,7 +1581,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     C *bnext = (t & 1) ? b1 : b0;
     const double mu0 = eta * lam_t;
     // d_t, axis 0 inverse
-    plane_cols_inv_load<T, N, NT>(L, tw, [&](int f, int e) -> C {
+    plane_cols_inv_load<T, N, NT, N>(L, tw, [&](int f, int e) -> C {
       const C v = Bs[e * NH + f];
       const double x = 1.0 + eta * Lm[e * NH + f] + mu0;
       const double sc = (e == 0 && f == 0) ? 0.0 : rcp64(x);
@@ -1437,7 +1589,7 @@ __global__ __launch_bounds__(NT) void k_sub2d(Geo g, Prm p, const c2<T> *__restr
     });
     __syncthreads();
     // rows inverse, x Gamma' (rows 2f, 2f + 1), rows forward
-    plane_rows_inv<T, N, NT>(L, tw, [&](int f, int e, C v, int, int) {
+    plane_rows_inv<T, N, NT, N / 2>(L, tw, [&](int f, int e, C v, int, int) {
       L[f * PR + e] = C{v.x * Gp[(2 * f) * N + e], v.y * Gp[(2 * f + 1) * N + e]};
     });
     __syncthreads();

@@ -35,6 +35,7 @@ struct PassArgs {
   ColGeo cg{};
   RowGeo rg{};
   const void *tw = nullptr;
+  const void *tw1 = nullptr;  // axis-1 twiddles (pair-split inverse pass)
   const void *in = nullptr;
   void *out = nullptr;
   void *out2 = nullptr;
@@ -72,6 +73,11 @@ struct NFuncs {
   void (*plane_inner)(const PassArgs &, int n0) = nullptr;
   // the same pass with 256, 512 and 1024 threads (autotuner candidates; null where not built)
   void (*plane_inner_nt[3])(const PassArgs &, int n0) = {nullptr, nullptr, nullptr};
+  // the half-plane pass (pair-split order) with 256, 512 and 1024 threads, and
+  // the built-in thread count (null where it does not apply)
+  void (*plane_half_nt[3])(const PassArgs &, int n0) = {nullptr, nullptr, nullptr};
+  int plane_half_default = -1;
+  int plane_nt_default = 0;  // threads of plane_inner
   void (*plane_fwd_phys)(const PassArgs &, int n0) = nullptr;  // v -> out (+ Gamma' v partials)
   void (*plane_inv_phys)(const PassArgs &, int n0) = nullptr;  // in -> hv
   // whole subproblem of one square 2D instance in one workgroup (null when it does not fit)
@@ -93,24 +99,31 @@ template <typename T, int N> struct Impl {
   }
   // the ops below come in two forms: orthorhombic (|Bk|^2 without cross
   // terms, the benchmark's) and general lattice; a.g.general picks one
-  template <bool GEN> static void cols_inv_scale_d_t(const PassArgs &a) {
-    lbk::OpInvScaleD<T, GEN> op{};
+  // (a.cg.hsplit > 0: the pair-split forms that feed and follow the half-plane pass)
+  template <bool GEN, bool SPLIT> static void cols_inv_scale_d_t(const PassArgs &a) {
+    lbk::OpInvScaleD<T, GEN, SPLIT> op{};
     op.g = a.g;
     op.p = a.p;
     op.b0 = (const C2 *)a.b0;
     op.b1 = (const C2 *)a.b1;
     op.out = (C2 *)a.out;
     op.st = a.st;
+    op.twn = (const C2 *)a.tw1;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
-              (const C2 *)a.tw, op);
+    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, SPLIT>>), dim3(a.nblocks), dim3(NT), 0, a.stream,
+              a.cg, (const C2 *)a.tw, op);
   }
   static void cols_inv_scale_d(const PassArgs &a) {
-    if (a.g.general) cols_inv_scale_d_t<true>(a);
-    else cols_inv_scale_d_t<false>(a);
+    if (a.cg.hsplit) {
+      if (a.g.general) cols_inv_scale_d_t<true, true>(a);
+      else cols_inv_scale_d_t<false, true>(a);
+    } else {
+      if (a.g.general) cols_inv_scale_d_t<true, false>(a);
+      else cols_inv_scale_d_t<false, false>(a);
+    }
   }
-  template <bool GEN> static void cols_fwd_update_t(const PassArgs &a) {
-    lbk::OpFwdUpdate<T, GEN> op{};
+  template <bool GEN, bool SPLIT> static void cols_fwd_update_t(const PassArgs &a) {
+    lbk::OpFwdUpdate<T, GEN, SPLIT> op{};
     op.g = a.g;
     op.p = a.p;
     op.tmp = (const C2 *)a.in;
@@ -123,12 +136,17 @@ template <typename T, int N> struct Impl {
     op.inv_n = a.inv_n;
     op.cpi = a.cg.cpi;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T, GEN>>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg,
-              (const C2 *)a.tw, op);
+    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T, GEN, SPLIT>>), dim3(a.nblocks), dim3(NT), 0, a.stream,
+              a.cg, (const C2 *)a.tw, op);
   }
   static void cols_fwd_update(const PassArgs &a) {
-    if (a.g.general) cols_fwd_update_t<true>(a);
-    else cols_fwd_update_t<false>(a);
+    if (a.cg.hsplit) {
+      if (a.g.general) cols_fwd_update_t<true, true>(a);
+      else cols_fwd_update_t<false, true>(a);
+    } else {
+      if (a.g.general) cols_fwd_update_t<true, false>(a);
+      else cols_fwd_update_t<false, false>(a);
+    }
   }
   template <bool GEN> static void cols_fwd_hess_t(const PassArgs &a) {
     lbk::OpFwdHess<T, GEN> op{};
@@ -194,6 +212,11 @@ template <typename T, int N> struct Impl {
       LB_LAUNCH((lbk::k_plane_inner<T, N, NTV>), dim3(n0 * a.g.batch), dim3(NTV), 0, a.stream, n0, a.g.nh, a.g.N,
                 (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
   }
+  template <int NTV> static void plane_half_nt(const PassArgs &a, int n0) {
+    if constexpr (lbk::HalfCfg<T, N>::fits)
+      LB_LAUNCH((lbk::k_plane_inner_half<T, N, NTV>), dim3(2 * n0 * a.g.batch), dim3(NTV), 0, a.stream, n0, a.g.nh,
+                a.g.N, (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
+  }
   static void plane_fwd_phys(const PassArgs &a, int n0) {
     if constexpr (lbk::PlaneCfg<T, N>::fits)
       LB_LAUNCH((lbk::k_plane_fwd_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
@@ -234,6 +257,13 @@ template <typename T, int N> struct Impl {
       f.plane_inner_nt[1] = &plane_inner_nt<512>;
       f.plane_inner_nt[2] = &plane_inner_nt<1024>;
     }
+    if constexpr (lbk::HalfCfg<T, N>::fits) {
+      f.plane_half_nt[0] = &plane_half_nt<256>;
+      f.plane_half_nt[1] = &plane_half_nt<512>;
+      f.plane_half_nt[2] = &plane_half_nt<1024>;
+      f.plane_half_default = lbk::HalfCfg<T, N>::NT == 256 ? 0 : lbk::HalfCfg<T, N>::NT == 512 ? 1 : 2;
+    }
+    f.plane_nt_default = lbk::PlaneCfg<T, N>::fits ? lbk::PlaneCfg<T, N>::NT : 0;
     f.plane_fwd_phys = lbk::PlaneCfg<T, N>::fits ? &plane_fwd_phys : nullptr;
     f.plane_inv_phys = lbk::PlaneCfg<T, N>::fits ? &plane_inv_phys : nullptr;
     f.sub2d = SUB2D ? &sub2d : nullptr;

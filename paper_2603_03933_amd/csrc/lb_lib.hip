@@ -148,6 +148,8 @@ struct lb_plan {
   hipStream_t stream = nullptr;
   hipStream_t own = nullptr;  // private stream for captured launch sequences (created on first use)
   int plane_nt = -1;          // autotuned plane-pass variant (index into plane_inner_nt), -1: built-in choice
+  int plane_split = 0;        // inner iteration in pair-split order with the half-plane pass (1) or not (0)
+  int half_nt = -1;           // its thread-count variant (index into plane_half_nt), -1: built-in choice
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
   // general Bravais lattice (lb_plan_set_lattice): the reciprocal metric
   // G = B^T B by axis slot (0 leading, 1 middle, 2 last); unused when 0
@@ -1077,6 +1079,19 @@ extern "C" int lb_param_grad_vjp(lb_plan *P, const double *psi, const double *ct
 }
 
 // the plane pass of the inner iteration, in the variant the autotuner chose
+// the inner iteration may run in pair-split order: 3D, plane pass, a built
+// half-plane kernel, column workgroups whose halves pair up without a ragged
+// end ((n1/2) n_half columns a multiple of C/2)
+static bool split_ok(const lb_plan *P, int prec) {
+  if (P->dim != 3 || P->n1 != P->nl || P->n1 % 2) return false;
+  const NFuncs *f1 = F(P, 1, prec);
+  const NFuncs *f0 = F(P, 0, prec);
+  if (!f1 || !f1->plane_inner || f1->plane_half_default < 0 || !f0 || f0->C % 2) return false;
+  const long hcols = (long)(P->n1 / 2) * P->nhl;
+  return hcols % (f0->C / 2) == 0 && bpi_col0(P) * f0->C == 2 * hcols;
+}
+static bool use_split(const lb_plan *P, int prec) { return P->plane_split == 1 && split_ok(P, prec); }
+
 static void plane_pass(lb_plan *P, const NFuncs *f1, const PassArgs &a) {
   if (P->plane_nt >= 0 && f1->plane_inner_nt[P->plane_nt]) f1->plane_inner_nt[P->plane_nt](a, P->n0);
   else f1->plane_inner(a, P->n0);
@@ -1155,21 +1170,36 @@ static void launch_newton(lb_plan *P, const PassArgs &u, const Prm &p, int B) {
             u.cg.bpi, (long)u.cg.bpi * B, (const double *)P->partial, u.cg.bpi, (const C2 *)P->B0, (const C2 *)P->B1,
             u.cg.cpi, P->st);
 }
-static void enqueue_step(lb_plan *P, const Prm &p, int t, int B = 1) {
+// the three passes of step t (inverse with the scale, axes 1 and 2 with
+// Gamma', forward with the update); returns the update's arguments
+static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
   const int prec = P->prec;
   t &= 1;
+  const bool split = use_split(P, prec);
+  const int hsplit = split ? (P->n1 / 2) * P->nhl : 0;
   PassArgs a = args_col(P, prec, B, p, 0);
   a.step = t;
   a.b0 = P->B0;
   a.b1 = P->B1;
   a.out = P->WT;
   a.st = P->st;
+  a.cg.hsplit = hsplit;
+  a.tw1 = split ? TW(P, 1, prec) : nullptr;
   {
     KT kt_(P, "col0_inv_scale_d");
     F(P, 0, prec)->cols_inv_scale_d(a);
   }
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
-  if (f1 && f1->plane_inner && P->n1 == P->nl) {
+  if (split) {
+    // axis 1 split by the parity of x1, rows with Gamma': two workgroups per plane
+    PassArgs pl = args_col(P, prec, B, p, 1);
+    pl.out = P->WT;
+    pl.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
+    pl.st = P->st;
+    const int v = P->half_nt >= 0 && f1->plane_half_nt[P->half_nt] ? P->half_nt : f1->plane_half_default;
+    KT kt_(P, "plane_inner");
+    f1->plane_half_nt[v](pl, P->n0);
+  } else if (f1 && f1->plane_inner && P->n1 == P->nl) {
     // axis-1 inverse, rows with Gamma', axis-1 forward: one plane pass in LDS
     PassArgs pl = args_col(P, prec, B, p, 1);
     pl.out = P->WT;
@@ -1208,6 +1238,7 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t, int B = 1) {
     }
   }
   PassArgs u = args_col(P, prec, B, p, 0);
+  u.cg.hsplit = hsplit;
   u.in = P->WT;
   u.b0 = P->B0;
   u.b1 = P->B1;
@@ -1221,6 +1252,12 @@ static void enqueue_step(lb_plan *P, const Prm &p, int t, int B = 1) {
     KT kt_(P, "col0_fwd_update");
     F(P, 0, prec)->cols_fwd_update(u);
   }
+  return u;
+}
+
+static void enqueue_step(lb_plan *P, const Prm &p, int t, int B = 1) {
+  const int prec = P->prec;
+  const PassArgs u = enqueue_passes(P, p, t, B);
   {
     KT kt_(P, "newton");
     const bool gen = u.g.general != 0;
@@ -2279,34 +2316,89 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
     LB_LAUNCH(lbk::k_gamma_p, dim3((unsigned)std::min<long>(cdiv(P->N * P->batch, lbk::EW_NT), 4096)), dim3(lbk::EW_NT),
               0, P->stream, P->N, P->batch, p, psi, P->gp64, P->gp32);
   }
-  PassArgs pl = args_col(P, prec, 1, p, 1);
-  pl.out = P->WT;
-  pl.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
-  pl.st = nullptr;
+  // a running subproblem state for instance 0 and zeroed b buffers: the three
+  // passes of an inner iteration run on them as in a solve (the update pass
+  // leaves the state alone; Newton is the same in every variant and not timed)
+  SubState s0{};
+  s0.eta = 0.05;
+  s0.max_inner = 1 << 30;
+  LB_HIP(hipMemcpyAsync(P->st, &s0, sizeof(SubState), hipMemcpyHostToDevice, P->stream));
+  const size_t bbytes = (size_t)P->nh * (prec == LB_FP64 ? sizeof(double2) : sizeof(float2));
+  LB_HIP(hipMemsetAsync(P->B0, 0, bbytes, P->stream));
+  LB_HIP(hipMemsetAsync(P->B1, 0, bbytes, P->stream));
   hipEvent_t e0, e1;
   LB_HIP(hipEventCreate(&e0));
   LB_HIP(hipEventCreate(&e1));
   const int nts[3] = {256, 512, 1024};
+  const int keep_split = P->plane_split, keep_nt = P->plane_nt, keep_half = P->half_nt;
   float best = 0.0f;
-  int pick = -1;
-  for (int v = 0; v < 3; ++v) {
-    f1->plane_inner_nt[v](pl, P->n0);  // warm
-    LB_HIP(hipEventRecord(e0, P->stream));
-    for (int r = 0; r < reps; ++r) f1->plane_inner_nt[v](pl, P->n0);
-    LB_HIP(hipEventRecord(e1, P->stream));
-    LB_HIP(hipEventSynchronize(e1));
-    float ms = 0.0f;
-    LB_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (pick < 0 || ms < best) {
-      best = ms;
-      pick = v;
+  int pick_split = -1, pick = -1;
+  for (int split = 0; split < 2; ++split) {
+    for (int v = 0; v < 3; ++v) {
+      if (split && (!split_ok(P, prec) || !f1->plane_half_nt[v])) continue;
+      if (!split && !f1->plane_inner_nt[v]) continue;
+      P->plane_split = split;
+      if (split) P->half_nt = v;
+      else P->plane_nt = v;
+      enqueue_passes(P, p, 1, 1);  // warm
+      LB_HIP(hipEventRecord(e0, P->stream));
+      for (int r = 0; r < reps; ++r) enqueue_passes(P, p, r + 2, 1);
+      LB_HIP(hipEventRecord(e1, P->stream));
+      LB_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      LB_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (pick < 0 || ms < best) {
+        best = ms;
+        pick = v;
+        pick_split = split;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  P->plane_split = keep_split;
+  P->plane_nt = keep_nt;
+  P->half_nt = keep_half;
   LB_TRY(check_launch("lb_plan_autotune"));
-  P->plane_nt = pick;
+  P->plane_split = pick_split;
+  if (pick_split) P->half_nt = pick;
+  else P->plane_nt = pick;
   *threads = nts[pick];
+  return LB_OK;
+}
+
+extern "C" int lb_plan_set_plane_split(lb_plan *P, int split, int threads) {
+  if (!P) return fail(LB_ERR_ARG, "null plan");
+  if (split != 0 && split != 1) return fail(LB_ERR_ARG, "split must be 0 or 1");
+  const int v = threads == 0 ? -1 : threads == 256 ? 0 : threads == 512 ? 1 : threads == 1024 ? 2 : -2;
+  if (v == -2) return fail(LB_ERR_ARG, "plane threads must be 0, 256, 512 or 1024");
+  if (split) {
+    if (!split_ok(P, P->prec)) return fail(LB_ERR_UNSUPPORTED, "this grid has no pair-split inner iteration");
+    if (v >= 0 && !F(P, 1, P->prec)->plane_half_nt[v]) return fail(LB_ERR_UNSUPPORTED, "half-plane pass not built with that thread count");
+    P->half_nt = v;
+  } else if (v >= 0) {
+    LB_TRY(lb_plan_set_plane_threads(P, threads));
+  }
+  P->plane_split = split;
+  return LB_OK;
+}
+
+extern "C" int lb_plan_get_plane_variant(lb_plan *P, int *split, int *threads) {
+  if (!P || !split || !threads) return fail(LB_ERR_ARG, "null argument");
+  *split = 0;
+  *threads = 0;
+  const int prec = P->prec;
+  const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
+  if (!f1 || !f1->plane_inner || P->n1 != P->nl) return LB_OK;
+  const int nts[3] = {256, 512, 1024};
+  if (use_split(P, prec)) {
+    *split = 1;
+    *threads = nts[P->half_nt >= 0 && f1->plane_half_nt[P->half_nt] ? P->half_nt : f1->plane_half_default];
+  } else if (P->plane_nt >= 0 && f1->plane_inner_nt[P->plane_nt]) {
+    *threads = nts[P->plane_nt];
+  } else {
+    *threads = f1->plane_nt_default;
+  }
   return LB_OK;
 }
 

@@ -154,6 +154,8 @@ _SIGS = {
     "lb_imex_tr_solve_batch": (_I, [_P, C.POINTER(LbParams), _P, C.POINTER(LbTrOpts), C.POINTER(LbTrInfo), C.POINTER(_I)]),
     "lb_plan_autotune": (_I, [_P, C.POINTER(LbParams), _P, _I, C.POINTER(_I)]),
     "lb_plan_set_plane_threads": (_I, [_P, _I]),
+    "lb_plan_set_plane_split": (_I, [_P, _I, _I]),
+    "lb_plan_get_plane_variant": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
 }
 
 
@@ -301,7 +303,8 @@ class Plan:
         return out
 
     def lb_plan_autotune(self, params, psi, reps=20):
-        """Time the plane-pass variants on this plan and keep the fastest; returns its thread count (0: none)."""
+        """Time the inner iteration's plane-stage variants (both orders, each thread count) and keep the
+        fastest; returns its thread count (0: nothing to tune)."""
         self._sync_stream()
         nt = C.c_int()
         _check(lib().lb_plan_autotune(self._h, _params_array(params, self.batch), _ptr(psi, self.N * self.batch, "psi"), int(reps), C.byref(nt)))
@@ -310,6 +313,16 @@ class Plan:
     def lb_plan_set_plane_threads(self, threads):
         """Pin the plane-pass variant (256, 512 or 1024 threads; 0: the built-in choice)."""
         _check(lib().lb_plan_set_plane_threads(self._h, int(threads)))
+
+    def lb_plan_set_plane_split(self, split, threads=0):
+        """Inner iteration in pair-split order (1: half-plane pass, two workgroups per plane) or not (0)."""
+        _check(lib().lb_plan_set_plane_split(self._h, int(split), int(threads)))
+
+    def lb_plan_get_plane_variant(self):
+        """(split, threads) of the inner iteration's plane stage in use."""
+        sp, nt = C.c_int(), C.c_int()
+        _check(lib().lb_plan_get_plane_variant(self._h, C.byref(sp), C.byref(nt)))
+        return sp.value, nt.value
 
     def lb_energy_grad(self, params, psi, energy=None, grad=None, want_grad=True):
         self._sync_stream()

@@ -52,17 +52,24 @@ def _oracle_iterations(r, k):
 
 @pytest.mark.parametrize("r,direct", [(0.1, 0), (0.1, 1), (1.0, 0)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_bcc128_subproblem_iterations_match_oracle(r, direct, precision, tol):
+@pytest.mark.parametrize("split", [0, 1])
+def test_bcc128_subproblem_iterations_match_oracle(r, direct, precision, tol, split):
     """Five iterations of Algorithm 3 at the 128^3 BCC input through the
     benchmark's kernels, element by element against the oracle's five. With
     r = 0.1 the constraint is active (lambda > 0): the Newton kernel's series
     form (direct = 0, the benchmark's) and its full spectral sums (direct = 1)
-    are both checked; with r = 1 the iterates stay interior (lambda = 0)."""
+    are both checked; with r = 1 the iterates stay interior (lambda = 0).
+    Both orders of the inner iteration the benchmark's autotuner chooses from:
+    one 1024-thread workgroup per plane, and the pair-split order with its
+    half-plane pass (built-in thread count)."""
     inst, m, g_hat, eta = _bcc128()
-    print(f"bcc 128^3 subproblem r={r} direct={direct} {precision}", flush=True)
+    print(f"bcc 128^3 subproblem r={r} direct={direct} {precision} split={split}", flush=True)
     ref = _oracle_iterations(r, 5)
     plan = lb.Plan(inst.grid.n, inst.grid.box, precision=precision)
-    plan.lb_plan_set_plane_threads(1024)  # the variant the benchmark's autotuner picks on this grid
+    if split:
+        plan.lb_plan_set_plane_split(1, 0)
+    else:
+        plan.lb_plan_set_plane_threads(1024)
     d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(inst.psi0), dev(O.inv(g_hat)), r,
                                         lb.sub_opts(eta=eta, eps_sub=0.0, max_inner=5, newton_direct=direct))
     d = host(d)

@@ -550,9 +550,17 @@ def test_plane_pass_variants_give_the_same_results(precision):
         res[nt] = (host(d), info.iters, info.lambda_, host(s), it)
     tuned = plan.lb_plan_autotune(prm, dev(psi), reps=5)
     assert tuned in (256, 512, 1024)
+    split, threads = plan.lb_plan_get_plane_variant()
+    assert threads == tuned
     d, info, rc = plan.lb_tr_subproblem(prm, dev(psi), g, 0.5, lb.sub_opts(eps_sub=eps, max_inner=300))
-    # the autotuned plan runs the variant it reports
-    assert np.array_equal(host(d), res[tuned][0]) and (info.iters, info.lambda_) == res[tuned][1:3]
+    # the autotuned plan runs the variant it reports (either inner-iteration order)
+    if split:
+        pinned = lb.Plan(shape, box, precision=precision)
+        pinned.lb_plan_set_plane_split(1, threads)
+        dp, infop, _ = pinned.lb_tr_subproblem(prm, dev(psi), g, 0.5, lb.sub_opts(eps_sub=eps, max_inner=300))
+        assert np.array_equal(host(d), host(dp)) and (info.iters, info.lambda_) == (infop.iters, infop.lambda_)
+    else:
+        assert np.array_equal(host(d), res[tuned][0]) and (info.iters, info.lambda_) == res[tuned][1:3]
     ref = res[1024]
     assert np.array_equal(res[0][0], ref[0])  # the built-in choice at 128 is 1024
     tol = 1e-12 if precision == "fp64" else 1e-5

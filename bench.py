@@ -392,11 +392,12 @@ def main():
     def choose_variant(p):
         """The inner iteration's plane stage: autotuned, or pinned by --plane-split."""
         if args.plane_split == "auto":
-            p.lb_plan_autotune(prm, psi0, reps=20)
+            p.lb_plan_autotune(prm, psi0, reps=50)
         else:
             p.lb_plan_set_plane_split(int(args.plane_split), 0)
-        split, threads = p.lb_plan_get_plane_variant()
-        return {"pair_split": split, "plane_pass_threads": threads, "chosen_by": "autotuner" if args.plane_split == "auto" else "pinned"}
+        split, threads, cplan = p.lb_plan_get_variant()
+        return {"pair_split": split, "plane_pass_threads": threads, "column_plan": cplan,
+                "chosen_by": "autotuner" if args.plane_split == "auto" else "pinned"}
 
     if args.kernel_sample:
         sp = plan if args.sample_precision == "fp64" else lb.Plan(n, box, precision="fp32")

@@ -391,12 +391,14 @@ int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double
 /* Autotuner: on grids whose inner iteration uses the plane pass (3D with
  * n1 = n2 >= 64), time the inner iteration's three passes (Section 3.2: the
  * scaled inverse, the product with Gamma', the forward update) in each built
- * variant: one workgroup per plane with 256, 512 or 1024 threads, and the
+ * variant: one workgroup per plane with 256, 512 or 1024 threads, or the
  * pair-split order (lb_plan_set_plane_split) with 256, 512 or 1024 threads per
- * half-plane workgroup, `reps` iterations each on the plan's own buffers
- * (Gamma' from psi), and use the fastest from then on. *threads receives the
- * chosen variant's thread count (0 when the plan has nothing to tune;
- * lb_plan_get_plane_variant tells the order). Synchronises the stream;
+ * half-plane workgroup, each with every built radix plan of the axis-0 passes
+ * (lb_plan_set_column_plan), `reps` iterations each on the plan's own buffers
+ * (Gamma' from psi) in two interleaved rounds (each candidate keeps its faster
+ * round), and use the fastest from then on. *threads receives the
+ * chosen plane stage's thread count (0 when the plan has nothing to tune;
+ * lb_plan_get_variant tells the whole choice). Synchronises the stream;
  * overwrites workspaces only. */
 int lb_plan_autotune(lb_plan *plan, const lb_params *params, const double *psi, int reps, int *threads);
 
@@ -424,10 +426,19 @@ int lb_plan_set_plane_threads(lb_plan *plan, int threads);
  * The Hessian products of CONTRACT and Lanczos keep one workgroup per plane. */
 int lb_plan_set_plane_split(lb_plan *plan, int split, int threads);
 
-/* The inner iteration's order in use: *split = 1 for the pair-split order,
- * and *threads the plane or half-plane pass's thread count (both 0 when the
- * grid has no plane pass). */
-int lb_plan_get_plane_variant(lb_plan *plan, int *split, int *threads);
+/* Radix plan of the inner iteration's two axis-0 passes (the same columns
+ * per workgroup in each): 0, radix 8 first (the built-in plan); 1, radix 4
+ * first (more threads per transform, one pass more at length 128); 2, radix
+ * 16 first (fewer threads, one pass fewer). Plans 1 and 2 exist for axis-0
+ * lengths 64 to 256 (LB_ERR_UNSUPPORTED otherwise; LB_ERR_ARG for other
+ * values). The plans compute the same transforms: results agree to rounding,
+ * and each is deterministic. */
+int lb_plan_set_column_plan(lb_plan *plan, int column_plan);
+
+/* The inner iteration's variant in use: *split = 1 for the pair-split order,
+ * *threads the plane or half-plane pass's thread count (both 0 when the grid
+ * has no plane pass), *column_plan the axis-0 passes' radix plan. */
+int lb_plan_get_variant(lb_plan *plan, int *split, int *threads, int *column_plan);
 
 #ifdef __cplusplus
 }

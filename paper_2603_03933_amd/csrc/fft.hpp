@@ -63,11 +63,34 @@ constexpr int span_before(int N, int p) {  // product of the radices of passes <
   for (int i = 0; i < p; ++i) s *= radix_at(N, i);
   return s;
 }
+// Radix plan 2: radix 4 while 4 divides what is left, then 2s and 3s (more,
+// shorter passes: N = 128 as 4, 4, 4, 2 with 32 threads per transform).
+constexpr int radix_at4(int N, int p) {
+  int n = N, i = 0;
+  while (n % 4 == 0) {
+    if (i == p) return 4;
+    n /= 4;
+    ++i;
+  }
+  while (n % 2 == 0) {
+    if (i == p) return 2;
+    n /= 2;
+    ++i;
+  }
+  while (n % 3 == 0) {
+    if (i == p) return 3;
+    n /= 3;
+    ++i;
+  }
+  return 0;
+}
 // Radix plan 1: a first pass of radix 16 when 16 divides N, then plan 0
 // (two passes for N = 128 instead of three; used where data lives in LDS).
 template <int PLAN> constexpr int radix_p(int N, int p) {
   if constexpr (PLAN == 0) {
     return radix_at(N, p);
+  } else if constexpr (PLAN == 2) {
+    return radix_at4(N, p);
   } else {
     if (N % 16 == 0 && N > 16) return p == 0 ? 16 : radix_at(N / 16, p - 1);
     return radix_at(N, p);

@@ -153,13 +153,21 @@ constexpr int pow2_floor(int x) {
   while (p * 2 <= x) p *= 2;
   return p;
 }
-template <int N> struct Cfg {
-  static constexpr int TPF = Shape<N>::TPF;
-  // 256 threads, or 512 for long transforms so that a workgroup still spans
-  // 16 adjacent columns (>= 128 B runs per row in FP32)
-  static constexpr int C0 = pow2_floor((TPF >= 32 ? 512 : 256) / TPF);
+// Column-pass shape. V = 0: radix plan 0 (8s first), TPF = N / 8 threads per
+// transform; 256 threads per workgroup, or 512 for long transforms so that a
+// workgroup still spans 16 adjacent columns (>= 128 B runs per row in FP32).
+// V = 1: radix plan 2 (4s first: more threads per transform, one pass more at
+// N = 128); V = 2: radix plan 1 (16 first: fewer threads, one pass fewer). The
+// variants keep the C columns of V = 0 (autotuner candidates for the inner
+// iteration's axis-0 passes; ok: they fit a workgroup).
+template <int N, int V = 0> struct Cfg {
+  static constexpr int PLAN = V == 0 ? 0 : (V == 1 ? 2 : 1);
+  static constexpr int TPF0 = Shape<N>::TPF;
+  static constexpr int C0 = pow2_floor((TPF0 >= 32 ? 512 : 256) / TPF0);
   static constexpr int C = C0 > 64 ? 64 : (C0 < 1 ? 1 : C0);  // transforms per workgroup
-  static constexpr int NT = C * TPF;                            // threads per workgroup
+  static constexpr int TPF = N / lbfft::radix_p<PLAN>(N, 0);    // threads per transform
+  static constexpr int NT = C * TPF;                             // threads per workgroup
+  static constexpr bool ok = NT >= 64 && NT <= 1024 && lbfft::npass_p<PLAN>(N) > 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -441,11 +449,11 @@ template <typename T, int N, int NT, int STRIDE = 1> struct TwStage {
 // Ops are stateless: begin(b) returns per-workgroup state and column(...)
 // per-column state by value; fetch(...) returns what the final store needs
 // besides the transform output (loaded ahead of the last pass).
-template <typename T, int N, bool INV, class Op>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__restrict__ tw, const Op op) {
+template <typename T, int N, bool INV, class Op, int V = 0>
+__global__ __launch_bounds__((Cfg<N, V>::NT)) void k_cols(ColGeo cg, const c2<T> *__restrict__ tw, const Op op) {
   using C = c2<T>;
-  constexpr int CC = Cfg<N>::C;
-  constexpr int NT = Cfg<N>::NT;
+  constexpr int CC = Cfg<N, V>::C;
+  constexpr int NT = Cfg<N, V>::NT;
   __shared__ C lds[N * CC];
   // the twiddle table in LDS: loaded with the first pass (which needs none),
   // stored before its barrier, so later passes read it without a memory round trip
@@ -471,7 +479,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols(ColGeo cg, const c2<T> *__r
   const auto bs = op.begin(b);
   const auto cs = op.column(b, mls);
   double acc = 0.0;
-  fft_run<T, N, INV>(
+  fft_run<T, N, INV, 0, Cfg<N, V>::PLAN>(
       t, c, lds, [](int cc, int e) { return e * CC + cc; }, twl,
       [&](int e) -> C {
         if constexpr (Op::eager_loads) {

@@ -56,10 +56,12 @@ struct PassArgs {
   int zero_dc = 0;
   int keep_dc = 0;  // Hessian product: keep Lambda_0 (no projection)
   int step = 0;     // subproblem step index
+  int colv = 0;     // column-pass variant of the inner iteration's axis-0 passes (lbk::Cfg V)
 };
 
 struct NFuncs {
   int C = 0, NT = 0;  // transforms and threads per workgroup
+  int colv_built = 1;  // bit V: the inner iteration's axis-0 passes built in column variant V
   void (*cols_plain)(const PassArgs &, bool inv) = nullptr;
   void (*cols_inv_scale_d)(const PassArgs &) = nullptr;
   void (*cols_fwd_update)(const PassArgs &) = nullptr;
@@ -100,7 +102,10 @@ template <typename T, int N> struct Impl {
   // the ops below come in two forms: orthorhombic (|Bk|^2 without cross
   // terms, the benchmark's) and general lattice; a.g.general picks one
   // (a.cg.hsplit > 0: the pair-split forms that feed and follow the half-plane pass)
-  template <bool GEN, bool SPLIT> static void cols_inv_scale_d_t(const PassArgs &a) {
+  // column variants beyond V = 0 are built for the lengths the 3D inner
+  // iteration uses most (64 .. 256) where they fit a workgroup
+  template <int V> static constexpr bool COLV = V == 0 || (N >= 64 && N <= 256 && lbk::Cfg<N, V>::ok);
+  template <bool GEN, bool SPLIT, int V> static void cols_inv_scale_d_t(const PassArgs &a) {
     lbk::OpInvScaleD<T, GEN, SPLIT> op{};
     op.g = a.g;
     op.p = a.p;
@@ -110,19 +115,28 @@ template <typename T, int N> struct Impl {
     op.st = a.st;
     op.twn = (const C2 *)a.tw1;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, SPLIT>>), dim3(a.nblocks), dim3(NT), 0, a.stream,
-              a.cg, (const C2 *)a.tw, op);
+    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, SPLIT>, V>), dim3(a.nblocks),
+              dim3(lbk::Cfg<N, V>::NT), 0, a.stream, a.cg, (const C2 *)a.tw, op);
+  }
+  template <bool GEN, bool SPLIT> static void cols_inv_scale_d_v(const PassArgs &a) {
+    if constexpr (COLV<1>) {
+      if (a.colv == 1) return cols_inv_scale_d_t<GEN, SPLIT, 1>(a);
+    }
+    if constexpr (COLV<2>) {
+      if (a.colv == 2) return cols_inv_scale_d_t<GEN, SPLIT, 2>(a);
+    }
+    cols_inv_scale_d_t<GEN, SPLIT, 0>(a);
   }
   static void cols_inv_scale_d(const PassArgs &a) {
     if (a.cg.hsplit) {
-      if (a.g.general) cols_inv_scale_d_t<true, true>(a);
-      else cols_inv_scale_d_t<false, true>(a);
+      if (a.g.general) cols_inv_scale_d_v<true, true>(a);
+      else cols_inv_scale_d_v<false, true>(a);
     } else {
-      if (a.g.general) cols_inv_scale_d_t<true, false>(a);
-      else cols_inv_scale_d_t<false, false>(a);
+      if (a.g.general) cols_inv_scale_d_v<true, false>(a);
+      else cols_inv_scale_d_v<false, false>(a);
     }
   }
-  template <bool GEN, bool SPLIT> static void cols_fwd_update_t(const PassArgs &a) {
+  template <bool GEN, bool SPLIT, int V> static void cols_fwd_update_t(const PassArgs &a) {
     lbk::OpFwdUpdate<T, GEN, SPLIT> op{};
     op.g = a.g;
     op.p = a.p;
@@ -136,16 +150,25 @@ template <typename T, int N> struct Impl {
     op.inv_n = a.inv_n;
     op.cpi = a.cg.cpi;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T, GEN, SPLIT>>), dim3(a.nblocks), dim3(NT), 0, a.stream,
-              a.cg, (const C2 *)a.tw, op);
+    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T, GEN, SPLIT>, V>), dim3(a.nblocks),
+              dim3(lbk::Cfg<N, V>::NT), 0, a.stream, a.cg, (const C2 *)a.tw, op);
+  }
+  template <bool GEN, bool SPLIT> static void cols_fwd_update_v(const PassArgs &a) {
+    if constexpr (COLV<1>) {
+      if (a.colv == 1) return cols_fwd_update_t<GEN, SPLIT, 1>(a);
+    }
+    if constexpr (COLV<2>) {
+      if (a.colv == 2) return cols_fwd_update_t<GEN, SPLIT, 2>(a);
+    }
+    cols_fwd_update_t<GEN, SPLIT, 0>(a);
   }
   static void cols_fwd_update(const PassArgs &a) {
     if (a.cg.hsplit) {
-      if (a.g.general) cols_fwd_update_t<true, true>(a);
-      else cols_fwd_update_t<false, true>(a);
+      if (a.g.general) cols_fwd_update_v<true, true>(a);
+      else cols_fwd_update_v<false, true>(a);
     } else {
-      if (a.g.general) cols_fwd_update_t<true, false>(a);
-      else cols_fwd_update_t<false, false>(a);
+      if (a.g.general) cols_fwd_update_v<true, false>(a);
+      else cols_fwd_update_v<false, false>(a);
     }
   }
   template <bool GEN> static void cols_fwd_hess_t(const PassArgs &a) {
@@ -242,6 +265,7 @@ template <typename T, int N> struct Impl {
     NFuncs f;
     f.C = lbk::Cfg<N>::C;
     f.NT = NT;
+    f.colv_built = 1 | (COLV<1> ? 2 : 0) | (COLV<2> ? 4 : 0);
     f.cols_plain = &cols_plain;
     f.cols_inv_scale_d = &cols_inv_scale_d;
     f.cols_fwd_update = &cols_fwd_update;

@@ -150,6 +150,7 @@ struct lb_plan {
   int plane_nt = -1;          // autotuned plane-pass variant (index into plane_inner_nt), -1: built-in choice
   int plane_split = 0;        // inner iteration in pair-split order with the half-plane pass (1) or not (0)
   int half_nt = -1;           // its thread-count variant (index into plane_half_nt), -1: built-in choice
+  int colv = 0;               // column variant (radix plan) of the inner iteration's axis-0 passes
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
   // general Bravais lattice (lb_plan_set_lattice): the reciprocal metric
   // G = B^T B by axis slot (0 leading, 1 middle, 2 last); unused when 0
@@ -1185,6 +1186,7 @@ static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
   a.st = P->st;
   a.cg.hsplit = hsplit;
   a.tw1 = split ? TW(P, 1, prec) : nullptr;
+  a.colv = P->colv;
   {
     KT kt_(P, "col0_inv_scale_d");
     F(P, 0, prec)->cols_inv_scale_d(a);
@@ -1239,6 +1241,7 @@ static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
   }
   PassArgs u = args_col(P, prec, B, p, 0);
   u.cg.hsplit = hsplit;
+  u.colv = P->colv;
   u.in = P->WT;
   u.b0 = P->B0;
   u.b1 = P->B1;
@@ -2330,16 +2333,28 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
   LB_HIP(hipEventCreate(&e0));
   LB_HIP(hipEventCreate(&e1));
   const int nts[3] = {256, 512, 1024};
-  const int keep_split = P->plane_split, keep_nt = P->plane_nt, keep_half = P->half_nt;
-  float best = 0.0f;
-  int pick_split = -1, pick = -1;
-  for (int split = 0; split < 2; ++split) {
+  const int keep_split = P->plane_split, keep_nt = P->plane_nt, keep_half = P->half_nt, keep_colv = P->colv;
+  const int colv_built = F(P, 0, prec)->colv_built;
+  // every candidate is timed in two rounds (interleaved, so that clock and
+  // cache drift hit all alike) and keeps its faster round
+  struct Cand {
+    int split, v, cv;
+    float ms;
+  };
+  std::vector<Cand> cands;
+  for (int split = 0; split < 2; ++split)
     for (int v = 0; v < 3; ++v) {
       if (split && (!split_ok(P, prec) || !f1->plane_half_nt[v])) continue;
       if (!split && !f1->plane_inner_nt[v]) continue;
-      P->plane_split = split;
-      if (split) P->half_nt = v;
-      else P->plane_nt = v;
+      for (int cv = 0; cv < 3; ++cv)
+        if (colv_built >> cv & 1) cands.push_back(Cand{split, v, cv, 0.0f});
+    }
+  for (int round = 0; round < 2; ++round) {
+    for (Cand &c : cands) {
+      P->plane_split = c.split;
+      if (c.split) P->half_nt = c.v;
+      else P->plane_nt = c.v;
+      P->colv = c.cv;
       enqueue_passes(P, p, 1, 1);  // warm
       LB_HIP(hipEventRecord(e0, P->stream));
       for (int r = 0; r < reps; ++r) enqueue_passes(P, p, r + 2, 1);
@@ -2347,22 +2362,29 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
       LB_HIP(hipEventSynchronize(e1));
       float ms = 0.0f;
       LB_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (pick < 0 || ms < best) {
-        best = ms;
-        pick = v;
-        pick_split = split;
-      }
+      c.ms = round == 0 ? ms : std::min(c.ms, ms);
     }
   }
+  int pick_split = -1, pick = -1, pick_colv = 0;
+  float best = 0.0f;
+  for (const Cand &c : cands)
+    if (pick < 0 || c.ms < best) {
+      best = c.ms;
+      pick = c.v;
+      pick_split = c.split;
+      pick_colv = c.cv;
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   P->plane_split = keep_split;
   P->plane_nt = keep_nt;
   P->half_nt = keep_half;
+  P->colv = keep_colv;
   LB_TRY(check_launch("lb_plan_autotune"));
   P->plane_split = pick_split;
   if (pick_split) P->half_nt = pick;
   else P->plane_nt = pick;
+  P->colv = pick_colv;
   *threads = nts[pick];
   return LB_OK;
 }
@@ -2383,10 +2405,11 @@ extern "C" int lb_plan_set_plane_split(lb_plan *P, int split, int threads) {
   return LB_OK;
 }
 
-extern "C" int lb_plan_get_plane_variant(lb_plan *P, int *split, int *threads) {
-  if (!P || !split || !threads) return fail(LB_ERR_ARG, "null argument");
+extern "C" int lb_plan_get_variant(lb_plan *P, int *split, int *threads, int *column_plan) {
+  if (!P || !split || !threads || !column_plan) return fail(LB_ERR_ARG, "null argument");
   *split = 0;
   *threads = 0;
+  *column_plan = P->colv;
   const int prec = P->prec;
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
   if (!f1 || !f1->plane_inner || P->n1 != P->nl) return LB_OK;
@@ -2399,6 +2422,15 @@ extern "C" int lb_plan_get_plane_variant(lb_plan *P, int *split, int *threads) {
   } else {
     *threads = f1->plane_nt_default;
   }
+  return LB_OK;
+}
+
+extern "C" int lb_plan_set_column_plan(lb_plan *P, int column_plan) {
+  if (!P) return fail(LB_ERR_ARG, "null plan");
+  if (column_plan < 0 || column_plan > 2) return fail(LB_ERR_ARG, "column plan must be 0, 1 or 2");
+  if (!(F(P, 0, P->prec)->colv_built >> column_plan & 1))
+    return fail(LB_ERR_UNSUPPORTED, "column plan not built for this axis-0 length");
+  P->colv = column_plan;
   return LB_OK;
 }
 

@@ -155,7 +155,8 @@ _SIGS = {
     "lb_plan_autotune": (_I, [_P, C.POINTER(LbParams), _P, _I, C.POINTER(_I)]),
     "lb_plan_set_plane_threads": (_I, [_P, _I]),
     "lb_plan_set_plane_split": (_I, [_P, _I, _I]),
-    "lb_plan_get_plane_variant": (_I, [_P, C.POINTER(_I), C.POINTER(_I)]),
+    "lb_plan_set_column_plan": (_I, [_P, _I]),
+    "lb_plan_get_variant": (_I, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
 }
 
 
@@ -318,11 +319,15 @@ class Plan:
         """Inner iteration in pair-split order (1: half-plane pass, two workgroups per plane) or not (0)."""
         _check(lib().lb_plan_set_plane_split(self._h, int(split), int(threads)))
 
-    def lb_plan_get_plane_variant(self):
-        """(split, threads) of the inner iteration's plane stage in use."""
-        sp, nt = C.c_int(), C.c_int()
-        _check(lib().lb_plan_get_plane_variant(self._h, C.byref(sp), C.byref(nt)))
-        return sp.value, nt.value
+    def lb_plan_set_column_plan(self, column_plan):
+        """Radix plan of the inner iteration's axis-0 passes (0: 8 first, 1: 4 first, 2: 16 first)."""
+        _check(lib().lb_plan_set_column_plan(self._h, int(column_plan)))
+
+    def lb_plan_get_variant(self):
+        """(split, threads, column_plan) of the inner iteration in use."""
+        sp, nt, cp = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().lb_plan_get_variant(self._h, C.byref(sp), C.byref(nt), C.byref(cp)))
+        return sp.value, nt.value, cp.value
 
     def lb_energy_grad(self, params, psi, energy=None, grad=None, want_grad=True):
         self._sync_stream()

@@ -550,13 +550,17 @@ def test_plane_pass_variants_give_the_same_results(precision):
         res[nt] = (host(d), info.iters, info.lambda_, host(s), it)
     tuned = plan.lb_plan_autotune(prm, dev(psi), reps=5)
     assert tuned in (256, 512, 1024)
-    split, threads = plan.lb_plan_get_plane_variant()
+    split, threads, cplan = plan.lb_plan_get_variant()
     assert threads == tuned
     d, info, rc = plan.lb_tr_subproblem(prm, dev(psi), g, 0.5, lb.sub_opts(eps_sub=eps, max_inner=300))
     # the autotuned plan runs the variant it reports (either inner-iteration order)
-    if split:
+    if split or cplan:
         pinned = lb.Plan(shape, box, precision=precision)
-        pinned.lb_plan_set_plane_split(1, threads)
+        if split:
+            pinned.lb_plan_set_plane_split(1, threads)
+        else:
+            pinned.lb_plan_set_plane_threads(threads)
+        pinned.lb_plan_set_column_plan(cplan)
         dp, infop, _ = pinned.lb_tr_subproblem(prm, dev(psi), g, 0.5, lb.sub_opts(eps_sub=eps, max_inner=300))
         assert np.array_equal(host(d), host(dp)) and (info.iters, info.lambda_) == (infop.iters, infop.lambda_)
     else:

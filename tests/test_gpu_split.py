@@ -5,6 +5,7 @@ with two workgroups per plane) against the oracle's Algorithm 3 (Section 3.2),
 on orthorhombic boxes and a general lattice, in FP64 and FP32, for each
 thread count of the half-plane pass; batched instances equal single ones bit
 for bit; the variant API and the autotuner."""
+import functools
 import math
 
 import numpy as np
@@ -65,10 +66,10 @@ def test_split_subproblem_matches_oracle(n, box, precision, tol):
     d_or = O.inv(ref.d)
     plan = lb.Plan(n, box, precision=precision)
     d_plane, info_p, _ = _subproblem(plan, m, psi, g_hat, r, k)
-    assert plan.lb_plan_get_plane_variant() == (0, plan.lb_plan_get_plane_variant()[1])
+    assert plan.lb_plan_get_variant()[0] == 0
     for threads in (256, 512, 1024):
         plan.lb_plan_set_plane_split(1, threads)
-        assert plan.lb_plan_get_plane_variant() == (1, threads)
+        assert plan.lb_plan_get_variant() == (1, threads, 0)
         d, info, rc = _subproblem(plan, m, psi, g_hat, r, k)
         d = host(d)
         err = rms(d - d_or) / rms(d_or)
@@ -78,7 +79,40 @@ def test_split_subproblem_matches_oracle(n, box, precision, tol):
         assert err <= tol
         assert rms(d - host(d_plane)) <= tol * rms(d_or)
     plan.lb_plan_set_plane_split(0, 0)
-    assert plan.lb_plan_get_plane_variant()[0] == 0
+    assert plan.lb_plan_get_variant()[0] == 0
+
+
+@functools.lru_cache(maxsize=4)
+def _oracle_case(i):
+    n, box = GRIDS[i]
+    m = O.Model(O.Grid(n, box), -0.15, 0.25, 1.05, 0.95)
+    psi = I.zero_mean_noise(n, 0.2, 91)
+    g_hat = O.gradient(m, psi)
+    ref = O.imex_subproblem(m, psi, g_hat, 0.05, O.SubOpts(eta=0.1, eps_sub=0.0, max_inner=6))
+    return m, psi, g_hat, ref
+
+
+@pytest.mark.parametrize("i", [0, 2, 3])  # axis-0 lengths 64, 96, 128
+@pytest.mark.parametrize("column_plan", [1, 2])
+@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_column_plans_match_oracle(i, column_plan, split, precision, tol):
+    """The axis-0 passes in radix plans 1 (4 first) and 2 (16 first), in both
+    orders of the inner iteration, against the oracle's iterations."""
+    n, box = GRIDS[i]
+    print(f"column plan {column_plan}, split {split}, {n} {precision}", flush=True)
+    m, psi, g_hat, ref = _oracle_case(i)
+    plan = lb.Plan(n, box, precision=precision)
+    plan.lb_plan_set_column_plan(column_plan)
+    if split:
+        plan.lb_plan_set_plane_split(1, 0)
+    assert plan.lb_plan_get_variant()[0::2] == (split, column_plan)
+    d, info, rc = _subproblem(plan, m, psi, g_hat, 0.05, 6)
+    d_or = O.inv(ref.d)
+    err = rms(host(d) - d_or) / rms(d_or)
+    print(f"  lambda {info.lambda_:.15e} (oracle {ref.lam:.15e}), iterate error {err:.2e}")
+    assert info.iters == ref.iters == 6
+    assert abs(info.lambda_ - ref.lam) <= tol * max(1.0, ref.lam) and err <= tol
 
 
 def test_split_general_lattice_matches_oracle():
@@ -160,6 +194,10 @@ def test_split_api_and_autotune():
     prm = lb.Params(-0.15, 0.25)
     psi = dev(I.zero_mean_noise((64, 64, 64), 0.2, 94))
     threads = plan.lb_plan_autotune(prm, psi, reps=5)
-    split, t2 = plan.lb_plan_get_plane_variant()
-    print(f"autotune 64^3: split {split}, threads {threads}")
-    assert threads in (256, 512, 1024) and t2 == threads and split in (0, 1)
+    split, t2, cp = plan.lb_plan_get_variant()
+    print(f"autotune 64^3: split {split}, threads {threads}, column plan {cp}")
+    assert threads in (256, 512, 1024) and t2 == threads and split in (0, 1) and cp in (0, 1, 2)
+    with pytest.raises(lb.LBError):
+        plan.lb_plan_set_column_plan(3)
+    with pytest.raises(lb.LBError):  # axis-0 length 32: only the built-in plan
+        lb.Plan((32, 32, 32), (4 * math.pi,) * 3).lb_plan_set_column_plan(1)

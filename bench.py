@@ -77,12 +77,16 @@ def kernel_bytes(name: str, prec: str, n) -> float | None:
     return table.get(name)
 
 
+# the files that define the profiled kernels and their launch shapes (the
+# host logic in lb_lib.hip chooses among them; the variant is checked apart)
+KERNEL_SOURCES = ("fft.hpp", "kernels.hpp", "launch.hpp")
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2603_03933_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hpp", ".hip")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -97,12 +101,17 @@ def _pmc():
     return d if d.get("source_hash") == source_hash() else None
 
 
-def traffic_from_profiles(kernel: str, section: str = "kernels"):
+def traffic_from_profiles(kernel: str, section: str = "kernels", variant=None):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources (else None)."""
+    taken on the current kernel sources and (for the inner iteration) in the
+    variant the benchmark ran (else None)."""
     d = _pmc()
     if d is None:
         return None
+    if variant is not None and section == "kernels":
+        want = d.get("variant")
+        if want is None or any(variant.get(k) != v for k, v in want.items()):
+            return None
     k = d.get(section, {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
 
@@ -450,7 +459,7 @@ def main():
     unit_s = sum(v["avg_us"] for v in per_kernel.values()) * 1e-6
     unit_bytes = 32.0 * N
     achieved = unit_bytes / unit_s / 1e9 if unit_s > 0 else None
-    counter = [traffic_from_profiles(k) for k in per_kernel if k != "newton"]
+    counter = [traffic_from_profiles(k, variant=tuned) for k in per_kernel if k != "newton"]
     traffic = sum(counter) if counter and all(c is not None for c in counter) else None
     dominant = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
     dom_alg = kernel_bytes(dominant, "fp64", n)
@@ -471,7 +480,7 @@ def main():
         "dominant_kernel_pass_bytes": {
             "kernel": dominant, "alg_bytes_per_launch": dom_alg, "avg_launch_us": dom_s * 1e6,
             "achieved": dom_alg / dom_s / 1e9, "frac": dom_alg / dom_s / 1e9 / HBM_PEAK_GBS,
-            "traffic": traffic_from_profiles(dominant)},
+            "traffic": traffic_from_profiles(dominant, variant=tuned)},
         "wall_iteration_us": elapsed / max(1, sum(i[0].inner_total for i in infos)) * 1e6,
     }
 

@@ -396,7 +396,8 @@ int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double
  * half-plane workgroup, each with every built radix plan of the axis-0 passes
  * (lb_plan_set_column_plan), `reps` iterations each on the plan's own buffers
  * (Gamma' from psi) in two interleaved rounds (each candidate keeps its faster
- * round), and use the fastest from then on. *threads receives the
+ * round), and use the fastest from then on; the built-in variant stays unless
+ * another is more than 2 % faster. *threads receives the
  * chosen plane stage's thread count (0 when the plan has nothing to tune;
  * lb_plan_get_variant tells the whole choice). Synchronises the stream;
  * overwrites workspaces only. */
@@ -425,6 +426,15 @@ int lb_plan_set_plane_threads(lb_plan *plan, int threads);
  * the same iteration: results agree to rounding, and each is deterministic.
  * The Hessian products of CONTRACT and Lanczos keep one workgroup per plane. */
 int lb_plan_set_plane_split(lb_plan *plan, int split, int threads);
+
+/* Order of lb_hessvec and lb_hessvec_raw on grids with a pair-split order
+ * (see lb_plan_set_plane_split): split = 1 runs the three passes of the
+ * product with two half-plane workgroups per plane and the axis-1 radix-2
+ * steps in the axis-0 pass; 0 with one workgroup per plane; -1 the built-in
+ * choice (lb_hessvec_noalloc always takes the built-in choice).
+ * LB_ERR_UNSUPPORTED when split = 1 and the grid has no such order. Both
+ * orders compute the same product; results agree to rounding. */
+int lb_plan_set_hessvec_split(lb_plan *plan, int split);
 
 /* Radix plan of the inner iteration's two axis-0 passes (the same columns
  * per workgroup in each): 0, radix 8 first (the built-in plan); 1, radix 4

@@ -805,9 +805,15 @@ template <typename T, bool GEN> struct OpFwdHess {
 
 // Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
 // (k = 0 removed unless keep_dc), inverse transform, all in one workgroup pass.
-template <typename T, int N, bool GEN>
+// SPLIT (pair-split order, between the half-plane passes of the product):
+// the loads form Y = Z_0 +- Z_1 of the column pair (k1, k1 + n1/2) and the
+// stores leave s_0 / s_1 (the radix-2 steps of the axis-1 transforms split by
+// the parity of x1, as in the inner iteration's axis-0 passes); tw1 is the
+// axis-1 twiddle table
+template <typename T, int N, bool GEN, bool SPLIT = false>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo g, Prm p, const c2<T> *__restrict__ tw,
-                                                                  c2<T> *data, double inv_n, int keep_dc) {
+                                                                  c2<T> *data, double inv_n, int keep_dc,
+                                                                  const c2<T> *__restrict__ tw1) {
   using C = c2<T>;
   constexpr int CC = Cfg<N>::C;
   __shared__ C lds[N * CC];
@@ -817,16 +823,25 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   const int b = blockIdx.x / cg.bpi;
   const int lb = blockIdx.x - b * cg.bpi;
   const int c = threadIdx.x % CC, t = threadIdx.x / CC;
-  const int ml = lb * CC + c;
+  const int ml = col_of<CC>(cg, lb, c);
   const bool ok = ml < cg.cpi;
   const long base = b * cg.inst + (ok ? ml : 0);  // axis 0: every column starts in the first slab
   const ColInfo ci = col_info<GEN>(g, ok ? ml : 0);
   const double xi = p.xi[b], q = p.q[b];
+  C ptw{T(1), T(0)};  // SPLIT: e^{-2 pi i k'/n1} of a partner column k1 = k' + n1/2
+  if constexpr (SPLIT) {
+    const int k1 = (ok ? ml : 0) / g.nhl, h1 = g.n1 / 2;
+    ptw = tw1[k1 >= h1 ? k1 - h1 : 0];
+  }
   auto lidx = [](int cc, int e) { return e * CC + cc; };
   fft_run<T, N, false>(
       t, c, lds, lidx, twl,
       [&](int e) -> C {
-        const C v = data[base + e * cg.S];
+        C v = data[base + e * cg.S];
+        if constexpr (SPLIT) {
+          const C u = lane_xor2<CC / 2, T>(v);
+          v = c < CC / 2 ? C{v.x + u.x, v.y + u.y} : C{u.x - v.x, u.y - v.y};
+        }
         return ok ? v : C{T(0), T(0)};
       },
       [&](int e) { return kk_e<GEN>(g, e, ci); },
@@ -842,6 +857,15 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   fft_run<T, N, true>(
       t, c, lds, lidx, twl, [&](int e) -> C { return lds[lidx(c, e)]; }, NoFetch{},
       [&](int e, C v, NoAux) {
+        if constexpr (SPLIT) {
+          const C u = lane_xor2<CC / 2, T>(v);
+          if (c < CC / 2) {
+            v = C{v.x + u.x, v.y + u.y};
+          } else {
+            const C d{u.x - v.x, u.y - v.y};
+            v = C{d.x * ptw.x + d.y * ptw.y, d.y * ptw.x - d.x * ptw.y};  // d conj(ptw)
+          }
+        }
         if (ok) data[base + e * cg.S] = v;
       });
 }
@@ -1515,6 +1539,123 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np,
       hv[ia] = double(z.x) + bscale * (gpv(ia) - mean);
       hv[ib] = double(z.y) + bscale * (gpv(ib) - mean);
     }
+  });
+}
+
+// Hessian-vector product in the pair-split order: workgroup (i0, p) of the
+// forward pass takes the physical rows x1 = 2m + p of its plane, transforms
+// the rows, then over m (length N/2) and stores Z_p (rows p N/2 ..); the
+// axis-0 pass (k_cols_fwd_mul_inv with SPLIT) forms Y, applies Lambda and
+// leaves s_0 / s_1; workgroup (i0, p) of the inverse pass transforms s_p over
+// k' (length N/2) into the rows x1 = 2m + p, transforms them back to real
+// values and writes those rows of hv. The mean of Gamma'(psi) v has 2 n0
+// partials per instance.
+template <typename T, int N, int NT = HalfCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_plane_fwd_phys_half(int n0, long nh, long Np, Prm p,
+                                                            const c2<T> *__restrict__ tw, const double *__restrict__ v,
+                                                            const double *__restrict__ psi, c2<T> *out,
+                                                            double *partial) {
+  using C = c2<T>;
+  constexpr int H = N / 2, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = H / 2, PR = plane_pr<N>();
+  __shared__ C L[H * NH];
+  __shared__ C twl[N];
+  __shared__ C twh[H];
+  __shared__ double red[NT / 64];  // wave sums of the mean partial
+  TwStage<T, N, NT> tv;
+  TwStage<T, H, NT, 2> th;
+  tv.load(tw);
+  th.load(tw);
+  const int pl = blockIdx.x >> 1, par = blockIdx.x & 1;
+  const int b = pl / n0, i0 = pl - b * n0;
+  const long off = b * Np + (long)i0 * (N * N);
+  const double tau = p.tau[b], gam = p.gamma[b];
+  double acc = 0.0;
+  // packed row q holds the local rows 2q and 2q + 1: x1 = 4q + p and 4q + 2 + p
+  for (int i = threadIdx.x; i < NRW * N; i += NT) {
+    const int q = i / N, x = i - q * N;
+    const long ia = off + (long)(4 * q + par) * N + x, ib = ia + 2 * N;
+    const double va = v[ia], vb = v[ib];
+    if (partial) {
+      const double pa = psi[ia], pb = psi[ib];
+      acc += (tau - gam * pa + 0.5 * pa * pa) * va + (tau - gam * pb + 0.5 * pb * pb) * vb;
+    }
+    L[q * PR + x] = C{T(va), T(vb)};
+  }
+  tv.store(twl);
+  th.store(twh);
+  if (partial) {  // the wave sums now; the passes' barriers order them before thread 0 adds them
+    const double ws = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
+  }
+  __syncthreads();
+  sk_lds_passes<T, N, false, NT, NRW, true, 0, NP>(L, PR, 1, twl);  // rows, forward
+  C *half = out + b * nh + (long)i0 * (N * NH) + (long)par * (H * NH);
+  auto store = [&](int f, int e, C val, int, int) {
+    if (par) val = cmul(val, twl[e]);
+    half[e * NH + f] = val;
+  };
+  plane_cols_fwd_store<T, N, NT, decltype(store), false, H>(L, twh, store);
+  if (partial && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+template <typename T, int N, int NT = HalfCfg<T, N>::NT>
+__global__ __launch_bounds__(NT) void k_plane_inv_phys_half(int n0, long nh, long Np, Prm p,
+                                                            const c2<T> *__restrict__ tw, const c2<T> *__restrict__ in,
+                                                            const double *__restrict__ psi,
+                                                            const double *__restrict__ v,
+                                                            const double *__restrict__ mpart, double *hv,
+                                                            double bscale) {
+  using C = c2<T>;
+  constexpr int H = N / 2, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = H / 2;
+  constexpr int NW = NT / 64, MV = (1024 + NT - 1) / NT;  // 2 n0 <= 1024 partials
+  __shared__ C L[H * NH];
+  __shared__ C twl[N];
+  __shared__ C twh[H];
+  __shared__ double red[NW];
+  TwStage<T, N, NT> tv;
+  TwStage<T, H, NT, 2> th;
+  tv.load(tw);
+  th.load(tw);
+  const int pl = blockIdx.x >> 1, par = blockIdx.x & 1;
+  const int b = pl / n0, i0 = pl - b * n0;
+  const long off = b * Np + (long)i0 * (N * N);
+  const double tau = p.tau[b], gam = p.gamma[b];
+  const int np = 2 * n0;
+  double mv = 0.0;
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int i = threadIdx.x + u * NT;
+    if (mpart && i < np) mv += mpart[(long)b * np + i];
+  }
+  auto gpv = [&](long i) {
+    const double ps = psi[i];
+    return (tau - gam * ps + 0.5 * ps * ps) * v[i];
+  };
+  const C *half = in + b * nh + (long)i0 * (N * NH) + (long)par * (H * NH);
+  plane_cols_inv_load<T, N, NT, H>(
+      L, twh, [&](int f, int e) -> C { return half[e * NH + f]; },
+      [&]() {
+        tv.store(twl);
+        th.store(twh);
+      });
+  {
+    const double ws = wave_sum(mv);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
+  }
+  __syncthreads();
+  double msum = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) msum += red[w];
+  const double mean = mpart ? msum / (double)Np : 0.0;
+  // packed row f holds the local rows 2f and 2f + 1: x1 = 4f + p and 4f + 2 + p
+  plane_rows_inv<T, N, NT, NRW>(L, twl, [&](int f, int x, C z, int, int) {
+    const long ia = off + (long)(4 * f + par) * N + x, ib = ia + 2 * N;
+    hv[ia] = double(z.x) + bscale * (gpv(ia) - mean);
+    hv[ib] = double(z.y) + bscale * (gpv(ib) - mean);
   });
 }
 

@@ -82,6 +82,9 @@ struct NFuncs {
   int plane_nt_default = 0;  // threads of plane_inner
   void (*plane_fwd_phys)(const PassArgs &, int n0) = nullptr;  // v -> out (+ Gamma' v partials)
   void (*plane_inv_phys)(const PassArgs &, int n0) = nullptr;  // in -> hv
+  // the same two passes in the pair-split order (two workgroups per plane)
+  void (*plane_fwd_phys_half)(const PassArgs &, int n0) = nullptr;
+  void (*plane_inv_phys_half)(const PassArgs &, int n0) = nullptr;
   // whole subproblem of one square 2D instance in one workgroup (null when it does not fit)
   void (*sub2d)(const PassArgs &) = nullptr;
 };
@@ -187,14 +190,20 @@ template <typename T, int N> struct Impl {
     if (a.g.general) cols_fwd_hess_t<true>(a);
     else cols_fwd_hess_t<false>(a);
   }
-  static void cols_fwd_mul_inv(const PassArgs &a) {
-    if (a.g.general)
-      LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N, true>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
-                (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc);
-    else
-      LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N, false>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
-                (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc);
+  template <bool GEN, bool SPLIT> static void cols_fwd_mul_inv_t(const PassArgs &a) {
+    LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N, GEN, SPLIT>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
+              (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc, (const C2 *)a.tw1);
   }
+  static void cols_fwd_mul_inv(const PassArgs &a) {
+    if (a.cg.hsplit) {
+      if (a.g.general) cols_fwd_mul_inv_t<true, true>(a);
+      else cols_fwd_mul_inv_t<false, true>(a);
+    } else {
+      if (a.g.general) cols_fwd_mul_inv_t<true, false>(a);
+      else cols_fwd_mul_inv_t<false, false>(a);
+    }
+  }
+
   static void rows_r2c(const PassArgs &a, int mode) {
     if (mode == 1)
       LB_LAUNCH((lbk::k_rows_r2c<T, N, 1>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.rg, a.g, a.p,
@@ -245,6 +254,17 @@ template <typename T, int N> struct Impl {
       LB_LAUNCH((lbk::k_plane_fwd_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
                 a.g.nh, a.g.N, a.p, (const C2 *)a.tw, a.v, a.psi, (C2 *)a.out, a.partial);
   }
+  static void plane_fwd_phys_half(const PassArgs &a, int n0) {
+    if constexpr (lbk::HalfCfg<T, N>::fits)
+      LB_LAUNCH((lbk::k_plane_fwd_phys_half<T, N>), dim3(2 * n0 * a.g.batch), dim3(lbk::HalfCfg<T, N>::NT), 0,
+                a.stream, n0, a.g.nh, a.g.N, a.p, (const C2 *)a.tw, a.v, a.psi, (C2 *)a.out, a.partial);
+  }
+  static void plane_inv_phys_half(const PassArgs &a, int n0) {
+    if constexpr (lbk::HalfCfg<T, N>::fits)
+      LB_LAUNCH((lbk::k_plane_inv_phys_half<T, N>), dim3(2 * n0 * a.g.batch), dim3(lbk::HalfCfg<T, N>::NT), 0,
+                a.stream, n0, a.g.nh, a.g.N, a.p, (const C2 *)a.tw, (const C2 *)a.in, a.psi, a.v, a.mpart,
+                (double *)a.out, a.scale);
+  }
   static void plane_inv_phys(const PassArgs &a, int n0) {
     if constexpr (lbk::PlaneCfg<T, N>::fits)
       LB_LAUNCH((lbk::k_plane_inv_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
@@ -290,6 +310,8 @@ template <typename T, int N> struct Impl {
     f.plane_nt_default = lbk::PlaneCfg<T, N>::fits ? lbk::PlaneCfg<T, N>::NT : 0;
     f.plane_fwd_phys = lbk::PlaneCfg<T, N>::fits ? &plane_fwd_phys : nullptr;
     f.plane_inv_phys = lbk::PlaneCfg<T, N>::fits ? &plane_inv_phys : nullptr;
+    f.plane_fwd_phys_half = lbk::HalfCfg<T, N>::fits ? &plane_fwd_phys_half : nullptr;
+    f.plane_inv_phys_half = lbk::HalfCfg<T, N>::fits ? &plane_inv_phys_half : nullptr;
     f.sub2d = SUB2D ? &sub2d : nullptr;
     return f;
   }

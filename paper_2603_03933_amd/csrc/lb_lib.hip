@@ -151,6 +151,7 @@ struct lb_plan {
   int plane_split = 0;        // inner iteration in pair-split order with the half-plane pass (1) or not (0)
   int half_nt = -1;           // its thread-count variant (index into plane_half_nt), -1: built-in choice
   int colv = 0;               // column variant (radix plan) of the inner iteration's axis-0 passes
+  int hv_split = -1;          // lb_hessvec in pair-split order: 1 yes, 0 no, -1 built-in choice
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
   // general Bravais lattice (lb_plan_set_lattice): the reciprocal metric
   // G = B^T B by axis slot (0 leading, 1 middle, 2 last); unused when 0
@@ -812,6 +813,29 @@ extern "C" int lb_energy_grad(lb_plan *P, const lb_params *params, const double 
 
 // ---------------------------------------------------------------------------
 // Hessian-vector product on physical fields
+// the inner iteration may run in pair-split order: 3D, plane pass, a built
+// half-plane kernel, column workgroups whose halves pair up without a ragged
+// end ((n1/2) n_half columns a multiple of C/2)
+static bool split_ok(const lb_plan *P, int prec) {
+  if (P->dim != 3 || P->n1 != P->nl || P->n1 % 2) return false;
+  const NFuncs *f1 = F(P, 1, prec);
+  const NFuncs *f0 = F(P, 0, prec);
+  if (!f1 || !f1->plane_inner || f1->plane_half_default < 0 || !f0 || f0->C % 2) return false;
+  const long hcols = (long)(P->n1 / 2) * P->nhl;
+  return hcols % (f0->C / 2) == 0 && bpi_col0(P) * f0->C == 2 * hcols;
+}
+static bool use_split(const lb_plan *P, int prec) { return P->plane_split == 1 && split_ok(P, prec); }
+// lb_hessvec in the pair-split order: where the order exists, when pinned on,
+// or by the built-in choice: FP64 planes of 96 points and more (measured at
+// 128^3: 3-5 % faster in FP64; in FP32 the pair steps cost the axis-0 pass
+// more than the half planes save)
+static bool hv_split_on(const lb_plan *P, int prec) {
+  if (P->hv_split == 0 || !split_ok(P, prec) || P->n0 > 512) return false;
+  const NFuncs *f1 = F(P, 1, prec);
+  if (!f1->plane_fwd_phys_half || !f1->plane_inv_phys_half) return false;
+  return P->hv_split == 1 || (prec == LB_FP64 && P->n1 >= 96);
+}
+
 // ---------------------------------------------------------------------------
 // mode 0: P(L v + Gamma' v); 1: P L v + Gamma' v; 2: (L v + Gamma' v) / N (raw coordinates)
 static int hessvec_phys(lb_plan *P, const lb_params *params, const double *psi, const double *v, double *hv,
@@ -825,6 +849,42 @@ static int hessvec_phys(lb_plan *P, const lb_params *params, const double *psi, 
   const int B = P->batch, prec = P->prec;
   void *work = P->WT;
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
+  if (hv_split_on(P, prec)) {
+    // three passes in the pair-split order: half planes forward, axis 0 with
+    // Lambda and the radix-2 steps of axis 1, half planes inverse
+    const int hsplit = (P->n1 / 2) * P->nhl;
+    PassArgs a = args_col(P, prec, B, p, 1);
+    a.v = v;
+    a.psi = psi;
+    a.out = work;
+    a.partial = project ? P->partial : nullptr;
+    {
+      KT kt_(P, "plane_fwd_phys");
+      f1->plane_fwd_phys_half(a, P->n0);
+    }
+    PassArgs c0 = args_col(P, prec, B, p, 0);
+    c0.out = work;
+    c0.inv_n = bscale / (double)P->N;
+    c0.keep_dc = keep_dc;
+    c0.cg.hsplit = hsplit;
+    c0.tw1 = TW(P, 1, prec);
+    {
+      KT kt_(P, "col0_fwd_mul_inv");
+      F(P, 0, prec)->cols_fwd_mul_inv(c0);
+    }
+    PassArgs o = args_col(P, prec, B, p, 1);
+    o.in = work;
+    o.out = hv;
+    o.psi = psi;
+    o.v = v;
+    o.scale = bscale;
+    o.mpart = project ? P->partial : nullptr;
+    {
+      KT kt_(P, "plane_inv_phys");
+      f1->plane_inv_phys_half(o, P->n0);
+    }
+    return check_launch("lb_hessvec");
+  }
   if (f1 && f1->plane_fwd_phys && P->n1 == P->nl) {
     // three passes: axes 2 and 1 forward per plane, axis 0 with Lambda, axes 1 and 2 inverse per plane
     PassArgs a = args_col(P, prec, B, p, 1);
@@ -1044,7 +1104,7 @@ extern "C" int lb_hessvec_noalloc(const lb_grid *g, const lb_params *params, con
   }
   V.partial = (double *)(sb + kTwBytes);
   V.partial_len = (long)kPartialDoubles;
-  const long need = std::max(bpi_pairs(&V), (long)V.n0);
+  const long need = std::max(bpi_pairs(&V), 2L * V.n0);  // 2 n0: the pair-split order's mean partials
   if (need > (long)kPartialDoubles) return fail(LB_ERR_ARG, "grid needs more partial sums than the fixed workspace holds");
   V.WT = (void *)(sb + kSpecOffset);
   const int rc = hessvec_phys(&V, params, psi, v, hv, project ? 0 : 1);
@@ -1080,18 +1140,6 @@ extern "C" int lb_param_grad_vjp(lb_plan *P, const double *psi, const double *ct
 }
 
 // the plane pass of the inner iteration, in the variant the autotuner chose
-// the inner iteration may run in pair-split order: 3D, plane pass, a built
-// half-plane kernel, column workgroups whose halves pair up without a ragged
-// end ((n1/2) n_half columns a multiple of C/2)
-static bool split_ok(const lb_plan *P, int prec) {
-  if (P->dim != 3 || P->n1 != P->nl || P->n1 % 2) return false;
-  const NFuncs *f1 = F(P, 1, prec);
-  const NFuncs *f0 = F(P, 0, prec);
-  if (!f1 || !f1->plane_inner || f1->plane_half_default < 0 || !f0 || f0->C % 2) return false;
-  const long hcols = (long)(P->n1 / 2) * P->nhl;
-  return hcols % (f0->C / 2) == 0 && bpi_col0(P) * f0->C == 2 * hcols;
-}
-static bool use_split(const lb_plan *P, int prec) { return P->plane_split == 1 && split_ok(P, prec); }
 
 static void plane_pass(lb_plan *P, const NFuncs *f1, const PassArgs &a) {
   if (P->plane_nt >= 0 && f1->plane_inner_nt[P->plane_nt]) f1->plane_inner_nt[P->plane_nt](a, P->n0);
@@ -2374,6 +2422,16 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
       pick_split = c.split;
       pick_colv = c.cv;
     }
+  // the built-in variant (one workgroup per plane, built-in threads, column
+  // plan 0) stays unless another is faster by more than 2 %: near-ties are
+  // timing noise, and in FP32 the variants' rounding can change a solve's path
+  const int v0 = f1->plane_nt_default == 256 ? 0 : f1->plane_nt_default == 512 ? 1 : 2;
+  for (const Cand &c : cands)
+    if (c.split == 0 && c.v == v0 && c.cv == 0 && c.ms <= 1.02f * best) {
+      pick = c.v;
+      pick_split = 0;
+      pick_colv = 0;
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   P->plane_split = keep_split;
@@ -2422,6 +2480,14 @@ extern "C" int lb_plan_get_variant(lb_plan *P, int *split, int *threads, int *co
   } else {
     *threads = f1->plane_nt_default;
   }
+  return LB_OK;
+}
+
+extern "C" int lb_plan_set_hessvec_split(lb_plan *P, int split) {
+  if (!P) return fail(LB_ERR_ARG, "null plan");
+  if (split < -1 || split > 1) return fail(LB_ERR_ARG, "split must be -1, 0 or 1");
+  if (split == 1 && !split_ok(P, P->prec)) return fail(LB_ERR_UNSUPPORTED, "this grid has no pair-split order");
+  P->hv_split = split;
   return LB_OK;
 }
 

@@ -156,6 +156,7 @@ _SIGS = {
     "lb_plan_set_plane_threads": (_I, [_P, _I]),
     "lb_plan_set_plane_split": (_I, [_P, _I, _I]),
     "lb_plan_set_column_plan": (_I, [_P, _I]),
+    "lb_plan_set_hessvec_split": (_I, [_P, _I]),
     "lb_plan_get_variant": (_I, [_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)]),
 }
 
@@ -318,6 +319,10 @@ class Plan:
     def lb_plan_set_plane_split(self, split, threads=0):
         """Inner iteration in pair-split order (1: half-plane pass, two workgroups per plane) or not (0)."""
         _check(lib().lb_plan_set_plane_split(self._h, int(split), int(threads)))
+
+    def lb_plan_set_hessvec_split(self, split):
+        """lb_hessvec in pair-split order (1), one workgroup per plane (0) or the built-in choice (-1)."""
+        _check(lib().lb_plan_set_hessvec_split(self._h, int(split)))
 
     def lb_plan_set_column_plan(self, column_plan):
         """Radix plan of the inner iteration's axis-0 passes (0: 8 first, 1: 4 first, 2: 16 first)."""

@@ -115,6 +115,44 @@ def test_column_plans_match_oracle(i, column_plan, split, precision, tol):
     assert abs(info.lambda_ - ref.lam) <= tol * max(1.0, ref.lam) and err <= tol
 
 
+@pytest.mark.parametrize("n,box", GRIDS)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_split_hessvec_matches_oracle(n, box, precision, tol):
+    """lb_hessvec (projected) and lb_hessvec_raw in the pair-split order
+    against the oracle's products (Section 2: Lambda in reciprocal space,
+    Gamma'(psi) pointwise), and against the plane order to rounding; a batch
+    of two fields."""
+    print(f"pair-split Hv {n} {precision}", flush=True)
+    m = O.Model(O.Grid(n, box), -0.2, 0.3, 1.1, 0.9)
+    psi = I.zero_mean_noise(n, 0.4, 95)
+    v = I.hessvec_direction(n, 96)
+    prm = lb.Params(m.tau, m.gamma, m.xi, m.q)
+    plan = lb.Plan(n, box, precision=precision)
+    plan.lb_plan_set_hessvec_split(0)
+    hv_plane = host(plan.lb_hessvec(prm, dev(psi), dev(v)))
+    plan.lb_plan_set_hessvec_split(1)
+    hv = host(plan.lb_hessvec(prm, dev(psi), dev(v)))
+    raw = host(plan.lb_hessvec_raw(prm, dev(psi), dev(v)))
+    h_or = O.hessvec_phys(m, psi, v)
+    scale = rms(O.inv(m.Lam * O.fwd(v))) + rms(O.Gamma_p(psi, m.tau, m.gamma) * v)
+    err = rms(hv - h_or) / scale
+    print(f"  projected: error {err:.2e} of the term scale, vs plane order {rms(hv - hv_plane) / scale:.2e}")
+    assert err <= tol and rms(hv - hv_plane) <= tol * scale
+    r_or = O.hessvec_raw(m, psi, v)
+    assert rms(raw - r_or) <= tol * scale / psi.size
+    # a batch of two fields: instance 1 with other parameters
+    prm2 = [prm, lb.Params(-0.1, 0.2, 1.1, 0.9)]
+    psi2 = np.stack([psi, I.zero_mean_noise(n, 0.3, 97)])
+    v2 = np.stack([v, I.hessvec_direction(n, 98)])
+    pb = lb.Plan(n, box, batch=2, precision=precision)
+    pb.lb_plan_set_hessvec_split(1)
+    hb = host(pb.lb_hessvec(prm2, dev(psi2), dev(v2)))
+    assert np.array_equal(hb[0], hv)  # same kernels, same order: identical bits
+    m2 = O.Model(O.Grid(n, box), -0.1, 0.2, 1.1, 0.9)
+    scale2 = rms(O.inv(m2.Lam * O.fwd(v2[1]))) + rms(O.Gamma_p(psi2[1], m2.tau, m2.gamma) * v2[1])
+    assert rms(hb[1] - O.hessvec_phys(m2, psi2[1], v2[1])) <= tol * scale2
+
+
 def test_split_general_lattice_matches_oracle():
     """A triclinic cell (cross terms in |Bk|^2, the general-lattice kernels):
     pair-split subproblem iterations against the oracle."""
@@ -199,5 +237,9 @@ def test_split_api_and_autotune():
     assert threads in (256, 512, 1024) and t2 == threads and split in (0, 1) and cp in (0, 1, 2)
     with pytest.raises(lb.LBError):
         plan.lb_plan_set_column_plan(3)
+    with pytest.raises(lb.LBError):
+        plan.lb_plan_set_hessvec_split(2)
+    with pytest.raises(lb.LBError):
+        lb.Plan((32, 32, 32), (4 * math.pi,) * 3).lb_plan_set_hessvec_split(1)
     with pytest.raises(lb.LBError):  # axis-0 length 32: only the built-in plan
         lb.Plan((32, 32, 32), (4 * math.pi,) * 3).lb_plan_set_column_plan(1)

@@ -388,12 +388,14 @@ int lb_imex_tr_solve_batch(lb_plan *plan, const lb_params *params, double *psi, 
 int lb_imex_tr_solve_many(lb_plan *const *plans, const lb_params *params, double *const *psi, int count,
                           const lb_tr_opts *opts, int workers, lb_tr_info *infos, int *status);
 
-/* Autotuner: on grids whose inner iteration uses the plane pass (3D with
- * n1 = n2 >= 64), time the inner iteration's three passes (Section 3.2: the
- * scaled inverse, the product with Gamma', the forward update) in each built
- * variant: one workgroup per plane with 256, 512 or 1024 threads, or the
- * pair-split order (lb_plan_set_plane_split) with 256, 512 or 1024 threads per
- * half-plane workgroup, each with every built radix plan of the axis-0 passes
+/* Autotuner: on grids whose inner iteration has a plane pass or a split
+ * order (3D with n1 = n2), time the inner iteration's passes (Section 3.2:
+ * the scaled inverse, the product with Gamma', the forward update) in each
+ * built variant: one workgroup per plane with 256, 512 or 1024 threads (or
+ * the five passes where the plane does not fit in LDS), or the
+ * split order with 2 or 4 parts (lb_plan_set_plane_split) with each built
+ * thread count of its split-plane pass, each with every built radix plan of
+ * the axis-0 passes
  * (lb_plan_set_column_plan), `reps` iterations each on the plan's own buffers
  * (Gamma' from psi) in two interleaved rounds (each candidate keeps its faster
  * round), and use the fastest from then on; the built-in variant stays unless
@@ -411,28 +413,35 @@ int lb_plan_autotune(lb_plan *plan, const lb_params *params, const double *psi, 
  * to rounding, and each variant is deterministic. */
 int lb_plan_set_plane_threads(lb_plan *plan, int threads);
 
-/* Order of the inner iteration on grids with the plane pass (3D, n1 = n2; the
- * product T d of Section 3.2 by pointwise products and FFTs). split = 1 splits
- * the axis-1 transform by the parity of x1 = 2m + p: the axis-0 inverse pass
- * does its first radix-2 step across the column pairs (k1, k1 + n1/2) and the
- * forward update pass its last, and a half-plane pass with two workgroups per
- * plane does the rest (twice the workgroups of the plane pass, half the LDS
- * each). split = 0 keeps one workgroup per plane. threads = 256, 512 or 1024
- * pins the half-plane pass's thread count, 0 keeps the built-in one (with
- * split = 0 a nonzero count pins the plane pass's, as
- * lb_plan_set_plane_threads). LB_ERR_UNSUPPORTED when split = 1 and the grid
- * has no such order (the (n1/2)(n2/2 + 1) columns with k1 < n1/2 must fill
- * whole column workgroups); LB_ERR_ARG for other values. Both orders compute
- * the same iteration: results agree to rounding, and each is deterministic.
- * The Hessian products of CONTRACT and Lanczos keep one workgroup per plane. */
+/* Order of the inner iteration on 3D grids with n1 = n2 (the product T d of
+ * Section 3.2 by pointwise products and FFTs). split = 1 or 2 splits the
+ * axis-1 transform by x1 mod K with K = 2 or 4 parts: the axis-0 inverse pass
+ * does its first K-point step across the column groups (k1 + q n1/K), the
+ * forward update pass its last, and a split-plane pass with K workgroups per
+ * plane, each holding 1/K of the plane in LDS, does the rest (twice or four
+ * times the workgroups of the plane pass; with 4 parts a 256^3 grid keeps
+ * three passes instead of the five of the column and row kernels).
+ * split = 0 runs one workgroup per plane where the plane fits in LDS, else
+ * the five passes. threads = 256, 512 or 1024 pins the (split-)plane pass's
+ * thread count where that variant is built, 0 keeps the built-in one.
+ * Without a call the plan takes the built-in order: one workgroup per plane
+ * where the plane fits, else the five passes (measured faster at 256^3 than
+ * the four-part order, whose axis-0 passes move 4-column runs). LB_ERR_UNSUPPORTED when the grid
+ * has no such order (the (n1/K)(n2/2 + 1) columns of a part must fill whole
+ * column-workgroup shares; four parts need 16 columns per workgroup);
+ * LB_ERR_ARG for other values. All orders compute the same iteration: results
+ * agree to rounding, and each is deterministic. The Hessian products of
+ * CONTRACT and Lanczos keep one workgroup per plane (or the five passes). */
 int lb_plan_set_plane_split(lb_plan *plan, int split, int threads);
 
-/* Order of lb_hessvec and lb_hessvec_raw on grids with a pair-split order
- * (see lb_plan_set_plane_split): split = 1 runs the three passes of the
- * product with two half-plane workgroups per plane and the axis-1 radix-2
- * steps in the axis-0 pass; 0 with one workgroup per plane; -1 the built-in
- * choice (lb_hessvec_noalloc always takes the built-in choice).
- * LB_ERR_UNSUPPORTED when split = 1 and the grid has no such order. Both
+/* Order of lb_hessvec and lb_hessvec_raw (see lb_plan_set_plane_split):
+ * split = 1 or 2 runs the three passes of the product in the split order
+ * with 2 or 4 parts (K split-plane workgroups per plane, the axis-1 K-point
+ * steps in the axis-0 pass); 0 one workgroup per plane, or the five passes
+ * where the plane does not fit; -1 the built-in choice (2 parts for FP64
+ * planes of 96 points and more that fit in LDS, else none; where the plane
+ * does not fit, 4 parts in FP32 and the five passes in FP64). lb_hessvec_noalloc always takes the
+ * built-in choice. LB_ERR_UNSUPPORTED when the grid has no such order. All
  * orders compute the same product; results agree to rounding. */
 int lb_plan_set_hessvec_split(lb_plan *plan, int split);
 
@@ -445,9 +454,10 @@ int lb_plan_set_hessvec_split(lb_plan *plan, int split);
  * and each is deterministic. */
 int lb_plan_set_column_plan(lb_plan *plan, int column_plan);
 
-/* The inner iteration's variant in use: *split = 1 for the pair-split order,
- * *threads the plane or half-plane pass's thread count (both 0 when the grid
- * has no plane pass), *column_plan the axis-0 passes' radix plan. */
+/* The inner iteration's variant in use: *split = 0, 1 or 2 (no split, 2 or
+ * 4 parts), *threads the plane or split-plane pass's thread count (0 when the
+ * inner iteration runs the five passes), *column_plan the axis-0 passes'
+ * radix plan. */
 int lb_plan_get_variant(lb_plan *plan, int *split, int *threads, int *column_plan);
 
 #ifdef __cplusplus

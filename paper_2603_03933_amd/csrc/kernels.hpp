@@ -385,17 +385,20 @@ struct ColGeo {
   long outer;
   long S;     // element stride along the transformed axis
   long inst;  // instance stride
-  int hsplit = 0;  // > 0: pair-split column order (col_of), hsplit = (n1/2) n_half columns
+  int hsplit = 0;  // > 0: split column order (col_of), hsplit = (n1/K) n_half columns per part
+  int kparts = 2;  // K, the parts of the split order (2 or 4)
 };
 
 // Column of lane c in workgroup lb of an instance. Plain order: lb CC + c.
-// Pair-split order: lanes c < CC/2 take column lb CC/2 + c (k1 < n1/2) and
-// lanes c >= CC/2 the partner of lane c - CC/2, hsplit columns further on
-// (k1 + n1/2), so that a pair sits in lanes c and c ^ CC/2 of one wave.
+// Split order with K parts: lane c belongs to part q = c / (CC/K) and takes
+// column q hsplit + lb CC/K + c mod CC/K, i.e. the column (k1 + q n1/K, k2) of
+// the group whose first member is (k1, k2); the K members of a group sit in
+// lanes CC/K apart in one wave (K = 2: lanes c and c ^ CC/2).
 template <int CC> __device__ __forceinline__ int col_of(const ColGeo &cg, int lb, int c) {
   if (cg.hsplit == 0) return lb * CC + c;
-  constexpr int HC = CC / 2;
-  return c < HC ? lb * HC + c : cg.hsplit + lb * HC + (c - HC);
+  const int qc = CC / cg.kparts;
+  const int q = c / qc;
+  return q * cg.hsplit + lb * qc + (c - q * qc);
 }
 // the value lane ^ M holds (M = 8: row_ror:8 within rows of 16 lanes;
 // otherwise a lane permute)
@@ -411,6 +414,47 @@ template <int M> __device__ __forceinline__ float lane_xor(float x) {
 template <int M, typename T> __device__ __forceinline__ c2<T> lane_xor2(c2<T> v) {
   return c2<T>{lane_xor<M>(v.x), lane_xor<M>(v.y)};
 }
+// DPP row_ror:R within rows of 16 lanes (lane i receives lane (i - R) mod 16)
+template <int R> __device__ __forceinline__ double ror_d(double x) { return dpp_d<0x120 + R, 0xf, false>(x); }
+template <int R> __device__ __forceinline__ float ror_d(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x120 + R, 0xf, 0xf, false));
+}
+template <int R, typename T> __device__ __forceinline__ c2<T> ror2(c2<T> v) {
+  return c2<T>{ror_d<R>(v.x), ror_d<R>(v.y)};
+}
+// v times i^e (e in 0..3: quarter turns)
+template <typename T> __device__ __forceinline__ c2<T> mul_iq(c2<T> v, int e) {
+  const T x = (e & 1) ? -v.y : v.x, y = (e & 1) ? v.x : v.y;
+  return (e & 2) ? c2<T>{-x, -y} : c2<T>{x, y};
+}
+// The K-point step of the split order across the K lanes of a group, for the
+// lane of part q (its own value v = a_q). INV: s = sum_p a_p w^{p q} with
+// w = e^{+2 pi i / K} (the first step of the inverse axis-1 transform split
+// by x1 mod K); forward: Y = sum_p Z_p w^{-q p} (its last step). K = 2: lane
+// ^ CC/2; K = 4 (CC = 16): DPP rotates by 4, 8 and 12 within rows of 16.
+template <int K, int CC, bool INV, typename T> __device__ __forceinline__ c2<T> split_dft(c2<T> v, int q) {
+  if constexpr (K == 2) {
+    const c2<T> u = lane_xor2<CC / 2, T>(v);
+    if (q == 0) return c2<T>{v.x + u.x, v.y + u.y};
+    return c2<T>{u.x - v.x, u.y - v.y};  // a_0 - a_1 (INV) or Z_0 - Z_1 (forward)
+  } else {
+    static_assert(K == 4 && CC == 16, "four parts: groups within rows of 16 lanes");
+    c2<T> a[4];  // a[r]: the value of part (q + r) mod 4
+    a[0] = v;
+    a[1] = ror2<12, T>(v);  // lane i + 4
+    a[2] = ror2<8, T>(v);
+    a[3] = ror2<4, T>(v);  // lane i - 4
+    c2<T> s{T(0), T(0)};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pq = ((q + r) * q) & 3;
+      const c2<T> t = mul_iq<T>(a[r], INV ? pq : (4 - pq) & 3);
+      s = c2<T>{s.x + t.x, s.y + t.y};
+    }
+    return s;
+  }
+}
+
 // pair butterfly of an axis-0 pass on the pair-split order: PAIR = 1 at the
 // loads, 2 at the stores (Op::PAIR; 0 or absent: none)
 template <class Op, class = void> struct OpPair {
@@ -538,14 +582,17 @@ template <typename T> struct StepBlk {
 // pair-split partner column (k1 = k' + n1/2)
 template <typename T> struct ColTw : ColInfo {
   c2<T> tw;
+  int q;  // the column's part
 };
 
 // step t of the subproblem, axis-0 inverse pass: d_t = b_{t-1} / (1 + eta (Lambda + lambda_t)).
-// SPLIT (pair-split order, for the half-plane pass): the stores leave
-// s_0(k') = a(k') + a(k' + n1/2) in row k' and s_1(k') = (a(k') - a(k' + n1/2))
-// e^{+2 pi i k'/n1} in row k' + n1/2 (a: the axis-0 inverse of d_t), the
-// first radix-2 step of the axis-1 inverse transform split by the parity of x1
-template <typename T, bool GEN, bool SPLIT = false> struct OpInvScaleD {
+// KS > 1 (split order with KS parts, for the split-plane pass): the stores
+// leave s_q(k') = e^{+2 pi i k' q/n1} sum_p a(k' + p n1/KS) e^{+2 pi i p q/KS}
+// in row k' + q n1/KS (a: the axis-0 inverse of d_t), the first step of the
+// axis-1 inverse transform split by x1 mod KS (KS = 2: s_0 = a(k') + a(k' +
+// n1/2), s_1 = (a(k') - a(k' + n1/2)) e^{+2 pi i k'/n1})
+template <typename T, bool GEN, int KS = 1> struct OpInvScaleD {
+  static constexpr bool SPLIT = KS > 1;
   static constexpr bool eager_loads = true;
   static constexpr int PAIR = SPLIT ? 2 : 0;
   Geo g;
@@ -556,6 +603,7 @@ template <typename T, bool GEN, bool SPLIT = false> struct OpInvScaleD {
   const c2<T> *twn;  // SPLIT: the axis-1 twiddle table (e^{-2 pi i k/n1})
   int t;  // step index (known to the host when it enqueues the step)
   using CI = std::conditional_t<SPLIT, ColTw<T>, ColInfo>;
+  // (with SPLIT, ColTw::q holds the column's part and tw = e^{-2 pi i k' q/n1})
   __device__ bool skip(int b) const { return st[b].done != 0; }
   __device__ StepBlk<T> begin(int b) const {
     StepBlk<T> s;
@@ -571,17 +619,19 @@ template <typename T, bool GEN, bool SPLIT = false> struct OpInvScaleD {
     CI ci;
     static_cast<ColInfo &>(ci) = col_info<GEN>(g, ml);
     if constexpr (SPLIT) {
-      const int k1 = ml / g.nhl, h1 = g.n1 / 2;
-      ci.tw = twn[k1 >= h1 ? k1 - h1 : 0];
+      const int k1 = ml / g.nhl, part = g.n1 / KS;
+      const int q = k1 / part;
+      ci.q = q;
+      ci.tw = twn[(k1 - q * part) * q];
     }
     return ci;
   }
-  // lane c holds a(k1) of its column, lane c ^ CC/2 that of the partner
+  // lane c holds a(k1) of its column, the other lanes of its group those of
+  // the other parts
   template <int CC> __device__ c2<T> pair_out(const CI &ci, int c, c2<T> v) const {
-    const c2<T> u = lane_xor2<CC / 2, T>(v);
-    if (c < CC / 2) return c2<T>{v.x + u.x, v.y + u.y};
     if constexpr (SPLIT) {
-      const c2<T> d{u.x - v.x, u.y - v.y};
+      const c2<T> d = split_dft<KS, CC, true, T>(v, ci.q);
+      if (ci.q == 0) return d;
       return c2<T>{d.x * ci.tw.x + d.y * ci.tw.y, d.y * ci.tw.x - d.x * ci.tw.y};  // d conj(tw)
     } else {
       return v;
@@ -608,11 +658,12 @@ template <typename T> struct UpdAux {
   c2<T> bp, gg;
   double kk;  // |Bk|^2 of the element
 };
-// SPLIT (pair-split order, after the half-plane pass): the loads form
-// Y(k'') = Z_0(k'') + Z_1(k'') in row k'' and Y(k'' + n1/2) = Z_0(k'') - Z_1(k'')
-// from Z_0 in row k'' and Z_1 in row k'' + n1/2, the last radix-2 step of the
-// axis-1 forward transform split by the parity of x1
-template <typename T, bool GEN, bool SPLIT = false> struct OpFwdUpdate {
+// KS > 1 (split order with KS parts, after the split-plane pass): the loads
+// form Y(k'' + q n1/KS) = sum_p Z_p(k'') e^{-2 pi i q p/KS} from Z_p in row
+// k'' + p n1/KS, the last step of the axis-1 forward transform split by
+// x1 mod KS (KS = 2: Y(k'') = Z_0 + Z_1, Y(k'' + n1/2) = Z_0 - Z_1)
+template <typename T, bool GEN, int KS = 1> struct OpFwdUpdate {
+  static constexpr bool SPLIT = KS > 1;
   static constexpr bool eager_loads = true;
   static constexpr int PAIR = SPLIT ? 1 : 0;
   Geo g;
@@ -639,10 +690,10 @@ template <typename T, bool GEN, bool SPLIT = false> struct OpFwdUpdate {
   }
   __device__ ColInfo column(int, int ml) const { return col_info<GEN>(g, ml); }
   __device__ c2<T> load(const StepBlk<T> &, const ColInfo &, long h, int) const { return tmp[h]; }
-  // lane c holds Z_0 (c < CC/2) or Z_1 of its column pair, lane c ^ CC/2 the other
+  // lane c holds Z_q of its column (q = c / (CC/KS)), the other lanes of its
+  // group the other parts
   template <int CC> __device__ c2<T> pair_in(int c, c2<T> v) const {
-    const c2<T> u = lane_xor2<CC / 2, T>(v);
-    return c < CC / 2 ? c2<T>{v.x + u.x, v.y + u.y} : c2<T>{u.x - v.x, u.y - v.y};
+    return split_dft<KS, CC, false, T>(v, c / (CC / KS));
   }
   __device__ UpdAux<T> fetch(const StepBlk<T> &bs, const ColInfo &ci, bool ok, long h, int e) const {
     UpdAux<T> a;
@@ -805,12 +856,12 @@ template <typename T, bool GEN> struct OpFwdHess {
 
 // Hessian-vector product, axis-0: forward transform, multiply by Lambda / N
 // (k = 0 removed unless keep_dc), inverse transform, all in one workgroup pass.
-// SPLIT (pair-split order, between the half-plane passes of the product):
-// the loads form Y = Z_0 +- Z_1 of the column pair (k1, k1 + n1/2) and the
-// stores leave s_0 / s_1 (the radix-2 steps of the axis-1 transforms split by
-// the parity of x1, as in the inner iteration's axis-0 passes); tw1 is the
-// axis-1 twiddle table
-template <typename T, int N, bool GEN, bool SPLIT = false>
+// KS > 1 (split order with KS parts, between the split-plane passes of the
+// product): the loads form Y from the parts Z_p of a column group and the
+// stores leave the parts s_q (the first and last steps of the axis-1
+// transforms split by x1 mod KS, as in the inner iteration's axis-0 passes);
+// tw1 is the axis-1 twiddle table
+template <typename T, int N, bool GEN, int KS = 1>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo g, Prm p, const c2<T> *__restrict__ tw,
                                                                   c2<T> *data, double inv_n, int keep_dc,
                                                                   const c2<T> *__restrict__ tw1) {
@@ -828,20 +879,20 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   const long base = b * cg.inst + (ok ? ml : 0);  // axis 0: every column starts in the first slab
   const ColInfo ci = col_info<GEN>(g, ok ? ml : 0);
   const double xi = p.xi[b], q = p.q[b];
-  C ptw{T(1), T(0)};  // SPLIT: e^{-2 pi i k'/n1} of a partner column k1 = k' + n1/2
-  if constexpr (SPLIT) {
-    const int k1 = (ok ? ml : 0) / g.nhl, h1 = g.n1 / 2;
-    ptw = tw1[k1 >= h1 ? k1 - h1 : 0];
+  // KS > 1: the column's part and e^{-2 pi i k' part/n1} (k1 = k' + part n1/KS)
+  int part = 0;
+  C ptw{T(1), T(0)};
+  if constexpr (KS > 1) {
+    const int k1 = (ok ? ml : 0) / g.nhl, len = g.n1 / KS;
+    part = c / (CC / KS);
+    ptw = tw1[(k1 - part * len) * part];
   }
   auto lidx = [](int cc, int e) { return e * CC + cc; };
   fft_run<T, N, false>(
       t, c, lds, lidx, twl,
       [&](int e) -> C {
         C v = data[base + e * cg.S];
-        if constexpr (SPLIT) {
-          const C u = lane_xor2<CC / 2, T>(v);
-          v = c < CC / 2 ? C{v.x + u.x, v.y + u.y} : C{u.x - v.x, u.y - v.y};
-        }
+        if constexpr (KS > 1) v = split_dft<KS, CC, false, T>(v, part);
         return ok ? v : C{T(0), T(0)};
       },
       [&](int e) { return kk_e<GEN>(g, e, ci); },
@@ -857,14 +908,9 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_cols_fwd_mul_inv(ColGeo cg, Geo 
   fft_run<T, N, true>(
       t, c, lds, lidx, twl, [&](int e) -> C { return lds[lidx(c, e)]; }, NoFetch{},
       [&](int e, C v, NoAux) {
-        if constexpr (SPLIT) {
-          const C u = lane_xor2<CC / 2, T>(v);
-          if (c < CC / 2) {
-            v = C{v.x + u.x, v.y + u.y};
-          } else {
-            const C d{u.x - v.x, u.y - v.y};
-            v = C{d.x * ptw.x + d.y * ptw.y, d.y * ptw.x - d.x * ptw.y};  // d conj(ptw)
-          }
+        if constexpr (KS > 1) {
+          const C d = split_dft<KS, CC, true, T>(v, part);
+          v = part == 0 ? d : C{d.x * ptw.x + d.y * ptw.y, d.y * ptw.x - d.x * ptw.y};  // d conj(ptw)
         }
         if (ok) data[base + e * cg.S] = v;
       });
@@ -1352,49 +1398,51 @@ __global__ __launch_bounds__(NT) void k_plane_inner(int n0, long nh, long Np, co
   });
 }
 
-// Half-plane pass of the inner iteration (pair-split order, n1 = n_last = N):
-// the axis-1 transform of length N split by the parity p of x1 = 2m + p. The
-// axis-0 inverse pass leaves s_0 in rows 0 .. N/2 - 1 of each plane and s_1
-// in rows N/2 .. N - 1 (OpInvScaleD with SPLIT); values at x1 = 2m + p are the
-// length-N/2 inverse transform of s_p. Workgroup (i0, p) transforms its half,
-// does the row transforms with the product with Gamma' on rows x1 = 2m + p,
-// transforms back over m (length N/2) into Y_p and stores
-// Z_p(k'') = e^{-2 pi i p k''/N} Y_p(k'') in the same rows (OpFwdUpdate with
-// SPLIT combines Z_0 and Z_1). Each workgroup touches only its own rows, and
-// holds half a plane in LDS: two workgroups per plane.
-template <typename T, int N> struct HalfCfg {
-  static constexpr int H = N / 2, NH = N / 2 + 1;
-  static constexpr bool fits =
-      PlaneCfg<T, N>::fits && N >= 32 && N % 4 == 0 && (H * NH) % 8 == 0 && lbfft::npass_p<1>(H) > 0;
+// Split-plane pass of the inner iteration (split order with K parts, n1 =
+// n_last = N): the axis-1 transform of length N split by x1 mod K, x1 = Km + p.
+// The axis-0 inverse pass leaves s_p in rows p N/K .. (p + 1) N/K - 1 of each
+// plane (OpInvScaleD with KS = K); values at x1 = Km + p are the length-N/K
+// inverse transform of s_p. Workgroup (i0, p) transforms its part, does the
+// row transforms with the product with Gamma' on rows x1 = Km + p, transforms
+// back over m (length N/K) into Y_p and stores Z_p(k'') = e^{-2 pi i p k''/N}
+// Y_p(k'') in the same rows (OpFwdUpdate with KS = K combines the parts). Each
+// workgroup touches only its own rows and holds 1/K of a plane in LDS: K
+// workgroups per plane (K = 2 at 128^3, K = 4 where a half plane does not fit,
+// as at 256^3).
+template <typename T, int N, int K> struct SplitCfg {
+  static constexpr int L = N / K, NH = N / 2 + 1;
+  static constexpr long LDS = (long)L * NH * sizeof(c2<T>) + (long)(N + L) * sizeof(c2<T>) + 256;
+  static constexpr bool fits = (K == 2 || K == 4) && N % (2 * K) == 0 && L >= 8 && N <= 256 &&
+                               LDS <= 160 * 1024 && lbfft::npass_p<1>(L) > 0 && lbfft::npass_p<1>(N) > 0;
   static constexpr int NT = N >= 96 ? 512 : 256;
 };
-template <typename T, int N, int NT = HalfCfg<T, N>::NT>
-__global__ __launch_bounds__(NT) void k_plane_inner_half(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
-                                                         c2<T> *data, const T *__restrict__ gp, const SubState *st) {
+template <typename T, int N, int K, int NT = SplitCfg<T, N, K>::NT>
+__global__ __launch_bounds__(NT) void k_plane_inner_split(int n0, long nh, long Np, const c2<T> *__restrict__ tw,
+                                                          c2<T> *data, const T *__restrict__ gp, const SubState *st) {
   using C = c2<T>;
-  constexpr int H = N / 2, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = H / 2, PR = plane_pr<N>();
-  static_assert(NRW * PR <= H * NH, "packed rows fit in the half plane");
-  __shared__ C L[H * NH];
-  __shared__ C twl[N];  // length-N twiddles (rows, and Z_1's factor), stored during the first pass
-  __shared__ C twh[H];  // length-N/2 twiddles (axis 1)
+  constexpr int L = N / K, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = L / 2, PR = plane_pr<N>();
+  static_assert(NRW * PR <= L * NH, "packed rows fit in the part");
+  __shared__ C Ls[L * NH];
+  __shared__ C twl[N];  // length-N twiddles (rows, and Z_p's factor), stored during the first pass
+  __shared__ C twh[L];  // length-N/K twiddles (axis 1)
   TwStage<T, N, NT> tv;
-  TwStage<T, H, NT, 2> th;
+  TwStage<T, L, NT, K> th;
   tv.load(tw);
   th.load(tw);
-  const int pl = blockIdx.x >> 1, par = blockIdx.x & 1;
+  const int pl = blockIdx.x / K, par = blockIdx.x - pl * K;
   const int b = pl / n0, i0 = pl - b * n0;
   const bool sk = st && st[b].done;  // applied at the stores
-  C *half = data + b * nh + (long)i0 * (N * NH) + (long)par * (H * NH);
+  C *part = data + b * nh + (long)i0 * (N * NH) + (long)par * (L * NH);
   const T *g = gp + b * Np + (long)i0 * (N * N);
-  plane_cols_inv_load<T, N, NT, H>(
-      L, twh, [&](int f, int e) -> C { return half[e * NH + f]; },
+  plane_cols_inv_load<T, N, NT, L>(
+      Ls, twh, [&](int f, int e) -> C { return part[e * NH + f]; },
       [&]() {
         tv.store(twl);
         th.store(twh);
       });
   __syncthreads();
   // Gamma' for the last inverse row pass: packed row f holds the local rows
-  // 2f and 2f + 1, i.e. x1 = 4f + p and 4f + 2 + p
+  // 2f and 2f + 1, i.e. x1 = 2Kf + p and 2Kf + K + p
   using LastS = PassShape<T, N, true, NT, NRW, false, NP - 1>;
   T g0[LastS::K][LastS::R], g1[LastS::K][LastS::R];
 #pragma unroll
@@ -1405,21 +1453,21 @@ __global__ __launch_bounds__(NT) void k_plane_inner_half(int n0, long nh, long N
 #pragma unroll
       for (int r = 0; r < LastS::R; ++r) {
         const int e = j + r * LastS::NS;
-        g0[k][r] = g[(4 * f + par) * N + e];
-        g1[k][r] = g[(4 * f + 2 + par) * N + e];
+        g0[k][r] = g[(2 * K * f + par) * N + e];
+        g1[k][r] = g[(2 * K * f + K + par) * N + e];
       }
     }
   }
-  plane_rows_inv<T, N, NT, NRW>(L, twl, [&](int f, int e, C v, int k, int r) {
-    L[f * PR + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
+  plane_rows_inv<T, N, NT, NRW>(Ls, twl, [&](int f, int e, C v, int k, int r) {
+    Ls[f * PR + e] = C{v.x * g0[k][r], v.y * g1[k][r]};
   });
   __syncthreads();
-  sk_lds_passes<T, N, false, NT, NRW, true, 0, NP>(L, PR, 1, twl);  // rows, forward
+  sk_lds_passes<T, N, false, NT, NRW, true, 0, NP>(Ls, PR, 1, twl);  // rows, forward
   auto store = [&](int f, int e, C v, int, int) {
-    if (par) v = cmul(v, twl[e]);
-    if (!sk) half[e * NH + f] = v;
+    if (par) v = cmul(v, twl[par * e]);
+    if (!sk) part[e * NH + f] = v;
   };
-  plane_cols_fwd_store<T, N, NT, decltype(store), false, H>(L, twh, store);
+  plane_cols_fwd_store<T, N, NT, decltype(store), false, L>(Ls, twh, store);
 }
 
 // Hessian-vector product, axes 2 and 1 forward from the physical field v:
@@ -1542,44 +1590,45 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys(int n0, long nh, long Np,
   });
 }
 
-// Hessian-vector product in the pair-split order: workgroup (i0, p) of the
-// forward pass takes the physical rows x1 = 2m + p of its plane, transforms
-// the rows, then over m (length N/2) and stores Z_p (rows p N/2 ..); the
-// axis-0 pass (k_cols_fwd_mul_inv with SPLIT) forms Y, applies Lambda and
-// leaves s_0 / s_1; workgroup (i0, p) of the inverse pass transforms s_p over
-// k' (length N/2) into the rows x1 = 2m + p, transforms them back to real
-// values and writes those rows of hv. The mean of Gamma'(psi) v has 2 n0
-// partials per instance.
-template <typename T, int N, int NT = HalfCfg<T, N>::NT>
-__global__ __launch_bounds__(NT) void k_plane_fwd_phys_half(int n0, long nh, long Np, Prm p,
-                                                            const c2<T> *__restrict__ tw, const double *__restrict__ v,
-                                                            const double *__restrict__ psi, c2<T> *out,
-                                                            double *partial) {
+// Hessian-vector product in the split order with K parts: workgroup (i0, p)
+// of the forward pass takes the physical rows x1 = Km + p of its plane,
+// transforms the rows, then over m (length N/K) and stores Z_p (rows p N/K
+// ..); the axis-0 pass (k_cols_fwd_mul_inv with KS = K) forms Y, applies
+// Lambda and leaves the parts s_q; workgroup (i0, p) of the inverse pass
+// transforms s_p over k' (length N/K) into the rows x1 = Km + p, transforms
+// them back to real values and writes those rows of hv. The mean of
+// Gamma'(psi) v has K n0 partials per instance.
+template <typename T, int N, int K, int NT = SplitCfg<T, N, K>::NT>
+__global__ __launch_bounds__(NT) void k_plane_fwd_phys_split(int n0, long nh, long Np, Prm p,
+                                                             const c2<T> *__restrict__ tw,
+                                                             const double *__restrict__ v,
+                                                             const double *__restrict__ psi, c2<T> *out,
+                                                             double *partial) {
   using C = c2<T>;
-  constexpr int H = N / 2, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = H / 2, PR = plane_pr<N>();
-  __shared__ C L[H * NH];
+  constexpr int L = N / K, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = L / 2, PR = plane_pr<N>();
+  __shared__ C Ls[L * NH];
   __shared__ C twl[N];
-  __shared__ C twh[H];
+  __shared__ C twh[L];
   __shared__ double red[NT / 64];  // wave sums of the mean partial
   TwStage<T, N, NT> tv;
-  TwStage<T, H, NT, 2> th;
+  TwStage<T, L, NT, K> th;
   tv.load(tw);
   th.load(tw);
-  const int pl = blockIdx.x >> 1, par = blockIdx.x & 1;
+  const int pl = blockIdx.x / K, par = blockIdx.x - pl * K;
   const int b = pl / n0, i0 = pl - b * n0;
   const long off = b * Np + (long)i0 * (N * N);
   const double tau = p.tau[b], gam = p.gamma[b];
   double acc = 0.0;
-  // packed row q holds the local rows 2q and 2q + 1: x1 = 4q + p and 4q + 2 + p
+  // packed row q holds the local rows 2q and 2q + 1: x1 = 2Kq + p and 2Kq + K + p
   for (int i = threadIdx.x; i < NRW * N; i += NT) {
     const int q = i / N, x = i - q * N;
-    const long ia = off + (long)(4 * q + par) * N + x, ib = ia + 2 * N;
+    const long ia = off + (long)(2 * K * q + par) * N + x, ib = ia + (long)K * N;
     const double va = v[ia], vb = v[ib];
     if (partial) {
       const double pa = psi[ia], pb = psi[ib];
       acc += (tau - gam * pa + 0.5 * pa * pa) * va + (tau - gam * pb + 0.5 * pb * pb) * vb;
     }
-    L[q * PR + x] = C{T(va), T(vb)};
+    Ls[q * PR + x] = C{T(va), T(vb)};
   }
   tv.store(twl);
   th.store(twh);
@@ -1588,13 +1637,13 @@ __global__ __launch_bounds__(NT) void k_plane_fwd_phys_half(int n0, long nh, lon
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ws;
   }
   __syncthreads();
-  sk_lds_passes<T, N, false, NT, NRW, true, 0, NP>(L, PR, 1, twl);  // rows, forward
-  C *half = out + b * nh + (long)i0 * (N * NH) + (long)par * (H * NH);
+  sk_lds_passes<T, N, false, NT, NRW, true, 0, NP>(Ls, PR, 1, twl);  // rows, forward
+  C *part = out + b * nh + (long)i0 * (N * NH) + (long)par * (L * NH);
   auto store = [&](int f, int e, C val, int, int) {
-    if (par) val = cmul(val, twl[e]);
-    half[e * NH + f] = val;
+    if (par) val = cmul(val, twl[par * e]);
+    part[e * NH + f] = val;
   };
-  plane_cols_fwd_store<T, N, NT, decltype(store), false, H>(L, twh, store);
+  plane_cols_fwd_store<T, N, NT, decltype(store), false, L>(Ls, twh, store);
   if (partial && threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < NT / 64; ++w) s += red[w];
@@ -1602,29 +1651,30 @@ __global__ __launch_bounds__(NT) void k_plane_fwd_phys_half(int n0, long nh, lon
   }
 }
 
-template <typename T, int N, int NT = HalfCfg<T, N>::NT>
-__global__ __launch_bounds__(NT) void k_plane_inv_phys_half(int n0, long nh, long Np, Prm p,
-                                                            const c2<T> *__restrict__ tw, const c2<T> *__restrict__ in,
-                                                            const double *__restrict__ psi,
-                                                            const double *__restrict__ v,
-                                                            const double *__restrict__ mpart, double *hv,
-                                                            double bscale) {
+template <typename T, int N, int K, int NT = SplitCfg<T, N, K>::NT>
+__global__ __launch_bounds__(NT) void k_plane_inv_phys_split(int n0, long nh, long Np, Prm p,
+                                                             const c2<T> *__restrict__ tw,
+                                                             const c2<T> *__restrict__ in,
+                                                             const double *__restrict__ psi,
+                                                             const double *__restrict__ v,
+                                                             const double *__restrict__ mpart, double *hv,
+                                                             double bscale) {
   using C = c2<T>;
-  constexpr int H = N / 2, NH = N / 2 + 1, NP = lbfft::npass_p<1>(N), NRW = H / 2;
-  constexpr int NW = NT / 64, MV = (1024 + NT - 1) / NT;  // 2 n0 <= 1024 partials
-  __shared__ C L[H * NH];
+  constexpr int L = N / K, NH = N / 2 + 1, NRW = L / 2;
+  constexpr int NW = NT / 64, MV = (512 * K + NT - 1) / NT;  // K n0 <= 512 K partials
+  __shared__ C Ls[L * NH];
   __shared__ C twl[N];
-  __shared__ C twh[H];
+  __shared__ C twh[L];
   __shared__ double red[NW];
   TwStage<T, N, NT> tv;
-  TwStage<T, H, NT, 2> th;
+  TwStage<T, L, NT, K> th;
   tv.load(tw);
   th.load(tw);
-  const int pl = blockIdx.x >> 1, par = blockIdx.x & 1;
+  const int pl = blockIdx.x / K, par = blockIdx.x - pl * K;
   const int b = pl / n0, i0 = pl - b * n0;
   const long off = b * Np + (long)i0 * (N * N);
   const double tau = p.tau[b], gam = p.gamma[b];
-  const int np = 2 * n0;
+  const int np = K * n0;
   double mv = 0.0;
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -1635,9 +1685,9 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys_half(int n0, long nh, lon
     const double ps = psi[i];
     return (tau - gam * ps + 0.5 * ps * ps) * v[i];
   };
-  const C *half = in + b * nh + (long)i0 * (N * NH) + (long)par * (H * NH);
-  plane_cols_inv_load<T, N, NT, H>(
-      L, twh, [&](int f, int e) -> C { return half[e * NH + f]; },
+  const C *part = in + b * nh + (long)i0 * (N * NH) + (long)par * (L * NH);
+  plane_cols_inv_load<T, N, NT, L>(
+      Ls, twh, [&](int f, int e) -> C { return part[e * NH + f]; },
       [&]() {
         tv.store(twl);
         th.store(twh);
@@ -1651,9 +1701,9 @@ __global__ __launch_bounds__(NT) void k_plane_inv_phys_half(int n0, long nh, lon
 #pragma unroll
   for (int w = 0; w < NW; ++w) msum += red[w];
   const double mean = mpart ? msum / (double)Np : 0.0;
-  // packed row f holds the local rows 2f and 2f + 1: x1 = 4f + p and 4f + 2 + p
-  plane_rows_inv<T, N, NT, NRW>(L, twl, [&](int f, int x, C z, int, int) {
-    const long ia = off + (long)(4 * f + par) * N + x, ib = ia + 2 * N;
+  // packed row f holds the local rows 2f and 2f + 1: x1 = 2Kf + p and 2Kf + K + p
+  plane_rows_inv<T, N, NT, NRW>(Ls, twl, [&](int f, int x, C z, int, int) {
+    const long ia = off + (long)(2 * K * f + par) * N + x, ib = ia + (long)K * N;
     hv[ia] = double(z.x) + bscale * (gpv(ia) - mean);
     hv[ib] = double(z.y) + bscale * (gpv(ib) - mean);
   });

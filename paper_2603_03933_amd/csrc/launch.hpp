@@ -75,16 +75,17 @@ struct NFuncs {
   void (*plane_inner)(const PassArgs &, int n0) = nullptr;
   // the same pass with 256, 512 and 1024 threads (autotuner candidates; null where not built)
   void (*plane_inner_nt[3])(const PassArgs &, int n0) = {nullptr, nullptr, nullptr};
-  // the half-plane pass (pair-split order) with 256, 512 and 1024 threads, and
-  // the built-in thread count (null where it does not apply)
-  void (*plane_half_nt[3])(const PassArgs &, int n0) = {nullptr, nullptr, nullptr};
-  int plane_half_default = -1;
+  // the split-plane pass (split order with 2 or 4 parts: index 0, 1) with
+  // 256, 512 and 1024 threads, and the built-in thread count (null / -1
+  // where it does not apply)
+  void (*plane_split_nt[2][3])(const PassArgs &, int n0) = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  int plane_split_default[2] = {-1, -1};
   int plane_nt_default = 0;  // threads of plane_inner
   void (*plane_fwd_phys)(const PassArgs &, int n0) = nullptr;  // v -> out (+ Gamma' v partials)
   void (*plane_inv_phys)(const PassArgs &, int n0) = nullptr;  // in -> hv
-  // the same two passes in the pair-split order (two workgroups per plane)
-  void (*plane_fwd_phys_half)(const PassArgs &, int n0) = nullptr;
-  void (*plane_inv_phys_half)(const PassArgs &, int n0) = nullptr;
+  // the same two passes in the split order (2 or 4 workgroups per plane: index 0, 1)
+  void (*plane_fwd_phys_split[2])(const PassArgs &, int n0) = {nullptr, nullptr};
+  void (*plane_inv_phys_split[2])(const PassArgs &, int n0) = {nullptr, nullptr};
   // whole subproblem of one square 2D instance in one workgroup (null when it does not fit)
   void (*sub2d)(const PassArgs &) = nullptr;
 };
@@ -104,12 +105,13 @@ template <typename T, int N> struct Impl {
   }
   // the ops below come in two forms: orthorhombic (|Bk|^2 without cross
   // terms, the benchmark's) and general lattice; a.g.general picks one
-  // (a.cg.hsplit > 0: the pair-split forms that feed and follow the half-plane pass)
+  // (a.cg.hsplit > 0: the split forms with a.cg.kparts parts that feed and
+  // follow the split-plane pass)
   // column variants beyond V = 0 are built for the lengths the 3D inner
   // iteration uses most (64 .. 256) where they fit a workgroup
   template <int V> static constexpr bool COLV = V == 0 || (N >= 64 && N <= 256 && lbk::Cfg<N, V>::ok);
-  template <bool GEN, bool SPLIT, int V> static void cols_inv_scale_d_t(const PassArgs &a) {
-    lbk::OpInvScaleD<T, GEN, SPLIT> op{};
+  template <bool GEN, int KS, int V> static void cols_inv_scale_d_t(const PassArgs &a) {
+    lbk::OpInvScaleD<T, GEN, KS> op{};
     op.g = a.g;
     op.p = a.p;
     op.b0 = (const C2 *)a.b0;
@@ -118,29 +120,35 @@ template <typename T, int N> struct Impl {
     op.st = a.st;
     op.twn = (const C2 *)a.tw1;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, SPLIT>, V>), dim3(a.nblocks),
+    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, KS>, V>), dim3(a.nblocks),
               dim3(lbk::Cfg<N, V>::NT), 0, a.stream, a.cg, (const C2 *)a.tw, op);
   }
-  template <bool GEN, bool SPLIT> static void cols_inv_scale_d_v(const PassArgs &a) {
+  template <bool GEN, int KS> static void cols_inv_scale_d_v(const PassArgs &a) {
     if constexpr (COLV<1>) {
-      if (a.colv == 1) return cols_inv_scale_d_t<GEN, SPLIT, 1>(a);
+      if (a.colv == 1) return cols_inv_scale_d_t<GEN, KS, 1>(a);
     }
     if constexpr (COLV<2>) {
-      if (a.colv == 2) return cols_inv_scale_d_t<GEN, SPLIT, 2>(a);
+      if (a.colv == 2) return cols_inv_scale_d_t<GEN, KS, 2>(a);
     }
-    cols_inv_scale_d_t<GEN, SPLIT, 0>(a);
+    cols_inv_scale_d_t<GEN, KS, 0>(a);
+  }
+  // four parts need 16 columns per workgroup (groups within rows of 16 lanes)
+  static constexpr bool K4 = lbk::Cfg<N>::C == 16;
+  template <bool GEN> static void cols_inv_scale_d_g(const PassArgs &a) {
+    if (a.cg.hsplit && a.cg.kparts == 4) {
+      if constexpr (K4) cols_inv_scale_d_v<GEN, 4>(a);
+    } else if (a.cg.hsplit) {
+      cols_inv_scale_d_v<GEN, 2>(a);
+    } else {
+      cols_inv_scale_d_v<GEN, 1>(a);
+    }
   }
   static void cols_inv_scale_d(const PassArgs &a) {
-    if (a.cg.hsplit) {
-      if (a.g.general) cols_inv_scale_d_v<true, true>(a);
-      else cols_inv_scale_d_v<false, true>(a);
-    } else {
-      if (a.g.general) cols_inv_scale_d_v<true, false>(a);
-      else cols_inv_scale_d_v<false, false>(a);
-    }
+    if (a.g.general) cols_inv_scale_d_g<true>(a);
+    else cols_inv_scale_d_g<false>(a);
   }
-  template <bool GEN, bool SPLIT, int V> static void cols_fwd_update_t(const PassArgs &a) {
-    lbk::OpFwdUpdate<T, GEN, SPLIT> op{};
+  template <bool GEN, int KS, int V> static void cols_fwd_update_t(const PassArgs &a) {
+    lbk::OpFwdUpdate<T, GEN, KS> op{};
     op.g = a.g;
     op.p = a.p;
     op.tmp = (const C2 *)a.in;
@@ -153,26 +161,30 @@ template <typename T, int N> struct Impl {
     op.inv_n = a.inv_n;
     op.cpi = a.cg.cpi;
     op.t = a.step;
-    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T, GEN, SPLIT>, V>), dim3(a.nblocks),
+    LB_LAUNCH((lbk::k_cols<T, N, false, lbk::OpFwdUpdate<T, GEN, KS>, V>), dim3(a.nblocks),
               dim3(lbk::Cfg<N, V>::NT), 0, a.stream, a.cg, (const C2 *)a.tw, op);
   }
-  template <bool GEN, bool SPLIT> static void cols_fwd_update_v(const PassArgs &a) {
+  template <bool GEN, int KS> static void cols_fwd_update_v(const PassArgs &a) {
     if constexpr (COLV<1>) {
-      if (a.colv == 1) return cols_fwd_update_t<GEN, SPLIT, 1>(a);
+      if (a.colv == 1) return cols_fwd_update_t<GEN, KS, 1>(a);
     }
     if constexpr (COLV<2>) {
-      if (a.colv == 2) return cols_fwd_update_t<GEN, SPLIT, 2>(a);
+      if (a.colv == 2) return cols_fwd_update_t<GEN, KS, 2>(a);
     }
-    cols_fwd_update_t<GEN, SPLIT, 0>(a);
+    cols_fwd_update_t<GEN, KS, 0>(a);
+  }
+  template <bool GEN> static void cols_fwd_update_g(const PassArgs &a) {
+    if (a.cg.hsplit && a.cg.kparts == 4) {
+      if constexpr (K4) cols_fwd_update_v<GEN, 4>(a);
+    } else if (a.cg.hsplit) {
+      cols_fwd_update_v<GEN, 2>(a);
+    } else {
+      cols_fwd_update_v<GEN, 1>(a);
+    }
   }
   static void cols_fwd_update(const PassArgs &a) {
-    if (a.cg.hsplit) {
-      if (a.g.general) cols_fwd_update_v<true, true>(a);
-      else cols_fwd_update_v<false, true>(a);
-    } else {
-      if (a.g.general) cols_fwd_update_v<true, false>(a);
-      else cols_fwd_update_v<false, false>(a);
-    }
+    if (a.g.general) cols_fwd_update_g<true>(a);
+    else cols_fwd_update_g<false>(a);
   }
   template <bool GEN> static void cols_fwd_hess_t(const PassArgs &a) {
     lbk::OpFwdHess<T, GEN> op{};
@@ -190,18 +202,22 @@ template <typename T, int N> struct Impl {
     if (a.g.general) cols_fwd_hess_t<true>(a);
     else cols_fwd_hess_t<false>(a);
   }
-  template <bool GEN, bool SPLIT> static void cols_fwd_mul_inv_t(const PassArgs &a) {
-    LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N, GEN, SPLIT>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
+  template <bool GEN, int KS> static void cols_fwd_mul_inv_t(const PassArgs &a) {
+    LB_LAUNCH((lbk::k_cols_fwd_mul_inv<T, N, GEN, KS>), dim3(a.nblocks), dim3(NT), 0, a.stream, a.cg, a.g, a.p,
               (const C2 *)a.tw, (C2 *)a.out, a.inv_n, a.keep_dc, (const C2 *)a.tw1);
   }
-  static void cols_fwd_mul_inv(const PassArgs &a) {
-    if (a.cg.hsplit) {
-      if (a.g.general) cols_fwd_mul_inv_t<true, true>(a);
-      else cols_fwd_mul_inv_t<false, true>(a);
+  template <bool GEN> static void cols_fwd_mul_inv_g(const PassArgs &a) {
+    if (a.cg.hsplit && a.cg.kparts == 4) {
+      if constexpr (K4) cols_fwd_mul_inv_t<GEN, 4>(a);
+    } else if (a.cg.hsplit) {
+      cols_fwd_mul_inv_t<GEN, 2>(a);
     } else {
-      if (a.g.general) cols_fwd_mul_inv_t<true, false>(a);
-      else cols_fwd_mul_inv_t<false, false>(a);
+      cols_fwd_mul_inv_t<GEN, 1>(a);
     }
+  }
+  static void cols_fwd_mul_inv(const PassArgs &a) {
+    if (a.g.general) cols_fwd_mul_inv_g<true>(a);
+    else cols_fwd_mul_inv_g<false>(a);
   }
 
   static void rows_r2c(const PassArgs &a, int mode) {
@@ -244,24 +260,24 @@ template <typename T, int N> struct Impl {
       LB_LAUNCH((lbk::k_plane_inner<T, N, NTV>), dim3(n0 * a.g.batch), dim3(NTV), 0, a.stream, n0, a.g.nh, a.g.N,
                 (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
   }
-  template <int NTV> static void plane_half_nt(const PassArgs &a, int n0) {
-    if constexpr (lbk::HalfCfg<T, N>::fits)
-      LB_LAUNCH((lbk::k_plane_inner_half<T, N, NTV>), dim3(2 * n0 * a.g.batch), dim3(NTV), 0, a.stream, n0, a.g.nh,
-                a.g.N, (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
+  template <int K, int NTV> static void plane_split_nt(const PassArgs &a, int n0) {
+    if constexpr (lbk::SplitCfg<T, N, K>::fits)
+      LB_LAUNCH((lbk::k_plane_inner_split<T, N, K, NTV>), dim3(K * n0 * a.g.batch), dim3(NTV), 0, a.stream, n0,
+                a.g.nh, a.g.N, (const C2 *)a.tw, (C2 *)a.out, (const T *)a.gp, (const SubState *)a.st);
   }
   static void plane_fwd_phys(const PassArgs &a, int n0) {
     if constexpr (lbk::PlaneCfg<T, N>::fits)
       LB_LAUNCH((lbk::k_plane_fwd_phys<T, N>), dim3(n0 * a.g.batch), dim3(lbk::PlaneCfg<T, N>::NT), 0, a.stream, n0,
                 a.g.nh, a.g.N, a.p, (const C2 *)a.tw, a.v, a.psi, (C2 *)a.out, a.partial);
   }
-  static void plane_fwd_phys_half(const PassArgs &a, int n0) {
-    if constexpr (lbk::HalfCfg<T, N>::fits)
-      LB_LAUNCH((lbk::k_plane_fwd_phys_half<T, N>), dim3(2 * n0 * a.g.batch), dim3(lbk::HalfCfg<T, N>::NT), 0,
+  template <int K> static void plane_fwd_phys_split(const PassArgs &a, int n0) {
+    if constexpr (lbk::SplitCfg<T, N, K>::fits)
+      LB_LAUNCH((lbk::k_plane_fwd_phys_split<T, N, K>), dim3(K * n0 * a.g.batch), dim3(lbk::SplitCfg<T, N, K>::NT), 0,
                 a.stream, n0, a.g.nh, a.g.N, a.p, (const C2 *)a.tw, a.v, a.psi, (C2 *)a.out, a.partial);
   }
-  static void plane_inv_phys_half(const PassArgs &a, int n0) {
-    if constexpr (lbk::HalfCfg<T, N>::fits)
-      LB_LAUNCH((lbk::k_plane_inv_phys_half<T, N>), dim3(2 * n0 * a.g.batch), dim3(lbk::HalfCfg<T, N>::NT), 0,
+  template <int K> static void plane_inv_phys_split(const PassArgs &a, int n0) {
+    if constexpr (lbk::SplitCfg<T, N, K>::fits)
+      LB_LAUNCH((lbk::k_plane_inv_phys_split<T, N, K>), dim3(K * n0 * a.g.batch), dim3(lbk::SplitCfg<T, N, K>::NT), 0,
                 a.stream, n0, a.g.nh, a.g.N, a.p, (const C2 *)a.tw, (const C2 *)a.in, a.psi, a.v, a.mpart,
                 (double *)a.out, a.scale);
   }
@@ -281,6 +297,24 @@ template <typename T, int N> struct Impl {
                 (C2 *)a.b0, (C2 *)a.b1, (const C2 *)a.gh, (const T *)a.gp, a.st);
   }
 
+  // the split kernels with K parts: thread-count variants where the whole
+  // plane pass has them (n <= 128), else the built-in count only
+  template <int K> static void fill_split(NFuncs &f, int ki) {
+    if constexpr (lbk::SplitCfg<T, N, K>::fits) {
+      constexpr int D = lbk::SplitCfg<T, N, K>::NT;
+      constexpr int di = D == 256 ? 0 : D == 512 ? 1 : 2;
+      if constexpr (N <= 128) {
+        f.plane_split_nt[ki][0] = &plane_split_nt<K, 256>;
+        f.plane_split_nt[ki][1] = &plane_split_nt<K, 512>;
+        f.plane_split_nt[ki][2] = &plane_split_nt<K, 1024>;
+      } else {
+        f.plane_split_nt[ki][di] = &plane_split_nt<K, D>;
+      }
+      f.plane_split_default[ki] = di;
+      f.plane_fwd_phys_split[ki] = &plane_fwd_phys_split<K>;
+      f.plane_inv_phys_split[ki] = &plane_inv_phys_split<K>;
+    }
+  }
   static NFuncs table() {
     NFuncs f;
     f.C = lbk::Cfg<N>::C;
@@ -301,17 +335,12 @@ template <typename T, int N> struct Impl {
       f.plane_inner_nt[1] = &plane_inner_nt<512>;
       f.plane_inner_nt[2] = &plane_inner_nt<1024>;
     }
-    if constexpr (lbk::HalfCfg<T, N>::fits) {
-      f.plane_half_nt[0] = &plane_half_nt<256>;
-      f.plane_half_nt[1] = &plane_half_nt<512>;
-      f.plane_half_nt[2] = &plane_half_nt<1024>;
-      f.plane_half_default = lbk::HalfCfg<T, N>::NT == 256 ? 0 : lbk::HalfCfg<T, N>::NT == 512 ? 1 : 2;
-    }
+    fill_split<2>(f, 0);
+    fill_split<4>(f, 1);
     f.plane_nt_default = lbk::PlaneCfg<T, N>::fits ? lbk::PlaneCfg<T, N>::NT : 0;
     f.plane_fwd_phys = lbk::PlaneCfg<T, N>::fits ? &plane_fwd_phys : nullptr;
     f.plane_inv_phys = lbk::PlaneCfg<T, N>::fits ? &plane_inv_phys : nullptr;
-    f.plane_fwd_phys_half = lbk::HalfCfg<T, N>::fits ? &plane_fwd_phys_half : nullptr;
-    f.plane_inv_phys_half = lbk::HalfCfg<T, N>::fits ? &plane_inv_phys_half : nullptr;
+
     f.sub2d = SUB2D ? &sub2d : nullptr;
     return f;
   }

@@ -148,10 +148,10 @@ struct lb_plan {
   hipStream_t stream = nullptr;
   hipStream_t own = nullptr;  // private stream for captured launch sequences (created on first use)
   int plane_nt = -1;          // autotuned plane-pass variant (index into plane_inner_nt), -1: built-in choice
-  int plane_split = 0;        // inner iteration in pair-split order with the half-plane pass (1) or not (0)
-  int half_nt = -1;           // its thread-count variant (index into plane_half_nt), -1: built-in choice
+  int plane_split = -1;       // parts K of the inner iteration's split order (1: none, 2, 4), -1: built-in choice
+  int split_nt = -1;          // thread-count variant of its split-plane pass (index into plane_split_nt), -1: built-in
   int colv = 0;               // column variant (radix plan) of the inner iteration's axis-0 passes
-  int hv_split = -1;          // lb_hessvec in pair-split order: 1 yes, 0 no, -1 built-in choice
+  int hv_split = -1;          // parts K of lb_hessvec's split order (1: none, 2, 4), -1: built-in choice
   AxisTab ax[3];  // ax[0] leading axis, ax[1] middle axis (3D), ax[2] last axis
   // general Bravais lattice (lb_plan_set_lattice): the reciprocal metric
   // G = B^T B by axis slot (0 leading, 1 middle, 2 last); unused when 0
@@ -813,27 +813,53 @@ extern "C" int lb_energy_grad(lb_plan *P, const lb_params *params, const double 
 
 // ---------------------------------------------------------------------------
 // Hessian-vector product on physical fields
-// the inner iteration may run in pair-split order: 3D, plane pass, a built
-// half-plane kernel, column workgroups whose halves pair up without a ragged
-// end ((n1/2) n_half columns a multiple of C/2)
-static bool split_ok(const lb_plan *P, int prec) {
-  if (P->dim != 3 || P->n1 != P->nl || P->n1 % 2) return false;
+// The split order with K parts (2 or 4) exists on 3D grids with n1 = n_last
+// whose split-plane kernels are built for K, and whose axis-0 workgroups
+// hold whole groups of K columns without a ragged end ((n1/K) n_half columns
+// per part, a multiple of C/K; four parts need C = 16: groups within rows of
+// 16 lanes).
+static int kidx(int K) { return K == 4 ? 1 : 0; }
+static bool split_ok(const lb_plan *P, int prec, int K) {
+  if (K != 2 && K != 4) return false;
+  if (P->dim != 3 || P->n1 != P->nl || P->n1 % (2 * K)) return false;
   const NFuncs *f1 = F(P, 1, prec);
   const NFuncs *f0 = F(P, 0, prec);
-  if (!f1 || !f1->plane_inner || f1->plane_half_default < 0 || !f0 || f0->C % 2) return false;
-  const long hcols = (long)(P->n1 / 2) * P->nhl;
-  return hcols % (f0->C / 2) == 0 && bpi_col0(P) * f0->C == 2 * hcols;
+  if (!f1 || f1->plane_split_default[kidx(K)] < 0 || !f0 || f0->C % K) return false;
+  if (K == 4 && f0->C != 16) return false;
+  const long hcols = (long)(P->n1 / K) * P->nhl;
+  return hcols % (f0->C / K) == 0 && bpi_col0(P) * f0->C == K * hcols;
 }
-static bool use_split(const lb_plan *P, int prec) { return P->plane_split == 1 && split_ok(P, prec); }
-// lb_hessvec in the pair-split order: where the order exists, when pinned on,
-// or by the built-in choice: FP64 planes of 96 points and more (measured at
-// 128^3: 3-5 % faster in FP64; in FP32 the pair steps cost the axis-0 pass
-// more than the half planes save)
-static bool hv_split_on(const lb_plan *P, int prec) {
-  if (P->hv_split == 0 || !split_ok(P, prec) || P->n0 > 512) return false;
-  const NFuncs *f1 = F(P, 1, prec);
-  if (!f1->plane_fwd_phys_half || !f1->plane_inv_phys_half) return false;
-  return P->hv_split == 1 || (prec == LB_FP64 && P->n1 >= 96);
+// the parts K of the inner iteration in use: pinned, or the built-in choice
+// K = 1: one workgroup per plane where the plane fits in LDS, else the five
+// passes of the column and row kernels (measured at 256^3: the split order's
+// axis-0 passes, with groups of four 4-column runs per workgroup, cost more
+// than its split planes save: 747 against 590 us per FP64 iteration); the
+// autotuner may pick a split order
+static int plane_k(const lb_plan *P, int prec) {
+  if (P->plane_split == 2 || P->plane_split == 4) return split_ok(P, prec, P->plane_split) ? P->plane_split : 1;
+  return 1;
+}
+// the parts K of lb_hessvec: pinned, or the built-in choice, as measured:
+// where the plane fits, two parts for FP64 planes of 96 points and more
+// (128^3: 3-5 % faster; in FP32 the pair steps cost the axis-0 pass more than
+// the half planes save), else one workgroup per plane; where it does not fit,
+// four parts in FP32 (256^3: 252 against 270 us per product) and the five
+// passes in FP64 (378 against 363 us: the four-part axis-0 pass's 64 B runs)
+static int hv_k(const lb_plan *P, int prec) {
+  if (P->n0 > 512) return 1;
+  if (P->hv_split == 2 || P->hv_split == 4) return split_ok(P, prec, P->hv_split) ? P->hv_split : 1;
+  if (P->hv_split == 1) return 1;
+  const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
+  if (f1 && f1->plane_fwd_phys && P->n1 == P->nl)
+    return (prec == LB_FP64 && P->n1 >= 96 && split_ok(P, prec, 2)) ? 2 : 1;
+  if (prec == LB_FP32 && split_ok(P, prec, 4)) return 4;
+  return 1;
+}
+// the split order with K parts on an axis-0 pass's arguments
+static void set_pair_split(const lb_plan *P, PassArgs &a, int prec, int K) {
+  a.cg.hsplit = (P->n1 / K) * P->nhl;
+  a.cg.kparts = K;
+  a.tw1 = TW(P, 1, prec);
 }
 
 // ---------------------------------------------------------------------------
@@ -849,10 +875,11 @@ static int hessvec_phys(lb_plan *P, const lb_params *params, const double *psi, 
   const int B = P->batch, prec = P->prec;
   void *work = P->WT;
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
-  if (hv_split_on(P, prec)) {
-    // three passes in the pair-split order: half planes forward, axis 0 with
-    // Lambda and the radix-2 steps of axis 1, half planes inverse
-    const int hsplit = (P->n1 / 2) * P->nhl;
+  const int hk = hv_k(P, prec);
+  if (hk > 1) {
+    // three passes in the split order: split planes forward, axis 0 with
+    // Lambda and the first and last steps of the split axis-1 transforms,
+    // split planes inverse
     PassArgs a = args_col(P, prec, B, p, 1);
     a.v = v;
     a.psi = psi;
@@ -860,14 +887,13 @@ static int hessvec_phys(lb_plan *P, const lb_params *params, const double *psi, 
     a.partial = project ? P->partial : nullptr;
     {
       KT kt_(P, "plane_fwd_phys");
-      f1->plane_fwd_phys_half(a, P->n0);
+      f1->plane_fwd_phys_split[kidx(hk)](a, P->n0);
     }
     PassArgs c0 = args_col(P, prec, B, p, 0);
     c0.out = work;
     c0.inv_n = bscale / (double)P->N;
     c0.keep_dc = keep_dc;
-    c0.cg.hsplit = hsplit;
-    c0.tw1 = TW(P, 1, prec);
+    set_pair_split(P, c0, prec, hk);
     {
       KT kt_(P, "col0_fwd_mul_inv");
       F(P, 0, prec)->cols_fwd_mul_inv(c0);
@@ -881,7 +907,7 @@ static int hessvec_phys(lb_plan *P, const lb_params *params, const double *psi, 
     o.mpart = project ? P->partial : nullptr;
     {
       KT kt_(P, "plane_inv_phys");
-      f1->plane_inv_phys_half(o, P->n0);
+      f1->plane_inv_phys_split[kidx(hk)](o, P->n0);
     }
     return check_launch("lb_hessvec");
   }
@@ -1104,7 +1130,7 @@ extern "C" int lb_hessvec_noalloc(const lb_grid *g, const lb_params *params, con
   }
   V.partial = (double *)(sb + kTwBytes);
   V.partial_len = (long)kPartialDoubles;
-  const long need = std::max(bpi_pairs(&V), 2L * V.n0);  // 2 n0: the pair-split order's mean partials
+  const long need = std::max(bpi_pairs(&V), 4L * V.n0);  // K n0 (K <= 4): the split order's mean partials
   if (need > (long)kPartialDoubles) return fail(LB_ERR_ARG, "grid needs more partial sums than the fixed workspace holds");
   V.WT = (void *)(sb + kSpecOffset);
   const int rc = hessvec_phys(&V, params, psi, v, hv, project ? 0 : 1);
@@ -1224,31 +1250,30 @@ static void launch_newton(lb_plan *P, const PassArgs &u, const Prm &p, int B) {
 static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
   const int prec = P->prec;
   t &= 1;
-  const bool split = use_split(P, prec);
-  const int hsplit = split ? (P->n1 / 2) * P->nhl : 0;
+  const int K = plane_k(P, prec);
   PassArgs a = args_col(P, prec, B, p, 0);
   a.step = t;
   a.b0 = P->B0;
   a.b1 = P->B1;
   a.out = P->WT;
   a.st = P->st;
-  a.cg.hsplit = hsplit;
-  a.tw1 = split ? TW(P, 1, prec) : nullptr;
+  if (K > 1) set_pair_split(P, a, prec, K);
   a.colv = P->colv;
   {
     KT kt_(P, "col0_inv_scale_d");
     F(P, 0, prec)->cols_inv_scale_d(a);
   }
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
-  if (split) {
-    // axis 1 split by the parity of x1, rows with Gamma': two workgroups per plane
+  if (K > 1) {
+    // axis 1 split by x1 mod K, rows with Gamma': K workgroups per plane
     PassArgs pl = args_col(P, prec, B, p, 1);
     pl.out = P->WT;
     pl.gp = (prec == LB_FP64) ? (const void *)P->gp64 : (const void *)P->gp32;
     pl.st = P->st;
-    const int v = P->half_nt >= 0 && f1->plane_half_nt[P->half_nt] ? P->half_nt : f1->plane_half_default;
+    const int ki = kidx(K);
+    const int v = P->split_nt >= 0 && f1->plane_split_nt[ki][P->split_nt] ? P->split_nt : f1->plane_split_default[ki];
     KT kt_(P, "plane_inner");
-    f1->plane_half_nt[v](pl, P->n0);
+    f1->plane_split_nt[ki][v](pl, P->n0);
   } else if (f1 && f1->plane_inner && P->n1 == P->nl) {
     // axis-1 inverse, rows with Gamma', axis-1 forward: one plane pass in LDS
     PassArgs pl = args_col(P, prec, B, p, 1);
@@ -1288,7 +1313,7 @@ static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
     }
   }
   PassArgs u = args_col(P, prec, B, p, 0);
-  u.cg.hsplit = hsplit;
+  if (K > 1) set_pair_split(P, u, prec, K);
   u.colv = P->colv;
   u.in = P->WT;
   u.b0 = P->B0;
@@ -2359,7 +2384,8 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
   *threads = 0;
   const int prec = P->prec;
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
-  if (!f1 || !f1->plane_inner || P->n1 != P->nl || !f1->plane_inner_nt[0]) return LB_OK;  // nothing to tune
+  const bool whole = f1 && f1->plane_inner && P->n1 == P->nl && f1->plane_inner_nt[0];
+  if (!whole && !split_ok(P, prec, 2) && !split_ok(P, prec, 4)) return LB_OK;  // nothing to tune
   Prm p;
   LB_TRY(pack_params(P, params, P->batch, &p));
   {
@@ -2381,26 +2407,35 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
   LB_HIP(hipEventCreate(&e0));
   LB_HIP(hipEventCreate(&e1));
   const int nts[3] = {256, 512, 1024};
-  const int keep_split = P->plane_split, keep_nt = P->plane_nt, keep_half = P->half_nt, keep_colv = P->colv;
+  const int keep_split = P->plane_split, keep_nt = P->plane_nt, keep_snt = P->split_nt, keep_colv = P->colv;
   const int colv_built = F(P, 0, prec)->colv_built;
-  // every candidate is timed in two rounds (interleaved, so that clock and
-  // cache drift hit all alike) and keeps its faster round
+  // the built-in variant, which stays unless another is faster by more than
+  // 2 % (near-ties are timing noise, and in FP32 the variants' rounding can
+  // change a solve's path): plane_k's choice, its built-in threads, plan 0
+  P->plane_split = -1;
+  const int k0 = plane_k(P, prec);
+  const int v0 = k0 > 1 ? f1->plane_split_default[kidx(k0)]
+                        : !whole ? 0 : (f1->plane_nt_default == 256 ? 0 : f1->plane_nt_default == 512 ? 1 : 2);
+  // every candidate (parts K, thread variant, column plan) is timed in two
+  // rounds (interleaved, so that clock and cache drift hit all alike) and
+  // keeps its faster round
   struct Cand {
-    int split, v, cv;
+    int k, v, cv;
     float ms;
   };
   std::vector<Cand> cands;
-  for (int split = 0; split < 2; ++split)
+  for (int k : {1, 2, 4})
     for (int v = 0; v < 3; ++v) {
-      if (split && (!split_ok(P, prec) || !f1->plane_half_nt[v])) continue;
-      if (!split && !f1->plane_inner_nt[v]) continue;
+      // K = 1: the plane pass's thread variants, or once the five passes
+      if (k == 1 && (whole ? !f1->plane_inner_nt[v] : v != 0)) continue;
+      if (k > 1 && (!split_ok(P, prec, k) || !f1->plane_split_nt[kidx(k)][v])) continue;
       for (int cv = 0; cv < 3; ++cv)
-        if (colv_built >> cv & 1) cands.push_back(Cand{split, v, cv, 0.0f});
+        if (colv_built >> cv & 1) cands.push_back(Cand{k, v, cv, 0.0f});
     }
   for (int round = 0; round < 2; ++round) {
     for (Cand &c : cands) {
-      P->plane_split = c.split;
-      if (c.split) P->half_nt = c.v;
+      P->plane_split = c.k;
+      if (c.k > 1) P->split_nt = c.v;
       else P->plane_nt = c.v;
       P->colv = c.cv;
       enqueue_passes(P, p, 1, 1);  // warm
@@ -2413,53 +2448,48 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
       c.ms = round == 0 ? ms : std::min(c.ms, ms);
     }
   }
-  int pick_split = -1, pick = -1, pick_colv = 0;
-  float best = 0.0f;
+  const Cand *pick = nullptr;
   for (const Cand &c : cands)
-    if (pick < 0 || c.ms < best) {
-      best = c.ms;
-      pick = c.v;
-      pick_split = c.split;
-      pick_colv = c.cv;
-    }
-  // the built-in variant (one workgroup per plane, built-in threads, column
-  // plan 0) stays unless another is faster by more than 2 %: near-ties are
-  // timing noise, and in FP32 the variants' rounding can change a solve's path
-  const int v0 = f1->plane_nt_default == 256 ? 0 : f1->plane_nt_default == 512 ? 1 : 2;
+    if (!pick || c.ms < pick->ms) pick = &c;
   for (const Cand &c : cands)
-    if (c.split == 0 && c.v == v0 && c.cv == 0 && c.ms <= 1.02f * best) {
-      pick = c.v;
-      pick_split = 0;
-      pick_colv = 0;
-    }
+    if (c.k == k0 && c.v == v0 && c.cv == 0 && c.ms <= 1.02f * pick->ms) pick = &c;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   P->plane_split = keep_split;
   P->plane_nt = keep_nt;
-  P->half_nt = keep_half;
+  P->split_nt = keep_snt;
   P->colv = keep_colv;
   LB_TRY(check_launch("lb_plan_autotune"));
-  P->plane_split = pick_split;
-  if (pick_split) P->half_nt = pick;
-  else P->plane_nt = pick;
-  P->colv = pick_colv;
-  *threads = nts[pick];
+  if (!pick) return LB_OK;
+  P->plane_split = pick->k;
+  if (pick->k > 1) P->split_nt = pick->v;
+  else if (whole) P->plane_nt = pick->v;
+  P->colv = pick->cv;
+  *threads = (pick->k == 1 && !whole) ? 0 : nts[pick->v];
   return LB_OK;
 }
 
+// split codes of the API: 0 none, 1 two parts, 2 four parts
+static int k_of_code(int code) { return code == 0 ? 1 : code == 1 ? 2 : code == 2 ? 4 : -1; }
+static int code_of_k(int K) { return K == 2 ? 1 : K == 4 ? 2 : 0; }
+
 extern "C" int lb_plan_set_plane_split(lb_plan *P, int split, int threads) {
   if (!P) return fail(LB_ERR_ARG, "null plan");
-  if (split != 0 && split != 1) return fail(LB_ERR_ARG, "split must be 0 or 1");
+  const int K = k_of_code(split);
+  if (K < 0) return fail(LB_ERR_ARG, "split must be 0, 1 or 2");
   const int v = threads == 0 ? -1 : threads == 256 ? 0 : threads == 512 ? 1 : threads == 1024 ? 2 : -2;
   if (v == -2) return fail(LB_ERR_ARG, "plane threads must be 0, 256, 512 or 1024");
-  if (split) {
-    if (!split_ok(P, P->prec)) return fail(LB_ERR_UNSUPPORTED, "this grid has no pair-split inner iteration");
-    if (v >= 0 && !F(P, 1, P->prec)->plane_half_nt[v]) return fail(LB_ERR_UNSUPPORTED, "half-plane pass not built with that thread count");
-    P->half_nt = v;
+  if (K > 1) {
+    if (!split_ok(P, P->prec, K)) return fail(LB_ERR_UNSUPPORTED, "this grid has no split order with that many parts");
+    if (v >= 0 && !F(P, 1, P->prec)->plane_split_nt[kidx(K)][v])
+      return fail(LB_ERR_UNSUPPORTED, "split-plane pass not built with that thread count");
+    P->split_nt = v;
   } else if (v >= 0) {
+    // one workgroup per plane with a pinned thread count (without a plane
+    // pass, split = 0 selects the column and row passes and takes no count)
     LB_TRY(lb_plan_set_plane_threads(P, threads));
   }
-  P->plane_split = split;
+  P->plane_split = K;
   return LB_OK;
 }
 
@@ -2470,24 +2500,28 @@ extern "C" int lb_plan_get_variant(lb_plan *P, int *split, int *threads, int *co
   *column_plan = P->colv;
   const int prec = P->prec;
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
-  if (!f1 || !f1->plane_inner || P->n1 != P->nl) return LB_OK;
   const int nts[3] = {256, 512, 1024};
-  if (use_split(P, prec)) {
-    *split = 1;
-    *threads = nts[P->half_nt >= 0 && f1->plane_half_nt[P->half_nt] ? P->half_nt : f1->plane_half_default];
-  } else if (P->plane_nt >= 0 && f1->plane_inner_nt[P->plane_nt]) {
-    *threads = nts[P->plane_nt];
-  } else {
-    *threads = f1->plane_nt_default;
+  const int K = plane_k(P, prec);
+  if (K > 1) {
+    const int ki = kidx(K);
+    *split = code_of_k(K);
+    *threads = nts[P->split_nt >= 0 && f1->plane_split_nt[ki][P->split_nt] ? P->split_nt : f1->plane_split_default[ki]];
+  } else if (f1 && f1->plane_inner && P->n1 == P->nl) {
+    *threads = (P->plane_nt >= 0 && f1->plane_inner_nt[P->plane_nt]) ? nts[P->plane_nt] : f1->plane_nt_default;
   }
   return LB_OK;
 }
 
 extern "C" int lb_plan_set_hessvec_split(lb_plan *P, int split) {
   if (!P) return fail(LB_ERR_ARG, "null plan");
-  if (split < -1 || split > 1) return fail(LB_ERR_ARG, "split must be -1, 0 or 1");
-  if (split == 1 && !split_ok(P, P->prec)) return fail(LB_ERR_UNSUPPORTED, "this grid has no pair-split order");
-  P->hv_split = split;
+  if (split == -1) {
+    P->hv_split = -1;
+    return LB_OK;
+  }
+  const int K = k_of_code(split);
+  if (K < 0) return fail(LB_ERR_ARG, "split must be -1, 0, 1 or 2");
+  if (K > 1 && !split_ok(P, P->prec, K)) return fail(LB_ERR_UNSUPPORTED, "this grid has no split order with that many parts");
+  P->hv_split = K;
   return LB_OK;
 }
 

@@ -1,6 +1,7 @@
 """GPU: the largest configuration (256^3, FP64 and FP32) against the oracle,
 degenerate inputs (psi = 0, the interior and the tiny-radius subproblem), and
 limits of the plan."""
+import functools
 import math
 
 import numpy as np
@@ -28,13 +29,18 @@ def rms(a):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
-def test_large_256_energy_gradient_hessvec(precision, tol):
-    """The 256^3 workload (N(0, 0.05^2) start) at full size, every element."""
+@pytest.mark.parametrize("hv_split", [-1, 0, 2])
+def test_large_256_energy_gradient_hessvec(precision, tol, hv_split):
+    """The 256^3 workload (N(0, 0.05^2) start) at full size, every element;
+    the product in the built-in order (four parts in FP32, five passes in
+    FP64), the five passes and the four-part split order."""
+    print(f"256^3 E/g/Hv {precision} hv_split {hv_split}", flush=True)
     inst = I.large_3d(256)
     shape, box = inst.grid.n, inst.grid.box
     m = O.Model(O.Grid(shape, box), inst.params.tau, inst.params.gamma)
     v = I.hessvec_direction(shape, 1)
     plan = lb.Plan(shape, box, precision=precision)
+    plan.lb_plan_set_hessvec_split(hv_split)
     prm = lb.Params(m.tau, m.gamma)
     E, g = plan.lb_energy_grad(prm, dev(inst.psi0))
     hv = plan.lb_hessvec(prm, dev(inst.psi0), dev(v))
@@ -49,20 +55,36 @@ def test_large_256_energy_gradient_hessvec(precision, tol):
     assert rms(host(hv) - ho) <= tol * hs
 
 
-def test_large_256_subproblem_iterations_fp32():
-    """Five iterations of Algorithm 3 at 256^3 in FP32 against the oracle's five (FP64)."""
+@functools.lru_cache(maxsize=1)
+def _large_subproblem_oracle():
     inst = I.large_3d(256)
     shape, box = inst.grid.n, inst.grid.box
     m = O.Model(O.Grid(shape, box), inst.params.tau, inst.params.gamma)
     g_hat = O.gradient(m, inst.psi0)
-    r = 0.02
-    ref = O.imex_subproblem(m, inst.psi0, g_hat, r, O.SubOpts(eta=0.1, eps_sub=0.0, max_inner=5))
-    plan = lb.Plan(shape, box, precision="fp32")
-    d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(inst.psi0), dev(O.inv(g_hat)), r,
+    ref = O.imex_subproblem(m, inst.psi0, g_hat, 0.02, O.SubOpts(eta=0.1, eps_sub=0.0, max_inner=5))
+    return inst, m, g_hat, ref
+
+
+@pytest.mark.parametrize("precision,tol,split", [("fp32", 1e-5, -1), ("fp64", 1e-12, -1), ("fp32", 1e-5, 2),
+                                               ("fp64", 1e-12, 2)])
+def test_large_256_subproblem_iterations(precision, tol, split):
+    """Five iterations of Algorithm 3 at 256^3 against the oracle's five
+    (FP64): the built-in five passes of the column and row kernels, and the
+    four-part split order (split = 2), in FP32 and FP64."""
+    print(f"256^3 subproblem {precision} split {split}", flush=True)
+    inst, m, g_hat, ref = _large_subproblem_oracle()
+    shape, box = inst.grid.n, inst.grid.box
+    plan = lb.Plan(shape, box, precision=precision)
+    if split > 0:
+        plan.lb_plan_set_plane_split(split, 0)
+    assert plan.lb_plan_get_variant()[0] == max(split, 0)
+    d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(inst.psi0), dev(O.inv(g_hat)), 0.02,
                                         lb.sub_opts(eta=0.1, eps_sub=0.0, max_inner=5))
+    err = rms(host(d) - O.inv(ref.d)) / rms(O.inv(ref.d))
+    print(f"  lambda {info.lambda_:.15e} (oracle {ref.lam:.15e}), iterate error {err:.2e}")
     assert rc == lb.LB_NOT_CONVERGED and info.iters == 5
-    assert abs(info.lambda_ - ref.lam) <= 1e-5 * max(1.0, ref.lam)
-    assert rms(host(d) - O.inv(ref.d)) <= 1e-5 * rms(O.inv(ref.d))
+    assert abs(info.lambda_ - ref.lam) <= tol * max(1.0, ref.lam)
+    assert err <= tol
 
 
 def test_psi_zero_is_a_stationary_point_with_hessian_lambda_plus_tau():

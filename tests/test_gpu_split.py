@@ -1,10 +1,11 @@
-"""GPU: the inner iteration in pair-split order (lb_plan_set_plane_split: the
-axis-1 transform split by the parity of x1, its first inverse and last forward
-radix-2 step done across column pairs in the axis-0 passes, a half-plane pass
-with two workgroups per plane) against the oracle's Algorithm 3 (Section 3.2),
-on orthorhombic boxes and a general lattice, in FP64 and FP32, for each
-thread count of the half-plane pass; batched instances equal single ones bit
-for bit; the variant API and the autotuner."""
+"""GPU: the inner iteration in the split order (lb_plan_set_plane_split: the
+axis-1 transform split by x1 mod K, K = 2 or 4, its first inverse and last
+forward K-point steps done across column groups in the axis-0 passes, a
+split-plane pass with K workgroups per plane) against the oracle's Algorithm 3
+(Section 3.2), on orthorhombic boxes and a general lattice, in FP64 and FP32,
+for each thread count of the split-plane pass; the Hessian product in the
+same orders; batched instances equal single ones bit for bit; the variant
+API and the autotuner."""
 import functools
 import math
 
@@ -80,6 +81,46 @@ def test_split_subproblem_matches_oracle(n, box, precision, tol):
         assert rms(d - host(d_plane)) <= tol * rms(d_or)
     plan.lb_plan_set_plane_split(0, 0)
     assert plan.lb_plan_get_variant()[0] == 0
+
+
+# grids with a four-part order (axis-0 workgroups of 16 columns): 128^3 and a
+# 128 x 64 x 64 grid (parts of 32 and 16 rows)
+GRIDS4 = [
+    ((128, 128, 128), (8 * math.sqrt(2) * math.pi,) * 3),
+    ((128, 64, 64), (8 * math.sqrt(2) * math.pi, 4 * math.sqrt(2) * math.pi, 4 * math.sqrt(2) * math.pi)),
+]
+
+
+@pytest.mark.parametrize("n,box", GRIDS4)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_four_part_subproblem_and_hessvec_match_oracle(n, box, precision, tol):
+    """Four parts (DPP rotates by 4, 8 and 12 within rows of 16 lanes): the
+    subproblem iterations and the Hessian product against the oracle."""
+    print(f"four-part split {n} {precision}", flush=True)
+    m = O.Model(O.Grid(n, box), -0.15, 0.25, 1.05, 0.95)
+    psi = I.zero_mean_noise(n, 0.2, 91)
+    g_hat = O.gradient(m, psi)
+    k, r = 6, 0.05
+    ref = O.imex_subproblem(m, psi, g_hat, r, O.SubOpts(eta=0.1, eps_sub=0.0, max_inner=k))
+    d_or = O.inv(ref.d)
+    plan = lb.Plan(n, box, precision=precision)
+    for threads in (256, 512, 1024):
+        plan.lb_plan_set_plane_split(2, threads)
+        assert plan.lb_plan_get_variant() == (2, threads, 0)
+        d, info, rc = _subproblem(plan, m, psi, g_hat, r, k)
+        err = rms(host(d) - d_or) / rms(d_or)
+        print(f"  threads {threads}: lambda {info.lambda_:.15e} (oracle {ref.lam:.15e}), iterate error {err:.2e}")
+        assert info.iters == ref.iters == k and ref.lam > 0
+        assert abs(info.lambda_ - ref.lam) <= tol * max(1.0, ref.lam) and err <= tol
+    v = I.hessvec_direction(n, 96)
+    prm = lb.Params(m.tau, m.gamma, m.xi, m.q)
+    plan.lb_plan_set_hessvec_split(2)
+    hv = host(plan.lb_hessvec(prm, dev(psi), dev(v)))
+    raw = host(plan.lb_hessvec_raw(prm, dev(psi), dev(v)))
+    scale = rms(O.inv(m.Lam * O.fwd(v))) + rms(O.Gamma_p(psi, m.tau, m.gamma) * v)
+    err = rms(hv - O.hessvec_phys(m, psi, v)) / scale
+    print(f"  Hv: error {err:.2e} of the term scale")
+    assert err <= tol and rms(raw - O.hessvec_raw(m, psi, v)) <= tol * scale / psi.size
 
 
 @functools.lru_cache(maxsize=4)
@@ -226,7 +267,7 @@ def test_split_api_and_autotune():
         lb.Plan((32, 32, 32), (4 * math.pi,) * 3).lb_plan_set_plane_split(1, 0)
     plan = lb.Plan((64, 64, 64), (8 * math.pi,) * 3)
     with pytest.raises(lb.LBError):
-        plan.lb_plan_set_plane_split(2, 0)
+        plan.lb_plan_set_plane_split(3, 0)
     with pytest.raises(lb.LBError):
         plan.lb_plan_set_plane_split(1, 384)
     prm = lb.Params(-0.15, 0.25)
@@ -238,8 +279,18 @@ def test_split_api_and_autotune():
     with pytest.raises(lb.LBError):
         plan.lb_plan_set_column_plan(3)
     with pytest.raises(lb.LBError):
-        plan.lb_plan_set_hessvec_split(2)
+        plan.lb_plan_set_hessvec_split(3)
     with pytest.raises(lb.LBError):
         lb.Plan((32, 32, 32), (4 * math.pi,) * 3).lb_plan_set_hessvec_split(1)
+    with pytest.raises(lb.LBError):  # four parts need 16 columns per axis-0 workgroup (64^3 has 32)
+        plan.lb_plan_set_plane_split(2, 0)
+    big = lb.Plan((256, 256, 256), (16 * math.pi,) * 3, precision="fp32")
+    assert big.lb_plan_get_variant()[:2] == (0, 0)  # built in: the five passes where the plane does not fit
+    big.lb_plan_set_plane_split(2, 0)
+    assert big.lb_plan_get_variant() == (2, 512, 0)  # four parts, the built-in 512 threads
+    big.lb_plan_set_plane_split(0, 0)
+    assert big.lb_plan_get_variant()[:2] == (0, 0)
+    with pytest.raises(lb.LBError):  # only the built-in thread count at 256
+        big.lb_plan_set_plane_split(2, 1024)
     with pytest.raises(lb.LBError):  # axis-0 length 32: only the built-in plan
         lb.Plan((32, 32, 32), (4 * math.pi,) * 3).lb_plan_set_column_plan(1)

@@ -101,6 +101,16 @@ typedef struct lb_sub_opts {
                             of two iterations' launches on a private stream (same kernels,
                             same results); 0 (default, faster on the current runtime): direct
                             launches. Not used while kernel timing is on. */
+  int fused_newton;      /* The multiplier step of each iteration (Newton on eq.
+                            lambda_update_rule, and the stop test) in the next iteration's
+                            first pass, where every workgroup sums all the update pass's
+                            partials in the same order (one launch fewer per iteration, at
+                            the price of those redundant reads); an iteration whose series
+                            Newton needs sums over the spectrum falls back to the separate
+                            launch. 1 (default): fused where the redundant reads stay below
+                            16 MB per pass (grids up to about 96^3; not 128^3); 2: always;
+                            0: always the separate one-workgroup launch. The results are the
+                            same bits either way. Not used with newton_direct or graph. */
 } lb_sub_opts;
 
 typedef struct lb_sub_info {

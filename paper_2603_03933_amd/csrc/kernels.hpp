@@ -253,7 +253,7 @@ struct SubState {
   double resid;       // residual norm of the iterate tested last
   double lam_final;   // multiplier of the returned iterate
   int step;           // current step t
-  int done;           // 0 running, 1 converged, 2 iteration cap
+  int done;           // 0 running, 1 converged, 2 iteration cap, 3 paused (a multiplier step left to k_newton)
   int final_step;
   int newton_total;
   int max_inner, max_newton;
@@ -463,6 +463,14 @@ template <class Op, class = void> struct OpPair {
 template <class Op> struct OpPair<Op, std::void_t<decltype(Op::PAIR)>> {
   static constexpr int value = Op::PAIR;
 };
+// ops with pre(bs, b, lb), run by every thread after begin() and before the
+// transform's loads
+template <class Op, class = void> struct OpHasPre {
+  static constexpr bool value = false;
+};
+template <class Op> struct OpHasPre<Op, std::void_t<decltype(Op::HAS_PRE)>> {
+  static constexpr bool value = Op::HAS_PRE;
+};
 
 // A twiddle table of N entries staged into LDS: load() reads it with a
 // kernel's first loads, one scalar (real or imaginary part) per thread, and
@@ -520,7 +528,8 @@ __global__ __launch_bounds__((Cfg<N, V>::NT)) void k_cols(ColGeo cg, const c2<T>
   const int mls = ok ? ml : 0;
   const int mo = mls / cg.inner;
   const long base = b * cg.inst + (long)mo * cg.outer + (mls - mo * cg.inner);
-  const auto bs = op.begin(b);
+  auto bs = op.begin(b);
+  if constexpr (OpHasPre<Op>::value) op.template pre<NT>(bs, b, lb);
   const auto cs = op.column(b, mls);
   double acc = 0.0;
   fft_run<T, N, INV, 0, Cfg<N, V>::PLAN>(
@@ -576,6 +585,7 @@ template <typename T> struct StepBlk {
   const c2<T> *bprev;
   c2<T> *bnext;
   double lam_t, eta, xi, q;
+  int stop;  // the multiplier step taken at the start of the pass stopped (or paused) the subproblem
 };
 
 // column information plus the pair twiddle e^{-2 pi i k'/n1} of a
@@ -591,17 +601,32 @@ template <typename T> struct ColTw : ColInfo {
 // in row k' + q n1/KS (a: the axis-0 inverse of d_t), the first step of the
 // axis-1 inverse transform split by x1 mod KS (KS = 2: s_0 = a(k') + a(k' +
 // n1/2), s_1 = (a(k') - a(k' + n1/2)) e^{+2 pi i k'/n1})
+//
+// With tn >= 1 the pass first takes the multiplier step of iteration tn - 1
+// (what k_newton does between the update pass and this one): every workgroup
+// sums the update pass's nmb per-workgroup partials of its instance in the
+// order k_newton uses, so all of them, and k_newton, get the same bits, runs
+// the stop test and the series Newton, and scales with the resulting lambda;
+// the instance's first workgroup records the step in the state. An iteration
+// whose series Newton needs sums over the spectrum pauses the subproblem
+// (done = 3, nothing stored) for the host to take that step with k_newton.
 template <typename T, bool GEN, int KS = 1> struct OpInvScaleD {
   static constexpr bool SPLIT = KS > 1;
   static constexpr bool eager_loads = true;
   static constexpr int PAIR = SPLIT ? 2 : 0;
+  static constexpr bool HAS_PRE = true;
   Geo g;
   Prm p;
   const c2<T> *b0, *b1;  // b buffers: b_{t-1} lives in (t - 1) & 1
   c2<T> *out;
-  const SubState *st;
+  SubState *st;
   const c2<T> *twn;  // SPLIT: the axis-1 twiddle table (e^{-2 pi i k/n1})
   int t;  // step index (known to the host when it enqueues the step)
+  int tn;  // >= 1: the step index, and the multiplier step of step tn - 1 runs first; else lambda_t from the state
+  const double *mom;    // tn >= 1: the update pass's moment partials, value j of workgroup i at
+  const double *rpart;  //   mom[j mstride + inst nmb + i]; residual partials at rpart[inst nmb + i]
+  long mstride;
+  int nmb;
   using CI = std::conditional_t<SPLIT, ColTw<T>, ColInfo>;
   // (with SPLIT, ColTw::q holds the column's part and tw = e^{-2 pi i k' q/n1})
   __device__ bool skip(int b) const { return st[b].done != 0; }
@@ -609,11 +634,116 @@ template <typename T, bool GEN, int KS = 1> struct OpInvScaleD {
     StepBlk<T> s;
     s.bprev = ((t - 1) & 1) ? b1 : b0;
     s.bnext = nullptr;
-    s.lam_t = st[b].lam[t & 1];
+    s.lam_t = tn >= 1 ? 0.0 : st[b].lam[t & 1];  // tn >= 1: set by pre()
     s.eta = st[b].eta;
     s.xi = p.xi[b];
     s.q = p.q[b];
+    s.stop = 0;
     return s;
+  }
+  // the multiplier step (tn >= 1), before the pass's loads (which need its
+  // lambda); all threads of the workgroup call it
+  template <int NT> __device__ void pre(StepBlk<T> &bs, int b, int lb) const {
+    if (tn < 1) return;  // uniform
+    constexpr int NW = NT / 64;                  // whole waves (NT = 96: the second wave, half full, idles)
+    static_assert(NW >= 1, "one wave at least");
+    constexpr int NV = MOM_NV + 1;               // phi(0), the power sums, the residual
+    constexpr int VPW = (NV + NW - 1) / NW;      // values per wave: v = wave + u NW
+    constexpr int KU = (40 / VPW) < 1 ? 1 : ((40 / VPW) > 9 ? 9 : 40 / VPW);  // loads per value per lane in flight
+    __shared__ double M[NV];
+    __shared__ SubState S0;
+    __shared__ double lam_w;
+    __shared__ int it_w, nd_w;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double *src[VPW];
+    double acc[VPW];
+#pragma unroll
+    for (int u = 0; u < VPW; ++u) {
+      const int v = wv + u * NW;
+      src[u] = v < MOM_NV ? mom + (long)v * mstride + (long)b * nmb : rpart + (long)b * nmb;
+      acc[u] = 0.0;
+    }
+    // the state as this workgroup sees it, read once and shared through LDS
+    // (the instance's first workgroup may update it while others read)
+    if (threadIdx.x == 0) S0 = st[b];
+    // per lane, workgroups i = lane + 64 k in increasing k, then across the
+    // wave: the summation order of k_newton
+    for (int i0 = 0; wv < NW && i0 < nmb; i0 += 64 * KU) {
+      double x[VPW][KU];
+#pragma unroll
+      for (int u = 0; u < VPW; ++u) {
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+          const int i = i0 + lane + 64 * k;
+          x[u][k] = (wv + u * NW < NV) ? src[u][i < nmb ? i : 0] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < VPW; ++u) {
+#pragma unroll
+        for (int k = 0; k < KU; ++k) {
+          const int i = i0 + lane + 64 * k;
+          if (i < nmb) acc[u] += x[u][k];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VPW; ++u) {
+      const int v = wv + u * NW;
+      if (wv < NW && v < NV) {  // uniform in the wave
+        const double a = wave_sum(acc[u]);
+        if (lane == 0) M[v] = a;
+      }
+    }
+    __syncthreads();
+    const bool writer = lb == 0 && threadIdx.x == 0;
+    if (S0.done) {
+      bs.stop = 1;
+      return;
+    }
+    const int t1 = tn - 1;  // the iteration whose multiplier step this is
+    const double resid = sqrt(M[MOM_NV]);
+    const bool bad = !(resid == resid) || resid > 1e300;
+    const double lam_prev = S0.lam[t1 & 1];
+    if ((t1 >= 1 && resid < S0.tol) || t1 >= S0.max_inner || bad) {
+      if (writer) {
+        st[b].resid = resid;
+        st[b].done = (resid < S0.tol) ? 1 : 2;
+        if (bad) st[b].nonfinite = 1;
+        st[b].final_step = t1;
+        st[b].lam_final = lam_prev;
+      }
+      bs.stop = 1;
+      return;
+    }
+    const NewtonPar np{S0.eta, S0.r2, lam_prev, S0.newton_rtol, S0.newton_steptol, S0.max_newton, S0.newton_phi,
+                       S0.newton_direct_only};
+    if (threadIdx.x < 64) {  // the series Newton in one wave, as k_newton runs it
+      auto stub = [&](double, double &phi, double &dphi) {
+        phi = np.r2;
+        dphi = -1.0;
+      };
+      int it1 = 0, nd1 = 0;
+      const double l1 = multiplier_newton(M, np, stub, it1, nd1);
+      if (threadIdx.x == 0) {
+        lam_w = l1;
+        it_w = it1;
+        nd_w = nd1;
+      }
+    }
+    __syncthreads();
+    if (nd_w != 0) {  // needs sums over the spectrum: pause for k_newton
+      if (writer) st[b].done = 3;
+      bs.stop = 1;
+      return;
+    }
+    if (writer) {
+      st[b].resid = resid;
+      st[b].lam[tn & 1] = lam_w;
+      st[b].newton_total = S0.newton_total + it_w;
+      st[b].step = tn;
+    }
+    bs.lam_t = lam_w;
   }
   __device__ CI column(int, int ml) const {
     CI ci;
@@ -644,9 +774,9 @@ template <typename T, bool GEN, int KS = 1> struct OpInvScaleD {
     return c2<T>{T(double(v.x) * s), T(double(v.y) * s)};
   }
   __device__ Empty fetch(const StepBlk<T> &, const ColInfo &, bool, long, int) const { return Empty{}; }
-  __device__ void store(const StepBlk<T> &, const ColInfo &, long h, int, c2<T> v, const Empty &, double &,
+  __device__ void store(const StepBlk<T> &bs, const ColInfo &, long h, int, c2<T> v, const Empty &, double &,
                         double *) const {
-    out[h] = v;
+    if (!bs.stop) out[h] = v;
   }
   template <int NT, int N, int CC, class B> __device__ void end(const B &, double, double *, int, int, int) const {}
 };
@@ -686,6 +816,7 @@ template <typename T, bool GEN, int KS = 1> struct OpFwdUpdate {
     s.eta = st[b].eta;
     s.xi = p.xi[b];
     s.q = p.q[b];
+    s.stop = 0;
     return s;
   }
   __device__ ColInfo column(int, int ml) const { return col_info<GEN>(g, ml); }

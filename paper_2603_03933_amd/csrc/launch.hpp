@@ -56,6 +56,8 @@ struct PassArgs {
   int zero_dc = 0;
   int keep_dc = 0;  // Hessian product: keep Lambda_0 (no projection)
   int step = 0;     // subproblem step index
+  int fuse_t = -1;  // >= 1: the axis-0 inverse pass of step fuse_t first takes the multiplier step of fuse_t - 1
+  long mstride = 0;  // stride between the moment partials' values (workgroups per instance x batch)
   int colv = 0;     // column-pass variant of the inner iteration's axis-0 passes (lbk::Cfg V)
 };
 
@@ -120,6 +122,11 @@ template <typename T, int N> struct Impl {
     op.st = a.st;
     op.twn = (const C2 *)a.tw1;
     op.t = a.step;
+    op.tn = a.fuse_t;
+    op.mom = a.mom;
+    op.rpart = a.partial;
+    op.mstride = a.mstride;
+    op.nmb = a.cg.bpi;
     LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, KS>, V>), dim3(a.nblocks),
               dim3(lbk::Cfg<N, V>::NT), 0, a.stream, a.cg, (const C2 *)a.tw, op);
   }

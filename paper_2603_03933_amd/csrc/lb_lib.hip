@@ -1246,8 +1246,10 @@ static void launch_newton(lb_plan *P, const PassArgs &u, const Prm &p, int B) {
             u.cg.cpi, P->st);
 }
 // the three passes of step t (inverse with the scale, axes 1 and 2 with
-// Gamma', forward with the update); returns the update's arguments
-static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
+// Gamma', forward with the update); returns the update's arguments. fuse_t
+// = t >= 1: the inverse pass first takes the multiplier step of t - 1 (the
+// Newton kernel's work); -1: it reads lambda_t from the state
+static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B, int fuse_t = -1) {
   const int prec = P->prec;
   t &= 1;
   const int K = plane_k(P, prec);
@@ -1259,6 +1261,10 @@ static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
   a.st = P->st;
   if (K > 1) set_pair_split(P, a, prec, K);
   a.colv = P->colv;
+  a.fuse_t = fuse_t;
+  a.mom = P->mom;
+  a.partial = P->partial;
+  a.mstride = (long)a.cg.bpi * B;
   {
     KT kt_(P, "col0_inv_scale_d");
     F(P, 0, prec)->cols_inv_scale_d(a);
@@ -1331,20 +1337,22 @@ static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B) {
   return u;
 }
 
-static void enqueue_step(lb_plan *P, const Prm &p, int t, int B = 1) {
-  const int prec = P->prec;
-  const PassArgs u = enqueue_passes(P, p, t, B);
-  {
-    KT kt_(P, "newton");
-    const bool gen = u.g.general != 0;
-    if (prec == LB_FP64) {
-      if (gen) launch_newton<double, true>(P, u, p, B);
-      else launch_newton<double, false>(P, u, p, B);
-    } else {
-      if (gen) launch_newton<float, true>(P, u, p, B);
-      else launch_newton<float, false>(P, u, p, B);
-    }
+// the Newton kernel after the update pass whose arguments are u
+static void enqueue_newton(lb_plan *P, const Prm &p, const PassArgs &u, int B) {
+  KT kt_(P, "newton");
+  const bool gen = u.g.general != 0;
+  if (P->prec == LB_FP64) {
+    if (gen) launch_newton<double, true>(P, u, p, B);
+    else launch_newton<double, false>(P, u, p, B);
+  } else {
+    if (gen) launch_newton<float, true>(P, u, p, B);
+    else launch_newton<float, false>(P, u, p, B);
   }
+}
+
+static void enqueue_step(lb_plan *P, const Prm &p, int t, int B = 1) {
+  const PassArgs u = enqueue_passes(P, p, t, B);
+  enqueue_newton(P, p, u, B);
 }
 
 // Runs Algorithm 3 for the B instances at the front of the batch (radius r[b],
@@ -1428,7 +1436,8 @@ static int run_subproblem(lb_plan *P, const Prm &p, int B, const double *r, cons
   } gs{P, P->stream};
   hipGraphExec_t &gexec = gs.exec;
   const hipStream_t user = P->stream;
-  if (o.graph && !P->timing.on && launched < max_steps && max_steps >= 128) {
+  const bool use_graph = o.graph && !P->timing.on && launched < max_steps && max_steps >= 128;
+  if (use_graph) {
     // capture and replay on the plan's own stream (the null stream cannot be
     // captured), ordered after the work already on the caller's stream
     if (!P->own) LB_HIP(hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking));
@@ -1459,6 +1468,64 @@ static int run_subproblem(lb_plan *P, const Prm &p, int B, const double *r, cons
       if (!P->st_h[b].done) return false;
     return true;
   };
+  // enqueues chunks of steps, then reads the stop flags (while the timings of
+  // the chunk before are read)
+  auto poll = [&]() -> int {
+    LB_TRY(check_launch("subproblem step"));
+    if (timed_done) {
+      timing_flush(P, timed_done);
+      timed_done = 0;
+    }
+    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState) * B, hipMemcpyDeviceToHost, P->stream));
+    LB_HIP(hipStreamSynchronize(P->stream));
+    timed_done = P->timing.pending.size();
+    return 0;
+  };
+  // the multiplier step fused into the inverse pass costs every workgroup of
+  // that pass a read of all the update pass's partials: nmb^2 (MOM_NV + 1)
+  // doubles per instance over the pass. Measured per iteration: 1-1.7 us saved
+  // up to 96^3 (15 MB of such reads), 3 us lost at 128^3 (48 MB); option 1
+  // fuses below 16 MB, option 2 always
+  const double nmb = (double)bpi_col0(P);
+  const double red_bytes = (double)B * nmb * nmb * (lbk::MOM_NV + 1) * 8.0;
+  const bool fuse = o.fused_newton == 2 || (o.fused_newton == 1 && red_bytes <= 16e6);
+  if (!use_graph && fuse && !o.newton_direct && launched < max_steps) {
+    // the multiplier step of step t - 1 runs in the first pass of step t, so
+    // steps 0 .. max_inner + 1 are launched (the last one's first pass takes
+    // the multiplier step of max_inner, which ends the subproblem at the cap)
+    const long tend = (long)o.max_inner + 2;
+    auto run_steps = [&](long t0, bool classic_first) -> int {
+      for (long tn = t0; tn < tend;) {
+        const int n = (int)std::min<long>(chunk, tend - tn);
+        for (int i = 0; i < n; ++i) {
+          const long ti = tn + i;
+          enqueue_passes(P, p, (int)ti, B, (classic_first && ti == t0) ? -1 : (int)ti);
+        }
+        tn += n;
+        LB_TRY(poll());
+        if (all_done()) break;
+      }
+      return 0;
+    };
+    LB_TRY(run_steps(0, false));
+    for (;;) {
+      // an instance paused at a multiplier step whose series Newton needs
+      // sums over the spectrum: that step in the Newton kernel (every other
+      // instance has stopped or paused, so its workgroups return at once),
+      // then the instance's next step reads the multiplier from the state
+      int b = -1;
+      for (int i = 0; i < B && b < 0; ++i)
+        if (P->st_h[i].done == 3) b = i;
+      if (b < 0) break;
+      const long t1 = P->st_h[b].step;
+      P->st_h[b].done = 0;
+      LB_HIP(hipMemcpyAsync(P->st + b, P->st_h + b, sizeof(SubState), hipMemcpyHostToDevice, P->stream));
+      PassArgs u = args_col(P, prec, B, p, 0);
+      enqueue_newton(P, p, u, B);
+      LB_TRY(run_steps(t1 + 1, true));
+    }
+    launched = max_steps;
+  }
   while (launched < max_steps) {
     const int n = (int)std::min<long>(chunk, max_steps - launched);
     if (gexec) {
@@ -1471,14 +1538,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, int B, const double *r, cons
       for (int i = 0; i < n; ++i) enqueue_step(P, p, (int)(launched + i), B);
       launched += n;
     }
-    LB_TRY(check_launch("subproblem step"));
-    if (timed_done) {
-      timing_flush(P, timed_done);
-      timed_done = 0;
-    }
-    LB_HIP(hipMemcpyAsync(P->st_h, P->st, sizeof(SubState) * B, hipMemcpyDeviceToHost, P->stream));
-    LB_HIP(hipStreamSynchronize(P->stream));
-    timed_done = P->timing.pending.size();
+    LB_TRY(poll());
     if (all_done()) break;
   }
   // the loop ended with a synchronisation of the stream it ran on, so the
@@ -1526,6 +1586,7 @@ extern "C" void lb_sub_opts_default(lb_sub_opts *o) {
   o->newton_direct = 0;
   o->single_workgroup = 1;
   o->graph = 0;
+  o->fused_newton = 1;
 }
 
 extern "C" void lb_tr_opts_default(lb_tr_opts *o) {

@@ -46,6 +46,7 @@ class LbSubOpts(C.Structure):
         ("newton_direct", C.c_int),
         ("single_workgroup", C.c_int),
         ("graph", C.c_int),
+        ("fused_newton", C.c_int),
     ]
 
 
@@ -317,7 +318,8 @@ class Plan:
         _check(lib().lb_plan_set_plane_threads(self._h, int(threads)))
 
     def lb_plan_set_plane_split(self, split, threads=0):
-        """Inner iteration in pair-split order (1: half-plane pass, two workgroups per plane) or not (0)."""
+        """Inner iteration in the split order with two (1) or four (2) split-plane workgroups per plane, or one
+        workgroup per plane (0); threads 0: the built-in thread count."""
         _check(lib().lb_plan_set_plane_split(self._h, int(split), int(threads)))
 
     def lb_plan_set_hessvec_split(self, split):

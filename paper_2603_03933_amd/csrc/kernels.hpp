@@ -610,11 +610,11 @@ template <typename T> struct ColTw : ColInfo {
 // the instance's first workgroup records the step in the state. An iteration
 // whose series Newton needs sums over the spectrum pauses the subproblem
 // (done = 3, nothing stored) for the host to take that step with k_newton.
-template <typename T, bool GEN, int KS = 1> struct OpInvScaleD {
+template <typename T, bool GEN, int KS = 1, bool FUSE = false> struct OpInvScaleD {
   static constexpr bool SPLIT = KS > 1;
   static constexpr bool eager_loads = true;
   static constexpr int PAIR = SPLIT ? 2 : 0;
-  static constexpr bool HAS_PRE = true;
+  static constexpr bool HAS_PRE = FUSE;  // a separate instantiation: the step's registers stay out of the plain pass
   Geo g;
   Prm p;
   const c2<T> *b0, *b1;  // b buffers: b_{t-1} lives in (t - 1) & 1
@@ -634,7 +634,7 @@ template <typename T, bool GEN, int KS = 1> struct OpInvScaleD {
     StepBlk<T> s;
     s.bprev = ((t - 1) & 1) ? b1 : b0;
     s.bnext = nullptr;
-    s.lam_t = tn >= 1 ? 0.0 : st[b].lam[t & 1];  // tn >= 1: set by pre()
+    s.lam_t = (FUSE && tn >= 1) ? 0.0 : st[b].lam[t & 1];  // FUSE, tn >= 1: set by pre()
     s.eta = st[b].eta;
     s.xi = p.xi[b];
     s.q = p.q[b];
@@ -644,7 +644,7 @@ template <typename T, bool GEN, int KS = 1> struct OpInvScaleD {
   // the multiplier step (tn >= 1), before the pass's loads (which need its
   // lambda); all threads of the workgroup call it
   template <int NT> __device__ void pre(StepBlk<T> &bs, int b, int lb) const {
-    if (tn < 1) return;  // uniform
+    if (!FUSE || tn < 1) return;  // uniform
     constexpr int NW = NT / 64;                  // whole waves (NT = 96: the second wave, half full, idles)
     static_assert(NW >= 1, "one wave at least");
     constexpr int NV = MOM_NV + 1;               // phi(0), the power sums, the residual

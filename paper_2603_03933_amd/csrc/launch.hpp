@@ -112,8 +112,8 @@ template <typename T, int N> struct Impl {
   // column variants beyond V = 0 are built for the lengths the 3D inner
   // iteration uses most (64 .. 256) where they fit a workgroup
   template <int V> static constexpr bool COLV = V == 0 || (N >= 64 && N <= 256 && lbk::Cfg<N, V>::ok);
-  template <bool GEN, int KS, int V> static void cols_inv_scale_d_t(const PassArgs &a) {
-    lbk::OpInvScaleD<T, GEN, KS> op{};
+  template <bool GEN, int KS, int V, bool FUSE> static void cols_inv_scale_d_f(const PassArgs &a) {
+    lbk::OpInvScaleD<T, GEN, KS, FUSE> op{};
     op.g = a.g;
     op.p = a.p;
     op.b0 = (const C2 *)a.b0;
@@ -127,8 +127,13 @@ template <typename T, int N> struct Impl {
     op.rpart = a.partial;
     op.mstride = a.mstride;
     op.nmb = a.cg.bpi;
-    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, KS>, V>), dim3(a.nblocks),
+    LB_LAUNCH((lbk::k_cols<T, N, true, lbk::OpInvScaleD<T, GEN, KS, FUSE>, V>), dim3(a.nblocks),
               dim3(lbk::Cfg<N, V>::NT), 0, a.stream, a.cg, (const C2 *)a.tw, op);
+  }
+  // fuse_t >= 1: the variant that first takes the multiplier step of fuse_t - 1
+  template <bool GEN, int KS, int V> static void cols_inv_scale_d_t(const PassArgs &a) {
+    if (a.fuse_t >= 1) cols_inv_scale_d_f<GEN, KS, V, true>(a);
+    else cols_inv_scale_d_f<GEN, KS, V, false>(a);
   }
   template <bool GEN, int KS> static void cols_inv_scale_d_v(const PassArgs &a) {
     if constexpr (COLV<1>) {

@@ -159,6 +159,11 @@ typedef struct lb_tr_opts {
   double cg_precond_shift;    /* CONTRACT's CG (the paper leaves the solver open): c > 0 (default 1)
                                  preconditions (H + lambda~ I) by (Lambda + lambda~ + c)^-1, as in
                                  lb_shifted_solve; 0: plain CG */
+  int capped_reject;          /* Algorithm 1 takes s_j from a subproblem that meets its optimality
+                                 conditions; one stopped by max_inner does not. 0 (default): its
+                                 step is still tested by the ratio (counted in sub_capped);
+                                 1: it is rejected without a ratio test, the field stays and
+                                 r_{j+1} = gamma_C r_j */
 } lb_tr_opts;
 
 typedef struct lb_tr_info {

@@ -1612,6 +1612,7 @@ extern "C" void lb_tr_opts_default(lb_tr_opts *o) {
   o->cg_rtol = 1e-12;
   o->cg_maxiter = 1000;
   o->cg_precond_shift = 1.0;
+  o->capped_reject = 0;
   o->verbose = 0;
   o->hard_case = 0;
   o->hard_tol = 1e-12;
@@ -2242,6 +2243,16 @@ static int solve_core(lb_plan *P, const lb_params *params, double *psi, const lb
       if (su.status != LB_OK) inf.sub_capped++;
       const double lam = su.lam, sn = su.dnorm;
       if (!(sn > 0)) return fail(LB_ERR_NONFINITE, "zero trial step");
+      if (o.capped_reject && su.status != LB_OK) {
+        // no optimality conditions, no ratio test: the field stays, the radius shrinks
+        I.r *= o.gamma_c;
+        I.rho_prev = -1.0;  // a rejection for the next iteration's mu update
+        I.have_prev = true;
+        if (o.verbose)
+          std::fprintf(stderr, "[lb] i=%d j=%d E=%.15e |g|=%.3e r=%.3e inner=%d resid=%.2e capped: rejected\n", i2, j,
+                       I.eg.E, I.eg.gnorm, I.r, su.iters, su.resid);
+        continue;
+      }
       if (j > 0 && I.have_prev && I.rho_prev < o.theta) I.mu = std::max(I.mu, lam / sn);
       const double rho = dE[s2] / (sn * sn * sn);
       const char *branch;

@@ -92,6 +92,7 @@ class LbTrOpts(C.Structure):
         ("hard_precond_shift", C.c_double),
         ("seed", C.c_ulonglong),
         ("cg_precond_shift", C.c_double),
+        ("capped_reject", C.c_int),
     ]
 
 

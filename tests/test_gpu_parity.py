@@ -592,3 +592,36 @@ def test_plane_threads_setter_rejects_what_has_no_plane_pass():
     with pytest.raises(lb.LBError):
         plan.lb_plan_set_plane_threads(300)
     plan.lb_plan_set_plane_threads(256)
+
+
+def test_capped_subproblems_rejected_when_asked():
+    """lb_tr_opts.capped_reject: a subproblem stopped by max_inner does not meet
+    the optimality conditions Algorithm 1 takes its step from (Section 3). By
+    default its step still goes through the ratio test (every outer iteration
+    is an acceptance, a contraction or an expansion); with capped_reject = 1 it
+    is rejected outright (the field stays, the radius shrinks), so every
+    accepted step comes from a converged subproblem and the outer iterations
+    split into those three branches plus the capped ones. The 64^2 workload
+    with a 2000-iteration cap, against the oracle's gradient at the end."""
+    inst = I.single_2d(64)
+    shape, box = inst.grid.n, inst.grid.box
+    m = O.Model(O.Grid(shape, box), inst.params.tau, inst.params.gamma)
+    prm = lb.Params(inst.params.tau, inst.params.gamma)
+    plan = lb.Plan(shape, box)
+    e0 = O.energy(m, inst.psi0)
+    res = {}
+    for rej in (0, 1):
+        psi = dev(inst.psi0)
+        opts = lb.tr_opts(grad_norm_inf=0, eps=1e-8, max_outer=300, capped_reject=rej, sub={"max_inner": 2000})
+        info, rc = plan.lb_imex_tr_solve(prm, psi, opts)
+        res[rej] = (info, rc, host(psi))
+        print(f"capped_reject={rej}: rc {rc} outer {info.outer} accepted {info.accepted} contracted "
+              f"{info.contracted} expanded {info.expanded} capped {info.sub_capped} E {info.energy:.12e}")
+    i0, rc0, _ = res[0]
+    i1, rc1, x1 = res[1]
+    assert i0.sub_capped >= 1 and i1.sub_capped >= 1
+    assert i0.accepted + i0.contracted + i0.expanded == i0.outer
+    assert i1.accepted + i1.contracted + i1.expanded + i1.sub_capped == i1.outer
+    assert rc1 == lb.LB_OK
+    assert O.norm(O.gradient(m, x1)) < 1e-7
+    assert i1.energy <= e0

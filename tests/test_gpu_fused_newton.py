@@ -176,3 +176,37 @@ def test_fused_batched_solves_with_paused_instances():
         direct.append(a["newton_direct"])
     print(f"  newton_direct per instance {direct}, outer {[o1[k][0].outer for k in range(B)]}")
     assert max(direct) >= 1  # some instance paused
+
+
+def test_default_fuses_the_step_only_where_it_pays():
+    """fused_newton = 1 (the default) takes the step in the inverse pass while
+    the redundant partial reads stay small (32^3: 9 update workgroups) and
+    keeps the separate launch at 128^3 (520 workgroups: 48 MB of such reads
+    per pass), with the same results as either forced form."""
+    for n, expect_fused in ((32, True), (128, False)):
+        inst = I.bcc_3d(n)
+        plan = lb.Plan(inst.grid.n, inst.grid.box)
+        prm = lb.Params(inst.params.tau, inst.params.gamma)
+        psi = dev(inst.psi0)
+        _, g = plan.lb_energy_grad(prm, psi)
+        r = active_radius(plan, prm, psi, g, max_inner=100)
+        outs = {}
+        for mode in (1, 0, 2):
+            so = lb.sub_opts(eta=0.1, eps_sub=1e-300, max_inner=40, fused_newton=mode)
+            plan.lb_plan_set_timing(mode == 1, "")
+            d, info, rc = plan.lb_tr_subproblem(prm, psi, g, r, so)
+            torch.cuda.synchronize()
+            if mode == 1:
+                tm = plan.timings()
+                plan.lb_plan_set_timing(False, "")
+            outs[mode] = (d.cpu().numpy(), info.lambda_, info.iters, rc)
+            if mode == 1:
+                direct = info.newton_direct
+        launched = tm.get("newton", (0, 0.0))[0]
+        print(f"  {n}^3: separate Newton launches {launched} (steps needing full sums {direct})")
+        if expect_fused:  # only steps whose series needs full sums go to the separate kernel
+            assert launched <= direct < 41
+        else:
+            assert launched == 41  # steps 0 .. 40, one launch each
+        for mode in (0, 2):
+            assert np.array_equal(outs[1][0], outs[mode][0]) and outs[1][1:] == outs[mode][1:]

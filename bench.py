@@ -268,11 +268,14 @@ def large_solve(torch, I, lb, dev, prec="fp32", verbose=1):
     plan = lb.Plan(inst.grid.n, inst.grid.box, precision=prec)
     prm = lb.Params(inst.params.tau, inst.params.gamma)
     psi = torch.from_numpy(inst.psi0).to(dev)
+    # the inner iteration's order for this grid, as at 128^3 (inside the timed region)
     opts = lb.tr_opts(grad_norm_inf=0, eps=LARGE_TOL, max_outer=LARGE_CAPS["max_outer"], verbose=verbose,
                       sub={"max_inner": LARGE_CAPS["max_inner"], "poll_every": 64,
                            "eps_sub_rel": LARGE_CAPS["eps_sub_rel"] if prec == "fp32" else 0.0})
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    plan.lb_plan_autotune(prm, psi, reps=10)
+    variant = plan.lb_plan_get_variant()
     info, rc = plan.lb_imex_tr_solve(prm, psi, opts)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -290,6 +293,7 @@ def large_solve(torch, I, lb, dev, prec="fp32", verbose=1):
         "seconds": dt, "status": "converged" if rc == 0 else "not_converged", "energy": info.energy,
         "gnorm": info.gnorm, "outer": info.outer, "inner": info.inner_total, "cg": info.cg_total,
         "sub_capped": info.sub_capped,
+        "autotune": {"split": variant[0], "plane_pass_threads": variant[1], "column_plan": variant[2]},
         "lanczos30": [{"ritz": r, "residual": e} for r, e in ritz],
         "lambda_min_upper_bound": min(r for r, _ in ritz),
         "sp2_check_passed": min(r for r, _ in ritz) >= -1e-7,

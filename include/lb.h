@@ -460,19 +460,22 @@ int lb_plan_set_plane_split(lb_plan *plan, int split, int threads);
  * orders compute the same product; results agree to rounding. */
 int lb_plan_set_hessvec_split(lb_plan *plan, int split);
 
-/* Radix plan of the inner iteration's two axis-0 passes (the same columns
- * per workgroup in each): 0, radix 8 first (the built-in plan); 1, radix 4
- * first (more threads per transform, one pass more at length 128); 2, radix
- * 16 first (fewer threads, one pass fewer). Plans 1 and 2 exist for axis-0
- * lengths 64 to 256 (LB_ERR_UNSUPPORTED otherwise; LB_ERR_ARG for other
- * values). The plans compute the same transforms: results agree to rounding,
- * and each is deterministic. */
+/* Plan of the inner iteration's two axis-0 passes: 0, radix 8 first (the
+ * built-in plan); 1, radix 4 first (more threads per transform, one pass
+ * more at length 128); 2, radix 16 first (fewer threads, one pass fewer),
+ * with the same columns per workgroup; 3, radix 8 first with twice the
+ * columns per workgroup (longer contiguous runs per row in the split order,
+ * half the workgroups and partial sums; one or two parts only: with four,
+ * or where a part's columns do not fill its workgroups, the passes run plan
+ * 0). Plans 1 to 3 exist for axis-0 lengths 64 to 256 (LB_ERR_UNSUPPORTED
+ * otherwise; LB_ERR_ARG for other values). The plans compute the same
+ * transforms: results agree to rounding, and each is deterministic. */
 int lb_plan_set_column_plan(lb_plan *plan, int column_plan);
 
 /* The inner iteration's variant in use: *split = 0, 1 or 2 (no split, 2 or
  * 4 parts), *threads the plane or split-plane pass's thread count (0 when the
  * inner iteration runs the five passes), *column_plan the axis-0 passes'
- * radix plan. */
+ * plan (as they run it: 0 where plan 3 does not apply). */
 int lb_plan_get_variant(lb_plan *plan, int *split, int *threads, int *column_plan);
 
 #ifdef __cplusplus

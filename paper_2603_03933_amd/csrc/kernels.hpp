@@ -161,9 +161,9 @@ constexpr int pow2_floor(int x) {
 // variants keep the C columns of V = 0 (autotuner candidates for the inner
 // iteration's axis-0 passes; ok: they fit a workgroup).
 template <int N, int V = 0> struct Cfg {
-  static constexpr int PLAN = V == 0 ? 0 : (V == 1 ? 2 : 1);
+  static constexpr int PLAN = V == 0 || V == 3 ? 0 : (V == 1 ? 2 : 1);
   static constexpr int TPF0 = Shape<N>::TPF;
-  static constexpr int C0 = pow2_floor((TPF0 >= 32 ? 512 : 256) / TPF0);
+  static constexpr int C0 = pow2_floor((TPF0 >= 32 ? 512 : 256) / TPF0) * (V == 3 ? 2 : 1);  // V = 3: twice the columns
   static constexpr int C = C0 > 64 ? 64 : (C0 < 1 ? 1 : C0);  // transforms per workgroup
   static constexpr int TPF = N / lbfft::radix_p<PLAN>(N, 0);    // threads per transform
   static constexpr int NT = C * TPF;                             // threads per workgroup

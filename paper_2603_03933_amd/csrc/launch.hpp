@@ -64,6 +64,7 @@ struct PassArgs {
 struct NFuncs {
   int C = 0, NT = 0;  // transforms and threads per workgroup
   int colv_built = 1;  // bit V: the inner iteration's axis-0 passes built in column variant V
+  int C3 = 0;          // columns per workgroup of column variant 3 (0: not built)
   void (*cols_plain)(const PassArgs &, bool inv) = nullptr;
   void (*cols_inv_scale_d)(const PassArgs &) = nullptr;
   void (*cols_fwd_update)(const PassArgs &) = nullptr;
@@ -112,6 +113,9 @@ template <typename T, int N> struct Impl {
   // column variants beyond V = 0 are built for the lengths the 3D inner
   // iteration uses most (64 .. 256) where they fit a workgroup
   template <int V> static constexpr bool COLV = V == 0 || (N >= 64 && N <= 256 && lbk::Cfg<N, V>::ok);
+  // V = 3 (twice the columns of V = 0 per workgroup, same radix plan): the
+  // inner iteration's axis-0 passes in one and two parts (runs of C/2
+  // columns per part: 128 B in FP32 at 256^3)
   template <bool GEN, int KS, int V, bool FUSE> static void cols_inv_scale_d_f(const PassArgs &a) {
     lbk::OpInvScaleD<T, GEN, KS, FUSE> op{};
     op.g = a.g;
@@ -141,6 +145,9 @@ template <typename T, int N> struct Impl {
     }
     if constexpr (COLV<2>) {
       if (a.colv == 2) return cols_inv_scale_d_t<GEN, KS, 2>(a);
+    }
+    if constexpr (COLV<3> && KS <= 2) {
+      if (a.colv == 3) return cols_inv_scale_d_t<GEN, KS, 3>(a);
     }
     cols_inv_scale_d_t<GEN, KS, 0>(a);
   }
@@ -182,6 +189,9 @@ template <typename T, int N> struct Impl {
     }
     if constexpr (COLV<2>) {
       if (a.colv == 2) return cols_fwd_update_t<GEN, KS, 2>(a);
+    }
+    if constexpr (COLV<3> && KS <= 2) {
+      if (a.colv == 3) return cols_fwd_update_t<GEN, KS, 3>(a);
     }
     cols_fwd_update_t<GEN, KS, 0>(a);
   }
@@ -331,7 +341,8 @@ template <typename T, int N> struct Impl {
     NFuncs f;
     f.C = lbk::Cfg<N>::C;
     f.NT = NT;
-    f.colv_built = 1 | (COLV<1> ? 2 : 0) | (COLV<2> ? 4 : 0);
+    f.colv_built = 1 | (COLV<1> ? 2 : 0) | (COLV<2> ? 4 : 0) | (COLV<3> ? 8 : 0);
+    f.C3 = COLV<3> ? lbk::Cfg<N, 3>::C : 0;
     f.cols_plain = &cols_plain;
     f.cols_inv_scale_d = &cols_inv_scale_d;
     f.cols_fwd_update = &cols_fwd_update;

@@ -861,6 +861,28 @@ static void set_pair_split(const lb_plan *P, PassArgs &a, int prec, int K) {
   a.cg.kparts = K;
   a.tw1 = TW(P, 1, prec);
 }
+// column variant 3 (twice the columns per workgroup) takes one or two parts
+// whose columns fill its workgroups exactly
+static bool colv_ok(const lb_plan *P, int prec, int K, int cv) {
+  if (cv != 3) return true;
+  const int C3 = F(P, 0, prec)->C3;
+  if (C3 <= 0 || K > 2) return false;
+  if (K == 1) return true;
+  const long hcols = (long)(P->n1 / K) * P->nhl;
+  return hcols % (C3 / K) == 0 && cdiv((long)P->n1 * P->nhl, (long)C3) * C3 == K * hcols;
+}
+// the arguments of the inner iteration's axis-0 passes (inverse and update):
+// the split order with K parts and the column variant in use
+static PassArgs col0_args(const lb_plan *P, int prec, int B, const Prm &p, int K) {
+  PassArgs a = args_col(P, prec, B, p, 0);
+  if (K > 1) set_pair_split(P, a, prec, K);
+  a.colv = colv_ok(P, prec, K, P->colv) ? P->colv : 0;
+  if (a.colv == 3) {
+    a.cg.bpi = (int)cdiv((long)a.cg.cpi, (long)F(P, 0, prec)->C3);
+    a.nblocks = a.cg.bpi * B;
+  }
+  return a;
+}
 
 // ---------------------------------------------------------------------------
 // mode 0: P(L v + Gamma' v); 1: P L v + Gamma' v; 2: (L v + Gamma' v) / N (raw coordinates)
@@ -1253,14 +1275,12 @@ static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B, int fuse_
   const int prec = P->prec;
   t &= 1;
   const int K = plane_k(P, prec);
-  PassArgs a = args_col(P, prec, B, p, 0);
+  PassArgs a = col0_args(P, prec, B, p, K);
   a.step = t;
   a.b0 = P->B0;
   a.b1 = P->B1;
   a.out = P->WT;
   a.st = P->st;
-  if (K > 1) set_pair_split(P, a, prec, K);
-  a.colv = P->colv;
   a.fuse_t = fuse_t;
   a.mom = P->mom;
   a.partial = P->partial;
@@ -1318,9 +1338,7 @@ static PassArgs enqueue_passes(lb_plan *P, const Prm &p, int t, int B, int fuse_
       }
     }
   }
-  PassArgs u = args_col(P, prec, B, p, 0);
-  if (K > 1) set_pair_split(P, u, prec, K);
-  u.colv = P->colv;
+  PassArgs u = col0_args(P, prec, B, p, K);
   u.in = P->WT;
   u.b0 = P->B0;
   u.b1 = P->B1;
@@ -1520,7 +1538,7 @@ static int run_subproblem(lb_plan *P, const Prm &p, int B, const double *r, cons
       const long t1 = P->st_h[b].step;
       P->st_h[b].done = 0;
       LB_HIP(hipMemcpyAsync(P->st + b, P->st_h + b, sizeof(SubState), hipMemcpyHostToDevice, P->stream));
-      PassArgs u = args_col(P, prec, B, p, 0);
+      PassArgs u = col0_args(P, prec, B, p, plane_k(P, prec));
       enqueue_newton(P, p, u, B);
       LB_TRY(run_steps(t1 + 1, true));
     }
@@ -2501,8 +2519,8 @@ extern "C" int lb_plan_autotune(lb_plan *P, const lb_params *params, const doubl
       // K = 1: the plane pass's thread variants, or once the five passes
       if (k == 1 && (whole ? !f1->plane_inner_nt[v] : v != 0)) continue;
       if (k > 1 && (!split_ok(P, prec, k) || !f1->plane_split_nt[kidx(k)][v])) continue;
-      for (int cv = 0; cv < 3; ++cv)
-        if (colv_built >> cv & 1) cands.push_back(Cand{k, v, cv, 0.0f});
+      for (int cv = 0; cv < 4; ++cv)
+        if ((colv_built >> cv & 1) && colv_ok(P, prec, k, cv)) cands.push_back(Cand{k, v, cv, 0.0f});
     }
   for (int round = 0; round < 2; ++round) {
     for (Cand &c : cands) {
@@ -2569,11 +2587,11 @@ extern "C" int lb_plan_get_variant(lb_plan *P, int *split, int *threads, int *co
   if (!P || !split || !threads || !column_plan) return fail(LB_ERR_ARG, "null argument");
   *split = 0;
   *threads = 0;
-  *column_plan = P->colv;
   const int prec = P->prec;
   const NFuncs *f1 = P->dim == 3 ? F(P, 1, prec) : nullptr;
   const int nts[3] = {256, 512, 1024};
   const int K = plane_k(P, prec);
+  *column_plan = colv_ok(P, prec, K, P->colv) ? P->colv : 0;
   if (K > 1) {
     const int ki = kidx(K);
     *split = code_of_k(K);
@@ -2599,7 +2617,7 @@ extern "C" int lb_plan_set_hessvec_split(lb_plan *P, int split) {
 
 extern "C" int lb_plan_set_column_plan(lb_plan *P, int column_plan) {
   if (!P) return fail(LB_ERR_ARG, "null plan");
-  if (column_plan < 0 || column_plan > 2) return fail(LB_ERR_ARG, "column plan must be 0, 1 or 2");
+  if (column_plan < 0 || column_plan > 3) return fail(LB_ERR_ARG, "column plan must be 0, 1, 2 or 3");
   if (!(F(P, 0, P->prec)->colv_built >> column_plan & 1))
     return fail(LB_ERR_UNSUPPORTED, "column plan not built for this axis-0 length");
   P->colv = column_plan;

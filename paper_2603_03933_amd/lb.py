@@ -328,7 +328,8 @@ class Plan:
         _check(lib().lb_plan_set_hessvec_split(self._h, int(split)))
 
     def lb_plan_set_column_plan(self, column_plan):
-        """Radix plan of the inner iteration's axis-0 passes (0: 8 first, 1: 4 first, 2: 16 first)."""
+        """Plan of the inner iteration's axis-0 passes (0: radix 8 first, 1: 4 first, 2: 16 first, 3: 8 first with
+        twice the columns per workgroup, one or two parts only)."""
         _check(lib().lb_plan_set_column_plan(self._h, int(column_plan)))
 
     def lb_plan_get_variant(self):

@@ -65,19 +65,24 @@ def _large_subproblem_oracle():
     return inst, m, g_hat, ref
 
 
-@pytest.mark.parametrize("precision,tol,split", [("fp32", 1e-5, -1), ("fp64", 1e-12, -1), ("fp32", 1e-5, 2),
-                                               ("fp64", 1e-12, 2)])
-def test_large_256_subproblem_iterations(precision, tol, split):
+@pytest.mark.parametrize("precision,tol,split,cplan", [("fp32", 1e-5, -1, 0), ("fp64", 1e-12, -1, 0),
+                                                     ("fp32", 1e-5, 2, 0), ("fp64", 1e-12, 2, 0),
+                                                     ("fp32", 1e-5, 1, 3)])
+def test_large_256_subproblem_iterations(precision, tol, split, cplan):
     """Five iterations of Algorithm 3 at 256^3 against the oracle's five
-    (FP64): the built-in five passes of the column and row kernels, and the
-    four-part split order (split = 2), in FP32 and FP64."""
-    print(f"256^3 subproblem {precision} split {split}", flush=True)
+    (FP64): the built-in five passes of the column and row kernels, the
+    four-part split order (split = 2), in FP32 and FP64, and in FP32 the
+    two-part order (half planes of 132 KB) with the axis-0 passes in column
+    plan 3 (32 columns per workgroup)."""
+    print(f"256^3 subproblem {precision} split {split} column plan {cplan}", flush=True)
     inst, m, g_hat, ref = _large_subproblem_oracle()
     shape, box = inst.grid.n, inst.grid.box
     plan = lb.Plan(shape, box, precision=precision)
     if split > 0:
         plan.lb_plan_set_plane_split(split, 0)
-    assert plan.lb_plan_get_variant()[0] == max(split, 0)
+    if cplan:
+        plan.lb_plan_set_column_plan(cplan)
+    assert plan.lb_plan_get_variant()[0::2] == (max(split, 0), cplan)
     d, info, rc = plan.lb_tr_subproblem(lb.Params(m.tau, m.gamma), dev(inst.psi0), dev(O.inv(g_hat)), 0.02,
                                         lb.sub_opts(eta=0.1, eps_sub=0.0, max_inner=5))
     err = rms(host(d) - O.inv(ref.d)) / rms(O.inv(ref.d))

@@ -61,25 +61,27 @@ def test_solve_many_rejects_shared_plan_and_mismatched_params():
         lb.lb_imex_tr_solve_many([bplan], [prm], [torch.zeros(2 * psi0.size, dtype=torch.float64, device=DEV)])
 
 
-# (grid, box, precision): the multi-kernel 2D path, the one-workgroup 2D path
-# (one workgroup per instance), the 3D plane path, a 3D grid with axis-1 and
-# row passes
+# (grid, box, precision, axis-0 column plan): the multi-kernel 2D path, the
+# one-workgroup 2D path (one workgroup per instance), the 3D plane path, a 3D
+# grid with axis-1 and row passes, and axis-0 passes of 64 columns per
+# workgroup (column plan 3; nine per instance, the last one ragged)
 BATCH_CASES = [
-    ((48, 96), (6 * math.pi, 12 * math.pi), "fp64"),
-    ((48, 96), (6 * math.pi, 12 * math.pi), "fp32"),
-    ((32, 32), (4 * math.pi, 4 * math.pi), "fp64"),
-    ((32, 32, 32), (4 * math.sqrt(2) * math.pi,) * 3, "fp64"),
-    ((16, 24, 32), (2 * math.pi, 3 * math.pi, 4 * math.pi), "fp32"),
+    ((48, 96), (6 * math.pi, 12 * math.pi), "fp64", 0),
+    ((48, 96), (6 * math.pi, 12 * math.pi), "fp32", 0),
+    ((32, 32), (4 * math.pi, 4 * math.pi), "fp64", 0),
+    ((32, 32, 32), (4 * math.sqrt(2) * math.pi,) * 3, "fp64", 0),
+    ((16, 24, 32), (2 * math.pi, 3 * math.pi, 4 * math.pi), "fp32", 0),
+    ((64, 32, 32), (8 * math.sqrt(2) * math.pi, 4 * math.sqrt(2) * math.pi, 4 * math.sqrt(2) * math.pi), "fp64", 3),
 ]
 
 
-@pytest.mark.parametrize("shape,box,precision", BATCH_CASES)
-def test_batched_solve_equals_single_solves_bit_for_bit(shape, box, precision):
+@pytest.mark.parametrize("shape,box,precision,cplan", BATCH_CASES)
+def test_batched_solve_equals_single_solves_bit_for_bit(shape, box, precision, cplan):
     """Five instances ((tau, gamma) and noise per instance; they converge after
     different numbers of outer iterations and leave the batch at different
     times) solved in one batch against five single-instance solves: identical
     fields, iteration counts and energies."""
-    print(f"batched solve {shape} {precision}", flush=True)
+    print(f"batched solve {shape} {precision} column plan {cplan}", flush=True)
     B = 5
     prms = [lb.Params(-0.15 - 0.03 * k, 0.2 + 0.05 * k) for k in range(B)]
     psi0 = np.stack([I.zero_mean_noise(shape, 0.1, 90 + k) for k in range(B)])
@@ -89,11 +91,16 @@ def test_batched_solve_equals_single_solves_bit_for_bit(shape, box, precision):
     opts = lb.tr_opts(grad_norm_inf=0, eps=1e-8, max_outer=60, sub=sub)
     single = []
     p1 = lb.Plan(shape, box, precision=precision)
+    if cplan:
+        p1.lb_plan_set_column_plan(cplan)
     for k in range(B):
         psi = torch.from_numpy(psi0[k]).to(DEV)
         info, rc = p1.lb_imex_tr_solve(prms[k], psi, opts)
         single.append((info, rc, psi.cpu().numpy()))
     pb = lb.Plan(shape, box, batch=B, precision=precision)
+    if cplan:
+        pb.lb_plan_set_column_plan(cplan)
+        assert pb.lb_plan_get_variant()[2] == cplan
     psi = torch.from_numpy(psi0).to(DEV)
     res = pb.lb_imex_tr_solve_batch(prms, psi, opts)
     out = psi.cpu().numpy()
@@ -106,8 +113,10 @@ def test_batched_solve_equals_single_solves_bit_for_bit(shape, box, precision):
         assert info.energy == sinfo.energy and info.gnorm == sinfo.gnorm, k
         assert np.array_equal(out[k], spsi), k
     print(f"  outer iterations per instance: {outers}")
-    # one endpoint against the oracle (FP64 plans)
-    if precision == "fp64":
+    # one endpoint against the oracle (FP64 plans up to 32^3 points: the
+    # oracle's solve of the 64 x 32 x 32 case would take minutes; its batch
+    # differs from the 32^3 case only in the axis-0 column plan)
+    if precision == "fp64" and math.prod(shape) <= 32 ** 3:
         m = O.Model(O.Grid(shape, box), prms[1].tau, prms[1].gamma)
         ref = O.imex_tr_solve(m, psi0[1], O.TROpts(grad_norm="l2", eps=1e-8, max_outer=60, max_inner=3000))
         if ref.converged and res[1][1] == lb.LB_OK:
